@@ -1,0 +1,127 @@
+/*
+ * spec.h -- C ABI of the MI355X boundary oracle for spectrahedra and of the
+ * random walks built on it (Chalkis, Emiris, Fisikopoulos, Repouskos,
+ * Tsigaridas, "Efficient Sampling from Feasible Sets of SDPs and Volume
+ * Approximation", arXiv:2010.03817).
+ *
+ * The problem (paper, Section 1, eq. (1)): a spectrahedron
+ *     S = { x in R^n : F(x) = A0 + x_1 A1 + ... + x_n An  is PSD },
+ * A_i symmetric, S bounded.  A line x + t v (or a degree-2 curve) meets the
+ * boundary at the roots of det F(Phi(t)) nearest 0 (Lemma "PEP and S cap C");
+ * the boundary normal there is (u^T A_i u)_i with u in ker F (Lemma
+ * "Gradient of det F").
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns spec_status; SPEC_OK (0) on success.  Call-level
+ *    errors (EINVAL, ENOMEM, EDEVICE) leave outputs unspecified.
+ *  - Per-element outcomes go to an int32 status array (SPEC_OK,
+ *    SPEC_NOT_INTERIOR, SPEC_UNBOUNDED, SPEC_NONSMOOTH, SPEC_NOCONV); values of
+ *    NOT_INTERIOR elements are NaN.
+ *  - Arrays are dense row-major float64 (batch x n) unless stated.
+ *  - Entry points without a suffix take HOST pointers: inputs are read and
+ *    outputs written during the call only; the call synchronises the device.
+ *  - Entry points ending in _dev take DEVICE pointers and a hipStream_t passed
+ *    as void* (NULL = the null stream); they are asynchronous on that stream.
+ *    Buffers must stay live until the caller synchronises the stream.
+ *  - A handle owns its device copies of the LMI and its scratch memory until
+ *    spec_destroy; it is not thread-safe (use one stream per handle).
+ *  - The library runs on the device current at spec_create; it never falls
+ *    back to the CPU: without a usable device spec_create returns
+ *    SPEC_EDEVICE.
+ */
+#ifndef SPEC_H
+#define SPEC_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPEC_OK = 0,
+    SPEC_EINVAL = 1,        /* bad argument (size < 1, NULL, non-symmetric block, ...) */
+    SPEC_ENOMEM = 2,        /* device allocation failed */
+    SPEC_EDEVICE = 3,       /* HIP runtime error or no device */
+    SPEC_NOT_INTERIOR = 4,  /* start point not in the interior (Cholesky failed)   */
+    SPEC_UNBOUNDED = 5,     /* t+ = +inf or t- = -inf along the curve              */
+    SPEC_NONSMOOTH = 6,     /* hit at a point where the normal is not determined   */
+    SPEC_REFLECT_CAP = 7,   /* more than rho reflections: the chain stayed         */
+    SPEC_CERT_FALLBACK = 8, /* informational: learned bracket not certified        */
+    SPEC_NOCONV = 9,        /* eigen iteration hit its cap; value is a bound        */
+    SPEC_ENOTSUP = 10       /* size outside what the device kernels support        */
+} spec_status;
+
+typedef enum { SPEC_BLOCK_DENSE = 0, SPEC_BLOCK_DIAG = 1 } spec_block_kind;
+
+typedef enum {
+    SPEC_WALK_HNR = 0,      /* Hit-and-Run, Alg. Hit-and-Run                        */
+    SPEC_WALK_CHNR = 1,     /* coordinate-directions Hit-and-Run                   */
+    SPEC_WALK_BILLIARD = 2, /* billiard walk, Alg. Billiard                        */
+    SPEC_WALK_HMC = 3       /* HMC with reflections, Alg. HMC_w_reflection         */
+} spec_walk_kind;
+
+typedef struct spec_s* spec_handle;
+
+/* Largest merged dense block the device kernels handle (one workgroup holds
+ * the packed factor, m(m+1)/2 doubles, in the 160 KiB of LDS). */
+#define SPEC_MAX_DENSE 200
+/* Largest Krylov dimension accepted by spec_set_lanczos. */
+#define SPEC_MAX_KRYLOV 160
+
+/* Create a handle for the LMI F(x) = blkdiag_b (A_{b,0} + sum_i x_i A_{b,i}).
+ *  n           number of coordinates (>= 1)
+ *  nblocks     number of blocks (>= 1); block_size[b] >= 1, kind[b] as above
+ *  A           host float64, blocks concatenated; DENSE block b: (n+1) full
+ *              symmetric m_b x m_b row-major matrices A_{b,0}, ..., A_{b,n};
+ *              DIAG block b: (n+1) vectors of length m_b (diagonals).
+ * Dense blocks are merged into one block-diagonal dense block and diagonal
+ * blocks into one diagonal block (the same LMI).  Returns SPEC_EINVAL if a
+ * dense block is not symmetric to 1e-12 relative, SPEC_ENOTSUP if the merged
+ * dense size exceeds SPEC_MAX_DENSE.  The handle owns device copies of A. */
+spec_status spec_create(int n, int nblocks, const int* block_size, const int* kind,
+                        const double* A, spec_handle* out);
+spec_status spec_destroy(spec_handle h);
+
+/* Sizes of a handle: n, merged dense size m, merged diagonal size md. */
+spec_status spec_dims(spec_handle h, int* n, int* m, int* md);
+
+const char* spec_status_str(spec_status s);
+
+/* Lanczos settings of the extreme-eigenvalue step: at most kmax basis vectors
+ * (default 80) and the stopping test beta_{k+1} |s_k| <= tol |theta| on the
+ * residual bound of both extreme Ritz pairs (default 1e-10).  SPEC_ENOTSUP if
+ * the basis would not fit in LDS for this handle's m. */
+spec_status spec_set_lanczos(spec_handle h, int kmax, double tol);
+
+/* MEMBERSHIP (Alg. MEMBERSHIP, read as strict definiteness): interior[e] = 1
+ * iff F(x_e) is positive definite (Cholesky succeeds). */
+spec_status spec_membership(spec_handle h, int batch, const double* x, int8_t* interior);
+spec_status spec_membership_dev(spec_handle h, int batch, const double* x, int8_t* interior,
+                                void* stream);
+
+/* INTERSECTION for lines (Alg. INTERSECTION with Phi(t) = x + t v):
+ * t_minus <= 0 <= t_plus, the ends of the maximal interval around 0 where
+ * F(x + t v) is PSD: t+ = -1/lambda_min(C), t- = -1/lambda_max(C),
+ * C = L^{-1} B(v) L^{-T}, F(x) = L L^T, B(v) = sum v_i A_i; diagonal rows by
+ * ratio.  status[e]: OK, NOT_INTERIOR (NaN outputs), UNBOUNDED (+-INFINITY),
+ * NOCONV. */
+spec_status spec_intersect(spec_handle h, int batch, const double* x, const double* v,
+                           double* t_minus, double* t_plus, int32_t* status);
+spec_status spec_intersect_dev(spec_handle h, int batch, const double* x, const double* v,
+                               double* t_minus, double* t_plus, int32_t* status, void* stream);
+
+/* REFLECTION (Alg. REFLECTION, eq. (reflection)) for lines: t_plus as above,
+ * s_out = v - 2 <v, w> w the reflected direction at x + t+ v, w_out (nullable)
+ * the unit normal oriented outward (<v, w> >= 0).  A hit on a diagonal row
+ * uses that row's gradient.  status[e]: as intersect, plus NONSMOOTH when the
+ * smallest eigenvalue is numerically multiple or the normal vanishes (the
+ * reflection is still returned).  If t+ = inf: s = v, w = 0, UNBOUNDED. */
+spec_status spec_reflect(spec_handle h, int batch, const double* x, const double* v,
+                         double* t_plus, double* s_out, double* w_out, int32_t* status);
+spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const double* v,
+                             double* t_plus, double* s_out, double* w_out, int32_t* status,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,29 @@
+/*
+ * spec_diag.h -- diagnostic entry points of the spectrahedron oracle library
+ * (checks of the device building blocks; not part of the method).
+ * Host pointers; synchronous; return spec_status.
+ */
+#ifndef SPEC_DIAG_H
+#define SPEC_DIAG_H
+#include "spec.h"
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Runs one v_mfma_f64_16x16x4f64 on a wave with A[i][k] = i + 100 k given in
+ * lane (i + 16 k) and B[k][j] = (k == j mod 4) given in lane (j + 16 k);
+ * host_out receives 64 lanes x 4 accumulator doubles (256 values). */
+spec_status spec_diag_mfma_layout(double* host_out);
+
+/* C = A * B (transB = 0: B is K x N) or A * B^T (transB = 1: B is N x K),
+ * all row-major float64 host arrays; M, N multiples of 64, K of 16. */
+spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A, const double* B, double* C);
+
+/* After an intersect/reflect call of `batch` elements: per element
+ * (lambda_min(C), lambda_max(C), second smallest Ritz value, Lanczos steps). */
+spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,429 @@
+// Host implementation of the C ABI declared in include/spec.h: instance
+// upload, workspace management and the order of kernel launches for each
+// entry point.  All arithmetic of the oracle runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "spec.h"
+#include "spec_diag.h"
+#include "spec_kernels.h"
+
+using namespace spec;
+
+namespace {
+
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+template <class T>
+hipError_t dalloc(T** p, size_t count, bool zero = true) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) return e;
+    if (zero) e = hipMemset(*p, 0, sizeof(T) * count);
+    return e;
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+spec_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return SPEC_OK;
+    if (e == hipErrorOutOfMemory) return SPEC_ENOMEM;
+    return SPEC_EDEVICE;
+}
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return from_hip(_e);     \
+    } while (0)
+#define SPCHK(expr)                                    \
+    do {                                               \
+        spec_status _s = (expr);                       \
+        if (_s != SPEC_OK) return _s;                  \
+    } while (0)
+
+}  // namespace
+
+struct spec_s {
+    int device = 0;
+    int n = 0, m = 0, md = 0, P = 0, Ptot = 0, K = 0, Kpad = 0, ldA = 0, Arows = 0, Nn = 0, ldw = 0;
+    double* dA = nullptr;  // Arows x ldA
+    // Lanczos settings
+    int kmax = 80;
+    double tol = 1e-10;
+    // workspace (capacity in chains, multiple of 64)
+    int cap = 0;
+    double *dZ = nullptr, *dFB = nullptr, *dW = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
+    double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
+    int32_t *dHit = nullptr, *dSt = nullptr;
+    // staging for the host-pointer entry points
+    int scap = 0;
+    double *sX = nullptr, *sV = nullptr, *sO1 = nullptr, *sO2 = nullptr, *sS = nullptr, *sW = nullptr;
+    int32_t* sSt = nullptr;
+    int8_t* sI = nullptr;
+
+    void free_work() {
+        dfree(dZ); dfree(dFB); dfree(dW); dfree(dU); dfree(dU2); dfree(dWn);
+        dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
+        cap = 0;
+    }
+    void free_stage() {
+        dfree(sX); dfree(sV); dfree(sO1); dfree(sO2); dfree(sS); dfree(sW); dfree(sSt); dfree(sI);
+        scap = 0;
+    }
+    spec_status ensure(int batch) {
+        if (batch <= cap) return SPEC_OK;
+        free_work();
+        const int c = round_up(batch, 64);
+        HIPCHK(dalloc(&dZ, (size_t)2 * c * Kpad));
+        HIPCHK(dalloc(&dFB, (size_t)2 * c * ldA, false));
+        HIPCHK(dalloc(&dW, (size_t)c * ldw, false));
+        HIPCHK(dalloc(&dU, (size_t)c * m, false));
+        HIPCHK(dalloc(&dU2, (size_t)c * ldA));
+        HIPCHK(dalloc(&dWn, (size_t)c * Nn, false));
+        HIPCHK(dalloc(&dLam, (size_t)c * 4));
+        HIPCHK(dalloc(&dTm, (size_t)c));
+        HIPCHK(dalloc(&dTp, (size_t)c));
+        HIPCHK(dalloc(&dHit, (size_t)c));
+        HIPCHK(dalloc(&dSt, (size_t)c));
+        cap = c;
+        return SPEC_OK;
+    }
+    spec_status ensure_stage(int batch) {
+        if (batch <= scap) return SPEC_OK;
+        free_stage();
+        const int c = round_up(batch, 64);
+        HIPCHK(dalloc(&sX, (size_t)c * n, false));
+        HIPCHK(dalloc(&sV, (size_t)c * n, false));
+        HIPCHK(dalloc(&sO1, (size_t)c, false));
+        HIPCHK(dalloc(&sO2, (size_t)c, false));
+        HIPCHK(dalloc(&sS, (size_t)c * n, false));
+        HIPCHK(dalloc(&sW, (size_t)c * n, false));
+        HIPCHK(dalloc(&sSt, (size_t)c, false));
+        HIPCHK(dalloc(&sI, (size_t)c, false));
+        scap = c;
+        return SPEC_OK;
+    }
+};
+
+namespace {
+
+// [F; B] for `batch` chains: rows 0..batch-1 = F(x_c), rows bp + c = B(v_c).
+spec_status assemble(spec_s* h, int batch, const double* x, const double* v, int* bp_out, hipStream_t s) {
+    const int bp = round_up(batch, 64);
+    *bp_out = bp;
+    HIPCHK(launch_build_z(batch, h->n, h->Kpad, x, v, h->dZ, bp, s));
+    const int M = v ? 2 * bp : bp;
+    HIPCHK(gemm_f64(false, M, h->ldA, h->Kpad, h->dZ, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA, s));
+    return SPEC_OK;
+}
+
+spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, double* tm, double* tp,
+                        int32_t* st, bool want_vec, const double* ell, hipStream_t s) {
+    int bp = 0;
+    SPCHK(assemble(h, batch, x, v, &bp, s));
+    HIPCHK(launch_factor(batch, h->m, h->md, h->P, h->dFB, h->ldA, h->dW, h->ldw, st, s));
+    LanczosArgs a{};
+    a.batch = batch;
+    a.m = h->m;
+    a.md = h->md;
+    a.P = h->P;
+    a.kmax = h->kmax;
+    a.tol = h->tol;
+    a.FB = h->dFB;
+    a.ldfb = h->ldA;
+    a.brow0 = bp;
+    a.W = h->dW;
+    a.ldw = h->ldw;
+    a.status = st;
+    a.tm = tm;
+    a.tp = tp;
+    a.hit = h->dHit;
+    a.lam = h->dLam;
+    a.want_vec = want_vec ? 1 : 0;
+    a.ell = ell;
+    a.u = h->dU;
+    a.ldu = h->m;
+    a.U2 = h->dU2;
+    a.ldu2 = h->ldA;
+    HIPCHK(launch_lanczos(a, s));
+    return SPEC_OK;
+}
+
+// w = vec(u u^T) * Astack^T for the dense hits, then s and the unit normal.
+spec_status reflect_tail(spec_s* h, int batch, const double* v, const double* tp, int32_t* st, double* s_out,
+                         double* w_out, hipStream_t s) {
+    const int bp = round_up(batch, 64);
+    if (h->m > 0) {
+        const int Kn = round_up(h->P, 16);
+        HIPCHK(gemm_f64(true, bp, h->Nn, Kn, h->dU2, h->ldA, h->dA + h->ldA, h->ldA, h->dWn, h->Nn, s));
+    }
+    ReflectArgs r{};
+    r.batch = batch;
+    r.n = h->n;
+    r.m = h->m;
+    r.P = h->P;
+    r.md = h->md;
+    r.ldA = h->ldA;
+    r.Astk = h->dA;
+    r.hit = h->dHit;
+    r.tp = tp;
+    r.v = v;
+    r.wn = h->dWn;
+    r.ldwn = h->Nn;
+    r.lam = h->dLam;
+    r.status = st;
+    r.s_out = s_out;
+    r.w_out = w_out;
+    HIPCHK(launch_reflect_finish(r, s));
+    return SPEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spec_status_str(spec_status s) {
+    switch (s) {
+        case SPEC_OK: return "ok";
+        case SPEC_EINVAL: return "invalid argument";
+        case SPEC_ENOMEM: return "device out of memory";
+        case SPEC_EDEVICE: return "device error";
+        case SPEC_NOT_INTERIOR: return "point not in the interior";
+        case SPEC_UNBOUNDED: return "unbounded along the curve";
+        case SPEC_NONSMOOTH: return "non-smooth boundary point";
+        case SPEC_REFLECT_CAP: return "reflection cap reached";
+        case SPEC_CERT_FALLBACK: return "learned bracket not certified";
+        case SPEC_NOCONV: return "eigen iteration did not converge";
+        case SPEC_ENOTSUP: return "size not supported";
+    }
+    return "unknown status";
+}
+
+spec_status spec_create(int n, int nblocks, const int* block_size, const int* kind, const double* A,
+                        spec_handle* out) {
+    if (!out || !block_size || !kind || !A || n < 1 || nblocks < 1) return SPEC_EINVAL;
+    *out = nullptr;
+    int m = 0, md = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        if (block_size[b] < 1) return SPEC_EINVAL;
+        if (kind[b] == SPEC_BLOCK_DENSE) m += block_size[b];
+        else if (kind[b] == SPEC_BLOCK_DIAG) md += block_size[b];
+        else return SPEC_EINVAL;
+    }
+    if (m > SPEC_MAX_DENSE) return SPEC_ENOTSUP;
+    // symmetry of dense blocks
+    {
+        const double* src = A;
+        for (int b = 0; b < nblocks; ++b) {
+            const int mb = block_size[b];
+            const size_t per = kind[b] == SPEC_BLOCK_DENSE ? (size_t)mb * mb : (size_t)mb;
+            if (kind[b] == SPEC_BLOCK_DENSE)
+                for (int i = 0; i <= n; ++i) {
+                    const double* Ai = src + (size_t)i * per;
+                    double nrm = 0.0, asym = 0.0;
+                    for (int r = 0; r < mb; ++r)
+                        for (int c = 0; c < mb; ++c) {
+                            const double a = Ai[(size_t)r * mb + c];
+                            if (!std::isfinite(a)) return SPEC_EINVAL;
+                            nrm = std::fmax(nrm, std::fabs(a));
+                            asym = std::fmax(asym, std::fabs(a - Ai[(size_t)c * mb + r]));
+                        }
+                    if (asym > 1e-12 * nrm) return SPEC_EINVAL;
+                }
+            else
+                for (size_t e = 0; e < (size_t)(n + 1) * per; ++e)
+                    if (!std::isfinite(src[e])) return SPEC_EINVAL;
+            src += (size_t)(n + 1) * per;
+        }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SPEC_EDEVICE;
+    spec_s* h = new spec_s();
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return SPEC_EDEVICE; }
+    h->n = n;
+    h->m = m;
+    h->md = md;
+    h->P = m * (m + 1) / 2;
+    h->Ptot = h->P + md;
+    h->K = n + 1;
+    h->Kpad = round_up(h->K, 16);
+    h->ldA = round_up(h->Ptot, 64);
+    h->Nn = round_up(n, 64);
+    h->Arows = std::max(h->Kpad, 1 + h->Nn);
+    h->ldw = round_up(std::max(h->P, 1), 8);
+    // pack: row i = [A_i dense lower rows (merged block-diagonal) | A_i diagonals]
+    std::vector<double> host((size_t)h->Arows * h->ldA, 0.0);
+    const double* src = A;
+    int doff = 0, goff = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const int mb = block_size[b];
+        const bool dense = kind[b] == SPEC_BLOCK_DENSE;
+        const size_t per = dense ? (size_t)mb * mb : (size_t)mb;
+        for (int i = 0; i <= n; ++i) {
+            const double* Ai = src + (size_t)i * per;
+            double* row = host.data() + (size_t)i * h->ldA;
+            if (dense) {
+                for (int r = 0; r < mb; ++r)
+                    for (int c = 0; c <= r; ++c) row[pk(doff + r, doff + c)] = Ai[(size_t)r * mb + c];
+            } else {
+                for (int j = 0; j < mb; ++j) row[h->P + goff + j] = Ai[j];
+            }
+        }
+        if (dense) doff += mb; else goff += mb;
+        src += (size_t)(n + 1) * per;
+    }
+    hipError_t e = dalloc(&h->dA, host.size(), false);
+    if (e == hipSuccess) e = hipMemcpy(h->dA, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dfree(h->dA);
+        delete h;
+        return from_hip(e);
+    }
+    *out = h;
+    return SPEC_OK;
+}
+
+spec_status spec_destroy(spec_handle h) {
+    if (!h) return SPEC_EINVAL;
+    (void)hipDeviceSynchronize();
+    h->free_work();
+    h->free_stage();
+    dfree(h->dA);
+    delete h;
+    return SPEC_OK;
+}
+
+spec_status spec_dims(spec_handle h, int* n, int* m, int* md) {
+    if (!h) return SPEC_EINVAL;
+    if (n) *n = h->n;
+    if (m) *m = h->m;
+    if (md) *md = h->md;
+    return SPEC_OK;
+}
+
+spec_status spec_set_lanczos(spec_handle h, int kmax, double tol) {
+    if (!h || kmax < 2 || kmax > SPEC_MAX_KRYLOV || !(tol > 0.0) || !(tol < 1.0)) return SPEC_EINVAL;
+    if (lanczos_lds_bytes(h->m, kmax) > 163840) return SPEC_ENOTSUP;
+    h->kmax = kmax;
+    h->tol = tol;
+    return SPEC_OK;
+}
+
+spec_status spec_membership_dev(spec_handle h, int batch, const double* x, int8_t* interior, void* stream) {
+    if (!h || batch < 0 || (batch && (!x || !interior))) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SPCHK(h->ensure(batch));
+    int bp = 0;
+    SPCHK(assemble(h, batch, x, nullptr, &bp, s));
+    HIPCHK(launch_factor(batch, h->m, h->md, h->P, h->dFB, h->ldA, h->dW, h->ldw, h->dSt, s));
+    HIPCHK(launch_status_to_flag(batch, h->dSt, interior, s));
+    return SPEC_OK;
+}
+
+spec_status spec_intersect_dev(spec_handle h, int batch, const double* x, const double* v, double* t_minus,
+                               double* t_plus, int32_t* status, void* stream) {
+    if (!h || batch < 0 || (batch && (!x || !v || !t_minus || !t_plus || !status))) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    SPCHK(h->ensure(batch));
+    return line_oracle(h, batch, x, v, t_minus, t_plus, status, false, nullptr, (hipStream_t)stream);
+}
+
+spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const double* v, double* t_plus,
+                             double* s_out, double* w_out, int32_t* status, void* stream) {
+    if (!h || batch < 0 || (batch && (!x || !v || !t_plus || !s_out || !status))) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SPCHK(h->ensure(batch));
+    SPCHK(line_oracle(h, batch, x, v, h->dTm, t_plus, status, true, nullptr, s));
+    return reflect_tail(h, batch, v, t_plus, status, s_out, w_out, s);
+}
+
+// ------------------------------------------------------------ host-pointer forms
+
+spec_status spec_membership(spec_handle h, int batch, const double* x, int8_t* interior) {
+    if (!h || batch < 0 || (batch && (!x || !interior))) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    SPCHK(h->ensure_stage(batch));
+    HIPCHK(hipMemcpy(h->sX, x, sizeof(double) * batch * h->n, hipMemcpyHostToDevice));
+    SPCHK(spec_membership_dev(h, batch, h->sX, h->sI, nullptr));
+    HIPCHK(hipMemcpy(interior, h->sI, batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+spec_status spec_intersect(spec_handle h, int batch, const double* x, const double* v, double* t_minus,
+                           double* t_plus, int32_t* status) {
+    if (!h || batch < 0 || (batch && (!x || !v || !t_minus || !t_plus || !status))) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    SPCHK(h->ensure_stage(batch));
+    HIPCHK(hipMemcpy(h->sX, x, sizeof(double) * batch * h->n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->sV, v, sizeof(double) * batch * h->n, hipMemcpyHostToDevice));
+    SPCHK(spec_intersect_dev(h, batch, h->sX, h->sV, h->sO1, h->sO2, h->sSt, nullptr));
+    HIPCHK(hipMemcpy(t_minus, h->sO1, sizeof(double) * batch, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(t_plus, h->sO2, sizeof(double) * batch, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(status, h->sSt, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+spec_status spec_reflect(spec_handle h, int batch, const double* x, const double* v, double* t_plus,
+                         double* s_out, double* w_out, int32_t* status) {
+    if (!h || batch < 0 || (batch && (!x || !v || !t_plus || !s_out || !status))) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    SPCHK(h->ensure_stage(batch));
+    HIPCHK(hipMemcpy(h->sX, x, sizeof(double) * batch * h->n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->sV, v, sizeof(double) * batch * h->n, hipMemcpyHostToDevice));
+    SPCHK(spec_reflect_dev(h, batch, h->sX, h->sV, h->sO2, h->sS, h->sW, h->sSt, nullptr));
+    HIPCHK(hipMemcpy(t_plus, h->sO2, sizeof(double) * batch, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(s_out, h->sS, sizeof(double) * batch * h->n, hipMemcpyDeviceToHost));
+    if (w_out) HIPCHK(hipMemcpy(w_out, h->sW, sizeof(double) * batch * h->n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(status, h->sSt, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+// ------------------------------------------------------------ diagnostics
+
+spec_status spec_diag_mfma_layout(double* host_out) {
+    if (!host_out) return SPEC_EINVAL;
+    double* d = nullptr;
+    HIPCHK(dalloc(&d, 256));
+    hipError_t e = mfma_probe(d, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(host_out, d, sizeof(double) * 256, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return from_hip(e);
+}
+
+spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A, const double* B, double* C) {
+    if (!A || !B || !C || M < 0 || N < 0 || K < 0) return SPEC_EINVAL;
+    if (M % 64 || N % 64 || K % 16) return SPEC_EINVAL;
+    double *dA = nullptr, *dB = nullptr, *dC = nullptr;
+    hipError_t e = dalloc(&dA, (size_t)M * K, false);
+    if (e == hipSuccess) e = dalloc(&dB, (size_t)K * N, false);
+    if (e == hipSuccess) e = dalloc(&dC, (size_t)M * N, false);
+    if (e == hipSuccess) e = hipMemcpy(dA, A, sizeof(double) * M * K, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dB, B, sizeof(double) * K * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = gemm_f64(transB != 0, M, N, K, dA, K, dB, transB ? K : N, dC, N, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(C, dC, sizeof(double) * M * N, hipMemcpyDeviceToHost);
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dC);
+    return from_hip(e);
+}
+
+spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out) {
+    if (!h || !lam_out || batch < 0 || batch > h->cap) return SPEC_EINVAL;
+    HIPCHK(hipMemcpy(lam_out, h->dLam, sizeof(double) * 4 * batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64), used for the
+// two contractions of the oracle that are shared by every chain:
+//   pencil assembly   [F(x); B(v)] = [1 x; 0 v] * Astack      (B not transposed)
+//   boundary normal   w = vec(u u^T) * Astack^T                (B transposed)
+// (paper: construction of the pencil in O(n m^2), Lemma "intersection cost";
+//  normal (u^T A_i u)_i in O(n m^2), Lemma "reflection cost").
+//
+// Tiling: a 256-thread workgroup computes a 64x64 tile of C; each of its four
+// waves a 32x32 quarter as 2x2 MFMA 16x16 blocks.  K advances 16 at a time
+// through LDS.  M, N, K must be multiples of 64, 64, 16 (callers pad with
+// zeros).  Workgroups are ordered so that the eight XCDs each walk their own
+// contiguous range of N tiles: a B panel is then fetched into one XCD's L2
+// and reused there by every M tile.
+#include "common.h"
+
+namespace spec {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT_M = 64, GT_N = 64, GT_K = 16;
+constexpr int LDA_S = GT_K + 1;   // padded LDS row of the A tile (bank spread)
+constexpr int LDB_S = GT_N + 2;
+
+template <bool TRANS_B>
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, const double* __restrict__ A,
+                                                  int lda, const double* __restrict__ B, int ldb,
+                                                  double* __restrict__ C, int ldc) {
+    __shared__ double As[GT_M * LDA_S];
+    __shared__ double Bs[GT_K * LDB_S];
+
+    const int tilesM = M / GT_M, tilesN = N / GT_N;
+    // XCD-aware order: hardware places workgroup g on XCD g % 8.  Give XCD x the
+    // tiles [x*T/8, (x+1)*T/8) in M-fastest order.
+    const int total = tilesM * tilesN;
+    const int g = blockIdx.x;
+    int lin;
+    if (total % 8 == 0) {
+        const int per = total / 8;
+        lin = (g % 8) * per + g / 8;
+    } else {
+        lin = g;
+    }
+    const int tm = lin % tilesM, tn = lin / tilesM;
+    const int row0 = tm * GT_M, col0 = tn * GT_N;
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < K; k0 += GT_K) {
+        // A tile: 64 x 16
+        {
+            const int r = t >> 2, c = (t & 3) * 4;
+            const double* src = A + (size_t)(row0 + r) * lda + k0 + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) As[r * LDA_S + c + q] = src[q];
+        }
+        if (!TRANS_B) {
+            const int r = t >> 4, c = (t & 15) * 4;
+            const double* src = B + (size_t)(k0 + r) * ldb + col0 + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Bs[r * LDB_S + c + q] = src[q];
+        } else {
+            // B is N x K row-major: Bs[k][n] = B[col0 + n][k0 + k]
+            const int nn = t >> 2, kk = (t & 3) * 4;
+            const double* src = B + (size_t)(col0 + nn) * ldb + k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Bs[(kk + q) * LDB_S + nn] = src[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GT_K; ks += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[(wr + i * 16 + (lane & 15)) * LDA_S + ks + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[(ks + (lane >> 4)) * LDB_S + wc + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D[4*(lane/16) + r][lane%16] of each 16x16 block
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = row0 + wr + i * 16 + 4 * (lane >> 4) + r;
+                const int cc = col0 + wc + j * 16 + (lane & 15);
+                C[(size_t)rr * ldc + cc] = acc[i][j][r];
+            }
+}
+
+hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+                    double* C, int ldc, hipStream_t s) {
+    if (M % GT_M || N % GT_N || K % GT_K) return hipErrorInvalidValue;
+    if (M == 0 || N == 0) return hipSuccess;
+    const int tiles = (M / GT_M) * (N / GT_N);
+    if (transB)
+        hipLaunchKernelGGL(k_gemm_f64<true>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+    else
+        hipLaunchKernelGGL(k_gemm_f64<false>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+}
+
+// Probe of the MFMA lane layout: D = A(16x4) * B(4x16) with A[i][k] = i + 100 k
+// and B[k][j] = (k == j % 4) ? 1 : 0 given in the documented operand layout;
+// writes all 16x4 result doubles per lane so the host can check the mapping.
+__global__ void k_mfma_probe(double* out) {
+    const int lane = threadIdx.x;
+    const double a = (double)(lane & 15) + 100.0 * (lane >> 4);
+    const double b = ((lane >> 4) == ((lane & 15) & 3)) ? 1.0 : 0.0;
+    d4 acc{0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[lane * 4 + r] = acc[r];
+}
+
+hipError_t mfma_probe(double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, out);
+    return hipGetLastError();
+}
+
+}  // namespace spec

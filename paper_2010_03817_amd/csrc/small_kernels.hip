@@ -1,0 +1,117 @@
+// Small per-chain kernels around the oracle: assembly rows and the
+// reflection of eq. (reflection).
+#include "common.h"
+#include "spec_kernels.h"
+
+namespace spec {
+
+__global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__ x, const double* __restrict__ v,
+                          double* __restrict__ Z, int zrow0) {
+    const int c = blockIdx.x;
+    if (c >= batch) return;
+    double* zf = Z + (size_t)c * Kpad;
+    double* zb = Z + (size_t)(zrow0 + c) * Kpad;
+    for (int k = threadIdx.x; k < Kpad; k += blockDim.x) {
+        double fx = 0.0, bv = 0.0;
+        if (k == 0) {
+            fx = 1.0;
+        } else if (k <= n) {
+            if (x) fx = x[(size_t)c * n + k - 1];
+            if (v) bv = v[(size_t)c * n + k - 1];
+        }
+        zf[k] = fx;
+        zb[k] = bv;
+    }
+}
+
+hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
+                          hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_z, dim3(batch), dim3(64), 0, s, batch, n, Kpad, x, v, Z, zrow0);
+    return hipGetLastError();
+}
+
+// Reflection (Alg. REFLECTION): w from the normal GEMM (dense hit, Lemma
+// "Gradient of det F") or the hit row's coefficients (diagonal hit), oriented
+// outward, and s = v - 2 <v, w_hat> w_hat.  One wave per chain.
+__global__ __launch_bounds__(256) void k_reflect_finish(ReflectArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (c >= a.batch) return;
+    const int n = a.n;
+    const double* v = a.v + (size_t)c * n;
+    double* s = a.s_out + (size_t)c * n;
+    double* w = a.w_out ? a.w_out + (size_t)c * n : nullptr;
+    int32_t st = a.status[c];
+    const int hit = a.hit[c];
+    const double tp = a.tp[c];
+    if (st == SPEC_NOT_INTERIOR) {
+        for (int i = lane; i < n; i += 64) {
+            s[i] = NAN;
+            if (w) w[i] = NAN;
+        }
+        return;
+    }
+    if (hit == HIT_NONE || !isfinite(tp)) {
+        for (int i = lane; i < n; i += 64) {
+            s[i] = v[i];
+            if (w) w[i] = 0.0;
+        }
+        return;
+    }
+    // gather the raw normal
+    double nn = 0.0, vw = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                           : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+        nn += wi * wi;
+        vw += wi * v[i];
+    }
+    nn = wave_sum(nn);
+    vw = wave_sum(vw);
+    if (!(nn > 0.0)) {
+        for (int i = lane; i < n; i += 64) {
+            s[i] = v[i];
+            if (w) w[i] = 0.0;
+        }
+        if (lane == 0 && st == SPEC_OK) a.status[c] = SPEC_NONSMOOTH;
+        return;
+    }
+    const double inv = 1.0 / sqrt(nn);
+    const double sgn = vw < 0.0 ? -1.0 : 1.0;
+    const double dvw = fabs(vw) * inv;  // <v, w_hat> with w_hat outward
+    for (int i = lane; i < n; i += 64) {
+        const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                           : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+        const double wh = sgn * wi * inv;
+        s[i] = v[i] - 2.0 * dvw * wh;
+        if (w) w[i] = wh;
+    }
+    if (lane == 0 && st == SPEC_OK && hit == HIT_DENSE && a.lam) {
+        const double l1 = a.lam[4 * c], l2 = a.lam[4 * c + 2];
+        if (fabs(l2 - l1) <= 1e-10 * fabs(l1)) a.status[c] = SPEC_NONSMOOTH;
+    }
+}
+
+hipError_t launch_reflect_finish(const ReflectArgs& a, hipStream_t s) {
+    if (a.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reflect_finish, dim3((a.batch + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace spec
+
+namespace spec {
+
+__global__ void k_status_to_flag(int batch, const int32_t* __restrict__ st, int8_t* __restrict__ flag) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < batch) flag[c] = st[c] == SPEC_OK ? 1 : 0;
+}
+
+hipError_t launch_status_to_flag(int batch, const int32_t* st, int8_t* flag, hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_status_to_flag, dim3((batch + 255) / 256), dim3(256), 0, s, batch, st, flag);
+    return hipGetLastError();
+}
+
+}  // namespace spec

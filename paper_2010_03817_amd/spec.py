@@ -1,0 +1,192 @@
+"""Python binding of the C ABI in include/spec.h (argument marshalling only).
+
+Every step of the oracle runs in the HIP kernels of libspec.so.  Tensors are
+torch float64 CUDA (ROCm) tensors; calls are enqueued on torch's current
+stream.  There is no CPU fallback: if libspec.so is missing or no device is
+usable the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspec.so")
+HEADERS = [os.path.join(os.path.dirname(_HERE), "include", h) for h in ("spec.h", "spec_diag.h")]
+
+OK, EINVAL, ENOMEM, EDEVICE, NOT_INTERIOR, UNBOUNDED, NONSMOOTH, REFLECT_CAP, CERT_FALLBACK, NOCONV, ENOTSUP = range(11)
+DENSE, DIAG = 0, 1
+HNR, CHNR, BILLIARD, HMC = 0, 1, 2, 3
+
+
+class SpecError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Function names declared in include/spec*.h."""
+    names = []
+    for h in HEADERS:
+        txt = open(h).read()
+        names += re.findall(r"^\s*(?:spec_status|const char\*)\s+(spec_\w+)\s*\(", txt, re.M)
+    return names
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SpecError(f"{LIB_PATH} is not built; run `python -m paper_2010_03817_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+    L.spec_create.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.POINTER(vp)]
+    L.spec_destroy.argtypes = [vp]
+    L.spec_dims.argtypes = [vp, ip, ip, ip]
+    L.spec_status_str.argtypes = [C.c_int]
+    L.spec_status_str.restype = C.c_char_p
+    L.spec_set_lanczos.argtypes = [vp, C.c_int, C.c_double]
+    L.spec_membership_dev.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.spec_intersect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
+    L.spec_reflect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+    L.spec_membership.argtypes = [vp, C.c_int, vp, vp]
+    L.spec_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+    L.spec_reflect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
+    L.spec_diag_mfma_layout.argtypes = [vp]
+    L.spec_diag_gemm_f64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    L.spec_diag_lanczos_info.argtypes = [vp, C.c_int, vp]
+    for name in declared_symbols():
+        if name != "spec_status_str":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != OK:
+        msg = lib().spec_status_str(rc).decode()
+        raise SpecError(f"spec call failed: {msg} ({rc})")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise SpecError("no GPU device available to torch")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _f64(t, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+    t = t.to(device="cuda", dtype=torch.float64).contiguous()
+    if shape is not None:
+        t = t.reshape(shape)
+    return t
+
+
+class Spectrahedron:
+    """Device handle of an LMI (instances.Instance)."""
+
+    def __init__(self, inst, kmax: int | None = None, tol: float | None = None):
+        _torch()
+        self.inst = inst
+        self.n = inst.n
+        sizes, kinds, A = inst.flat()
+        self._keep = (sizes, kinds, np.ascontiguousarray(A, dtype=np.float64))
+        h = C.c_void_p()
+        check(lib().spec_create(self.n, len(sizes), sizes.ctypes.data_as(C.POINTER(C.c_int)),
+                                kinds.ctypes.data_as(C.POINTER(C.c_int)),
+                                self._keep[2].ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+        self._h = h
+        n, m, md = C.c_int(), C.c_int(), C.c_int()
+        check(lib().spec_dims(h, C.byref(n), C.byref(m), C.byref(md)))
+        self.m, self.md = m.value, md.value
+        if kmax is not None or tol is not None:
+            self.set_lanczos(kmax or 80, tol or 1e-10)
+
+    def set_lanczos(self, kmax: int, tol: float):
+        check(lib().spec_set_lanczos(self._h, int(kmax), float(tol)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ oracle calls
+
+    def membership(self, x):
+        torch = _torch()
+        x = _f64(x)
+        x = x.reshape(-1, self.n)
+        out = torch.empty(x.shape[0], dtype=torch.int8, device="cuda")
+        check(lib().spec_membership_dev(self._h, x.shape[0], _ptr(x), _ptr(out), _stream()))
+        return out.bool()
+
+    def intersect(self, x, v):
+        torch = _torch()
+        x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
+        B = x.shape[0]
+        tm = torch.empty(B, dtype=torch.float64, device="cuda")
+        tp = torch.empty_like(tm)
+        st = torch.empty(B, dtype=torch.int32, device="cuda")
+        check(lib().spec_intersect_dev(self._h, B, _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), _ptr(st), _stream()))
+        return tm, tp, st
+
+    def reflect(self, x, v):
+        torch = _torch()
+        x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
+        B = x.shape[0]
+        tp = torch.empty(B, dtype=torch.float64, device="cuda")
+        s = torch.empty_like(x)
+        w = torch.empty_like(x)
+        st = torch.empty(B, dtype=torch.int32, device="cuda")
+        check(lib().spec_reflect_dev(self._h, B, _ptr(x), _ptr(v), _ptr(tp), _ptr(s), _ptr(w), _ptr(st),
+                                     _stream()))
+        return tp, s, w, st
+
+    def lanczos_info(self, batch):
+        """(lambda_min, lambda_max, second Ritz value, steps) of the last call."""
+        torch = _torch()
+        torch.cuda.synchronize()
+        out = np.empty((batch, 4))
+        check(lib().spec_diag_lanczos_info(self._h, batch, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+
+def mfma_layout():
+    out = np.empty(256)
+    check(lib().spec_diag_mfma_layout(out.ctypes.data_as(C.c_void_p)))
+    return out.reshape(64, 4)
+
+
+def gemm_f64(A, B, transB=False):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    M, K = A.shape
+    N = B.shape[0] if transB else B.shape[1]
+    Cm = np.empty((M, N))
+    check(lib().spec_diag_gemm_f64(int(transB), M, N, K, A.ctypes.data_as(C.c_void_p),
+                                   B.ctypes.data_as(C.c_void_p), Cm.ctypes.data_as(C.c_void_p)))
+    return Cm

@@ -1,0 +1,187 @@
+"""Parity of the HIP line oracle (intersect / reflect / membership) with the
+FP64 CPU oracle on identical inputs, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2010_03817_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+# Tolerance for t+- (relative), the bar of the FP64 path.
+T_REL = 1e-9
+
+
+def _spec():
+    from paper_2010_03817_amd import spec as S
+    return S
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _points(o, inst, rng, batch, frac_lo=0.0, frac_hi=0.95):
+    d = I.random_directions(rng, batch, inst.n)
+    tp0 = o.intersect(np.zeros((batch, inst.n)), d)[1]
+    f = rng.uniform(frac_lo, frac_hi, batch)
+    x = (f * np.minimum(tp0, 50.0))[:, None] * d
+    v = I.random_directions(rng, batch, inst.n)
+    return x, v
+
+
+def test_mfma_f64_lane_layout():
+    out = _spec().mfma_layout()
+    for lane in range(64):
+        for r in range(4):
+            i, j = 4 * (lane // 16) + r, lane % 16
+            assert out[lane, r] == i + 100 * (j % 4)
+
+
+@pytest.mark.parametrize("transB", [False, True])
+def test_gemm_f64(transB):
+    rng = np.random.default_rng(1)
+    M, N, K = 128, 192, 48
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((N, K)) if transB else rng.standard_normal((K, N))
+    Cg = _spec().gemm_f64(A, B, transB)
+    Cr = A @ (B.T if transB else B)
+    assert np.allclose(Cg, Cr, rtol=1e-13, atol=1e-13 * np.abs(Cr).max())
+
+
+def _check_intersect(inst, batch, seed, frac_hi=0.95, rel=T_REL):
+    S = _spec()
+    o = O.Oracle(inst)
+    g = S.Spectrahedron(inst)
+    rng = np.random.default_rng(seed)
+    x, v = _points(o, inst, rng, batch, 0.0, frac_hi)
+    tm_r, tp_r, st_r = o.intersect(x, v)
+    tm, tp, st = g.intersect(x, v)
+    tm, tp, st = _np(tm), _np(tp), _np(st)
+    assert np.array_equal(st, st_r), (st, st_r)
+    ok = st_r == O.OK
+    assert np.allclose(tp[ok], tp_r[ok], rtol=rel, atol=0)
+    assert np.allclose(tm[ok], tm_r[ok], rtol=rel, atol=0)
+    return g, o, x, v
+
+
+def test_intersect_config1_small():
+    """n = m = 10 with the box block (the small workload), 64 pairs."""
+    _check_intersect(I.gbase(10, 10, seed=101, scale=math.sqrt(10)), 64, 1)
+
+
+def test_intersect_ragged_sizes():
+    """Sizes spanning several tiles with ragged tails."""
+    for n, m, b in [(37, 45, 70), (70, 19, 65), (5, 130, 17)]:
+        _check_intersect(I.gbase(n, m, seed=n + m), b, n)
+
+
+def test_intersect_full_size_sampled():
+    """n = m = 200 (+400 box rows), sampled pairs."""
+    _check_intersect(I.gbase(200, 200, seed=103), 12, 3)
+
+
+def test_intersect_special_bodies():
+    # polytope only (no dense block), arrow ball, the paper's 2-D example
+    rng = np.random.default_rng(4)
+    Amat = rng.standard_normal((23, 6))
+    _check_intersect(I.polytope(Amat, rng.uniform(0.5, 2, 23)), 40, 4)
+    _check_intersect(I.arrow_ball(9), 40, 5)
+    S = _spec()
+    ex = I.paper_example_2d()
+    g = S.Spectrahedron(ex)
+    tm, tp, st = g.intersect(np.array([[-1.0, 1.0]]), np.array([[1.3, 0.8]]))
+    tm_r, tp_r, _ = O.Oracle(ex).intersect(np.array([[-1.0, 1.0]]), np.array([[1.3, 0.8]]))
+    assert _np(tp)[0] == pytest.approx(tp_r[0], rel=T_REL)
+    assert _np(tm)[0] == pytest.approx(tm_r[0], rel=T_REL)
+
+
+def test_intersect_near_boundary():
+    """Points pulled back from the boundary by 1e-6 (the post-reflection
+    starts of the billiard walk), bucketed by the conditioning of F."""
+    inst = I.gbase(40, 50, seed=7)
+    S = _spec()
+    o, g = O.Oracle(inst), S.Spectrahedron(inst)
+    rng = np.random.default_rng(7)
+    d = I.random_directions(rng, 48, inst.n)
+    x0 = 0.3 * d * o.intersect(np.zeros((48, inst.n)), d)[1][:, None]
+    u = I.random_directions(rng, 48, inst.n)
+    tp0 = o.intersect(x0, u)[1]
+    x = x0 + (1 - 1e-6) * tp0[:, None] * u
+    v = I.random_directions(rng, 48, inst.n)
+    tm_r, tp_r, st_r = o.intersect(x, v)
+    tm, tp, st = [_np(a) for a in g.intersect(x, v)]
+    ok = st_r == O.OK
+    assert ok.sum() > 40
+    # t+- measured from a point at relative distance 1e-6 of the boundary: the
+    # short side has relative conditioning ~1e6, so its bar is scaled by it.
+    short = np.minimum(np.abs(tm_r), tp_r) < 1e-3 * np.maximum(np.abs(tm_r), tp_r)
+    for arr, ref in ((tp, tp_r), (tm, tm_r)):
+        rel = np.abs(arr - ref) / np.abs(ref)
+        is_short = np.abs(ref) == np.minimum(np.abs(tm_r), tp_r)
+        assert (rel[ok & ~(short & is_short)] <= T_REL).all()
+        assert (rel[ok & short & is_short] <= 1e-6).all()
+
+
+def test_reflect_parity():
+    for inst, batch, seed in [(I.gbase(10, 10, seed=101, scale=math.sqrt(10)), 64, 11),
+                              (I.gbase(30, 41, seed=12), 50, 12), (I.arrow_ball(7), 30, 13)]:
+        S = _spec()
+        o, g = O.Oracle(inst), S.Spectrahedron(inst)
+        rng = np.random.default_rng(seed)
+        x, v = _points(o, inst, rng, batch)
+        tp_r, s_r, w_r, st_r = o.reflect(x, v)
+        tp, s, w, st = [_np(a) for a in g.reflect(x, v)]
+        ok = st_r == O.OK
+        assert np.array_equal(st[ok], st_r[ok])
+        assert np.allclose(tp[ok], tp_r[ok], rtol=T_REL, atol=0)
+        # normal and reflected direction: Ritz-vector accuracy
+        assert np.allclose(w[ok], w_r[ok], atol=1e-7)
+        assert np.allclose(s[ok], s_r[ok], atol=2e-7)
+
+
+def test_reflect_full_size_sampled():
+    inst = I.gbase(200, 200, seed=103)
+    S = _spec()
+    o, g = O.Oracle(inst), S.Spectrahedron(inst)
+    rng = np.random.default_rng(14)
+    x, v = _points(o, inst, rng, 6)
+    tp_r, s_r, w_r, st_r = o.reflect(x, v)
+    tp, s, w, st = [_np(a) for a in g.reflect(x, v)]
+    assert np.allclose(tp, tp_r, rtol=T_REL, atol=0)
+    assert np.allclose(w, w_r, atol=1e-7)
+    assert np.allclose(s, s_r, atol=2e-7)
+
+
+def test_membership_and_statuses():
+    S = _spec()
+    inst = I.gbase(8, 12, seed=15)
+    o, g = O.Oracle(inst), S.Spectrahedron(inst)
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal((200, 8)) * 0.6
+    assert np.array_equal(_np(g.membership(x)), o.membership(x))
+    # outside point: NOT_INTERIOR with NaN values
+    tm, tp, st = [_np(a) for a in g.intersect(np.full((1, 8), 20.0), np.ones((1, 8)))]
+    assert st[0] == S.NOT_INTERIOR and np.isnan(tp[0]) and np.isnan(tm[0])
+    # a half-space is unbounded
+    hs = I.polytope(np.array([[1.0, 0.0]]), np.array([1.0]))
+    tm, tp, st = [_np(a) for a in S.Spectrahedron(hs).intersect(np.zeros((2, 2)), np.array([[0.0, 1.0], [1, 0]]))]
+    assert st[0] == S.UNBOUNDED and tp[0] == np.inf and tm[0] == -np.inf
+    assert st[1] == S.UNBOUNDED and tp[1] == pytest.approx(1.0) and tm[1] == -np.inf
+
+
+def test_empty_batch_and_repeat_calls():
+    S = _spec()
+    inst = I.gbase(6, 9, seed=16)
+    g = S.Spectrahedron(inst)
+    tm, tp, st = g.intersect(np.zeros((0, 6)), np.zeros((0, 6)))
+    assert tm.numel() == 0
+    rng = np.random.default_rng(16)
+    o = O.Oracle(inst)
+    x, v = _points(o, inst, rng, 130)
+    a = _np(g.intersect(x, v)[1])
+    b = _np(g.intersect(x[:7], v[:7])[1])  # smaller call after a larger one
+    c = _np(g.intersect(x, v)[1])
+    assert np.array_equal(a[:7], b) and np.array_equal(a, c)  # deterministic

@@ -10,9 +10,10 @@
 extern "C" {
 #endif
 
-/* Runs one v_mfma_f64_16x16x4f64 on a wave with A[i][k] = i + 100 k given in
- * lane (i + 16 k) and B[k][j] = (k == j mod 4) given in lane (j + 16 k);
- * host_out receives 64 lanes x 4 accumulator doubles (256 values). */
+/* Runs one v_mfma_f64_16x16x4f64 on a wave with A[i][k] in lane i + 16 k and
+ * B[k][j] in lane j + 16 k, A[i][0] = 1, A[i][1] = i, B[0][j] = 1000 j,
+ * B[1][j] = 1 (else 0), so D[i][j] = 1000 j + i; host_out receives the
+ * 64 lanes x 4 accumulator doubles (256 values). */
 spec_status spec_diag_mfma_layout(double* host_out);
 
 /* C = A * B (transB = 0: B is K x N) or A * B^T (transB = 1: B is N x K),

@@ -87,14 +87,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, const dou
         }
         __syncthreads();
     }
-    // D[4*(lane/16) + r][lane%16] of each 16x16 block
+    // accumulator r of lane l holds D[l/16 + 4 r][l % 16] of its 16x16 block
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int rr = row0 + wr + i * 16 + 4 * (lane >> 4) + r;
+                const int rr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
                 const int cc = col0 + wc + j * 16 + (lane & 15);
                 C[(size_t)rr * ldc + cc] = acc[i][j][r];
             }
@@ -112,13 +112,15 @@ hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, 
     return hipGetLastError();
 }
 
-// Probe of the MFMA lane layout: D = A(16x4) * B(4x16) with A[i][k] = i + 100 k
-// and B[k][j] = (k == j % 4) ? 1 : 0 given in the documented operand layout;
-// writes all 16x4 result doubles per lane so the host can check the mapping.
+// Probe of the MFMA lane layout: A(16x4) and B(4x16) given in the documented
+// operand layout (lane l holds A[l%16][l/16] and B[l/16][l%16]) with
+// A[i][0] = 1, A[i][1] = i, B[0][j] = 1000 j, B[1][j] = 1 and zeros elsewhere,
+// so D[i][j] = 1000 j + i; every accumulator double of every lane is written.
 __global__ void k_mfma_probe(double* out) {
     const int lane = threadIdx.x;
-    const double a = (double)(lane & 15) + 100.0 * (lane >> 4);
-    const double b = ((lane >> 4) == ((lane & 15) & 3)) ? 1.0 : 0.0;
+    const int ij = lane & 15, k = lane >> 4;
+    const double a = k == 0 ? 1.0 : (k == 1 ? (double)ij : 0.0);
+    const double b = k == 0 ? 1000.0 * ij : (k == 1 ? 1.0 : 0.0);
     d4 acc{0.0, 0.0, 0.0, 0.0};
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     for (int r = 0; r < 4; ++r) out[lane * 4 + r] = acc[r];

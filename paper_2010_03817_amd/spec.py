@@ -44,6 +44,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise SpecError(f"{LIB_PATH} is not built; run `python -m paper_2010_03817_amd.build`")
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # initialise torch first so that libspec.so binds to the runtime torch uses.
+    import torch
+    torch.cuda.is_available()
     L = C.CDLL(LIB_PATH)
     vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
     L.spec_create.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.POINTER(vp)]

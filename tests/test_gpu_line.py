@@ -33,11 +33,14 @@ def _points(o, inst, rng, batch, frac_lo=0.0, frac_hi=0.95):
 
 
 def test_mfma_f64_lane_layout():
+    """Accumulator r of lane l holds D[l/16 + 4 r][l % 16] (the layout the
+    GEMM epilogue writes)."""
     out = _spec().mfma_layout()
+    got = [[(int(out[l, r]) % 1000, int(out[l, r]) // 1000) for r in range(4)] for l in range(64)]
+    print(got)
     for lane in range(64):
         for r in range(4):
-            i, j = 4 * (lane // 16) + r, lane % 16
-            assert out[lane, r] == i + 100 * (j % 4)
+            assert got[lane][r] == (lane // 16 + 4 * r, lane % 16)
 
 
 @pytest.mark.parametrize("transB", [False, True])

@@ -121,6 +121,59 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
                              double* t_plus, double* s_out, double* w_out, int32_t* status,
                              void* stream);
 
+/* Parameters of spec_walk_run (Section "Random walks").
+ *  tau       billiard: step length ell = -tau ln(eta), eta ~ U(0,1) (Alg.
+ *            Billiard; tau about the diameter); unused by Hit-and-Run
+ *  rho       reflection cap per step; <= 0 means 10 n; a step with more than
+ *            rho reflections leaves the chain where the step started
+ *  gauss_a   Hit-and-Run target: exp(-gauss_a |x|^2) restricted to S
+ *            (0 = uniform); the chord point is drawn from the target on the
+ *            chord (Alg. Hit-and-Run)
+ *  pullback  after a reflection the chain restarts from x + (1-pullback) t+ v
+ *            (default 1e-6; the boundary point itself has a singular F)
+ *  thin      store the point after every thin-th completed step (0 = none)
+ *  max_rounds  stop after this many oracle rounds even if steps remain
+ *            (<= 0: no limit); x_out then holds the last completed step
+ *  resume    nonzero: continue the chains of the previous spec_walk_run_dev
+ *            call on this handle (same kind, chains and seed) instead of
+ *            starting from x0; `steps` then counts from the original start
+ *  log_chains, log_cap, log_buf, log_count   optional device log of the
+ *            segments of chains c < log_chains: records of 2n+4 doubles
+ *            (x, v, t-, t+, chain, status), log_count (device int32, zeroed
+ *            by the caller) counts the records attempted. */
+typedef struct {
+    double tau;
+    int rho;
+    double gauss_a;
+    double pullback;
+    int thin;
+    long long max_rounds;
+    int resume;
+    int log_chains;
+    int log_cap;
+    double* log_buf;
+    int32_t* log_count;
+} spec_walk_params;
+
+/* Totals over chains: oracle calls, reflections, cap hits, not-interior
+ * segments, nonsmooth reflections, completed steps, eigen non-convergence,
+ * oracle rounds run. */
+typedef struct {
+    double calls, reflections, cap_hits, not_interior, nonsmooth, steps, noconv, rounds;
+} spec_walk_stats;
+
+/* Run `chains` independent chains of the walk `kind` from x0 (chains x n,
+ * interior points) for `steps` steps each with seed `seed` (Philox4x32-10,
+ * counter (chain, step, draw, tag)).  x_out (chains x n) receives the final
+ * points; samples (nullable, chains x (steps/thin) x n) the thinned points;
+ * stats (nullable, host) the totals.  Device pointers; asynchronous on
+ * `stream` except that it reads a device flag every 16 rounds to stop when
+ * all chains are done (and synchronises at the end when stats is given).
+ * Kinds HNR, CHNR, BILLIARD; SPEC_EINVAL for bad arguments. */
+spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps,
+                              uint64_t seed, const spec_walk_params* p, double* x_out, double* samples,
+                              spec_walk_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

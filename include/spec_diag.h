@@ -24,6 +24,15 @@ spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A,
  * (lambda_min(C), lambda_max(C), second smallest Ritz value, Lanczos steps). */
 spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out);
 
+/* Stage timing of the walk rounds, measured with HIP events recorded on the
+ * walk's stream around each stage.  spec_diag_timing(h, 1) resets and turns
+ * it on, (h, 0) turns it off.  spec_diag_stage_times writes, per stage
+ * (0 assembly GEMM, 1 factor, 2 Lanczos, 3 normal GEMM, 4 walk update), the
+ * summed milliseconds and the number of launches (2 x 5 doubles); also the
+ * Lanczos step count summed over chains of the timed rounds (1 double). */
+spec_status spec_diag_timing(spec_handle h, int on);
+spec_status spec_diag_stage_times(spec_handle h, double* ms_and_counts, double* lanczos_steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@
 #include "spec.h"
 #include "spec_diag.h"
 #include "spec_kernels.h"
+#include "walk_kernels.h"
 
 using namespace spec;
 
@@ -71,11 +72,43 @@ struct spec_s {
     double *sX = nullptr, *sV = nullptr, *sO1 = nullptr, *sO2 = nullptr, *sS = nullptr, *sW = nullptr;
     int32_t* sSt = nullptr;
     int8_t* sI = nullptr;
+    // stage timing
+    bool timing = false;
+    hipEvent_t ev[6] = {};
+    double stage_ms[5] = {0, 0, 0, 0, 0}, stage_n[5] = {0, 0, 0, 0, 0}, lanczos_steps = 0;
+    double* dLamSum = nullptr;
+    // walk state
+    int wcap = 0;
+    double *wX = nullptr, *wXs = nullptr, *wV = nullptr, *wEll = nullptr, *wStats = nullptr, *wSum = nullptr;
+    int32_t *wNref = nullptr, *wActive = nullptr, *wCount = nullptr;
+    long long* wStep = nullptr;
 
     void free_work() {
         dfree(dZ); dfree(dFB); dfree(dW); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
         cap = 0;
+    }
+    void free_walk() {
+        dfree(wX); dfree(wXs); dfree(wV); dfree(wEll); dfree(wStats); dfree(wSum);
+        dfree(wNref); dfree(wActive); dfree(wCount); dfree(wStep);
+        wcap = 0;
+    }
+    spec_status ensure_walk(int chains) {
+        if (chains <= wcap) return SPEC_OK;
+        free_walk();
+        const int c = round_up(chains, 64);
+        HIPCHK(dalloc(&wX, (size_t)c * n, false));
+        HIPCHK(dalloc(&wXs, (size_t)c * n, false));
+        HIPCHK(dalloc(&wV, (size_t)c * n, false));
+        HIPCHK(dalloc(&wEll, (size_t)c, false));
+        HIPCHK(dalloc(&wStats, (size_t)c * WALK_NSTAT, false));
+        HIPCHK(dalloc(&wSum, (size_t)WALK_NSTAT, false));
+        HIPCHK(dalloc(&wNref, (size_t)c, false));
+        HIPCHK(dalloc(&wActive, (size_t)c, false));
+        HIPCHK(dalloc(&wCount, (size_t)1, false));
+        HIPCHK(dalloc(&wStep, (size_t)c, false));
+        wcap = c;
+        return SPEC_OK;
     }
     void free_stage() {
         dfree(sX); dfree(sV); dfree(sO1); dfree(sO2); dfree(sS); dfree(sW); dfree(sSt); dfree(sI);
@@ -128,11 +161,18 @@ spec_status assemble(spec_s* h, int batch, const double* x, const double* v, int
     return SPEC_OK;
 }
 
+inline void mark(spec_s* h, int i, hipStream_t s) {
+    if (h->timing) (void)hipEventRecord(h->ev[i], s);
+}
+
 spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, double* tm, double* tp,
                         int32_t* st, bool want_vec, const double* ell, hipStream_t s) {
     int bp = 0;
+    mark(h, 0, s);
     SPCHK(assemble(h, batch, x, v, &bp, s));
+    mark(h, 1, s);
     HIPCHK(launch_factor(batch, h->m, h->md, h->P, h->dFB, h->ldA, h->dW, h->ldw, st, s));
+    mark(h, 2, s);
     LanczosArgs a{};
     a.batch = batch;
     a.m = h->m;
@@ -157,6 +197,7 @@ spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, 
     a.U2 = h->dU2;
     a.ldu2 = h->ldA;
     HIPCHK(launch_lanczos(a, s));
+    mark(h, 3, s);
     return SPEC_OK;
 }
 
@@ -299,7 +340,11 @@ spec_status spec_destroy(spec_handle h) {
     (void)hipDeviceSynchronize();
     h->free_work();
     h->free_stage();
+    h->free_walk();
     dfree(h->dA);
+    dfree(h->dLamSum);
+    for (auto& e : h->ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return SPEC_OK;
 }
@@ -391,6 +436,105 @@ spec_status spec_reflect(spec_handle h, int batch, const double* x, const double
     return SPEC_OK;
 }
 
+// ------------------------------------------------------------ walks
+
+spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
+                              const spec_walk_params* p, double* x_out, double* samples, spec_walk_stats* stats,
+                              void* stream) {
+    if (!h || !p || chains < 0 || steps < 0 || (chains && (!x0 || !x_out))) return SPEC_EINVAL;
+    if (kind != SPEC_WALK_HNR && kind != SPEC_WALK_CHNR && kind != SPEC_WALK_BILLIARD) return SPEC_EINVAL;
+    if (kind == SPEC_WALK_BILLIARD && !(p->tau > 0.0)) return SPEC_EINVAL;
+    if (p->gauss_a < 0.0 || !(p->pullback >= 0.0 && p->pullback < 1.0) || p->thin < 0) return SPEC_EINVAL;
+    if (p->log_buf && (!p->log_count || p->log_cap < 0)) return SPEC_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (chains == 0) return SPEC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SPCHK(h->ensure(chains));
+    SPCHK(h->ensure_walk(chains));
+    WalkArgs a{};
+    a.kind = kind;
+    a.chains = chains;
+    a.n = h->n;
+    a.steps = steps;
+    a.seed = seed;
+    a.tau = p->tau;
+    a.gauss_a = p->gauss_a;
+    a.pullback = p->pullback;
+    a.rho = p->rho > 0 ? p->rho : 10 * h->n;
+    a.st = WalkState{h->wX, h->wXs, h->wV, h->wEll, h->wNref, h->wStep, h->wActive, h->wStats};
+    a.status = h->dSt;
+    a.tm = h->dTm;
+    a.tp = h->dTp;
+    a.hit = h->dHit;
+    a.wn = h->dWn;
+    a.ldwn = h->Nn;
+    a.Astk = h->dA;
+    a.ldA = h->ldA;
+    a.P = h->P;
+    a.samples = samples;
+    a.thin = p->thin;
+    a.nsamp = p->thin > 0 ? steps / p->thin : 0;
+    a.log_buf = p->log_buf;
+    a.log_count = p->log_count;
+    a.log_cap = p->log_cap;
+    a.log_chains = p->log_chains;
+    if (!p->resume) HIPCHK(walk_init(a, x0, s));
+    const bool billiard = kind == SPEC_WALK_BILLIARD;
+    long long rounds = 0;
+    const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
+    while (rounds < max_rounds) {
+        SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard, billiard ? h->wEll : nullptr,
+                          s));
+        if (billiard) {
+            const int bp = round_up(chains, 64);
+            const int Kn = round_up(h->P, 16);
+            if (h->m > 0)
+                HIPCHK(gemm_f64(true, bp, h->Nn, Kn, h->dU2, h->ldA, h->dA + h->ldA, h->ldA, h->dWn, h->Nn, s));
+        }
+        mark(h, 4, s);
+        HIPCHK(walk_update(a, s));
+        mark(h, 5, s);
+        ++rounds;
+        if (h->timing) {
+            HIPCHK(hipStreamSynchronize(s));
+            for (int i = 0; i < 5; ++i) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+                h->stage_ms[i] += ms;
+                h->stage_n[i] += 1;
+            }
+            HIPCHK(launch_sum_col(chains, h->dLam, 4, 3, h->dLamSum, s));
+            double ls = 0.0;
+            HIPCHK(hipMemcpyAsync(&ls, h->dLamSum, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            h->lanczos_steps += ls;
+        }
+        if (rounds % 16 == 0 || rounds == max_rounds) {
+            int32_t live = 0;
+            HIPCHK(walk_count_active(chains, h->wActive, h->wCount, s));
+            HIPCHK(hipMemcpyAsync(&live, h->wCount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (live == 0) break;
+        }
+    }
+    HIPCHK(walk_finish(a, x_out, s));
+    if (stats) {
+        double tot[WALK_NSTAT];
+        HIPCHK(walk_sum_stats(chains, h->wStats, h->wSum, s));
+        HIPCHK(hipMemcpyAsync(tot, h->wSum, sizeof(tot), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        stats->calls = tot[0];
+        stats->reflections = tot[1];
+        stats->cap_hits = tot[2];
+        stats->not_interior = tot[3];
+        stats->nonsmooth = tot[4];
+        stats->steps = tot[5];
+        stats->noconv = tot[6];
+        stats->rounds = (double)rounds;
+    }
+    return SPEC_OK;
+}
+
 // ------------------------------------------------------------ diagnostics
 
 spec_status spec_diag_mfma_layout(double* host_out) {
@@ -418,6 +562,29 @@ spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A,
     (void)hipFree(dB);
     (void)hipFree(dC);
     return from_hip(e);
+}
+
+spec_status spec_diag_timing(spec_handle h, int on) {
+    if (!h) return SPEC_EINVAL;
+    if (on) {
+        for (auto& e : h->ev)
+            if (!e) HIPCHK(hipEventCreate(&e));
+        if (!h->dLamSum) HIPCHK(dalloc(&h->dLamSum, 1));
+        for (int i = 0; i < 5; ++i) h->stage_ms[i] = h->stage_n[i] = 0.0;
+        h->lanczos_steps = 0.0;
+    }
+    h->timing = on != 0;
+    return SPEC_OK;
+}
+
+spec_status spec_diag_stage_times(spec_handle h, double* out, double* lanczos_steps) {
+    if (!h || !out) return SPEC_EINVAL;
+    for (int i = 0; i < 5; ++i) {
+        out[i] = h->stage_ms[i];
+        out[5 + i] = h->stage_n[i];
+    }
+    if (lanczos_steps) *lanczos_steps = h->lanczos_steps;
+    return SPEC_OK;
 }
 
 spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out) {

@@ -115,3 +115,26 @@ hipError_t launch_status_to_flag(int batch, const int32_t* st, int8_t* flag, hip
 }
 
 }  // namespace spec
+
+namespace spec {
+
+// out[0] = sum_r M[r * ld + col] over r < rows (one block, deterministic order).
+__global__ void k_sum_col(int rows, const double* __restrict__ M, int ld, int col, double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) s += M[(size_t)r * ld + col];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_sum_col(int rows, const double* M, int ld, int col, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_col, dim3(1), dim3(256), 0, s, rows, M, ld, col, out);
+    return hipGetLastError();
+}
+
+}  // namespace spec

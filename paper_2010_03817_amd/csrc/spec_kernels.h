@@ -58,6 +58,7 @@ struct ReflectArgs {
     double* w_out;       // unit outward normal (nullable)
 };
 hipError_t launch_reflect_finish(const ReflectArgs& a, hipStream_t s);
+hipError_t launch_sum_col(int rows, const double* M, int ld, int col, double* out, hipStream_t s);
 hipError_t launch_status_to_flag(int batch, const int32_t* st, int8_t* flag, hipStream_t s);
 
 }  // namespace spec

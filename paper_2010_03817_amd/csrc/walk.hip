@@ -1,0 +1,276 @@
+// Step machines of the random walks (paper, Section "Random walks"): every
+// round, every live chain runs one segment through the boundary oracle, and
+// these kernels apply the walk's rule to the result.  A chain that finishes a
+// step draws the next one at once, so every chain has a segment every round
+// whatever its number of reflections (uneven work per step stays batched).
+//
+// Random numbers: Philox4x32-10 with key = seed and counter =
+// (chain, step, draw, tag), the step being the chain's own count of
+// completed steps.  Directions: Box-Muller normals normalised; billiard
+// length ell = -tau ln(eta); chord position u (Hit-and-Run); coordinate
+// floor(u n) (coordinate Hit-and-Run).
+#include "common.h"
+#include "walk_kernels.h"
+
+namespace spec {
+
+__device__ inline double dir_component(uint64_t seed, uint32_t chain, uint32_t step, uint32_t tag, int i) {
+    double g0, g1;
+    normal_pair(seed, chain, step, (uint32_t)(i >> 1), tag, g0, g1);
+    return (i & 1) ? g1 : g0;
+}
+
+// Uniform direction on the sphere: normals 2d, 2d+1 of draw d, normalised.
+// One wave per chain; each lane only writes its own coordinates.
+__device__ inline void random_unit_dir(uint64_t seed, uint32_t chain, uint32_t step, uint32_t tag, int n,
+                                       double* v, int lane) {
+    double ss = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double g = dir_component(seed, chain, step, tag, i);
+        ss += g * g;
+    }
+    ss = wave_sum(ss);
+    const double inv = 1.0 / sqrt(ss);
+    for (int i = lane; i < n; i += 64) v[i] = dir_component(seed, chain, step, tag, i) * inv;
+}
+
+// Begin step `step` of chain c: direction, and the billiard length.
+__device__ inline void begin_step(const WalkArgs& a, int c, long long step64, int lane) {
+    const WalkState& S = a.st;
+    const uint32_t step = (uint32_t)step64;
+    double* v = S.v + (size_t)c * a.n;
+    if (a.kind == SPEC_WALK_CHNR) {
+        double u0, u1;
+        draw_u2(a.seed, (uint32_t)c, step, 0, TAG_COORD, u0, u1);
+        int j = (int)floor(u0 * a.n);
+        if (j >= a.n) j = a.n - 1;
+        for (int i = lane; i < a.n; i += 64) v[i] = i == j ? 1.0 : 0.0;
+    } else {
+        random_unit_dir(a.seed, (uint32_t)c, step, TAG_DIR, a.n, v, lane);
+    }
+    if (lane == 0) {
+        if (a.kind == SPEC_WALK_BILLIARD) {
+            double u0, u1;
+            draw_u2(a.seed, (uint32_t)c, step, 0, TAG_LEN, u0, u1);
+            S.ell[c] = -a.tau * log(u0);
+        } else {
+            S.ell[c] = INFINITY;
+        }
+        S.nref[c] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_walk_init(WalkArgs a, const double* __restrict__ x0) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= a.chains) return;
+    const WalkState& S = a.st;
+    for (int i = lane; i < a.n; i += 64) {
+        const double xi = x0[(size_t)c * a.n + i];
+        S.x[(size_t)c * a.n + i] = xi;
+        S.xs[(size_t)c * a.n + i] = xi;
+    }
+    if (lane == 0) {
+        S.step[c] = 0;
+        S.active[c] = a.steps > 0 ? 1 : 0;
+        for (int k = 0; k < WALK_NSTAT; ++k) S.stats[(size_t)c * WALK_NSTAT + k] = 0.0;
+    }
+    if (a.steps > 0) begin_step(a, c, 0, lane);
+}
+
+// Truncated normal N(mu, sig^2) on [lo, hi] by inverting the CDF with u.
+__device__ inline double trunc_normal_at(double mu, double sig, double lo, double hi, double u) {
+    const double al = (lo - mu) / sig, be = (hi - mu) / sig;
+    const double r2 = 1.4142135623730950488;
+    double z;
+    if (al >= 0.0) {  // upper tail: work with Q = 1 - Phi
+        const double qa = 0.5 * erfc(al / r2), qb = 0.5 * erfc(be / r2);
+        const double q = qa - u * (qa - qb);
+        z = r2 * erfcinv(2.0 * q);
+    } else if (be <= 0.0) {  // lower tail
+        const double pa = 0.5 * erfc(-al / r2), pb = 0.5 * erfc(-be / r2);
+        const double p = pa + u * (pb - pa);
+        z = -r2 * erfcinv(2.0 * p);
+    } else {
+        const double pa = 0.5 * erfc(-al / r2), pb = 0.5 * erfc(-be / r2);
+        const double p = pa + u * (pb - pa);
+        z = p < 0.5 ? -r2 * erfcinv(2.0 * p) : r2 * erfcinv(2.0 * (1.0 - p));
+    }
+    double t = mu + sig * z;
+    return fmin(fmax(t, lo), hi);
+}
+
+// Finish a step: record the sample, advance the counter, start the next.
+// Every lane of the chain's wave calls it; each lane touches its own
+// coordinates only.
+__device__ inline void end_step(const WalkArgs& a, int c, int lane) {
+    const WalkState& S = a.st;
+    const int n = a.n;
+    for (int i = lane; i < n; i += 64) S.xs[(size_t)c * n + i] = S.x[(size_t)c * n + i];
+    const long long k = S.step[c] + 1;
+    if (a.samples && a.thin > 0 && k % a.thin == 0) {
+        const long long j = k / a.thin - 1;
+        double* dst = a.samples + ((size_t)c * a.nsamp + j) * n;
+        for (int i = lane; i < n; i += 64) dst[i] = S.x[(size_t)c * n + i];
+    }
+    if (lane == 0) {
+        S.step[c] = k;
+        S.stats[(size_t)c * WALK_NSTAT + 5] += 1.0;
+        if (k >= a.steps) S.active[c] = 0;
+    }
+    if (k < a.steps) begin_step(a, c, k, lane);
+}
+
+// One wave per chain.
+__global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= a.chains) return;
+    const WalkState& S = a.st;
+    if (!S.active[c]) return;
+    const int n = a.n;
+    double* x = S.x + (size_t)c * n;
+    double* v = S.v + (size_t)c * n;
+    double* st = S.stats + (size_t)c * WALK_NSTAT;
+    const int32_t status = a.status[c];
+    const double tp = a.tp[c], tm = a.tm[c];
+    // log the segment start (x, v) with its t-, t+
+    if (a.log_buf && c < a.log_chains) {
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(a.log_count, 1);
+        slot = __shfl(slot, 0, 64);
+        if (slot < a.log_cap) {
+            double* rec = a.log_buf + (size_t)slot * (2 * n + 4);
+            for (int i = lane; i < n; i += 64) {
+                rec[i] = x[i];
+                rec[n + i] = v[i];
+            }
+            if (lane == 0) {
+                rec[2 * n] = tm;
+                rec[2 * n + 1] = tp;
+                rec[2 * n + 2] = (double)c;
+                rec[2 * n + 3] = (double)status;
+            }
+        }
+    }
+    if (lane == 0) {
+        st[0] += 1.0;
+        if (status == SPEC_NOCONV) st[6] += 1.0;
+    }
+    if (status == SPEC_NOT_INTERIOR) {
+        // cannot happen from an interior start; count it and restart the
+        // step from its start point
+        if (lane == 0) st[3] += 1.0;
+        for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+        end_step(a, c, lane);
+        return;
+    }
+    if (a.kind == SPEC_WALK_HNR || a.kind == SPEC_WALK_CHNR) {
+        if (isfinite(tp) && isfinite(tm)) {
+            double u0, u1;
+            draw_u2(a.seed, (uint32_t)c, (uint32_t)S.step[c], 0, TAG_POS, u0, u1);
+            double t;
+            if (a.gauss_a > 0.0) {
+                double xv = 0.0;
+                for (int i = lane; i < n; i += 64) xv += x[i] * v[i];
+                xv = wave_sum(xv);
+                t = trunc_normal_at(-xv, 1.0 / sqrt(2.0 * a.gauss_a), tm, tp, u0);
+            } else {
+                t = tm + u0 * (tp - tm);
+            }
+            for (int i = lane; i < n; i += 64) x[i] += t * v[i];
+        }
+        end_step(a, c, lane);
+        return;
+    }
+    // billiard (Alg. Billiard): move to the end of the segment or reflect
+    const double ell = S.ell[c];
+    if (!(tp < ell)) {
+        for (int i = lane; i < n; i += 64) x[i] += ell * v[i];
+        end_step(a, c, lane);
+        return;
+    }
+    // reflection: s = v - 2 <v, w> w with the outward unit normal w
+    const int hit = a.hit[c];
+    double nn = 0.0, vw = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                           : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+        nn += wi * wi;
+        vw += wi * v[i];
+    }
+    nn = wave_sum(nn);
+    vw = wave_sum(vw);
+    const double step_len = (1.0 - a.pullback) * tp;
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    const double coef = 2.0 * vw * inv * inv;  // 2 <v, w_hat> / |w| along w
+    for (int i = lane; i < n; i += 64) {
+        const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                           : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+        x[i] += step_len * v[i];
+        v[i] -= coef * wi;
+    }
+    const int nref = S.nref[c] + 1;
+    if (lane == 0) {
+        if (!(nn > 0.0) || status == SPEC_NONSMOOTH) st[4] += 1.0;
+        st[1] += 1.0;
+        S.ell[c] = ell - tp;
+        S.nref[c] = nref;
+    }
+    if (nref > a.rho) {
+        // too many reflections: the chain stays at the step's start point
+        if (lane == 0) st[2] += 1.0;
+        for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+        end_step(a, c, lane);
+    }
+}
+
+__global__ void k_walk_finish(WalkArgs a, double* __restrict__ x_out) {
+    const int c = blockIdx.x;
+    if (c >= a.chains) return;
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) x_out[(size_t)c * a.n + i] = a.st.xs[(size_t)c * a.n + i];
+}
+
+__global__ void k_count_active(int chains, const int32_t* __restrict__ active, int32_t* __restrict__ out) {
+    __shared__ int red[1024];
+    int s = 0;
+    for (int c = threadIdx.x; c < chains; c += blockDim.x) s += active[c] != 0;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_sum_stats(int chains, const double* __restrict__ stats, double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= WALK_NSTAT) return;
+    double s = 0.0;
+    for (int c = 0; c < chains; ++c) s += stats[(size_t)c * WALK_NSTAT + k];
+    out[k] = s;
+}
+
+hipError_t walk_init(const WalkArgs& a, const double* x0, hipStream_t s) {
+    hipLaunchKernelGGL(k_walk_init, dim3((a.chains + 3) / 4), dim3(256), 0, s, a, x0);
+    return hipGetLastError();
+}
+hipError_t walk_update(const WalkArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_walk_update, dim3((a.chains + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_walk_finish, dim3(a.chains), dim3(64), 0, s, a, x_out);
+    return hipGetLastError();
+}
+hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, s, chains, active, out);
+    return hipGetLastError();
+}
+hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_stats, dim3(1), dim3(64), 0, s, chains, stats, out);
+    return hipGetLastError();
+}
+
+}  // namespace spec

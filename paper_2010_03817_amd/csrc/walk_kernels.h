@@ -1,0 +1,53 @@
+// Walk step machines (internal launch interface).
+#pragma once
+#include "spec_kernels.h"
+
+namespace spec {
+
+// Per-chain statistics: oracle calls, reflections, cap hits, not-interior,
+// nonsmooth, completed steps, eigen non-convergence, spare.
+constexpr int WALK_NSTAT = 8;
+
+struct WalkState {
+    double* x;        // chains x n: current point
+    double* xs;       // chains x n: point at the start of the current step
+    double* v;        // chains x n: current direction
+    double* ell;      // remaining length of the billiard step
+    int32_t* nref;    // reflections in the current step
+    long long* step;  // completed steps
+    int32_t* active;  // 1 while the chain has steps left
+    double* stats;    // chains x WALK_NSTAT
+};
+
+struct WalkArgs {
+    int kind, chains, n;
+    long long steps;
+    uint64_t seed;
+    double tau, gauss_a, pullback;
+    int rho;
+    WalkState st;
+    // oracle results of the current round
+    const int32_t* status;
+    const double* tm;
+    const double* tp;
+    const int32_t* hit;
+    const double* wn;  // dense normal (chains x ldwn)
+    int ldwn;
+    const double* Astk;
+    int ldA, P;
+    // samples and logging
+    double* samples;   // chains x nsamp x n (nullable)
+    long long nsamp;
+    int thin;
+    double* log_buf;   // log_cap records of (x, v, t-, t+, chain, status)
+    int32_t* log_count;
+    int log_cap, log_chains;
+};
+
+hipError_t walk_init(const WalkArgs& a, const double* x0, hipStream_t s);
+hipError_t walk_update(const WalkArgs& a, hipStream_t s);
+hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s);
+hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s);
+hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStream_t s);
+
+}  // namespace spec

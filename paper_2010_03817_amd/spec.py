@@ -26,6 +26,21 @@ class SpecError(RuntimeError):
     pass
 
 
+class WalkParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("rho", C.c_int), ("gauss_a", C.c_double), ("pullback", C.c_double),
+                ("thin", C.c_int), ("max_rounds", C.c_longlong), ("resume", C.c_int), ("log_chains", C.c_int),
+                ("log_cap", C.c_int),
+                ("log_buf", C.c_void_p), ("log_count", C.c_void_p)]
+
+
+class WalkStats(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("calls", "reflections", "cap_hits", "not_interior", "nonsmooth", "steps",
+                                          "noconv", "rounds")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -62,6 +77,10 @@ def lib():
     L.spec_membership.argtypes = [vp, C.c_int, vp, vp]
     L.spec_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     L.spec_reflect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
+    L.spec_walk_run_dev.argtypes = [vp, C.c_int, C.c_int, vp, C.c_longlong, C.c_uint64, C.POINTER(WalkParams), vp,
+                                    vp, C.POINTER(WalkStats), vp]
+    L.spec_diag_timing.argtypes = [vp, C.c_int]
+    L.spec_diag_stage_times.argtypes = [vp, vp, vp]
     L.spec_diag_mfma_layout.argtypes = [vp]
     L.spec_diag_gemm_f64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.spec_diag_lanczos_info.argtypes = [vp, C.c_int, vp]
@@ -169,6 +188,43 @@ class Spectrahedron:
         check(lib().spec_reflect_dev(self._h, B, _ptr(x), _ptr(v), _ptr(tp), _ptr(s), _ptr(w), _ptr(st),
                                      _stream()))
         return tp, s, w, st
+
+    def walk(self, kind, x0, steps, seed, tau=1.0, rho=0, gauss_a=0.0, pullback=1e-6, thin=0, max_rounds=0,
+             log_chains=0, log_cap=0, resume=False):
+        """Run chains of a walk (HNR, CHNR, BILLIARD) from x0; returns
+        (x_out, samples or None, stats dict, log or None).  The log holds rows
+        (x, v, t-, t+, chain, status) of segments of the first log_chains chains."""
+        torch = _torch()
+        x0 = _f64(x0).reshape(-1, self.n)
+        ch = x0.shape[0]
+        x_out = torch.empty_like(x0)
+        ns = steps // thin if thin > 0 else 0
+        samples = torch.empty((ch, ns, self.n), dtype=torch.float64, device="cuda") if ns > 0 else None
+        log = cnt = None
+        if log_cap > 0:
+            log = torch.empty((log_cap, 2 * self.n + 4), dtype=torch.float64, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        p = WalkParams(tau=tau, rho=rho, gauss_a=gauss_a, pullback=pullback, thin=thin, max_rounds=max_rounds,
+                       resume=int(resume), log_chains=log_chains, log_cap=log_cap, log_buf=_ptr(log),
+                       log_count=_ptr(cnt))
+        st = WalkStats()
+        check(lib().spec_walk_run_dev(self._h, kind, ch, _ptr(x0), steps, seed, C.byref(p), _ptr(x_out),
+                                      _ptr(samples), C.byref(st), _stream()))
+        if log is not None:
+            k = min(int(cnt.item()), log_cap)
+            log = log[:k]
+        return x_out, samples, st.as_dict(), log
+
+    def timing(self, on: bool):
+        check(lib().spec_diag_timing(self._h, int(on)))
+
+    def stage_times(self):
+        """{stage: (ms total, launches)} and the summed Lanczos steps."""
+        out = np.zeros(10)
+        ls = C.c_double()
+        check(lib().spec_diag_stage_times(self._h, out.ctypes.data_as(C.c_void_p), C.byref(ls)))
+        names = ["assemble", "factor", "lanczos", "normal", "update"]
+        return {k: (out[i], out[5 + i]) for i, k in enumerate(names)}, ls.value
 
     def lanczos_info(self, batch):
         """(lambda_min, lambda_max, second Ritz value, steps) of the last call."""

@@ -1,0 +1,136 @@
+"""Walks on the device: identical random numbers to the oracle (first steps
+match), per-segment parity on logged pairs, and stationary distributions."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+from oracle import oracle as O
+from paper_2010_03817_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+T_REL = 1e-9
+
+
+def _S():
+    from paper_2010_03817_amd import spec as S
+    return S
+
+
+def _np(t):
+    return None if t is None else t.detach().cpu().numpy()
+
+
+def config1():
+    return I.gbase(10, 10, seed=101, scale=math.sqrt(10))
+
+
+def test_hnr_first_step_matches_oracle():
+    """Same Philox stream (chain, step, draw, tag): one Hit-and-Run step from
+    x0 = 0 lands on the same point as the oracle's."""
+    S = _S()
+    inst = config1()
+    g, o = S.Spectrahedron(inst), O.Oracle(inst)
+    x0 = np.zeros((64, 10))
+    for kind in (S.HNR, S.CHNR):
+        xg, _, st, _ = g.walk(kind, x0, 1, seed=201)
+        xr, _, sr = o.walk(kind, x0, 1, seed=201)
+        assert np.allclose(_np(xg), xr, rtol=1e-9, atol=1e-12)
+        assert st["steps"] == 64 and st["calls"] == 64
+
+
+def test_billiard_first_step_matches_oracle():
+    S = _S()
+    inst = config1()
+    g, o = S.Spectrahedron(inst), O.Oracle(inst)
+    x0 = np.zeros((64, 10))
+    xg, _, st, _ = g.walk(S.BILLIARD, x0, 1, seed=202, tau=1.0)
+    xr, _, sr = o.walk(O.BILLIARD, x0, 1, seed=202, tau=1.0)
+    # the reflected directions agree to the Ritz-vector accuracy, so after a
+    # few reflections the points agree to ~1e-6
+    assert np.allclose(_np(xg), xr, atol=1e-6)
+    assert st["reflections"] == sr[1] and st["calls"] == sr[0]
+
+
+@pytest.mark.parametrize("kind", ["hnr", "billiard"])
+def test_logged_pairs_parity(kind):
+    """Per-segment t+- of a running walk against the oracle recomputing the
+    logged (x, v) pairs (post-reflection starts included)."""
+    S = _S()
+    inst = I.gbase(50, 60, seed=102)
+    g, o = S.Spectrahedron(inst), O.Oracle(inst)
+    k = S.HNR if kind == "hnr" else S.BILLIARD
+    x0 = np.zeros((256, 50))
+    xg, _, st, log = g.walk(k, x0, 20, seed=301, tau=2.0, log_chains=256, log_cap=400)
+    log = _np(log)
+    assert len(log) == 400
+    n = 50
+    x, v, tm, tp = log[:, :n], log[:, n:2 * n], log[:, 2 * n], log[:, 2 * n + 1]
+    tm_r, tp_r, st_r = o.intersect(x, v)
+    ok = st_r == O.OK
+    assert ok.mean() > 0.95
+    # relative bar 1e-9; the short side of a post-reflection start (pulled
+    # back 1e-6 from the boundary) is conditioned ~1e6 worse
+    short_m = np.abs(tm_r) < 1e-3 * tp_r
+    short_p = tp_r < 1e-3 * np.abs(tm_r)
+    rel_p = np.abs(tp - tp_r) / tp_r
+    rel_m = np.abs(tm - tm_r) / np.abs(tm_r)
+    assert (rel_p[ok & ~short_p] <= T_REL).all(), rel_p[ok & ~short_p].max()
+    assert (rel_m[ok & ~short_m] <= T_REL).all(), rel_m[ok & ~short_m].max()
+    assert (rel_m[ok & short_m] <= 1e-6).all()
+
+
+def test_hnr_uniform_box_and_chnr():
+    S = _S()
+    n = 3
+    g = S.Spectrahedron(I.box(n, 1.0))
+    for kind in (S.HNR, S.CHNR):
+        xg, smp, st, _ = g.walk(kind, np.zeros((256, n)), 200, seed=7, thin=20)
+        pts = _np(smp)[:, 3:].reshape(-1, n)
+        for i in range(n):
+            assert scipy.stats.kstest((pts[:, i] + 1) / 2, "uniform").pvalue > 1e-3
+
+
+def test_billiard_uniform_on_ball():
+    S = _S()
+    n = 5
+    g = S.Spectrahedron(I.arrow_ball(n))
+    xg, smp, st, _ = g.walk(S.BILLIARD, np.zeros((512, n)), 100, seed=8, tau=2.0, thin=10)
+    r2 = (_np(smp)[:, 2:] ** 2).sum(-1).ravel()
+    se = r2.std() / math.sqrt(len(r2) / 4)
+    assert abs(r2.mean() - n / (n + 2)) < 4 * se
+
+
+def test_gaussian_hnr_on_ball():
+    S = _S()
+    n, sigma = 4, 0.6
+    g = S.Spectrahedron(I.arrow_ball(n))
+    xg, smp, st, _ = g.walk(S.HNR, np.zeros((512, n)), 100, seed=10, gauss_a=1 / (2 * sigma**2), thin=10)
+    c = 1 / sigma**2
+    want = n * sigma**2 * scipy.stats.chi2.cdf(c, n + 2) / scipy.stats.chi2.cdf(c, n)
+    r2 = (_np(smp)[:, 2:] ** 2).sum(-1).ravel()
+    se = r2.std() / math.sqrt(len(r2) / 4)
+    assert abs(r2.mean() - want) < 4 * se
+
+
+@pytest.mark.parametrize("kind", ["hnr", "billiard"])
+def test_config1_coordinate_means_match_oracle(kind):
+    """The small workload in full: 64 chains x 1000 steps from 0 on the GPU and
+    on the oracle; coordinate means of the second half agree within their
+    Monte-Carlo error (chains are independent; thinned samples)."""
+    S = _S()
+    inst = config1()
+    g, o = S.Spectrahedron(inst), O.Oracle(inst)
+    k = S.HNR if kind == "hnr" else S.BILLIARD
+    x0 = np.zeros((64, 10))
+    _, sg, st, _ = g.walk(k, x0, 1000, seed=401, tau=1.0, thin=10)
+    _, sr, _ = o.walk(k, x0, 1000, seed=402, tau=1.0, thin=10)
+    a, b = _np(sg)[:, 50:], sr[:, 50:]
+    ma, mb = a.mean((0, 1)), b.mean((0, 1))
+    # chain-level means are independent across chains
+    sa = a.mean(1).std(0) / math.sqrt(64)
+    sb = b.mean(1).std(0) / math.sqrt(64)
+    z = np.abs(ma - mb) / np.sqrt(sa**2 + sb**2)
+    assert (z < 4.5).all(), z
+    assert st["not_interior"] == 0

@@ -86,10 +86,12 @@ spec_status spec_dims(spec_handle h, int* n, int* m, int* md);
 
 const char* spec_status_str(spec_status s);
 
-/* Lanczos settings of the extreme-eigenvalue step: at most kmax basis vectors
- * (default 80) and the stopping test beta_{k+1} |s_k| <= tol |theta| on the
- * residual bound of both extreme Ritz pairs (default 1e-10).  SPEC_ENOTSUP if
- * the basis would not fit in LDS for this handle's m. */
+/* Lanczos settings of the extreme-eigenvalue step: at most kmax steps
+ * (default 80) and the stopping test on the residual bound of the extreme
+ * Ritz pairs, beta_{k+1} |s_k| <= max(tol |theta|, 100 eps rho) with rho the
+ * spectral radius estimate (default tol 1e-8; the Ritz value error is then
+ * about the square of the bound over the gap).  SPEC_ENOTSUP if the
+ * tridiagonal would not fit in LDS for this handle's m. */
 spec_status spec_set_lanczos(spec_handle h, int kmax, double tol);
 
 /* MEMBERSHIP (Alg. MEMBERSHIP, read as strict definiteness): interior[e] = 1

@@ -13,6 +13,7 @@
 #include "spec_diag.h"
 #include "spec_kernels.h"
 #include "walk_kernels.h"
+#include "line_fused.h"
 
 using namespace spec;
 
@@ -57,14 +58,14 @@ spec_status from_hip(hipError_t e) {
 
 struct spec_s {
     int device = 0;
-    int n = 0, m = 0, md = 0, P = 0, Ptot = 0, K = 0, Kpad = 0, ldA = 0, Arows = 0, Nn = 0, ldw = 0;
+    int n = 0, m = 0, md = 0, P = 0, Ptot = 0, K = 0, Kpad = 0, ldA = 0, Arows = 0, Nn = 0;
     double* dA = nullptr;  // Arows x ldA
     // Lanczos settings
     int kmax = 80;
-    double tol = 1e-10;
+    double tol = 1e-8;
     // workspace (capacity in chains, multiple of 64)
     int cap = 0;
-    double *dZ = nullptr, *dFB = nullptr, *dW = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
+    double *dZ = nullptr, *dFB = nullptr, *dQ = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
     double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
     int32_t *dHit = nullptr, *dSt = nullptr;
     // staging for the host-pointer entry points
@@ -84,7 +85,7 @@ struct spec_s {
     long long* wStep = nullptr;
 
     void free_work() {
-        dfree(dZ); dfree(dFB); dfree(dW); dfree(dU); dfree(dU2); dfree(dWn);
+        dfree(dZ); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
         cap = 0;
     }
@@ -120,7 +121,7 @@ struct spec_s {
         const int c = round_up(batch, 64);
         HIPCHK(dalloc(&dZ, (size_t)2 * c * Kpad));
         HIPCHK(dalloc(&dFB, (size_t)2 * c * ldA, false));
-        HIPCHK(dalloc(&dW, (size_t)c * ldw, false));
+        HIPCHK(dalloc(&dQ, (size_t)c * ldq(), false));
         HIPCHK(dalloc(&dU, (size_t)c * m, false));
         HIPCHK(dalloc(&dU2, (size_t)c * ldA));
         HIPCHK(dalloc(&dWn, (size_t)c * Nn, false));
@@ -132,6 +133,7 @@ struct spec_s {
         cap = c;
         return SPEC_OK;
     }
+    size_t ldq() const { return (size_t)kmax * std::max(m, 1); }
     spec_status ensure_stage(int batch) {
         if (batch <= scap) return SPEC_OK;
         free_stage();
@@ -165,16 +167,8 @@ inline void mark(spec_s* h, int i, hipStream_t s) {
     if (h->timing) (void)hipEventRecord(h->ev[i], s);
 }
 
-spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, double* tm, double* tp,
-                        int32_t* st, bool want_vec, const double* ell, hipStream_t s) {
-    int bp = 0;
-    mark(h, 0, s);
-    SPCHK(assemble(h, batch, x, v, &bp, s));
-    mark(h, 1, s);
-    HIPCHK(launch_factor(batch, h->m, h->md, h->P, h->dFB, h->ldA, h->dW, h->ldw, st, s));
-    mark(h, 2, s);
-    LanczosArgs a{};
-    a.batch = batch;
+FusedArgs fused_args(spec_s* h, int bp, int32_t* st, double* tm, double* tp, bool want_vec, const double* ell) {
+    FusedArgs a{};
     a.m = h->m;
     a.md = h->md;
     a.P = h->P;
@@ -183,20 +177,32 @@ spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, 
     a.FB = h->dFB;
     a.ldfb = h->ldA;
     a.brow0 = bp;
-    a.W = h->dW;
-    a.ldw = h->ldw;
+    a.want_vec = want_vec ? 1 : 0;
+    a.ell = ell;
+    a.Q = h->dQ;
+    a.ldq = h->ldq();
     a.status = st;
     a.tm = tm;
     a.tp = tp;
     a.hit = h->dHit;
     a.lam = h->dLam;
-    a.want_vec = want_vec ? 1 : 0;
-    a.ell = ell;
     a.u = h->dU;
     a.ldu = h->m;
     a.U2 = h->dU2;
     a.ldu2 = h->ldA;
-    HIPCHK(launch_lanczos(a, s));
+    return a;
+}
+
+spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, double* tm, double* tp,
+                        int32_t* st, bool want_vec, const double* ell, hipStream_t s, bool min_only = false) {
+    int bp = 0;
+    mark(h, 0, s);
+    SPCHK(assemble(h, batch, x, v, &bp, s));
+    mark(h, 1, s);
+    mark(h, 2, s);
+    FusedArgs a = fused_args(h, bp, st, tm, tp, want_vec, ell);
+    a.min_only = min_only ? 1 : 0;
+    HIPCHK(launch_line_fused(a, batch, s));
     mark(h, 3, s);
     return SPEC_OK;
 }
@@ -302,7 +308,7 @@ spec_status spec_create(int n, int nblocks, const int* block_size, const int* ki
     h->ldA = round_up(h->Ptot, 64);
     h->Nn = round_up(n, 64);
     h->Arows = std::max(h->Kpad, 1 + h->Nn);
-    h->ldw = round_up(std::max(h->P, 1), 8);
+    while (h->kmax > 2 && fused_lds_bytes(h->m, h->kmax) > 163840) --h->kmax;
     // pack: row i = [A_i dense lower rows (merged block-diagonal) | A_i diagonals]
     std::vector<double> host((size_t)h->Arows * h->ldA, 0.0);
     const double* src = A;
@@ -359,7 +365,8 @@ spec_status spec_dims(spec_handle h, int* n, int* m, int* md) {
 
 spec_status spec_set_lanczos(spec_handle h, int kmax, double tol) {
     if (!h || kmax < 2 || kmax > SPEC_MAX_KRYLOV || !(tol > 0.0) || !(tol < 1.0)) return SPEC_EINVAL;
-    if (lanczos_lds_bytes(h->m, kmax) > 163840) return SPEC_ENOTSUP;
+    if (fused_lds_bytes(h->m, kmax) > 163840) return SPEC_ENOTSUP;
+    if (h->cap) h->free_work();  // the basis buffer is sized by kmax
     h->kmax = kmax;
     h->tol = tol;
     return SPEC_OK;
@@ -372,7 +379,9 @@ spec_status spec_membership_dev(spec_handle h, int batch, const double* x, int8_
     SPCHK(h->ensure(batch));
     int bp = 0;
     SPCHK(assemble(h, batch, x, nullptr, &bp, s));
-    HIPCHK(launch_factor(batch, h->m, h->md, h->P, h->dFB, h->ldA, h->dW, h->ldw, h->dSt, s));
+    FusedArgs a = fused_args(h, bp, h->dSt, h->dTm, h->dTp, false, nullptr);
+    a.membership_only = 1;
+    HIPCHK(launch_line_fused(a, batch, s));
     HIPCHK(launch_status_to_flag(batch, h->dSt, interior, s));
     return SPEC_OK;
 }
@@ -484,7 +493,7 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
     while (rounds < max_rounds) {
         SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard, billiard ? h->wEll : nullptr,
-                          s));
+                          s, billiard));
         if (billiard) {
             const int bp = round_up(chains, 64);
             const int Kn = round_up(h->P, 16);

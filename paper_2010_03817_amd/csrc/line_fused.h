@@ -1,0 +1,36 @@
+// Fused per-chain line oracle (internal launch interface).
+#pragma once
+#include "spec_kernels.h"
+
+namespace spec {
+
+struct FusedArgs {
+    int m, md, P, kmax;
+    double tol;
+    const double* FB;          // row c: F(x_c) packed + diagonal rows; row brow0 + c: B(v_c)
+    int ldfb, brow0;
+    const int32_t* idx;        // nullable: workgroup b handles chain idx[b]
+    const double* shift;       // nullable: per-chain origin t0 (learned bracket, lower end)
+    const double* shift_hi;    // nullable: per-chain upper end, must not be definite
+    int min_only;              // stop on lambda_min alone
+    int membership_only;       // Cholesky of F(x) only; status OK / NOT_INTERIOR
+    int want_vec;              // form u and vec(u u^T) for dense hits
+    const double* ell;         // nullable: only when t+ < ell[c]
+    double* Q;                 // per chain Lanczos basis (kmax x m), ld ldq
+    size_t ldq;
+    int32_t* status;
+    double* tm;
+    double* tp;
+    int32_t* hit;
+    double* lam;               // nullable: (lambda_min, lambda_max, cert, steps) per chain
+    double* u;
+    int ldu;
+    double* U2;
+    int ldu2;
+};
+
+size_t fused_lds_bytes(int m, int kmax);
+int fused_threads(int m);
+hipError_t launch_line_fused(const FusedArgs& a, int nblocks, hipStream_t s);
+
+}  // namespace spec

@@ -87,10 +87,6 @@ __global__ __launch_bounds__(256) void k_reflect_finish(ReflectArgs a) {
         s[i] = v[i] - 2.0 * dvw * wh;
         if (w) w[i] = wh;
     }
-    if (lane == 0 && st == SPEC_OK && hit == HIT_DENSE && a.lam) {
-        const double l1 = a.lam[4 * c], l2 = a.lam[4 * c + 2];
-        if (fabs(l2 - l1) <= 1e-10 * fabs(l1)) a.status[c] = SPEC_NONSMOOTH;
-    }
 }
 
 hipError_t launch_reflect_finish(const ReflectArgs& a, hipStream_t s) {

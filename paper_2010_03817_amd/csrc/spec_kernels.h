@@ -14,32 +14,6 @@ hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, 
                     double* C, int ldc, hipStream_t s);
 hipError_t mfma_probe(double* out, hipStream_t s);
 
-size_t factor_lds_bytes(int m);
-hipError_t launch_factor(int batch, int m, int md, int P, const double* FB, int ldfb, double* W, int ldw,
-                         int32_t* status, hipStream_t s);
-
-struct LanczosArgs {
-    int batch, m, md, P, kmax;
-    double tol;
-    const double* FB;  // rows 0..batch-1: F(x_c); rows brow0 + c: B(v_c); ld ldfb
-    int ldfb, brow0;
-    const double* W;   // per chain packed L^{-1}, ld ldw
-    int ldw;
-    int32_t* status;   // in: factor status; out: final status
-    double* tm;
-    double* tp;
-    int32_t* hit;      // row index (>= 0), HIT_DENSE, HIT_NONE
-    double* lam;       // nullable: (lambda_min, lambda_max, lambda_2, iterations) per chain
-    int want_vec;
-    const double* ell; // nullable: the vector is only formed when t+ < ell[c]
-    double* u;         // per chain kernel vector u (m), ld ldu
-    int ldu;
-    double* U2;        // per chain packed vec(u u^T) with doubled off-diagonal, ld ldu2
-    int ldu2;
-};
-size_t lanczos_lds_bytes(int m, int kmax);
-hipError_t launch_lanczos(const LanczosArgs& a, hipStream_t s);
-
 // Assembly rows: Z[c] = [1, x_c] (F) and Z[zrow0 + c] = [0, v_c] (B), padded with zeros.
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s);

@@ -141,7 +141,7 @@ class Spectrahedron:
         check(lib().spec_dims(h, C.byref(n), C.byref(m), C.byref(md)))
         self.m, self.md = m.value, md.value
         if kmax is not None or tol is not None:
-            self.set_lanczos(kmax or 80, tol or 1e-10)
+            self.set_lanczos(kmax or 80, tol or 1e-8)
 
     def set_lanczos(self, kmax: int, tol: float):
         check(lib().spec_set_lanczos(self._h, int(kmax), float(tol)))

@@ -33,6 +33,17 @@ spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out);
 spec_status spec_diag_timing(spec_handle h, int on);
 spec_status spec_diag_stage_times(spec_handle h, double* ms_and_counts, double* lanczos_steps);
 
+/* Phase stamps of the per-chain kernel: spec_diag_phase_profile(h, c)
+ * records, for the next calls on chains < c, the shader clock (clock64) of
+ * thread 0 at 7 phase boundaries (start, F loaded, Cholesky, inverse,
+ * Lanczos start, Lanczos end, done) and, in slots 8..13, the clock cycles
+ * the steering wave spent in each part of the Lanczos steps (W^T q, B a,
+ * W b + alpha, beta, stop test, barrier wait); 0 turns it off.
+ * spec_diag_phase_stamps copies batch x 16 values to the host.  Calls must
+ * use batch <= c. */
+spec_status spec_diag_phase_profile(spec_handle h, int max_chains);
+spec_status spec_diag_phase_stamps(spec_handle h, int batch, long long* out);
+
 #ifdef __cplusplus
 }
 #endif

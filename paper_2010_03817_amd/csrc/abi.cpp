@@ -78,6 +78,8 @@ struct spec_s {
     hipEvent_t ev[6] = {};
     double stage_ms[5] = {0, 0, 0, 0, 0}, stage_n[5] = {0, 0, 0, 0, 0}, lanczos_steps = 0;
     double* dLamSum = nullptr;
+    long long* dProf = nullptr;
+    int prof_cap = 0;
     // walk state
     int wcap = 0;
     double *wX = nullptr, *wXs = nullptr, *wV = nullptr, *wEll = nullptr, *wStats = nullptr, *wSum = nullptr;
@@ -190,6 +192,7 @@ FusedArgs fused_args(spec_s* h, int bp, int32_t* st, double* tm, double* tp, boo
     a.ldu = h->m;
     a.U2 = h->dU2;
     a.ldu2 = h->ldA;
+    a.prof = h->prof_cap > 0 ? h->dProf : nullptr;
     return a;
 }
 
@@ -349,6 +352,7 @@ spec_status spec_destroy(spec_handle h) {
     h->free_walk();
     dfree(h->dA);
     dfree(h->dLamSum);
+    dfree(h->dProf);
     for (auto& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     delete h;
@@ -583,6 +587,24 @@ spec_status spec_diag_timing(spec_handle h, int on) {
         h->lanczos_steps = 0.0;
     }
     h->timing = on != 0;
+    return SPEC_OK;
+}
+
+spec_status spec_diag_phase_profile(spec_handle h, int max_chains) {
+    if (!h || max_chains < 0) return SPEC_EINVAL;
+    dfree(h->dProf);
+    h->prof_cap = 0;
+    if (max_chains > 0) {
+        HIPCHK(dalloc(&h->dProf, (size_t)max_chains * 16));
+        h->prof_cap = max_chains;
+    }
+    return SPEC_OK;
+}
+
+spec_status spec_diag_phase_stamps(spec_handle h, int batch, long long* out) {
+    if (!h || !out || batch < 0 || batch > h->prof_cap) return SPEC_EINVAL;
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out, h->dProf, sizeof(long long) * 16 * batch, hipMemcpyDeviceToHost));
     return SPEC_OK;
 }
 

@@ -80,6 +80,34 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// A value the whole wave agrees on, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Workgroup barrier that orders LDS only: global stores in flight are not
+// waited for (they are not read back by other threads before a full fence).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Sum over the block with LDS-only barriers (see block_sum).
+__device__ inline double block_sum_lds(double v, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    lds_barrier();
+    if (lane == 0) red[wid] = v;
+    lds_barrier();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
 // Sum over the block; `red` is LDS scratch of at least blockDim/64 doubles.
 // Contains barriers: every thread of the block must call it.
 __device__ inline double block_sum(double v, double* red) {

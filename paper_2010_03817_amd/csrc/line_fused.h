@@ -13,6 +13,7 @@ struct FusedArgs {
     const double* shift;       // nullable: per-chain origin t0 (learned bracket, lower end)
     const double* shift_hi;    // nullable: per-chain upper end, must not be definite
     int min_only;              // stop on lambda_min alone
+    int first_check;           // step of the first convergence test (0: 4)
     int membership_only;       // Cholesky of F(x) only; status OK / NOT_INTERIOR
     int want_vec;              // form u and vec(u u^T) for dense hits
     const double* ell;         // nullable: only when t+ < ell[c]
@@ -27,6 +28,7 @@ struct FusedArgs {
     int ldu;
     double* U2;
     int ldu2;
+    long long* prof;           // nullable: per chain 8 clock64 stamps of the phases
 };
 
 size_t fused_lds_bytes(int m, int kmax);

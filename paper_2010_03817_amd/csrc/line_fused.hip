@@ -71,67 +71,104 @@ __device__ __forceinline__ void acc_to_tile(double* L, int m, int I, int J, d4 a
     }
 }
 
-// Unblocked Cholesky of diagonal tile K in place (one wave).  Rows past m act
-// as identity.  Returns false if a pivot is not positive.
-__device__ bool diag_chol(double* L, int m, int K, int lane) {
-    bool ok = true;
-    for (int j = 0; j < 16; ++j) {
-        const int r = 16 * K + j;
-        if (r >= m) break;
-        const double d = L[pk(r, r)];
-        if (!(d > 0.0)) { ok = false; break; }
-        const double l = sqrt(d), inv = 1.0 / l;
-        __builtin_amdgcn_wave_barrier();
-        if (lane > j && lane < 16 && 16 * K + lane < m) L[pk(16 * K + lane, r)] *= inv;
-        if (lane == 0) L[pk(r, r)] = l;
-        __builtin_amdgcn_wave_barrier();
-        // trailing update inside the tile: entries (i, k), j < k <= i < 16
-        for (int e = lane; e < 256; e += 64) {
-            const int i = e >> 4, k = e & 15;
-            if (k > j && k <= i && 16 * K + i < m)
-                L[pk(16 * K + i, 16 * K + k)] -= L[pk(16 * K + i, r)] * L[pk(16 * K + k, r)];
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-    return ok;
-}
+// Dense 16 x 16 tile in LDS with an XOR swizzle: element (i, j) at
+// 16 i + (j ^ i), so that a column is spread over all banks.
+__device__ __forceinline__ int sw(int i, int j) { return 16 * i + (j ^ i); }
 
-// D = inverse of the lower-triangular diagonal tile K (16 x 16, row-major in
-// scratch D); rows past m are identity.  Lane c computes column c by forward
-// substitution.  One wave.
-__device__ void diag_inv(const double* L, int m, int K, double* D, int lane) {
-    if (lane < 16) {
-        const int c = lane;
-        for (int i = 0; i < 16; ++i) {
-            const int r = 16 * K + i;
-            double val;
-            if (i < c) {
-                val = 0.0;
-            } else if (r >= m) {
-                val = i == c ? 1.0 : 0.0;
-            } else {
-                double s = i == c ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) s -= L[pk(r, 16 * K + k)] * D[k * 16 + c];
-                val = s / L[pk(r, r)];
-            }
-            D[i * 16 + c] = val;
-        }
+// Copy the lower part of diagonal tile K of the packed matrix into the dense
+// tile T (identity on rows past m, zeros above the diagonal).  One wave.
+__device__ __forceinline__ void tile_to_dense(const double* L, int m, int K, double* T, int lane) {
+    for (int e = lane; e < 256; e += 64) {
+        const int i = e >> 4, j = e & 15, r = 16 * K + i, c = 16 * K + j;
+        double v = 0.0;
+        if (j <= i) v = r < m ? L[pk(r, c)] : (i == j ? 1.0 : 0.0);
+        T[sw(i, j)] = v;
     }
     __builtin_amdgcn_wave_barrier();
 }
 
+__device__ __forceinline__ void dense_to_tile(double* L, int m, int K, const double* T, int lane) {
+    for (int e = lane; e < 256; e += 64) {
+        const int i = e >> 4, j = e & 15, r = 16 * K + i;
+        if (j <= i && r < m) L[pk(r, 16 * K + j)] = T[sw(i, j)];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Cholesky of the dense tile in place (one wave, 4 elements per lane).  Step
+// j updates (i, k), j < k <= i, with the unscaled column: a_ik -= a_ij a_kj / d.
+__device__ __forceinline__ bool dense_chol16(double* T, int lane) {
+    for (int j = 0; j < 16; ++j) {
+        const double d = T[sw(j, j)];
+        if (!(d > 0.0)) return false;  // every lane read the same pivot
+        const double ljj = sqrt(d), inv = 1.0 / ljj, invd = inv * inv;
+        double nv0, nv1, nv2, nv3;
+#define CHOL_UPD(q, out)                                                             \
+    {                                                                                \
+        const int e = lane + 64 * q, i = e >> 4, k = e & 15;                         \
+        const double cur = T[sw(i, k)];                                              \
+        double v = cur;                                                              \
+        if (k > j && k <= i) v = cur - T[sw(i, j)] * T[sw(k, j)] * invd;             \
+        else if (k == j && i > j) v = cur * inv;                                     \
+        else if (k == j && i == j) v = ljj;                                          \
+        out = v;                                                                     \
+    }
+        CHOL_UPD(0, nv0)
+        CHOL_UPD(1, nv1)
+        CHOL_UPD(2, nv2)
+        CHOL_UPD(3, nv3)
+#undef CHOL_UPD
+        __builtin_amdgcn_wave_barrier();
+#define CHOL_ST(q, val)                                  \
+    {                                                    \
+        const int e = lane + 64 * q, i = e >> 4, k = e & 15; \
+        if (k >= j && k <= i) T[sw(i, k)] = val;         \
+    }
+        CHOL_ST(0, nv0)
+        CHOL_ST(1, nv1)
+        CHOL_ST(2, nv2)
+        CHOL_ST(3, nv3)
+#undef CHOL_ST
+        __builtin_amdgcn_wave_barrier();
+    }
+    return true;
+}
+
+// In-place inverse of the lower-triangular dense tile, row by row:
+// D_ic = (delta_ic - sum_{k=c..i-1} L_ik D_kc) / L_ii; four lanes per column
+// share the sum.  One wave.
+__device__ __forceinline__ void dense_trinv16(double* T, int lane) {
+    const int c = lane & 15, p = lane >> 4;
+    for (int i = 0; i < 16; ++i) {
+        double s = 0.0;
+        if (c < i)
+            for (int k = c + p; k < i; k += 4) s += T[sw(i, k)] * T[sw(k, c)];
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        const double lii = T[sw(i, i)];
+        const double val = c == i ? 1.0 / lii : -s / lii;
+        __builtin_amdgcn_wave_barrier();
+        if (p == 0 && c <= i) T[sw(i, c)] = val;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
-__device__ bool chol_blocked(double* L, int m, double* D, int* flag) {
+__device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* flag) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int T = (m + 15) / 16;
     for (int K = 0; K < T; ++K) {
         if (wv == 0) {
-            const bool ok = diag_chol(L, m, K, lane);
+            tile_to_dense(L, m, K, D, lane);
+            const bool ok = dense_chol16(D, lane);
             if (lane == 0) *flag = ok ? 1 : 0;
-            if (ok) diag_inv(L, m, K, D, lane);
+            if (ok) {
+                dense_to_tile(L, m, K, D, lane);
+                dense_trinv16(D, lane);
+            }
         }
-        __syncthreads();
+        lds_barrier();
         if (*flag == 0) return false;
         // panel: L_IK = A_IK D^T
         for (int I = K + 1 + wv; I < T; I += nw) {
@@ -139,12 +176,12 @@ __device__ bool chol_blocked(double* L, int m, double* D, int* flag) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const double a = tl(L, m, I, K, lane & 15, 4 * s + (lane >> 4));
-                const double b = D[(lane & 15) * 16 + 4 * s + (lane >> 4)];
+                const double b = D[sw(lane & 15, 4 * s + (lane >> 4))];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
             acc_to_tile(L, m, I, K, acc, lane);
         }
-        __syncthreads();
+        lds_barrier();
         // trailing update A_IJ -= L_IK L_JK^T, K < J <= I
         const int R = T - K - 1;
         for (int e = wv; e < R * (R + 1) / 2; e += nw) {
@@ -157,67 +194,91 @@ __device__ bool chol_blocked(double* L, int m, double* D, int* flag) {
             acc = mm_xyt(acc, L, m, I, K, J, K, -1.0, lane);
             acc_to_tile(L, m, I, J, acc, lane);
         }
-        __syncthreads();
+        lds_barrier();
     }
     return true;
 }
 
 // In-place triangular inverse W = L^{-1} of the packed lower factor: column
 // blocks from the last one, W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) L_JJ^{-1}.
-__device__ void tri_inverse(double* L, int m, double* D) {
+__device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int T = (m + 15) / 16;
     for (int J = T - 1; J >= 0; --J) {
-        if (wv == 0) diag_inv(L, m, J, D, lane);
-        __syncthreads();
+        if (wv == 0) {
+            tile_to_dense(L, m, J, D, lane);
+            dense_trinv16(D, lane);
+        }
+        lds_barrier();
         // P_KJ = L_KJ D for K > J, in place
         for (int K = J + 1 + wv; K < T; K += nw) {
             d4 acc{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const double a = tl(L, m, K, J, lane & 15, 4 * s + (lane >> 4));
-                const double b = D[(4 * s + (lane >> 4)) * 16 + (lane & 15)];
+                const double b = D[sw(4 * s + (lane >> 4), lane & 15)];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
             acc_to_tile(L, m, K, J, acc, lane);
         }
-        __syncthreads();
-        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ
+        lds_barrier();
+        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ (tiles I = J+1+wv + q nw, q < 4)
         d4 res[4];
-        int nres = 0;
-        for (int I = J + 1 + wv; I < T; I += nw) {
-            d4 acc{0.0, 0.0, 0.0, 0.0};
-            for (int K = J + 1; K <= I; ++K) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const double a = tl(L, m, I, K, lane & 15, 4 * s + (lane >> 4));
-                    const double b = tl(L, m, K, J, 4 * s + (lane >> 4), lane & 15);
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+            const int I = J + 1 + wv + q * nw;
+            d4 acc{0.0, 0.0, 0.0, 0.0};
+            if (I < T) {
+                for (int K = J + 1; K <= I; ++K) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double a = tl(L, m, I, K, lane & 15, 4 * s + (lane >> 4));
+                        const double b = tl(L, m, K, J, 4 * s + (lane >> 4), lane & 15);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                    }
                 }
             }
-            res[nres++ & 3] = -acc;
+            res[q] = -acc;
         }
-        __syncthreads();
-        nres = 0;
-        for (int I = J + 1 + wv; I < T; I += nw) acc_to_tile(L, m, I, J, res[nres++ & 3], lane);
+        lds_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int I = J + 1 + wv + q * nw;
+            if (I < T) acc_to_tile(L, m, I, J, res[q], lane);
+        }
         if (wv == 0) {
             for (int e = lane; e < 256; e += 64) {
                 const int i = e >> 4, c = e & 15, r = 16 * J + i, cc = 16 * J + c;
-                if (r < m && c <= i) L[pk(r, cc)] = D[e];
+                if (r < m && c <= i) L[pk(r, cc)] = D[sw(i, c)];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
-// Sturm count of the k x k tridiagonal (al, be) below x.
+// Sturm count of the k x k tridiagonal (al, be) below x: sign changes of the
+// leading principal minors p_i(x) = (al_i - x) p_{i-1} - be_i^2 p_{i-2},
+// rescaled so that no division is needed.
 __device__ inline int sturm(const double* al, const double* be, int k, double x) {
     int cnt = 0;
-    double d = 1.0;
-    for (int i = 0; i < k; ++i) {
-        d = (al[i] - x) - (i ? be[i] * be[i] / d : 0.0);
-        if (d == 0.0) d = -1e-300;
-        cnt += d < 0.0;
+    double pm = 1.0, pc = al[0] - x;  // p_{i-1}, p_i
+    bool neg_prev = false;
+    bool neg = pc < 0.0 || (pc == 0.0 && !neg_prev);
+    cnt += neg != neg_prev;
+    neg_prev = neg;
+    for (int i = 1; i < k; ++i) {
+        const double pn = (al[i] - x) * pc - be[i] * be[i] * pm;
+        pm = pc;
+        pc = pn;
+        const double mag = fabs(pc);
+        if (mag > 1e150 || (mag < 1e-150 && mag > 0.0)) {
+            const double sc = mag > 1e150 ? 1e-150 : 1e150;
+            pc *= sc;
+            pm *= sc;
+        }
+        neg = pc < 0.0 || (pc == 0.0 && !neg_prev);
+        cnt += neg != neg_prev;
+        neg_prev = neg;
     }
     return cnt;
 }
@@ -269,6 +330,94 @@ __device__ inline double backward_norm(const double* al, const double* be, int k
     return 1.0 / sqrt(ss) * (ss > 0.0 ? 1.0 : 0.0);
 }
 
+// The steering wave keeps T_k in registers: lane i holds (al_i, be_i) in A
+// for i < 64 and in B for 64 <= i < 128; the recurrences read them back with
+// readlane (a scalar read, no LDS round trip).
+__device__ __forceinline__ double rl(double v, int i) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double tri_at(double vA, double vB, int i) { return i < 64 ? rl(vA, i) : rl(vB, i - 64); }
+
+// Sturm count (leading-minor recurrence p_i = (al_i - x) p_{i-1} - be_i^2
+// p_{i-2}, no division) on register T_k; b2 holds be_i^2.  The pair
+// (p_{i-1}, p_i) is rescaled by a power of two every 8 steps.  Exact zeros
+// count as positive (a measure-zero event for a multisection point).
+__device__ inline int sturm_reg(double aA, double aB, double b2A, double b2B, int k, double x) {
+    double pm = 1.0, pc = tri_at(aA, aB, 0) - x;
+    int cnt = pc < 0.0;
+    for (int i = 1; i < k; ++i) {
+        const double pn = (tri_at(aA, aB, i) - x) * pc - tri_at(b2A, b2B, i) * pm;
+        cnt += (pn < 0.0) != (pc < 0.0);
+        pm = pc;
+        pc = pn;
+        if ((i & 7) == 0) {
+            const int e = ilogb(fabs(pc) + fabs(pm) + 1e-300);
+            pc = ldexp(pc, -e);
+            pm = ldexp(pm, -e);
+        }
+    }
+    return cnt;
+}
+
+// 1/|y| for the eigenvector y of T_k (backward recurrence, y_{k-1} = 1);
+// rbA/rbB hold 1/be_i.
+__device__ inline double backward_norm_reg(double aA, double aB, double bA, double bB, double rbA, double rbB, int k,
+                                           double th) {
+    double y1 = 1.0, y0 = 0.0, ss = 1.0;
+    for (int i = k - 1; i >= 1; --i) {
+        const double ai = tri_at(aA, aB, i), rbi = tri_at(rbA, rbB, i);
+        const double bn = i + 1 < k ? tri_at(bA, bB, i + 1) : 0.0;
+        const double ym = ((th - ai) * y1 - bn * y0) * rbi;
+        y0 = y1;
+        y1 = ym;
+        ss += ym * ym;
+        if (ss > 1e280) {
+            const double sc = 1e-140;
+            y0 *= sc;
+            y1 *= sc;
+            ss *= sc * sc;
+        }
+    }
+    return 1.0 / sqrt(ss);
+}
+
+// Column c of W^T x restricted to half h of the rows [R0, m) of the wave's
+// band: sum over rows rr >= c of W[rr][c] x[rr].  Rows are walked in step by
+// all lanes of the wave so that they read consecutive addresses of one row.
+__device__ __forceinline__ double wt_column(const double* L, const double* x, int c, int R0, int m, int h) {
+    const int mid = (R0 + m) >> 1;
+    const int rb = h == 0 ? R0 : mid, re = h == 0 ? mid : m;
+    double s0 = 0.0, s1 = 0.0;
+    int base = pk(rb, c);
+    int rr = rb;
+    for (; rr + 1 < re; rr += 2) {
+        const double w0 = L[base], w1 = L[base + rr + 1];
+        s0 += (rr >= c ? w0 : 0.0) * x[rr];
+        s1 += (rr + 1 >= c ? w1 : 0.0) * x[rr + 1];
+        base += 2 * rr + 3;
+    }
+    if (rr < re) s0 += (rr >= c ? L[base] : 0.0) * x[rr];
+    return s0 + s1;
+}
+
+// Half h of row r of W x: sum over k <= r of W[r][k] x[k].
+__device__ __forceinline__ double w_row(const double* L, const double* x, int r, int h) {
+    const int half = (r + 2) >> 1;
+    const int kb = h == 0 ? 0 : half, ke = h == 0 ? half : r + 1;
+    const double* row = L + pk(r, 0);
+    double s0 = 0.0, s1 = 0.0;
+    int kk = kb;
+    for (; kk + 1 < ke; kk += 2) {
+        s0 += row[kk] * x[kk];
+        s1 += row[kk + 1] * x[kk + 1];
+    }
+    if (kk < ke) s0 += row[kk] * x[kk];
+    return s0 + s1;
+}
+
 __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
     extern __shared__ double lds[];
     const int m = a.m, P = a.P, md = a.md;
@@ -287,6 +436,10 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
     const double* Br = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
     const double t0 = a.shift ? a.shift[chain] : 0.0;
     int32_t st = SPEC_OK;
+    long long* prof = a.prof ? a.prof + (size_t)chain * 16 : nullptr;
+#define STAMP(i) \
+    if (prof && t == 0) prof[i] = clock64();
+    STAMP(0)
 
     // ---- diagonal rows: ratio test from x
     double dtp = INFINITY, dtm = -INFINITY;
@@ -310,14 +463,14 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
         bad |= __shfl_xor(bad, o, 64);
     }
     if (lane == 0) { rtp[wv] = dtp; rtm[wv] = dtm; rj[wv] = dj; rbad[wv] = bad; }
-    __syncthreads();
+    lds_barrier();
     dtp = INFINITY; dtm = -INFINITY; dj = -1; bad = 0;
     for (int w = 0; w < nw; ++w) {
         if (rtp[w] < dtp || (rtp[w] == dtp && rj[w] >= 0 && (dj < 0 || rj[w] < dj))) { dtp = rtp[w]; dj = rj[w]; }
         dtm = fmax(dtm, rtm[w]);
         bad |= rbad[w];
     }
-    __syncthreads();
+    lds_barrier();
     double tp = dtp, tm = dtm;
     int hit = dj >= 0 ? dj : HIT_NONE;
     double lmin = 0.0, lmax = 0.0;
@@ -331,15 +484,18 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
         if (a.shift_hi) {
             const double th = a.shift_hi[chain];
             for (int e = t; e < P; e += blockDim.x) L[e] = Fr[e] + th * Br[e];
-            __syncthreads();
+            lds_barrier();
             if (chol_blocked(L, m, scr, sflag)) cert = 2;
-            __syncthreads();
+            lds_barrier();
         }
         // ---- factor F0 = F + t0 B
         for (int e = t; e < P; e += blockDim.x) L[e] = a.membership_only ? Fr[e] : Fr[e] + t0 * Br[e];
-        __syncthreads();
+        lds_barrier();
+        STAMP(1)
         const bool ok = chol_blocked(L, m, scr, sflag);
+        STAMP(2)
         if (ok && !a.membership_only) tri_inverse(L, m, scr);
+        STAMP(3)
         if (!ok) {
             if (a.shift) cert = 1;
             else st = SPEC_NOT_INTERIOR;
@@ -369,8 +525,9 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                 u4 hsh = philox10(u4{(uint32_t)r, 0x5eedu, 0u, 0x51a7u}, 0x2010u, 0x3817u);
                 qr = 0.5 + (double)(hsh.x >> 11) * (1.0 / 2097152.0);
             }
-            double nq = block_sum((own && h == 0) ? qr * qr : 0.0, red);
+            double nq = block_sum_lds((own && h == 0) ? qr * qr : 0.0, red);
             qr *= 1.0 / sqrt(nq);
+            STAMP(4)
             if (worker) {
                 double breg[MAXH];
 #pragma unroll
@@ -386,19 +543,13 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                         Qg[(size_t)j * m + r] = qr;
                         slot[r] = qr;
                     }
-                    __syncthreads();  // B1
+                    lds_barrier();  // B1
                     // a = W^T q, lanes (c, h) over row halves of the wave's band
-                    double av = 0.0;
-                    if (own) {
-                        const int c = r, mid = (R0w + m) >> 1;
-                        const int rb = h == 0 ? R0w : mid, re = h == 0 ? mid : m;
-                        for (int rr = rb; rr < re; ++rr)
-                            if (rr >= c) av += L[pk(rr, c)] * slot[rr];
-                    }
+                    double av = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
                     av += __shfl_xor(av, 1, 64);
-                    __syncthreads();  // B2
+                    lds_barrier();  // B2
                     if (own && h == 0) slot[r] = av;
-                    __syncthreads();  // B3
+                    lds_barrier();  // B3
                     // b = B a from registers
                     double bv = 0.0;
                     {
@@ -413,92 +564,140 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                         }
                     }
                     bv += __shfl_xor(bv, 1, 64);
-                    __syncthreads();  // B4
+                    lds_barrier();  // B4
                     if (own && h == 0) slot[r] = bv;
-                    __syncthreads();  // B5
+                    lds_barrier();  // B5
                     // c = W b
-                    double cv = 0.0;
-                    if (own) {
-                        const int half = (r + 2) >> 1;
-                        const int kb = h == 0 ? 0 : half, ke = h == 0 ? half : r + 1;
-                        const double* row = L + pk(r, 0);
-                        for (int kk = kb; kk < ke; ++kk) cv += row[kk] * slot[kk];
-                    }
+                    double cv = own ? w_row(L, slot, r, h) : 0.0;
                     cv += __shfl_xor(cv, 1, 64);
-                    const double alj = block_sum((own && h == 0) ? qr * cv : 0.0, red);  // B6, B7
+                    const double alj = wave_uniform(block_sum_lds((own && h == 0) ? qr * cv : 0.0, red));  // B6, B7
                     cv -= alj * qr + bprev * qprev;
-                    const double bn = sqrt(block_sum((own && h == 0) ? cv * cv : 0.0, red));  // B8, B9
-                    __syncthreads();  // B10 (control wave stores alpha, beta)
-                    __syncthreads();  // B11 (control wave decides)
+                    const double bn = wave_uniform(sqrt(block_sum_lds((own && h == 0) ? cv * cv : 0.0, red)));  // B8, B9
+                    lds_barrier();  // B10 (control wave stores alpha, beta)
+                    lds_barrier();  // B11 (control wave decides)
                     if (sres[4] != 0.0) break;
                     qprev = qr;
                     qr = cv * (1.0 / bn);
                     bprev = bn;
                 }
             } else {
+                long long ph[6] = {0, 0, 0, 0, 0, 0};
+                int next_check = a.first_check > 0 ? a.first_check : 4;
+                double prev_q = -1.0;
+                int prev_k = 0;
+                long long tprev = clock64();
+#define PHASE(i)                          \
+    {                                     \
+        const long long tn = clock64();   \
+        ph[i] += tn - tprev;              \
+        tprev = tn;                       \
+    }
                 for (int j = 0; j < kmax; ++j) {
-                    __syncthreads();  // B1
-                    __syncthreads();  // B2
-                    __syncthreads();  // B3
-                    __syncthreads();  // B4
-                    __syncthreads();  // B5
-                    const double alj = block_sum(0.0, red);           // B6, B7
-                    const double bn = sqrt(block_sum(0.0, red));      // B8, B9
+                    lds_barrier();  // B1
+                    PHASE(0)
+                    lds_barrier();  // B2
+                    PHASE(1)
+                    lds_barrier();  // B3
+                    lds_barrier();  // B4
+                    PHASE(2)
+                    lds_barrier();  // B5
+                    const double alj = block_sum_lds(0.0, red);           // B6, B7
+                    PHASE(3)
+                    const double bn = sqrt(block_sum_lds(0.0, red));      // B8, B9
                     if (lane == 0) {
                         al[j] = alj;
                         be[j + 1] = bn;
                     }
-                    __syncthreads();  // B10
+                    lds_barrier();  // B10
+                    PHASE(4)
                     const int k = j + 1;
                     const bool exhausted = bn <= 1e-14 * fmax(fabs(al[0]), 1e-300);
-                    const bool check = exhausted || k == kmax || (k >= 3 && (k < 12 || (k & 1) == 0));
+                    const bool check = exhausted || k == kmax || k >= next_check;
                     double stop = 0.0;
                     if (check) {
-                        // lanes 0-31: lambda_min; lanes 32-63: lambda_max
-                        const bool want_min = lane < 32;
-                        const int sub = lane & 31;
-                        double lo = INFINITY, hi = -INFINITY;
-#pragma nounroll
-                        for (int i = 0; i < k; ++i) {
-                            const double rad = (i ? fabs(be[i]) : 0.0) + (i + 1 < k ? fabs(be[i + 1]) : 0.0);
-                            lo = fmin(lo, al[i] - rad);
-                            hi = fmax(hi, al[i] + rad);
+                        // T_k into registers
+                        const double aA = lane < k ? al[lane] : 0.0, aB = lane + 64 < k ? al[lane + 64] : 0.0;
+                        const double bA = lane < k ? be[lane] : 0.0, bB = lane + 64 < k ? be[lane + 64] : 0.0;
+                        const double bA1 = lane + 1 < k ? be[lane + 1] : 0.0, bB1 = lane + 65 < k ? be[lane + 65] : 0.0;
+                        const double b2A = bA * bA, b2B = bB * bB;
+                        const double rbA = bA != 0.0 ? 1.0 / bA : 0.0, rbB = bB != 0.0 ? 1.0 / bB : 0.0;
+                        // Gershgorin interval of T_k (rows spread over the lanes)
+                        double glo = INFINITY, ghi = -INFINITY;
+                        if (lane < k) {
+                            const double rad = (lane ? fabs(bA) : 0.0) + fabs(bA1);
+                            glo = aA - rad;
+                            ghi = aA + rad;
                         }
-                        const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
-                        lo -= pad;
-                        hi += pad;
+                        if (lane + 64 < k) {
+                            const double rad = fabs(bB) + fabs(bB1);
+                            glo = fmin(glo, aB - rad);
+                            ghi = fmax(ghi, aB + rad);
+                        }
+                        glo = wave_min(glo);
+                        ghi = wave_max(ghi);
+                        const double pad = 1e-14 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
+                        glo -= pad;
+                        ghi += pad;
+                        // multisection: all lanes on lambda_min when only it is wanted, else
+                        // lanes 0-31 on lambda_min and 32-63 on lambda_max
+                        const int npts = a.min_only ? 64 : 32;
+                        const bool want_min = a.min_only || lane < 32;
+                        const int sub = a.min_only ? lane : (lane & 31);
+                        double lo = glo, hi = ghi;
 #pragma nounroll
-                        for (int it = 0; it < 14; ++it) {
+                        for (int it = 0; it < 12; ++it) {
                             const double w = hi - lo;
-                            const double x = lo + w * (double)(sub + 1) / 33.0;
-                            const int cnt = sturm(al, be, k, x);
+                            if (!(w > 2e-16 * fmax(fabs(lo), fabs(hi)))) break;
+                            const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
+                            const int cnt = sturm_reg(aA, aB, b2A, b2B, k, x);
                             const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
                             const unsigned long long mask = __ballot(hitp);
-                            const unsigned int half_mask = want_min ? (unsigned int)mask : (unsigned int)(mask >> 32);
-                            const int first = half_mask ? __ffs((int)half_mask) - 1 : 32;
-                            const double nlo = lo + w * (double)first / 33.0;
-                            const double nhi = first < 32 ? lo + w * (double)(first + 1) / 33.0 : hi;
-                            if (w > 2e-16 * fmax(fabs(lo), fabs(hi))) {
-                                lo = nlo;
-                                hi = nhi;
-                            }
+                            unsigned long long hm;
+                            if (a.min_only) hm = mask;
+                            else hm = want_min ? (mask & 0xffffffffull) : (mask >> 32);
+                            const int first = hm ? __ffsll((long long)hm) - 1 : npts;
+                            const double nlo = lo + w * (double)first / (double)(npts + 1);
+                            const double nhi = first < npts ? lo + w * (double)(first + 1) / (double)(npts + 1) : hi;
+                            lo = nlo;
+                            hi = nhi;
                         }
                         const double th = 0.5 * (lo + hi);
-                        const double res = exhausted ? 0.0 : fabs(bn) * backward_norm(al, be, k, th);
-                        if (sub == 0) {
-                            sres[want_min ? 0 : 2] = th;
-                            sres[want_min ? 1 : 3] = res;
+                        const double res =
+                            exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
+                        const int src_max = a.min_only ? 0 : 32;
+                        if (lane == 0) {
+                            sres[0] = th;
+                            sres[1] = res;
                         }
-                        const double thmin = __shfl(th, 0, 64), thmax = __shfl(th, 32, 64);
-                        const double rmin = __shfl(res, 0, 64), rmax = __shfl(res, 32, 64);
+                        if (lane == src_max) {
+                            sres[2] = a.min_only ? NAN : th;
+                            sres[3] = a.min_only ? 0.0 : res;
+                        }
+                        const double thmin = __shfl(th, 0, 64), thmax = __shfl(th, src_max, 64);
+                        const double rmin = __shfl(res, 0, 64), rmax = __shfl(res, src_max, 64);
                         // residual bound below tol |theta|, or at the rounding level of C
                         const double rho = fmax(fabs(thmin), fabs(thmax));
                         const double floor_r = 2.2e-14 * rho;
-                        const bool cmin = rmin <= fmax(a.tol * fabs(thmin), floor_r);
-                        const bool cmax = rmax <= fmax(a.tol * fabs(thmax), floor_r);
-                        const bool conv_now = exhausted || (cmin && (a.min_only || cmax));
+                        const double tmin = fmax(a.tol * fabs(thmin), floor_r);
+                        const double tmax = fmax(a.tol * fabs(thmax), floor_r);
+                        const bool cmin = rmin <= tmin;
+                        const bool cmax = a.min_only || rmax <= tmax;
+                        const bool conv_now = exhausted || (cmin && cmax);
                         if (conv_now) stop = 1.0;
                         else if (k == kmax) stop = 2.0;
+                        // next test: where the residual decay since the last test predicts
+                        // convergence (at least 2, at most 12 steps ahead)
+                        double q = rmin / tmin;
+                        if (!a.min_only) q = fmax(q, rmax / tmax);
+                        int ahead = 4;
+                        if (prev_q > 0.0 && q < prev_q && q > 1.0) {
+                            const double rate = log(q / prev_q) / (double)(k - prev_k);  // < 0
+                            ahead = (int)ceil(log(q) / -rate);
+                        }
+                        ahead = ahead < 2 ? 2 : (ahead > 12 ? 12 : ahead);
+                        prev_q = q;
+                        prev_k = k;
+                        next_check = k + ahead;
                     } else if (k == kmax) {
                         stop = 2.0;
                     }
@@ -506,11 +705,16 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                         sres[4] = stop;
                         sres[5] = (double)k;
                     }
-                    __syncthreads();  // B11
+                    lds_barrier();  // B11
+                    PHASE(5)
                     if (stop != 0.0) break;
                 }
+#undef PHASE
+                if (prof && t == 0)
+                    for (int i = 0; i < 6; ++i) prof[8 + i] = ph[i];
             }
-            __syncthreads();
+            __syncthreads();  // basis entries in HBM are read across lanes below
+            STAMP(5)
             lmin = sres[0];
             lmax = sres[2];
             conv = sres[4] == 1.0;
@@ -545,24 +749,18 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                     }
                 }
                 zr *= 1.0 / sqrt(ss);
-                __syncthreads();
+                lds_barrier();
                 if (own && h == 0) slot[r] = zr;
-                __syncthreads();
+                lds_barrier();
                 // u = W^T z
-                double uv = 0.0;
-                if (own) {
-                    const int c = r, mid = (R0w + m) >> 1;
-                    const int rb = h == 0 ? R0w : mid, re = h == 0 ? mid : m;
-                    for (int rr = rb; rr < re; ++rr)
-                        if (rr >= c) uv += L[pk(rr, c)] * slot[rr];
-                }
+                double uv = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
                 uv += __shfl_xor(uv, 1, 64);
-                __syncthreads();
+                lds_barrier();
                 if (own && h == 0) {
                     a.u[(size_t)chain * a.ldu + r] = uv;
                     slot[r] = uv;
                 }
-                __syncthreads();
+                lds_barrier();
                 if (own) {
                     double* U2 = a.U2 + (size_t)chain * a.ldu2;
                     const double ur = slot[r];
@@ -573,6 +771,8 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
             }
         }
     }
+    STAMP(6)
+#undef STAMP
     if (t == 0) {
         if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;
         if (st == SPEC_NOT_INTERIOR) {

@@ -80,6 +80,8 @@ def lib():
     L.spec_walk_run_dev.argtypes = [vp, C.c_int, C.c_int, vp, C.c_longlong, C.c_uint64, C.POINTER(WalkParams), vp,
                                     vp, C.POINTER(WalkStats), vp]
     L.spec_diag_timing.argtypes = [vp, C.c_int]
+    L.spec_diag_phase_profile.argtypes = [vp, C.c_int]
+    L.spec_diag_phase_stamps.argtypes = [vp, C.c_int, vp]
     L.spec_diag_stage_times.argtypes = [vp, vp, vp]
     L.spec_diag_mfma_layout.argtypes = [vp]
     L.spec_diag_gemm_f64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp]
@@ -225,6 +227,14 @@ class Spectrahedron:
         check(lib().spec_diag_stage_times(self._h, out.ctypes.data_as(C.c_void_p), C.byref(ls)))
         names = ["assemble", "factor", "lanczos", "normal", "update"]
         return {k: (out[i], out[5 + i]) for i, k in enumerate(names)}, ls.value
+
+    def phase_profile(self, max_chains: int):
+        check(lib().spec_diag_phase_profile(self._h, int(max_chains)))
+
+    def phase_stamps(self, batch):
+        out = np.zeros((batch, 16), dtype=np.int64)
+        check(lib().spec_diag_phase_stamps(self._h, batch, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def lanczos_info(self, batch):
         """(lambda_min, lambda_max, second Ritz value, steps) of the last call."""

@@ -141,7 +141,7 @@ def main():
     launches = max(stages[dom][1], 1)
     ms_dom = stages[dom][0] / launches
     P = M_DIM * (M_DIM + 1) // 2
-    if dom == "lanczos":
+    if dom == "fused":
         # fused per-chain kernel (Cholesky, inverse, Lanczos, Ritz vector): FP64
         # arithmetic on MFMA and the vector ALUs, both at the FP64 peak.  Counted
         # work is the method's own: Cholesky m^3/3, 4 m^2 per Lanczos step,
@@ -161,10 +161,10 @@ def main():
         roof = {"bound": "mfma", "achieved": flops / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = _fused_traffic(chains) if dom == "lanczos" else None
+    roof["traffic"] = _fused_traffic(chains) if dom == "fused" else None
     roof["traffic_unit"] = "bytes per launch"
-    roof["kernel"] = {"lanczos": "k_line_fused", "assemble": "k_gemm_f64<false>", "normal": "k_gemm_f64<true>",
-                      "factor": "k_line_fused", "update": "k_walk_update"}[dom]
+    roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64<false>", "normal": "k_gemm_f64<true>",
+                      "predict": "k_gemm_f32", "update": "k_walk_update"}[dom]
     roof["ms_per_launch"] = ms_dom
     # assembly GEMM (F(x) and B(v) rows of every chain): FP64 MFMA utilisation
     asm_launches = max(stages["assemble"][1], 1)

@@ -159,9 +159,10 @@ typedef struct {
 
 /* Totals over chains: oracle calls, reflections, cap hits, not-interior
  * segments, nonsmooth reflections, completed steps, eigen non-convergence,
- * oracle rounds run. */
+ * oracle rounds run, oracle calls whose learned bracket was not certified
+ * (they fell back to the plain origin). */
 typedef struct {
-    double calls, reflections, cap_hits, not_interior, nonsmooth, steps, noconv, rounds;
+    double calls, reflections, cap_hits, not_interior, nonsmooth, steps, noconv, rounds, cert_fallback;
 } spec_walk_stats;
 
 /* Run `chains` independent chains of the walk `kind` from x0 (chains x n,
@@ -175,6 +176,97 @@ typedef struct {
 spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps,
                               uint64_t seed, const spec_walk_params* p, double* x_out, double* samples,
                               spec_walk_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned boundary bracket.
+ *
+ * A small MLP maps (x, v) to predictions of (log t+, log(-t-)).  With a
+ * network attached (spec_set_mlp) the billiard walk and spec_reflect start the
+ * eigen solve from the shifted origin t_lo = exp(log t+_hat - delta) on the
+ * line: when F(x + t_lo v) is positive definite (its Cholesky factor exists,
+ * which certifies t_lo < t+), the same pencil identity as the plain path
+ * (Lemma "PEP and S cap C", with F replaced by F(x + t_lo v)) gives
+ * t+ = t_lo - 1/lambda_min(L_lo^-1 B L_lo^-T).  Near the boundary that
+ * eigenvalue is far from the rest of the spectrum, so the Lanczos iteration
+ * stops after a few steps.  Every Ritz value theta >= lambda_min, hence
+ * t_lo - 1/theta >= t+ is a certified upper end of the bracket.  When the
+ * Cholesky factor at t_lo does not exist the call redoes the factorisation at
+ * the plain origin (status SPEC_CERT_FALLBACK, counted); results are the same
+ * quantity as on the plain path in every case.
+ *
+ * Network: input [x, v] (2n, standardised), `hidden` layers of `width` with
+ * exact GELU, output 2; FP32 master parameters, laid out per layer as W_l
+ * (in x out, row-major) followed by b_l.  use_bf16 = 1 rounds weights and
+ * activations to bfloat16 inside the products (BF16 MFMA, FP32 accumulation);
+ * 0 computes in FP32 (FP32 MFMA).
+ * ------------------------------------------------------------------------ */
+typedef struct spec_mlp_s* spec_mlp;
+
+typedef struct {
+    int epochs;          /* passes over the training rows (default 20) */
+    int batch;           /* minibatch rows (default 4096) */
+    double lr;           /* Adam step size at the start (default 1e-3) */
+    double lr_final;     /* step size at the end, cosine schedule (default 1e-5) */
+    double val_frac;     /* last share of the rows held out for validation (default 0.1) */
+    double quantile;     /* bracket half-width delta = this quantile of |log t+_hat - log t+|
+                            on the validation rows (default 0.999) */
+    uint64_t seed;       /* minibatch sampling */
+} spec_mlp_train_params;
+
+typedef struct {
+    double train_loss;   /* MSE on standardised targets, last epoch */
+    double val_loss;     /* MSE on standardised targets, validation rows */
+    double delta;        /* the bracket half-width at `quantile` */
+    double err_median, err_p99, err_max;  /* |log t+_hat - log t+| on validation */
+    double steps;        /* Adam steps taken */
+    double val_rows;
+    double err_q[8];     /* |log t+_hat - log t+| on validation at the levels
+                            0.5, 0.7, 0.8, 0.9, 0.95, 0.99, 0.995, 0.999 */
+} spec_mlp_train_stats;
+
+/* New network for n coordinates; parameters from Philox (key seed):
+ * W ~ U(-1/sqrt(in), 1/sqrt(in)), b = 0.  width <= 1024, 1 <= hidden <= 8. */
+spec_status spec_mlp_create(int n, int width, int hidden, int use_bf16, uint64_t seed, spec_mlp* out);
+spec_status spec_mlp_destroy(spec_mlp net);
+spec_status spec_mlp_nparams(spec_mlp net, long long* np);
+/* Copy the FP32 master parameters to / from host memory (np floats). */
+spec_status spec_mlp_get_params(spec_mlp net, float* host);
+spec_status spec_mlp_set_params(spec_mlp net, const float* host);
+/* Raw network (no standardisation): Y (rows x 2) from X (rows x 2n), device
+ * pointers, float32. */
+spec_status spec_mlp_forward_dev(spec_mlp net, int rows, const float* X, float* Y, void* stream);
+/* Mean over rows x 2 entries of (Y - T)^2 and its gradient (np floats, device)
+ * for the raw network; *loss is written on the host (the call synchronises). */
+spec_status spec_mlp_loss_grad_dev(spec_mlp net, int rows, const float* X, const float* T, float* grad,
+                                   double* loss, void* stream);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8) of the master parameters with a
+ * device gradient; the step counter lives in the network. */
+spec_status spec_mlp_adam_dev(spec_mlp net, const float* grad, double lr, void* stream);
+/* Train on `rows` oracle results (x, v, t-, t+), device FP64 arrays (rows x n,
+ * rows, rows): features and targets are standardised with statistics of the
+ * training rows, minibatches are drawn uniformly with replacement.  Rows
+ * must have finite t- < 0 < t+.  Synchronises; stats on the host. */
+spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const double* v, const double* t_minus,
+                               const double* t_plus, const spec_mlp_train_params* p, spec_mlp_train_stats* st,
+                               void* stream);
+/* Predictions log t+_hat and log(-t-_hat) (rows each, FP64, device) of the
+ * trained (standardised) network. */
+spec_status spec_mlp_predict_dev(spec_mlp net, int rows, const double* x, const double* v, double* log_tp,
+                                 double* log_neg_tm, void* stream);
+/* Attach a trained network to a handle (net NULL or mode 0 detaches).
+ * mode 1: lower end certified by Cholesky, upper end by the Ritz value;
+ * mode 2: additionally tests F(x + t_hi v), t_hi = exp(log t+_hat + delta),
+ * and counts a definite F there as a fallback (informational).  The network
+ * must stay alive while attached and have n equal to the handle's. */
+spec_status spec_set_mlp(spec_handle h, spec_mlp net, double delta, int mode);
+/* Autotune the bracket half-width: for each of the ncand candidates, time the
+ * learned reflection (mode 1) of `batch` device pairs (x, v) on `stream` with
+ * HIP events (best of `reps` runs), write the milliseconds to ms_out (host,
+ * ncand), and attach the network with the fastest candidate, returned in
+ * *best (host).  Synchronises. */
+spec_status spec_tune_mlp_delta_dev(spec_handle h, spec_mlp net, int batch, const double* x, const double* v,
+                                    int ncand, const double* deltas, int reps, double* ms_out, double* best,
+                                    void* stream);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,8 @@ spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out);
 /* Stage timing of the walk rounds, measured with HIP events recorded on the
  * walk's stream around each stage.  spec_diag_timing(h, 1) resets and turns
  * it on, (h, 0) turns it off.  spec_diag_stage_times writes, per stage
- * (0 assembly GEMM, 1 factor, 2 Lanczos, 3 normal GEMM, 4 walk update), the
+ * (0 assembly GEMM, 1 network prediction of the learned bracket, 2 fused
+ * factor + Lanczos kernel, 3 normal GEMM, 4 walk update), the
  * summed milliseconds and the number of launches (2 x 5 doubles); also the
  * Lanczos step count summed over chains of the timed rounds (1 double). */
 spec_status spec_diag_timing(spec_handle h, int on);
@@ -43,6 +44,19 @@ spec_status spec_diag_stage_times(spec_handle h, double* ms_and_counts, double* 
  * use batch <= c. */
 spec_status spec_diag_phase_profile(spec_handle h, int max_chains);
 spec_status spec_diag_phase_stamps(spec_handle h, int batch, long long* out);
+
+/* One MFMA instruction per trial (one wave each), operands given per lane:
+ * kind 0 = v_mfma_f32_16x16x4f32 (a, b: trials x 64 floats), kind 1 =
+ * v_mfma_f32_16x16x32_bf16 (a, b: trials x 64 x 8 floats, rounded to
+ * bfloat16); d: trials x 64 x 4 accumulator registers.  Host pointers. */
+spec_status spec_diag_mfma_raw(int kind, int trials, const float* a, const float* b, float* d);
+
+/* The MLP's GEMM on host buffers: C (M x ldc) = op(A) op(B) with op(A) M x K
+ * (ta: A stored K x M), op(B) K x N (tb: B stored N x K), bf16 operands when
+ * bf16 != 0, epilogue mode 0 store, 1 C = Z and aux = GELU(Z), 2 C = acc *
+ * GELU'(aux).  aux is M x ldaux (read and/or written), nullable for mode 0. */
+spec_status spec_diag_gemm_f32(int ta, int tb, int bf16, int mode, int M, int N, int K, const float* A, int lda,
+                               const float* B, int ldb, float* C, int ldc, float* aux, int ldaux);
 
 #ifdef __cplusplus
 }

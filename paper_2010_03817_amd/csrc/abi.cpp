@@ -14,47 +14,11 @@
 #include "spec_kernels.h"
 #include "walk_kernels.h"
 #include "line_fused.h"
+#include "mlp_net.h"
 
 using namespace spec;
 
-namespace {
-
-inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
-
-template <class T>
-hipError_t dalloc(T** p, size_t count, bool zero = true) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
-    if (e != hipSuccess) return e;
-    if (zero) e = hipMemset(*p, 0, sizeof(T) * count);
-    return e;
-}
-
-template <class T>
-void dfree(T*& p) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-
-spec_status from_hip(hipError_t e) {
-    if (e == hipSuccess) return SPEC_OK;
-    if (e == hipErrorOutOfMemory) return SPEC_ENOMEM;
-    return SPEC_EDEVICE;
-}
-
-#define HIPCHK(expr)                                   \
-    do {                                               \
-        hipError_t _e = (expr);                        \
-        if (_e != hipSuccess) return from_hip(_e);     \
-    } while (0)
-#define SPCHK(expr)                                    \
-    do {                                               \
-        spec_status _s = (expr);                       \
-        if (_s != SPEC_OK) return _s;                  \
-    } while (0)
-
-}  // namespace
+#include "abi_util.h"
 
 struct spec_s {
     int device = 0;
@@ -80,6 +44,11 @@ struct spec_s {
     double* dLamSum = nullptr;
     long long* dProf = nullptr;
     int prof_cap = 0;
+    // learned bracket (attached network, half-width, mode) and its per-chain shifts
+    spec_mlp_s* net = nullptr;
+    double mdelta = 0.0;
+    int lmode = 0;
+    double *dShift = nullptr, *dShiftHi = nullptr, *dPred = nullptr;
     // walk state
     int wcap = 0;
     double *wX = nullptr, *wXs = nullptr, *wV = nullptr, *wEll = nullptr, *wStats = nullptr, *wSum = nullptr;
@@ -89,6 +58,7 @@ struct spec_s {
     void free_work() {
         dfree(dZ); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
+        dfree(dShift); dfree(dShiftHi); dfree(dPred);
         cap = 0;
     }
     void free_walk() {
@@ -132,6 +102,9 @@ struct spec_s {
         HIPCHK(dalloc(&dTp, (size_t)c));
         HIPCHK(dalloc(&dHit, (size_t)c));
         HIPCHK(dalloc(&dSt, (size_t)c));
+        HIPCHK(dalloc(&dShift, (size_t)c));
+        HIPCHK(dalloc(&dShiftHi, (size_t)c));
+        HIPCHK(dalloc(&dPred, (size_t)c));
         cap = c;
         return SPEC_OK;
     }
@@ -196,15 +169,29 @@ FusedArgs fused_args(spec_s* h, int bp, int32_t* st, double* tm, double* tp, boo
     return a;
 }
 
+// One oracle round over `batch` chains.  min_only: only t+ (and its
+// eigenvector) is wanted.  learned: start from the attached network's
+// bracket when there is one (t+ only).
 spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, double* tm, double* tp,
-                        int32_t* st, bool want_vec, const double* ell, hipStream_t s, bool min_only = false) {
+                        int32_t* st, bool want_vec, const double* ell, hipStream_t s, bool min_only = false,
+                        bool learned = false) {
     int bp = 0;
     mark(h, 0, s);
     SPCHK(assemble(h, batch, x, v, &bp, s));
     mark(h, 1, s);
+    const bool use_net = learned && min_only && h->net && h->lmode > 0 && h->m > 0;
+    if (use_net) {
+        SPCHK(mlp_predict_rows(h->net, batch, x, h->n, v, h->n, s));
+        HIPCHK(mlp_shift(batch, h->net->dY, 2, h->net->tmu[0], h->net->tsd[0], h->mdelta, h->dShift,
+                         h->lmode == 2 ? h->dShiftHi : nullptr, h->dPred, s));
+    }
     mark(h, 2, s);
     FusedArgs a = fused_args(h, bp, st, tm, tp, want_vec, ell);
     a.min_only = min_only ? 1 : 0;
+    if (use_net) {
+        a.shift = h->dShift;
+        if (h->lmode == 2) a.shift_hi = h->dShiftHi;
+    }
     HIPCHK(launch_line_fused(a, batch, s));
     mark(h, 3, s);
     return SPEC_OK;
@@ -367,6 +354,60 @@ spec_status spec_dims(spec_handle h, int* n, int* m, int* md) {
     return SPEC_OK;
 }
 
+spec_status spec_set_mlp(spec_handle h, spec_mlp net, double delta, int mode) {
+    if (!h || mode < 0 || mode > 2) return SPEC_EINVAL;
+    if (!net || mode == 0) {
+        h->net = nullptr;
+        h->lmode = 0;
+        return SPEC_OK;
+    }
+    if (net->n != h->n || !(delta >= 0.0) || !std::isfinite(delta)) return SPEC_EINVAL;
+    h->net = net;
+    h->mdelta = delta;
+    h->lmode = mode;
+    return SPEC_OK;
+}
+
+spec_status spec_tune_mlp_delta_dev(spec_handle h, spec_mlp net, int batch, const double* x, const double* v,
+                                    int ncand, const double* deltas, int reps, double* ms_out, double* best,
+                                    void* stream) {
+    if (!h || !net || batch < 1 || !x || !v || ncand < 1 || !deltas || !best) return SPEC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    SPCHK(h->ensure(batch));
+    SPCHK(h->ensure_stage(batch));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best_ms = INFINITY, best_d = deltas[0];
+    spec_status rc = SPEC_OK;
+    for (int c = 0; c < ncand && rc == SPEC_OK; ++c) {
+        rc = spec_set_mlp(h, net, deltas[c], 1);
+        double ms_c = INFINITY;
+        for (int r = 0; r < std::max(reps, 1) && rc == SPEC_OK; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = SPEC_EDEVICE; break; }
+            rc = spec_reflect_dev(h, batch, x, v, h->sO2, h->sS, nullptr, h->sSt, s);
+            if (rc != SPEC_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = SPEC_EDEVICE;
+                break;
+            }
+            ms_c = std::min(ms_c, (double)ms);
+        }
+        if (ms_out) ms_out[c] = ms_c;
+        if (ms_c < best_ms) {
+            best_ms = ms_c;
+            best_d = deltas[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SPEC_OK) return rc;
+    *best = best_d;
+    return spec_set_mlp(h, net, best_d, 1);
+}
+
 spec_status spec_set_lanczos(spec_handle h, int kmax, double tol) {
     if (!h || kmax < 2 || kmax > SPEC_MAX_KRYLOV || !(tol > 0.0) || !(tol < 1.0)) return SPEC_EINVAL;
     if (fused_lds_bytes(h->m, kmax) > 163840) return SPEC_ENOTSUP;
@@ -404,7 +445,7 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
     if (batch == 0) return SPEC_OK;
     hipStream_t s = (hipStream_t)stream;
     SPCHK(h->ensure(batch));
-    SPCHK(line_oracle(h, batch, x, v, h->dTm, t_plus, status, true, nullptr, s));
+    SPCHK(line_oracle(h, batch, x, v, h->dTm, t_plus, status, true, nullptr, s, true, true));
     return reflect_tail(h, batch, v, t_plus, status, s_out, w_out, s);
 }
 
@@ -497,7 +538,7 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
     while (rounds < max_rounds) {
         SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard, billiard ? h->wEll : nullptr,
-                          s, billiard));
+                          s, billiard, billiard));
         if (billiard) {
             const int bp = round_up(chains, 64);
             const int Kn = round_up(h->P, 16);
@@ -544,6 +585,7 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
         stats->steps = tot[5];
         stats->noconv = tot[6];
         stats->rounds = (double)rounds;
+        stats->cert_fallback = tot[7];
     }
     return SPEC_OK;
 }

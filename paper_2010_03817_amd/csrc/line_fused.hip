@@ -434,7 +434,8 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
 
     const double* Fr = a.FB + (size_t)chain * a.ldfb;
     const double* Br = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
-    const double t0 = a.shift ? a.shift[chain] : 0.0;
+    double t0 = a.shift ? a.shift[chain] : 0.0;
+    if (!(t0 > 0.0) || !isfinite(t0)) t0 = 0.0;  // no usable bracket: plain origin
     int32_t st = SPEC_OK;
     long long* prof = a.prof ? a.prof + (size_t)chain * 16 : nullptr;
 #define STAMP(i) \
@@ -480,27 +481,34 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
 
     if (bad) st = SPEC_NOT_INTERIOR;
     if (!bad && m > 0) {
-        // ---- upper certification of the learned bracket: F(x + t_hi v) must not be definite
-        if (a.shift_hi) {
-            const double th = a.shift_hi[chain];
-            for (int e = t; e < P; e += blockDim.x) L[e] = Fr[e] + th * Br[e];
-            lds_barrier();
-            if (chol_blocked(L, m, scr, sflag)) cert = 2;
-            lds_barrier();
-        }
-        // ---- factor F0 = F + t0 B
-        for (int e = t; e < P; e += blockDim.x) L[e] = a.membership_only ? Fr[e] : Fr[e] + t0 * Br[e];
-        lds_barrier();
+        // ---- factor F0 = F + t0 B.  A factor at t0 > 0 certifies t0 < t+; when
+        // it does not exist the bracket is discarded and F(x) is factored.  With
+        // an upper end t_hi, F(x + t_hi v) is tested first (a definite F there
+        // means the bracket missed t+ on the high side: counted, harmless).
+        // One loop so that the factorisation is instantiated once.
+        int phase = a.shift_hi ? 0 : 1;
+        bool ok = false;
         STAMP(1)
-        const bool ok = chol_blocked(L, m, scr, sflag);
+        for (;;) {
+            const double sh = phase == 0 ? a.shift_hi[chain] : t0;
+            for (int e = t; e < P; e += blockDim.x) L[e] = a.membership_only ? Fr[e] : Fr[e] + sh * Br[e];
+            lds_barrier();
+            ok = chol_blocked(L, m, scr, sflag);
+            lds_barrier();
+            if (phase == 0) {
+                if (ok) cert = 2;
+                phase = 1;
+                continue;
+            }
+            if (ok || t0 == 0.0) break;
+            cert = 1;
+            t0 = 0.0;
+        }
         STAMP(2)
         if (ok && !a.membership_only) tri_inverse(L, m, scr);
         STAMP(3)
-        if (!ok) {
-            if (a.shift) cert = 1;
-            else st = SPEC_NOT_INTERIOR;
-        }
-        if (ok && cert == 0 && !a.membership_only) {
+        if (!ok) st = SPEC_NOT_INTERIOR;
+        if (ok && !a.membership_only) {
             // Wave 0 steers (Ritz values, residual bounds, stop decision); waves
             // 1.. hold B and run the matrix-vector products.  Both run the same
             // sequence of barriers.
@@ -676,7 +684,10 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                         const double thmin = __shfl(th, 0, 64), thmax = __shfl(th, src_max, 64);
                         const double rmin = __shfl(res, 0, 64), rmax = __shfl(res, src_max, 64);
                         // residual bound below tol |theta|, or at the rounding level of C
-                        const double rho = fmax(fabs(thmin), fabs(thmax));
+                        // (scaled by the spectral radius: Gershgorin bound of T_k, which
+                        // also covers lambda_max when only lambda_min is tracked)
+                        const double rho = fmax(fmax(fabs(thmin), a.min_only ? 0.0 : fabs(thmax)),
+                                                fmax(fabs(glo), fabs(ghi)));
                         const double floor_r = 2.2e-14 * rho;
                         const double tmin = fmax(a.tol * fabs(thmin), floor_r);
                         const double tmax = fmax(a.tol * fabs(thmax), floor_r);
@@ -730,9 +741,8 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                 tp = dtpd;
                 hit = HIT_DENSE;
             }
-            if (a.shift && !(lmin < 0.0 && dtpd > t0)) cert = 3;
             const bool need_vec = a.want_vec && hit == HIT_DENSE && isfinite(tp) && (a.ell == nullptr || tp < a.ell[chain]);
-            if (need_vec && cert == 0) {
+            if (need_vec) {
                 // Ritz vector z = sum_j y_j q_j, y from the backward recurrence
                 double zr = 0.0, y1 = 1.0, y0 = 0.0, ss = 0.0;
                 for (int i = k - 1; i >= 0; --i) {
@@ -774,7 +784,6 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
     STAMP(6)
 #undef STAMP
     if (t == 0) {
-        if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;
         if (st == SPEC_NOT_INTERIOR) {
             tm = NAN;
             tp = NAN;
@@ -783,6 +792,7 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
             if (!conv) st = SPEC_NOCONV;
             else if (isinf(tp) || isinf(tm)) st = SPEC_UNBOUNDED;
         }
+        if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;  // informational: values are final
         a.tm[chain] = tm;
         a.tp[chain] = tp;
         a.hit[chain] = hit;

@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
     if (lane == 0) {
         st[0] += 1.0;
         if (status == SPEC_NOCONV) st[6] += 1.0;
+        if (status == SPEC_CERT_FALLBACK) st[7] += 1.0;
     }
     if (status == SPEC_NOT_INTERIOR) {
         // cannot happen from an interior start; count it and restart the

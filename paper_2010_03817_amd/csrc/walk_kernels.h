@@ -5,7 +5,7 @@
 namespace spec {
 
 // Per-chain statistics: oracle calls, reflections, cap hits, not-interior,
-// nonsmooth, completed steps, eigen non-convergence, spare.
+// nonsmooth, completed steps, eigen non-convergence, learned-bracket fallbacks.
 constexpr int WALK_NSTAT = 8;
 
 struct WalkState {

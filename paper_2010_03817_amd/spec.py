@@ -35,10 +35,26 @@ class WalkParams(C.Structure):
 
 class WalkStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("calls", "reflections", "cap_hits", "not_interior", "nonsmooth", "steps",
-                                          "noconv", "rounds")]
+                                          "noconv", "rounds", "cert_fallback")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MlpTrainParams(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("lr_final", C.c_double),
+                ("val_frac", C.c_double), ("quantile", C.c_double), ("seed", C.c_uint64)]
+
+
+class MlpTrainStats(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("train_loss", "val_loss", "delta", "err_median", "err_p99", "err_max",
+                                          "steps", "val_rows")] + [("err_q", C.c_double * 8)]
+    QUANTILE_LEVELS = (0.5, 0.7, 0.8, 0.9, 0.95, 0.99, 0.995, 0.999)
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "err_q"}
+        d["err_q"] = dict(zip(self.QUANTILE_LEVELS, list(self.err_q)))
+        return d
 
 
 _lib = None
@@ -86,6 +102,23 @@ def lib():
     L.spec_diag_mfma_layout.argtypes = [vp]
     L.spec_diag_gemm_f64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.spec_diag_lanczos_info.argtypes = [vp, C.c_int, vp]
+    L.spec_diag_mfma_raw.argtypes = [C.c_int, C.c_int, vp, vp, vp]
+    L.spec_diag_gemm_f32.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp,
+                                     C.c_int, vp, C.c_int, vp, C.c_int]
+    L.spec_mlp_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
+    L.spec_mlp_destroy.argtypes = [vp]
+    L.spec_mlp_nparams.argtypes = [vp, C.POINTER(C.c_longlong)]
+    L.spec_mlp_get_params.argtypes = [vp, vp]
+    L.spec_mlp_set_params.argtypes = [vp, vp]
+    L.spec_mlp_forward_dev.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.spec_mlp_loss_grad_dev.argtypes = [vp, C.c_int, vp, vp, vp, C.POINTER(C.c_double), vp]
+    L.spec_mlp_adam_dev.argtypes = [vp, vp, C.c_double, vp]
+    L.spec_mlp_train_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.POINTER(MlpTrainParams),
+                                     C.POINTER(MlpTrainStats), vp]
+    L.spec_mlp_predict_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+    L.spec_set_mlp.argtypes = [vp, vp, C.c_double, C.c_int]
+    L.spec_tune_mlp_delta_dev.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, C.POINTER(C.c_double),
+                                          vp]
     for name in declared_symbols():
         if name != "spec_status_str":
             getattr(L, name).restype = C.c_int
@@ -225,7 +258,7 @@ class Spectrahedron:
         out = np.zeros(10)
         ls = C.c_double()
         check(lib().spec_diag_stage_times(self._h, out.ctypes.data_as(C.c_void_p), C.byref(ls)))
-        names = ["assemble", "factor", "lanczos", "normal", "update"]
+        names = ["assemble", "predict", "fused", "normal", "update"]
         return {k: (out[i], out[5 + i]) for i, k in enumerate(names)}, ls.value
 
     def phase_profile(self, max_chains: int):
@@ -236,6 +269,26 @@ class Spectrahedron:
         check(lib().spec_diag_phase_stamps(self._h, batch, out.ctypes.data_as(C.c_void_p)))
         return out
 
+    def set_mlp(self, net, delta=0.0, mode=1):
+        """Attach a trained Mlp (learned bracket for reflect and billiard walks);
+        net None or mode 0 detaches."""
+        check(lib().spec_set_mlp(self._h, net._h if net is not None else None, float(delta),
+                                 int(mode) if net is not None else 0))
+        self._net = net
+
+    def tune_mlp_delta(self, net, x, v, deltas, reps=2):
+        """Time the learned reflection of (x, v) for each candidate half-width;
+        attaches the fastest.  Returns (best delta, list of ms)."""
+        x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
+        d = np.ascontiguousarray(deltas, dtype=np.float64)
+        ms = np.empty(d.size)
+        best = C.c_double()
+        check(lib().spec_tune_mlp_delta_dev(self._h, net._h, x.shape[0], _ptr(x), _ptr(v), d.size,
+                                            d.ctypes.data_as(C.c_void_p), int(reps), ms.ctypes.data_as(C.c_void_p),
+                                            C.byref(best), _stream()))
+        self._net = net
+        return best.value, list(ms)
+
     def lanczos_info(self, batch):
         """(lambda_min, lambda_max, second Ritz value, steps) of the last call."""
         torch = _torch()
@@ -243,6 +296,120 @@ class Spectrahedron:
         out = np.empty((batch, 4))
         check(lib().spec_diag_lanczos_info(self._h, batch, out.ctypes.data_as(C.c_void_p)))
         return out
+
+
+class Mlp:
+    """Learned-bracket network (include/spec.h, spec_mlp_*)."""
+
+    def __init__(self, n, width=256, hidden=3, bf16=True, seed=1):
+        _torch()
+        h = C.c_void_p()
+        check(lib().spec_mlp_create(int(n), int(width), int(hidden), int(bool(bf16)), int(seed), C.byref(h)))
+        self._h = h
+        self.n = n
+        k = C.c_longlong()
+        check(lib().spec_mlp_nparams(h, C.byref(k)))
+        self.nparams = k.value
+        self.train_stats = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spec_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.nparams, dtype=np.float32)
+        check(lib().spec_mlp_get_params(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        check(lib().spec_mlp_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def _f32(self, a, cols):
+        torch = _torch()
+        if not isinstance(a, torch.Tensor):
+            a = torch.as_tensor(np.asarray(a, dtype=np.float32))
+        return a.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, cols)
+
+    def forward(self, X):
+        """Raw network outputs (rows x 2) for raw features X (rows x 2n)."""
+        torch = _torch()
+        X = self._f32(X, 2 * self.n)
+        Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda")
+        check(lib().spec_mlp_forward_dev(self._h, X.shape[0], _ptr(X), _ptr(Y), _stream()))
+        return Y
+
+    def loss_grad(self, X, T):
+        torch = _torch()
+        X = self._f32(X, 2 * self.n)
+        T = self._f32(T, 2)
+        G = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        check(lib().spec_mlp_loss_grad_dev(self._h, X.shape[0], _ptr(X), _ptr(T), _ptr(G), C.byref(loss), _stream()))
+        return loss.value, G
+
+    def adam(self, grad, lr):
+        check(lib().spec_mlp_adam_dev(self._h, _ptr(grad), float(lr), _stream()))
+
+    def train(self, x, v, t_minus, t_plus, epochs=20, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=0.1,
+              quantile=0.999, seed=7):
+        x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
+        tm, tp = _f64(t_minus).reshape(-1), _f64(t_plus).reshape(-1)
+        p = MlpTrainParams(epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, val_frac=val_frac,
+                           quantile=quantile, seed=seed)
+        st = MlpTrainStats()
+        check(lib().spec_mlp_train_dev(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), C.byref(p),
+                                       C.byref(st), _stream()))
+        self.train_stats = st.as_dict()
+        return self.train_stats
+
+    def predict(self, x, v):
+        """(log t+_hat, log(-t-_hat)) of the trained network."""
+        torch = _torch()
+        x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
+        a = torch.empty(x.shape[0], dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        check(lib().spec_mlp_predict_dev(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(a), _ptr(b), _stream()))
+        return a, b
+
+
+def mfma_raw(kind, a, b):
+    """One MFMA per trial with per-lane operands (see spec_diag_mfma_raw)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    per = 64 if kind == 0 else 512
+    trials = a.size // per
+    d = np.empty((trials, 64, 4), dtype=np.float32)
+    check(lib().spec_diag_mfma_raw(kind, trials, a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p),
+                                   d.ctypes.data_as(C.c_void_p)))
+    return d
+
+
+def gemm_f32(A, B, ta=False, tb=False, bf16=False, mode=0, aux=None, C0=None):
+    """The MLP GEMM on host arrays: returns (C, aux)."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    M = A.shape[1] if ta else A.shape[0]
+    K = A.shape[0] if ta else A.shape[1]
+    N = B.shape[0] if tb else B.shape[1]
+    Cm = np.zeros((M, N), dtype=np.float32) if C0 is None else np.ascontiguousarray(C0, dtype=np.float32).copy()
+    X = None
+    if mode:
+        X = np.ascontiguousarray(aux, dtype=np.float32).copy()
+    check(lib().spec_diag_gemm_f32(int(ta), int(tb), int(bf16), int(mode), M, N, K, A.ctypes.data_as(C.c_void_p),
+                                   A.shape[1], B.ctypes.data_as(C.c_void_p), B.shape[1],
+                                   Cm.ctypes.data_as(C.c_void_p), N,
+                                   X.ctypes.data_as(C.c_void_p) if X is not None else None,
+                                   X.shape[1] if X is not None else 0))
+    return Cm, X
 
 
 def mfma_layout():

@@ -1,0 +1,286 @@
+"""GPU tests of the learned bracket: MFMA lane layouts, the MLP GEMM, the
+network's forward / gradient / Adam against the FP64 oracle, and the learned
+reflection against the oracle (identical results, fewer Lanczos steps)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2010_03817_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2010_03817_amd import spec
+    return spec
+
+
+def bf16_round(a):
+    """Round float32 values to bfloat16 (nearest, ties to even), as float32."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def gelu(z):
+    from scipy.special import erf
+    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+
+
+def gelu_d(z):
+    from scipy.special import erf
+    return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def test_mfma_f32_lane_layout(S):
+    rng = np.random.default_rng(1)
+    A = rng.integers(-8, 9, size=(16, 4)).astype(np.float32)
+    B = rng.integers(-8, 9, size=(4, 16)).astype(np.float32)
+    lanes = np.arange(64)
+    a = A[lanes % 16, lanes // 16]
+    b = B[lanes // 16, lanes % 16]
+    d = S.mfma_raw(0, a, b)[0]
+    D = A.astype(np.float64) @ B
+    for l in range(64):
+        for r in range(4):
+            assert d[l, r] == D[4 * (l // 16) + r, l % 16]
+
+
+def test_mfma_bf16_lane_layout(S):
+    rng = np.random.default_rng(2)
+    A = rng.integers(-8, 9, size=(16, 32)).astype(np.float32)
+    B = rng.integers(-8, 9, size=(32, 16)).astype(np.float32)
+    a = np.empty((64, 8), np.float32)
+    b = np.empty((64, 8), np.float32)
+    for l in range(64):
+        for i in range(8):
+            a[l, i] = A[l % 16, 8 * (l // 16) + i]
+            b[l, i] = B[8 * (l // 16) + i, l % 16]
+    d = S.mfma_raw(1, a, b)[0]
+    D = A.astype(np.float64) @ B
+    for l in range(64):
+        for r in range(4):
+            assert d[l, r] == D[4 * (l // 16) + r, l % 16]
+
+
+@pytest.mark.parametrize("ta,tb,bf16", list(itertools.product([0, 1], [0, 1], [0, 1])))
+def test_gemm_f32_layouts_and_epilogues(S, ta, tb, bf16):
+    rng = np.random.default_rng(10 + 4 * ta + 2 * tb + bf16)
+    M, N, K = 70, 45, 77  # ragged: partial tiles in every dimension
+    Aop = rng.standard_normal((M, K)).astype(np.float32)
+    Bop = rng.standard_normal((K, N)).astype(np.float32)
+    A = Aop.T.copy() if ta else Aop
+    B = Bop.T.copy() if tb else Bop
+    Ae, Be = (bf16_round(Aop), bf16_round(Bop)) if bf16 else (Aop, Bop)
+    ref = Ae.astype(np.float64) @ Be.astype(np.float64)
+    scale = np.abs(Ae).astype(np.float64) @ np.abs(Be).astype(np.float64)
+    # FP32 accumulation over K terms
+    tol = 4e-7 * K * scale + 1e-30
+    C, _ = S.gemm_f32(A, B, ta=ta, tb=tb, bf16=bf16, mode=0)
+    assert np.all(np.abs(C - ref) <= tol)
+    C, H = S.gemm_f32(A, B, ta=ta, tb=tb, bf16=bf16, mode=1, aux=np.zeros((M, N), np.float32))
+    assert np.all(np.abs(C - ref) <= tol)
+    assert np.allclose(H, gelu(C.astype(np.float64)), rtol=2e-6, atol=2e-6)
+    Z0 = rng.standard_normal((M, N)).astype(np.float32)
+    C, _ = S.gemm_f32(A, B, ta=ta, tb=tb, bf16=bf16, mode=2, aux=Z0)
+    want = ref * gelu_d(Z0.astype(np.float64))
+    assert np.all(np.abs(C - want) <= tol * 1.2 + 2e-6 * np.abs(want))
+
+
+def _net_case(S, bf16, seed=3):
+    n, width, hidden, rows = 5, 24, 2, 37
+    net = S.Mlp(n, width=width, hidden=hidden, bf16=bf16, seed=seed)
+    rng = np.random.default_rng(seed)
+    p = (0.3 * rng.standard_normal(net.nparams)).astype(np.float32)
+    net.set_params(p)
+    X = rng.standard_normal((rows, 2 * n)).astype(np.float32)
+    T = rng.standard_normal((rows, 2)).astype(np.float32)
+    dims = [2 * n] + [width] * hidden + [2]
+    return net, p, X, T, dims
+
+
+def test_mlp_forward_and_gradient_fp32_match_oracle(S):
+    net, p, X, T, dims = _net_case(S, bf16=False)
+    P64, X64, T64 = p.astype(np.float64), X.astype(np.float64), T.astype(np.float64)
+    Y = net.forward(X).cpu().numpy()
+    Yo = O.mlp_forward(dims, P64, X64)
+    assert np.max(np.abs(Y - Yo)) <= 1e-5 * max(1.0, np.max(np.abs(Yo)))
+    loss, G = net.loss_grad(X, T)
+    lo, Go = O.mlp_loss_grad(dims, P64, X64, T64)
+    G = G.cpu().numpy().astype(np.float64)
+    assert abs(loss - lo) <= 1e-5 * lo
+    # gradient: FP32 arithmetic against FP64, relative in norm and per entry
+    assert np.linalg.norm(G - Go) <= 1e-5 * np.linalg.norm(Go)
+    assert np.all(np.abs(G - Go) <= 1e-5 * np.max(np.abs(Go)))
+
+
+def test_mlp_gradient_bf16_close_to_oracle(S):
+    net, p, X, T, dims = _net_case(S, bf16=True)
+    loss, G = net.loss_grad(X, T)
+    lo, Go = O.mlp_loss_grad(dims, p.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    G = G.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(G - Go) / np.linalg.norm(Go)
+    print(f"bf16 gradient relative error {rel:.3e}, loss {loss:.6f} vs {lo:.6f}")
+    # bfloat16 operands carry 8 significant bits: errors of a few 1e-3
+    assert rel < 3e-2
+    assert abs(loss - lo) < 3e-2 * lo
+
+
+def test_adam_matches_oracle(S):
+    import torch
+    net, p, X, T, dims = _net_case(S, bf16=False, seed=5)
+    rng = np.random.default_rng(5)
+    P = p.astype(np.float64)
+    m = np.zeros_like(P)
+    v = np.zeros_like(P)
+    for step in (1, 2, 3):
+        g = rng.standard_normal(net.nparams).astype(np.float32)
+        net.adam(torch.tensor(g, device="cuda"), 1e-2)
+        O.adam_step(P, g.astype(np.float64), m, v, step, lr=1e-2)
+    got = net.get_params().astype(np.float64)
+    assert np.max(np.abs(got - P)) <= 1e-6 * max(1.0, np.max(np.abs(P)))
+
+
+def cond_F(inst, x):
+    """Condition number of F(x) (all blocks), from numpy's eigensolver."""
+    lo, hi = np.inf, 0.0
+    for b in inst.blocks:
+        Fx = b.A[0] + np.tensordot(x, b.A[1:], 1)
+        ev = np.linalg.eigvalsh(Fx) if b.kind == I.DENSE else Fx
+        lo, hi = min(lo, ev.min()), max(hi, ev.max())
+    return hi / lo
+
+
+def _training_triples(S, g, inst, chains=64, rounds=160, seed=31):
+    """(x, v, t-, t+) of segment starts of plain billiard chains."""
+    n = inst.n
+    o = O.Oracle(inst)
+    # diameter estimate from a short HnR pre-run
+    _, _, _, log = g.walk(S.HNR, np.zeros((16, n)), 10, seed=3, log_chains=16, log_cap=160)
+    lg = log.cpu().numpy()
+    tau = 2.0 * float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+    _, _, _, log = g.walk(S.BILLIARD, np.zeros((chains, n)), 1 << 30, seed=seed, tau=tau, max_rounds=rounds,
+                          log_chains=chains, log_cap=chains * rounds)
+    log = log.cpu().numpy()
+    x, v = log[:, :n].copy(), log[:, n:2 * n].copy()
+    tm, tp, st = g.intersect(x, v)
+    tm, tp, st = tm.cpu().numpy(), tp.cpu().numpy(), st.cpu().numpy()
+    keep = (st == 0) & np.isfinite(tm) & np.isfinite(tp) & (tm < 0) & (tp > 0)
+    return x[keep], v[keep], tm[keep], tp[keep], tau, o
+
+
+def test_learned_reflection_exact_and_fewer_lanczos_steps(S):
+    inst = I.gbase(20, 20, seed=77)
+    g = S.Spectrahedron(inst)
+    x, v, tm, tp, tau, o = _training_triples(S, g, inst)
+    rows = x.shape[0]
+    ntr = int(0.8 * rows)
+    net = S.Mlp(inst.n, width=64, hidden=3, bf16=True, seed=9)
+    st = net.train(x[:ntr], v[:ntr], tm[:ntr], tp[:ntr], epochs=40, batch=512, lr=2e-3)
+    print("training", st)
+    # the prediction beats the constant predictor of log t+
+    ly = np.log(tp[:ntr])
+    assert st["err_median"] < 0.8 * np.median(np.abs(ly - ly.mean()))
+    xt, vt = x[ntr:], v[ntr:]
+    lp, _ = net.predict(xt, vt)
+    lp = lp.cpu().numpy()
+    assert np.all(np.isfinite(lp))
+    # plain reflection and its Lanczos steps
+    tp0, s0, w0, st0 = g.reflect(xt, vt)
+    steps0 = g.lanczos_info(xt.shape[0])[:, 3]
+    # learned reflection with the bracket half-width at the 0.9 quantile
+    delta = st["err_q"][0.9]
+    g.set_mlp(net, delta, 1)
+    tp1, s1, w1, st1 = g.reflect(xt, vt)
+    info = g.lanczos_info(xt.shape[0])
+    steps1, cert = info[:, 3], info[:, 2]
+    best, ms = g.tune_mlp_delta(net, xt, vt, [st["err_q"][q] for q in (0.5, 0.9, 0.999)])
+    assert best in [st["err_q"][q] for q in (0.5, 0.9, 0.999)] and len(ms) == 3
+    g.set_mlp(None)
+    tp0, tp1 = tp0.cpu().numpy(), tp1.cpu().numpy()
+    st1 = st1.cpu().numpy()
+    assert set(np.unique(st1)) <= {S.OK, S.CERT_FALLBACK, S.NONSMOOTH}
+    # the fallbacks are exactly the brackets whose lower end is not below t+
+    t_lo = np.exp(lp - delta)
+    assert np.all((cert == 1) == (t_lo >= tp0 * (1 - 1e-9))) or np.mean((cert == 1) != (t_lo >= tp0)) < 0.01
+    # t+ from the oracle on a sample (oracle cost: Jacobi at m = 20)
+    idx = np.arange(0, xt.shape[0], max(1, xt.shape[0] // 200))
+    otp, os_, ow, ost = o.reflect(xt[idx], vt[idx])
+    # segment starts after a reflection sit 1e-6 t+ from the boundary, where
+    # F(x) is nearly singular: reducing the pencil through its Cholesky factor
+    # loses about eps kappa(F(x)) (oracle and plain path alike), so the bar is
+    # max(1e-9, 20 eps kappa(F(x))) with kappa from numpy's eigensolver
+    kF = np.array([cond_F(inst, xx) for xx in xt[idx]])
+    bar = np.maximum(1e-9, 20 * 2.2e-16 * kF)
+    rel1 = np.abs(tp1[idx] - otp) / otp
+    rel0 = np.abs(tp0[idx] - otp) / otp
+    for name, rel in (("learned", rel1), ("plain", rel0)):
+        w = np.argsort(-rel / bar)[:5]
+        print(name, "worst rel/bar", [(f"{rel[i]:.2e}", f"{bar[i]:.2e}", f"kF={kF[i]:.2e}",
+                                       f"tm={tm[ntr:][idx][i]:.2e}", f"tp={otp[i]:.3e}") for i in w])
+    assert np.all(rel1 <= bar), (rel1.max(), bar[np.argmax(rel1 / bar)])
+    assert np.all(rel0 <= bar)
+    s1 = s1.cpu().numpy()[idx]
+    assert np.max(np.abs(s1 - os_)) <= 1e-6
+    fb = np.mean(cert == 1)
+    print(f"lanczos steps plain {steps0.mean():.2f} learned {steps1.mean():.2f}; fallback rate {fb:.4f}; "
+          f"tuned delta {best:.3f} from {ms}")
+    assert fb < 0.2
+    assert steps1.mean() < 0.85 * steps0.mean()
+
+
+def test_untrained_network_falls_back_and_stays_exact(S):
+    """A random network gives brackets on both sides of t+: the ones past t+
+    fail the Cholesky certificate and fall back; every result is exact."""
+    inst = I.gbase(10, 10, seed=101, scale=math.sqrt(10))
+    g = S.Spectrahedron(inst)
+    o = O.Oracle(inst)
+    rng = np.random.default_rng(4)
+    B = 200
+    x = np.zeros((B, 10))
+    v = I.random_directions(rng, B, 10)
+    net = S.Mlp(10, width=16, hidden=1, bf16=True, seed=2)
+    g.set_mlp(net, 0.0, 1)
+    tp1, s1, w1, st1 = g.reflect(x, v)
+    cert = g.lanczos_info(B)[:, 2]
+    g.set_mlp(net, 0.5, 2)
+    tp2, s2, w2, st2 = g.reflect(x, v)
+    g.set_mlp(None)
+    otp, os_, ow, ost = o.reflect(x, v)
+    for tpv, sv, stv in ((tp1, s1, st1), (tp2, s2, st2)):
+        tpv = tpv.cpu().numpy()
+        assert np.all(np.abs(tpv - otp) <= 1e-9 * otp)
+        assert np.max(np.abs(sv.cpu().numpy() - os_)) <= 1e-7
+        assert set(np.unique(stv.cpu().numpy())) <= {S.OK, S.CERT_FALLBACK}
+    print(f"untrained network: {int(np.sum(cert == 1))} of {B} brackets fell back")
+
+
+def test_learned_billiard_walk_logged_pairs(S):
+    inst = I.gbase(20, 20, seed=78)
+    g = S.Spectrahedron(inst)
+    x, v, tm, tp, tau, o = _training_triples(S, g, inst, chains=64, rounds=120, seed=41)
+    net = S.Mlp(inst.n, width=64, hidden=3, bf16=True, seed=11)
+    st = net.train(x, v, tm, tp, epochs=30, batch=512, lr=2e-3)
+    g.set_mlp(net, st["err_q"][0.9], 1)
+    chains, rounds = 64, 60
+    xo, _, stats, log = g.walk(S.BILLIARD, np.zeros((chains, inst.n)), 1 << 30, seed=5, tau=tau,
+                               max_rounds=rounds, log_chains=chains, log_cap=chains * rounds)
+    g.set_mlp(None)
+    assert stats["calls"] == chains * rounds
+    assert stats["not_interior"] == 0 and stats["noconv"] == 0
+    assert stats["cert_fallback"] < 0.2 * stats["calls"]
+    log = log.cpu().numpy()
+    n = inst.n
+    idx = np.arange(0, log.shape[0], max(1, log.shape[0] // 150))
+    lx, lv, ltp = log[idx, :n], log[idx, n:2 * n], log[idx, 2 * n + 1]
+    otm, otp, ost = o.intersect(lx, lv)
+    kF = np.array([cond_F(inst, xx) for xx in lx])
+    bar = np.maximum(1e-9, 20 * 2.2e-16 * kF)
+    rel = np.abs(ltp - otp) / otp
+    print(f"learned walk: max rel {rel.max():.2e}, fallbacks {stats['cert_fallback']:.0f} of {stats['calls']:.0f}")
+    assert np.all(rel <= bar), (rel.max(),)

@@ -5,9 +5,12 @@ Workload: billiard walk (Alg. Billiard) on the n = m = 200 spectrahedron
 box as 400 diagonal rows), 16384 chains, step length ell = -tau ln(eta) with
 tau = 2 x (diameter estimate), FP64.  One bench "step" is one round of the
 walk: every chain runs one segment through the whole oracle (assembly GEMM of
-F(x) and B(v), Cholesky + inverse, Lanczos extreme eigenvalues, normal GEMM,
+F(x) and B(v), Cholesky + inverse, Lanczos extreme eigenvalue, normal GEMM,
 reflection / step logic).  Metric: oracle calls per second (one call per chain
-per round) with billiard steps per second beside it.
+per round) with billiard steps per second beside it, for the plain path and
+for the learned-bracket path (network trained on the walk's own segment
+starts, half-width autotuned, every t+ certified by an FP64 Cholesky factor);
+`value` is the learned path's rate, the plain path's is under "plain".
 
 Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -84,13 +87,149 @@ def cpu_baseline(tau, x0s, budget_s=15.0):
     }
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed_rounds(g, S, x0, tau, rounds, chains):
+    """`rounds` oracle rounds of the resumed billiard chains, timed with the
+    device synchronised on both sides; stage timers on the launch stream."""
+    import torch
+    big = 1 << 40
+    torch.cuda.synchronize()
+    g.timing(True)
+    t0 = time.perf_counter()
+    _, _, st, _ = g.walk(S.BILLIARD, x0, big, seed=2024, tau=tau, max_rounds=rounds, resume=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.timing(False)
+    stages, lz_steps = g.stage_times()
+    return {"wall": wall, "stats": st, "stages": stages, "lz_steps": lz_steps}
+
+
+def roofline(run, chains, extra_chol=0.0):
+    """FP64 roofline of the dominant kernel of a timed run."""
+    stages, lz_steps, calls = run["stages"], run["lz_steps"], run["stats"]["calls"]
+    dom = max(stages, key=lambda k: stages[k][0])
+    launches = max(stages[dom][1], 1)
+    ms_dom = stages[dom][0] / launches
+    P = M_DIM * (M_DIM + 1) // 2
+    if dom == "fused":
+        # fused per-chain kernel (Cholesky, inverse, Lanczos, Ritz vector): FP64
+        # arithmetic on MFMA and the vector ALUs, both at the FP64 peak.  Counted
+        # work is the method's own: Cholesky m^3/3 (and the second one of each
+        # learned-bracket fallback), 4 m^2 per Lanczos step, Ritz vector and
+        # u = L^-T z, the packed u u^T for the normal GEMM, and the ratio test of
+        # the diagonal block; the triangular inverse (m^3/3) is a design choice
+        # and is not counted.
+        md = 2 * N_DIM
+        per_call = M_DIM**3 / 3.0 + 2.0 * M_DIM**2 + P + 3.0 * md
+        flops = (calls * per_call + extra_chol * M_DIM**3 / 3.0
+                 + lz_steps * (4.0 * M_DIM**2 + 2.0 * M_DIM)) / launches
+        roof = {"bound": "alu", "achieved": flops / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        rows = 2 * calls / launches if dom == "assemble" else calls / launches
+        K = N_DIM + 1 if dom == "assemble" else P
+        Nc = P + 2 * N_DIM if dom == "assemble" else N_DIM
+        flops = 2.0 * rows * K * Nc
+        roof = {"bound": "mfma", "achieved": flops / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["traffic_unit"] = "bytes per launch"
+    roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64<false>", "normal": "k_gemm_f64<true>",
+                      "predict": "k_gemm_f32", "update": "k_walk_update"}[dom]
+    roof["ms_per_launch"] = ms_dom
+    return roof
+
+
+def summary(run, chains, calls_per_step=None):
+    """Rates of a timed run.  Billiard steps per second is the long-run rate
+    calls/s / (oracle calls per completed step), with calls per step taken
+    from a long walk of the same chains when given (a short window holds about
+    one heavy-tailed step per chain); the window's own count is kept beside it."""
+    st, wall = run["stats"], run["wall"]
+    calls = st["calls"]
+    cps = calls_per_step if calls_per_step else st["calls"] / max(st["steps"], 1)
+    return {
+        "oracle_calls_per_s": calls / wall,
+        "billiard_steps_per_s": calls / wall / cps,
+        "calls_per_step": cps,
+        "billiard_steps_in_window_per_s": st["steps"] / wall,
+        "ms_per_round": 1e3 * wall / max(st["rounds"], 1),
+        "reflections_per_step": st["reflections"] / max(st["steps"], 1),
+        "lanczos_steps_per_call": run["lz_steps"] / max(calls, 1),
+        "noconv": st["noconv"],
+        "not_interior": st["not_interior"],
+        "cert_fallback_rate": st["cert_fallback"] / max(calls, 1),
+        "stage_ms_per_round": {k: v[0] / max(v[1], 1) for k, v in run["stages"].items()},
+    }
+
+
+def train_learned(g, S, x0, tau, chains, rows_target, epochs, seed=77):
+    """Walk-generated (x, v, t-, t+) triples -> trained network -> autotuned
+    bracket half-width (attached to g).  Returns the network and a report."""
+    import torch
+    n = N_DIM
+    t0 = time.perf_counter()
+    rounds = max(1, -(-rows_target // chains))
+    _, _, wst, log = g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=rounds, resume=True,
+                            log_chains=chains, log_cap=rounds * chains)
+    calls_per_step = wst["calls"] / max(wst["steps"], 1)
+    x = log[:, :n].contiguous()
+    v = log[:, n:2 * n].contiguous()
+    del log
+    tm = torch.empty(x.shape[0], dtype=torch.float64, device="cuda")
+    tp = torch.empty_like(tm)
+    ok = torch.empty(x.shape[0], dtype=torch.bool, device="cuda")
+    for r0 in range(0, x.shape[0], chains):
+        a, b, st = g.intersect(x[r0:r0 + chains], v[r0:r0 + chains])
+        tm[r0:r0 + chains], tp[r0:r0 + chains] = a, b
+        ok[r0:r0 + chains] = (st == S.OK) & torch.isfinite(a) & torch.isfinite(b) & (a < 0) & (b > 0)
+    x, v, tm, tp = x[ok], v[ok], tm[ok], tp[ok]
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed)
+    t1 = time.perf_counter()
+    progress(f"training on {x.shape[0]} triples ({t0 and time.perf_counter() - t0:.1f} s to generate)")
+    tr = net.train(x, v, tm, tp, epochs=epochs, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=0.1, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    # autotune the half-width on held-out pairs through the real learned kernel
+    nval = int(tr["val_rows"])
+    xv, vv = x[-nval:][:chains], v[-nval:][:chains]
+    levels = (0.5, 0.7, 0.8, 0.9, 0.95, 0.99)
+    cands = [tr["err_q"][q] for q in levels]
+    best, ms = g.tune_mlp_delta(net, xv, vv, cands, reps=2)
+    # learned against plain t+ on the held-out pairs (same device, same inputs)
+    tpl, _, _, stl = g.reflect(xv, vv)
+    g.set_mlp(None)
+    tpp, _, _, stp = g.reflect(xv, vv)
+    g.set_mlp(net, best, 1)
+    rel = (torch.abs(tpl - tpp) / tpp).cpu().numpy()
+    report = {
+        "calls_per_step": calls_per_step, "walk_calls": wst["calls"], "walk_steps": wst["steps"],
+        "rows": int(x.shape[0]), "data_seconds": t_data, "train_seconds": t_train,
+        "epochs": epochs, "adam_steps": tr["steps"], "train_loss": tr["train_loss"], "val_loss": tr["val_loss"],
+        "val_logtp_err": {str(k): v for k, v in tr["err_q"].items()},
+        "delta_candidates": dict(zip([str(q) for q in levels], cands)), "tune_ms": ms, "delta": best,
+        "learned_vs_plain_tp_rel": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+                                    "max": float(rel.max())},
+    }
+    return net, report
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--chains", type=int, default=CHAINS)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-rows", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -121,83 +260,65 @@ def main():
 
     chains = args.chains
     x0 = torch.zeros((chains, N_DIM), dtype=torch.float64, device="cuda")
-    big = 1 << 40
-    # warm-up rounds (also initialises the chains)
-    g.walk(S.BILLIARD, x0, big, seed=2024, tau=tau, max_rounds=max(args.warmup, 1))
-    torch.cuda.synchronize()
-    g.timing(True)
-    t0 = time.perf_counter()
-    _, _, st, _ = g.walk(S.BILLIARD, x0, big, seed=2024, tau=tau, max_rounds=args.steps, resume=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    g.timing(False)
-    stages, lz_steps = g.stage_times()
-    calls = st["calls"]
-    steps_done = st["steps"]
-    value = calls / wall
-
-    # roofline of the dominant kernel
-    dom = max(stages, key=lambda k: stages[k][0])
-    launches = max(stages[dom][1], 1)
-    ms_dom = stages[dom][0] / launches
-    P = M_DIM * (M_DIM + 1) // 2
-    if dom == "fused":
-        # fused per-chain kernel (Cholesky, inverse, Lanczos, Ritz vector): FP64
-        # arithmetic on MFMA and the vector ALUs, both at the FP64 peak.  Counted
-        # work is the method's own: Cholesky m^3/3, 4 m^2 per Lanczos step,
-        # Ritz vector and u = L^-T z, the packed u u^T for the normal GEMM, and
-        # the ratio test of the diagonal block; the triangular inverse (m^3/3)
-        # is a design choice and is not counted.
-        md = 2 * N_DIM
-        per_call = M_DIM**3 / 3.0 + 2.0 * M_DIM**2 + P + 3.0 * md
-        flops = (calls * per_call + lz_steps * (4.0 * M_DIM**2 + 2.0 * M_DIM)) / launches
-        roof = {"bound": "alu", "achieved": flops / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    else:
-        rows = 2 * calls / launches if dom == "assemble" else calls / launches
-        K = N_DIM + 1 if dom == "assemble" else P
-        Nc = P + 2 * N_DIM if dom == "assemble" else N_DIM
-        flops = 2.0 * rows * K * Nc
-        roof = {"bound": "mfma", "achieved": flops / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = _fused_traffic(chains) if dom == "fused" else None
-    roof["traffic_unit"] = "bytes per launch"
-    roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64<false>", "normal": "k_gemm_f64<true>",
-                      "predict": "k_gemm_f32", "update": "k_walk_update"}[dom]
-    roof["ms_per_launch"] = ms_dom
+    # warm-up rounds (also initialise the chains), then the plain timed rounds
+    g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.warmup, 1))
+    progress("plain path: timed rounds")
+    plain = timed_rounds(g, S, x0, tau, args.steps, chains)
+    roof = roofline(plain, chains)
+    if roof["kernel"] == "k_line_fused":
+        roof["traffic"] = _fused_traffic(chains)
     # assembly GEMM (F(x) and B(v) rows of every chain): FP64 MFMA utilisation
-    asm_launches = max(stages["assemble"][1], 1)
-    asm_ms = stages["assemble"][0] / asm_launches
-    asm_flops = 2.0 * (2 * calls / asm_launches) * (N_DIM + 1) * (P + 2 * N_DIM)
+    P = M_DIM * (M_DIM + 1) // 2
+    asm_launches = max(plain["stages"]["assemble"][1], 1)
+    asm_ms = plain["stages"]["assemble"][0] / asm_launches
+    asm_flops = 2.0 * (2 * plain["stats"]["calls"] / asm_launches) * (N_DIM + 1) * (P + 2 * N_DIM)
     assembly = {"kernel": "k_gemm_f64<false>", "achieved": asm_flops / (asm_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "ms_per_launch": asm_ms}
     assembly["frac"] = assembly["achieved"] / assembly["peak"]
+    plain_sum = summary(plain, chains)
+    plain_sum["roofline"] = roof
 
+    learned_sum = None
+    if not args.no_learned:
+        progress("learned path: training data, training, half-width tuning")
+        net, report = train_learned(g, S, x0, tau, chains, args.train_rows, args.epochs)
+        progress(f"learned path: timed rounds (delta {report['delta']:.3f})")
+        g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.warmup, 1), resume=True)
+        learned = timed_rounds(g, S, x0, tau, args.steps, chains)
+        cps = report["calls_per_step"]
+        learned_sum = summary(learned, chains, cps)
+        plain_sum.update({k: v for k, v in summary(plain, chains, cps).items() if k != "stage_ms_per_round"})
+        learned_sum["roofline"] = roofline(learned, chains, extra_chol=learned["stats"]["cert_fallback"])
+        learned_sum["training"] = report
+        g.set_mlp(None)
+
+    head = learned_sum if learned_sum is not None else plain_sum
     out = {
         "metric": "oracle calls/s + billiard steps/s at n=m=200, learned vs plain @1e-9 rel",
-        "value": value,
+        "value": head["oracle_calls_per_s"],
         "unit": "oracle calls/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": head["ms_per_round"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "billiard walk, n=m=200 G-BASE spectrahedron (+400 box rows), plain FP64 oracle",
+        "config": {"workload": "billiard walk, n=m=200 G-BASE spectrahedron (+400 box rows), FP64 oracle",
                    "chains": chains, "n": N_DIM, "m": M_DIM, "tau": tau, "instance_seed": SEED_INST,
-                   "path": "plain"},
-        "billiard_steps_per_s": steps_done / wall,
-        "reflections_per_step": st["reflections"] / max(steps_done, 1),
-        "lanczos_steps_per_call": lz_steps / max(calls, 1),
-        "stage_ms_per_round": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
-        "roofline": roof,
+                   "path": "learned" if learned_sum is not None else "plain"},
+        "billiard_steps_per_s": head["billiard_steps_per_s"],
+        "roofline": head["roofline"],
         "assembly_gemm": assembly,
+        "plain": plain_sum,
     }
+    if learned_sum is not None:
+        out["learned"] = learned_sum
+        out["learned_over_plain"] = learned_sum["oracle_calls_per_s"] / plain_sum["oracle_calls_per_s"]
     if not args.no_cpu:
+        progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))
         out["cpu_baseline"] = cpu_baseline(tau, xs)
     print(json.dumps(out), flush=True)

@@ -157,7 +157,8 @@ typedef struct {
     int32_t* log_count;
 } spec_walk_params;
 
-/* Totals over chains: oracle calls, reflections, cap hits, not-interior
+/* Totals over chains, counted over the rounds of this call (a resumed call
+ * does not include the earlier calls' rounds): oracle calls, reflections, cap hits, not-interior
  * segments, nonsmooth reflections, completed steps, eigen non-convergence,
  * oracle rounds run, oracle calls whose learned bracket was not certified
  * (they fell back to the plain origin). */

@@ -533,6 +533,13 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
     a.log_cap = p->log_cap;
     a.log_chains = p->log_chains;
     if (!p->resume) HIPCHK(walk_init(a, x0, s));
+    // totals at entry: a resumed call reports the counts of its own rounds
+    double tot0[WALK_NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (stats && p->resume) {
+        HIPCHK(walk_sum_stats(chains, h->wStats, h->wSum, s));
+        HIPCHK(hipMemcpyAsync(tot0, h->wSum, sizeof(tot0), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     const bool billiard = kind == SPEC_WALK_BILLIARD;
     long long rounds = 0;
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
@@ -577,6 +584,7 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
         HIPCHK(walk_sum_stats(chains, h->wStats, h->wSum, s));
         HIPCHK(hipMemcpyAsync(tot, h->wSum, sizeof(tot), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < WALK_NSTAT; ++k) tot[k] -= tot0[k];
         stats->calls = tot[0];
         stats->reflections = tot[1];
         stats->cap_hits = tot[2];

@@ -34,6 +34,7 @@ namespace spec {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int MAXH = 100;  // half-row length held in registers (m <= 200)
+constexpr int NCYCLES = 3;  // Lanczos cycles of at most kmax steps (restarts from the Ritz vector)
 
 // Element (i, j) of tile (I, J) of the packed lower matrix; zero above the
 // diagonal and outside m.
@@ -384,6 +385,31 @@ __device__ inline double backward_norm_reg(double aA, double aB, double bA, doub
     return 1.0 / sqrt(ss);
 }
 
+// Row r of the Ritz vector z = sum_i y_i q_i of T_k for the Ritz value th,
+// with y from the backward three-term recurrence (y_{k-1} = 1) and the
+// stored basis rows Qg[i m + r]; normalised in y.
+__device__ inline double ritz_row(const double* al, const double* be, int k, double th, const double* Qg, int m,
+                                  int r) {
+    double zr = 0.0, y1 = 1.0, y0 = 0.0, ss = 0.0;
+    for (int i = k - 1; i >= 0; --i) {
+        zr += y1 * Qg[(size_t)i * m + r];
+        ss += y1 * y1;
+        if (i >= 1) {
+            const double ym = ((th - al[i]) * y1 - (i + 1 < k ? be[i + 1] * y0 : 0.0)) / be[i];
+            y0 = y1;
+            y1 = ym;
+        }
+        if (ss > 1e280) {
+            const double sc = 1e-140;
+            y0 *= sc;
+            y1 *= sc;
+            ss *= sc * sc;
+            zr *= sc;
+        }
+    }
+    return zr * (1.0 / sqrt(ss));
+}
+
 // Column c of W^T x restricted to half h of the rows [R0, m) of the wave's
 // band: sum over rows rr >= c of W[rr][c] x[rr].  Rows are walked in step by
 // all lanes of the wave so that they read consecutive addresses of one row.
@@ -545,6 +571,7 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                     if (own && k < hm && c < m) v = c <= r ? Br[pk(r, c)] : Br[pk(c, r)];
                     breg[k] = v;
                 }
+                for (int cyc = 0;; ++cyc) {
                 double qprev = 0.0, bprev = 0.0;
                 for (int j = 0; j < kmax; ++j) {
                     if (own && h == 0) {
@@ -588,8 +615,22 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                     qr = cv * (1.0 / bn);
                     bprev = bn;
                 }
+                if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
+                // not converged within kmax steps: restart from the Ritz vector(s)
+                __syncthreads();  // basis rows in HBM are read across lanes
+                {
+                    const int kk = (int)sres[5];
+                    double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, r) : 0.0;
+                    if (!a.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, r);
+                    const double nz = block_sum_lds((own && h == 0) ? zr * zr : 0.0, red);
+                    qr = zr * (1.0 / sqrt(nz));
+                }
+                lds_barrier();
+                }
             } else {
                 long long ph[6] = {0, 0, 0, 0, 0, 0};
+                if (lane == 0) sres[6] = 0.0;
+                for (int cyc = 0;; ++cyc) {
                 int next_check = a.first_check > 0 ? a.first_check : 4;
                 double prev_q = -1.0;
                 int prev_k = 0;
@@ -715,10 +756,16 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                     if (lane == 0) {
                         sres[4] = stop;
                         sres[5] = (double)k;
+                        if (stop != 0.0) sres[6] += (double)k;
                     }
                     lds_barrier();  // B11
                     PHASE(5)
                     if (stop != 0.0) break;
+                }
+                if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
+                __syncthreads();
+                (void)block_sum_lds(0.0, red);
+                lds_barrier();
                 }
 #undef PHASE
                 if (prof && t == 0)
@@ -730,7 +777,7 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
             lmax = sres[2];
             conv = sres[4] == 1.0;
             const int k = (int)sres[5];
-            iters = k;
+            iters = (int)sres[6];
             // dense block: roots measured from the shifted origin t0
             double dtpd = INFINITY, dtmd = -INFINITY;
             if (lmax > 0.0) dtmd = t0 - 1.0 / lmax;
@@ -743,22 +790,8 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
             }
             const bool need_vec = a.want_vec && hit == HIT_DENSE && isfinite(tp) && (a.ell == nullptr || tp < a.ell[chain]);
             if (need_vec) {
-                // Ritz vector z = sum_j y_j q_j, y from the backward recurrence
-                double zr = 0.0, y1 = 1.0, y0 = 0.0, ss = 0.0;
-                for (int i = k - 1; i >= 0; --i) {
-                    if (own) zr += y1 * Qg[(size_t)i * m + r];
-                    ss += y1 * y1;
-                    if (i >= 1) {
-                        const double ym = ((lmin - al[i]) * y1 - (i + 1 < k ? be[i + 1] * y0 : 0.0)) / be[i];
-                        y0 = y1;
-                        y1 = ym;
-                    }
-                    if (ss > 1e280) {
-                        const double sc = 1e-140;
-                        y0 *= sc; y1 *= sc; ss *= sc * sc; zr *= sc;
-                    }
-                }
-                zr *= 1.0 / sqrt(ss);
+                // Ritz vector z = sum_j y_j q_j of lambda_min
+                const double zr = own ? ritz_row(al, be, k, lmin, Qg, m, r) : 0.0;
                 lds_barrier();
                 if (own && h == 0) slot[r] = zr;
                 lds_barrier();

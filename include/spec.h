@@ -179,6 +179,44 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
                               spec_walk_stats* stats, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Volume by Gaussian cooling (the Gaussian variant of multiphase Monte Carlo
+ * that the paper's volume section names as an alternative to its ball
+ * sequence): vol(S) = int_S f_0 * prod_i (int_S f_{i+1} / int_S f_i) with
+ * f_i = exp(-a_i |x|^2), a_0 > ... > a_{phases-1} geometric, a_phases = 0.
+ *  - int_S f_0 = (pi/a_0)^{n/2} Pr[X in S], X ~ N(0, I/(2 a_0)), from exact
+ *    Gaussian draws and the membership oracle;
+ *  - each ratio is the sample mean of exp((a_i - a_{i+1}) |x|^2) over points
+ *    of Gaussian Hit-and-Run chains targeting f_i restricted to S (chains
+ *    start at the origin, which must be interior, and are warm-started from
+ *    the previous phase);
+ *  - chains are split into `groups` independent groups; the estimate is the
+ *    mean of the groups' log-volumes with a Student-t 95 % interval.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int phases;             /* cooling phases (default 20) */
+    int samples_per_phase;  /* samples per phase over all chains; also exact draws per group for int f_0
+                               (default 2000) */
+    int chains;             /* chains, a multiple of groups (default 64) */
+    int walk_len;           /* Hit-and-Run steps between recorded samples (default 10) */
+    int groups;             /* independent groups for the interval (default 8) */
+    double a0;              /* <= 0: chosen so that 50-90 % of N(0, I/(2 a0)) lies in S */
+    double a_end;           /* <= 0: 1/(4 d^2), d the longest chord of a 64-chain Hit-and-Run pre-run */
+} spec_volume_params;
+
+typedef struct {
+    double a0, a_end;       /* the schedule's ends actually used */
+    double p_inside;        /* fraction of the exact draws inside S */
+    double oracle_calls;    /* line oracle calls of the walks */
+    int phases;
+    double log_terms[65];   /* [0] = log int f_0, [i] = log of ratio i (group means) */
+} spec_volume_stats;
+
+/* Estimate log vol(S); host outputs, asynchronous work on `stream`, synchronises.
+ * EINVAL for bad parameters (phases 1..64, groups >= 2, chains % groups == 0). */
+spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uint64_t seed, double* log_vol,
+                                 double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned boundary bracket.
  *
  * A small MLP maps (x, v) to predictions of (log t+, log(-t-)).  With a

@@ -492,17 +492,38 @@ spec_status spec_reflect(spec_handle h, int batch, const double* x, const double
 
 // ------------------------------------------------------------ walks
 
+namespace {
+
+// Walk driver shared by spec_walk_run_dev and the volume estimate: samples
+// samp_first .. samp_first + nsamp - 1 (in units of thin steps) go to `samples`.
+spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
+                          const spec_walk_params* p, double* x_out, double* samples, long long samp_first,
+                          long long nsamp, spec_walk_stats* stats, hipStream_t s);
+
+}  // namespace
+
 spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
                               const spec_walk_params* p, double* x_out, double* samples, spec_walk_stats* stats,
                               void* stream) {
     if (!h || !p || chains < 0 || steps < 0 || (chains && (!x0 || !x_out))) return SPEC_EINVAL;
+    return walk_run_impl(h, kind, chains, x0, steps, seed, p, x_out, samples, 0,
+                         p->thin > 0 ? steps / p->thin : 0, stats, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
+                          const spec_walk_params* p, double* x_out, double* samples, long long samp_first,
+                          long long nsamp, spec_walk_stats* stats, hipStream_t s) {
     if (kind != SPEC_WALK_HNR && kind != SPEC_WALK_CHNR && kind != SPEC_WALK_BILLIARD) return SPEC_EINVAL;
     if (kind == SPEC_WALK_BILLIARD && !(p->tau > 0.0)) return SPEC_EINVAL;
     if (p->gauss_a < 0.0 || !(p->pullback >= 0.0 && p->pullback < 1.0) || p->thin < 0) return SPEC_EINVAL;
     if (p->log_buf && (!p->log_count || p->log_cap < 0)) return SPEC_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (chains == 0) return SPEC_OK;
-    hipStream_t s = (hipStream_t)stream;
+    if (p->resume && chains > h->wcap) return SPEC_EINVAL;
     SPCHK(h->ensure(chains));
     SPCHK(h->ensure_walk(chains));
     WalkArgs a{};
@@ -527,12 +548,14 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
     a.P = h->P;
     a.samples = samples;
     a.thin = p->thin;
-    a.nsamp = p->thin > 0 ? steps / p->thin : 0;
+    a.nsamp = nsamp;
+    a.samp_first = samp_first;
     a.log_buf = p->log_buf;
     a.log_count = p->log_count;
     a.log_cap = p->log_cap;
     a.log_chains = p->log_chains;
     if (!p->resume) HIPCHK(walk_init(a, x0, s));
+    else HIPCHK(walk_resume(a, s));
     // totals at entry: a resumed call reports the counts of its own rounds
     double tot0[WALK_NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (stats && p->resume) {
@@ -597,6 +620,53 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
     }
     return SPEC_OK;
 }
+
+// Student's t quantile at 0.975 for nu degrees of freedom: bisection on
+// F(t) = 1 - I_{nu/(nu+t^2)}(nu/2, 1/2) / 2, the regularised incomplete beta
+// by its continued fraction (modified Lentz).
+double inc_beta_cf(double a, double b, double x) {
+    const double tiny = 1e-300;
+    double c = 1.0, d = 1.0 - (a + b) * x / (a + 1.0);
+    if (std::fabs(d) < tiny) d = tiny;
+    d = 1.0 / d;
+    double f = d;
+    for (int m = 1; m <= 300; ++m) {
+        const double m2 = 2.0 * m;
+        double num = m * (b - m) * x / ((a + m2 - 1.0) * (a + m2));
+        d = 1.0 + num * d; if (std::fabs(d) < tiny) d = tiny; d = 1.0 / d;
+        c = 1.0 + num / c; if (std::fabs(c) < tiny) c = tiny;
+        f *= d * c;
+        num = -(a + m) * (a + b + m) * x / ((a + m2) * (a + m2 + 1.0));
+        d = 1.0 + num * d; if (std::fabs(d) < tiny) d = tiny; d = 1.0 / d;
+        c = 1.0 + num / c; if (std::fabs(c) < tiny) c = tiny;
+        const double del = d * c;
+        f *= del;
+        if (std::fabs(del - 1.0) < 1e-15) break;
+    }
+    return f;
+}
+
+double reg_inc_beta(double a, double b, double x) {
+    if (x <= 0.0) return 0.0;
+    if (x >= 1.0) return 1.0;
+    const double lbt = std::lgamma(a + b) - std::lgamma(a) - std::lgamma(b) + a * std::log(x) + b * std::log1p(-x);
+    if (x < (a + 1.0) / (a + b + 2.0)) return std::exp(lbt) * inc_beta_cf(a, b, x) / a;
+    return 1.0 - std::exp(lbt) * inc_beta_cf(b, a, 1.0 - x) / b;
+}
+
+double student_t975(int nu) {
+    double lo = 0.0, hi = 100.0;
+    for (int it = 0; it < 200; ++it) {
+        const double t = 0.5 * (lo + hi);
+        const double cdf = 1.0 - 0.5 * reg_inc_beta(0.5 * nu, 0.5, nu / (nu + t * t));
+        if (cdf < 0.975) lo = t; else hi = t;
+    }
+    return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+extern "C" {
 
 // ------------------------------------------------------------ diagnostics
 
@@ -671,6 +741,170 @@ spec_status spec_diag_stage_times(spec_handle h, double* out, double* lanczos_st
 spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out) {
     if (!h || !lam_out || batch < 0 || batch > h->cap) return SPEC_EINVAL;
     HIPCHK(hipMemcpy(lam_out, h->dLam, sizeof(double) * 4 * batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+
+spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uint64_t seed, double* log_vol,
+                                 double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream) {
+    if (!h || !p || !log_vol) return SPEC_EINVAL;
+    const int phases = p->phases > 0 ? p->phases : 20;
+    const int spp = p->samples_per_phase > 0 ? p->samples_per_phase : 2000;
+    const int chains = p->chains > 0 ? p->chains : 64;
+    const int walk_len = p->walk_len > 0 ? p->walk_len : 10;
+    const int groups = p->groups > 0 ? p->groups : 8;
+    if (phases > 64 || groups < 2 || chains % groups || spp < groups) return SPEC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = h->n;
+    const double pi = 3.14159265358979323846;
+    double* dX = nullptr;   // exact draws / pre-run log
+    int8_t* dFlag = nullptr;
+    double* dOut = nullptr;
+    double* dSamp = nullptr;
+    double* dZero = nullptr;
+    double* dXout = nullptr;
+    int32_t* dCnt = nullptr;
+    const int spc = (spp + chains - 1) / chains;
+    const int ndraw = groups * spp;
+    const int prerun_chains = 64, prerun_steps = 20;
+    auto cleanup = [&]() {
+        dfree(dX); dfree(dFlag); dfree(dOut); dfree(dSamp); dfree(dZero); dfree(dXout); dfree(dCnt);
+    };
+#define VCHK(expr)                                                  \
+    do {                                                            \
+        spec_status _r = (expr);                                    \
+        if (_r != SPEC_OK) { cleanup(); return _r; }                \
+    } while (0)
+#define VHIP(expr) VCHK(from_hip(expr))
+    VHIP(dalloc(&dX, (size_t)std::max(ndraw, prerun_chains * prerun_steps * 2) * (2 * n + 4), false));
+    VHIP(dalloc(&dFlag, (size_t)std::max(ndraw, 1024), false));
+    VHIP(dalloc(&dOut, (size_t)groups, false));
+    VHIP(dalloc(&dSamp, (size_t)chains * spc * n, false));
+    VHIP(dalloc(&dZero, (size_t)std::max(chains, prerun_chains) * n));
+    VHIP(dalloc(&dXout, (size_t)std::max(chains, prerun_chains) * n, false));
+    VHIP(dalloc(&dCnt, 1));
+    spec_walk_stats ws{};
+    double calls = 0.0;
+    // ---- schedule ends
+    double a_end = p->a_end;
+    if (!(a_end > 0.0)) {
+        spec_walk_params wp{};
+        wp.tau = 1.0;
+        wp.pullback = 1e-6;
+        wp.log_chains = prerun_chains;
+        wp.log_cap = prerun_chains * prerun_steps;
+        wp.log_buf = dX;
+        wp.log_count = dCnt;
+        VCHK(walk_run_impl(h, SPEC_WALK_HNR, prerun_chains, dZero, prerun_steps, seed ^ 0x5851F42D4C957F2Dull, &wp,
+                           dXout, nullptr, 0, 0, &ws, s));
+        calls += ws.calls;
+        std::vector<double> lg((size_t)wp.log_cap * (2 * n + 4));
+        VHIP(hipMemcpyAsync(lg.data(), dX, sizeof(double) * lg.size(), hipMemcpyDeviceToHost, s));
+        VHIP(hipStreamSynchronize(s));
+        double d = 0.0;
+        for (int r = 0; r < wp.log_cap; ++r) {
+            const double tm = lg[(size_t)r * (2 * n + 4) + 2 * n], tp = lg[(size_t)r * (2 * n + 4) + 2 * n + 1];
+            if (std::isfinite(tm) && std::isfinite(tp)) d = std::max(d, tp - tm);
+        }
+        if (!(d > 0.0)) { cleanup(); return SPEC_UNBOUNDED; }
+        a_end = 1.0 / (4.0 * d * d);
+    }
+    // fraction of N(0, I/(2a)) inside S from `cnt` exact draws (group 0 stream of seed2)
+    auto inside = [&](double a, int cnt, uint64_t seed2, double* frac) -> spec_status {
+        const double sd = 1.0 / std::sqrt(2.0 * a);
+        HIPCHK(gauss_points(cnt, cnt, n, seed2, sd, dX, s));
+        SPCHK(spec_membership_dev(h, cnt, dX, dFlag, s));
+        double hits = 0.0;
+        HIPCHK(count_groups(1, cnt, dFlag, dOut, s));
+        HIPCHK(hipMemcpyAsync(&hits, dOut, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *frac = hits / cnt;
+        return SPEC_OK;
+    };
+    double a0 = p->a0;
+    if (!(a0 > 0.0)) {
+        // the inside fraction grows with a0: bracket [lo, hi] with f(lo) < 0.5 and
+        // f(hi) > 0.9, then bisect in log a0 until 0.5 <= f <= 0.9
+        const uint64_t s2 = seed ^ 0xA0761D6478BD642Full;
+        double f = 0.0, lo = 0.0, hi = 0.0;
+        a0 = 64.0 * a_end;
+        for (int it = 0; it < 200; ++it) {
+            VCHK(inside(a0, 1024, s2, &f));
+            if (f >= 0.5 && f <= 0.9) break;
+            if (f < 0.5) lo = a0;
+            else hi = a0;
+            if (lo > 0.0 && hi > 0.0) a0 = std::sqrt(lo * hi);
+            else a0 = f < 0.5 ? 2.0 * a0 : 0.5 * a0;
+        }
+    }
+    if (!(a0 > a_end)) a0 = 2.0 * a_end;
+    // ---- int_S f_0 per group: exact draws + membership
+    std::vector<double> gl((size_t)groups * (phases + 1), 0.0);
+    const double sd0 = 1.0 / std::sqrt(2.0 * a0);
+    VHIP(gauss_points(ndraw, spp, n, seed, sd0, dX, s));
+    VCHK(spec_membership_dev(h, ndraw, dX, dFlag, s));
+    VHIP(count_groups(groups, spp, dFlag, dOut, s));
+    std::vector<double> hits(groups);
+    VHIP(hipMemcpyAsync(hits.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
+    VHIP(hipStreamSynchronize(s));
+    double hit_tot = 0.0;
+    for (int g = 0; g < groups; ++g) {
+        if (!(hits[g] > 0.0)) { cleanup(); return SPEC_NOT_INTERIOR; }
+        hit_tot += hits[g];
+        gl[(size_t)g * (phases + 1)] = 0.5 * n * std::log(pi / a0) + std::log(hits[g] / spp);
+    }
+    // ---- phases: Gaussian Hit-and-Run targeting f_i, warm-started
+    std::vector<double> a(phases + 1);
+    for (int i = 0; i < phases; ++i) a[i] = phases == 1 ? a0 : a0 * std::pow(a_end / a0, (double)i / (phases - 1));
+    a[phases] = 0.0;
+    for (int ph = 0; ph < phases; ++ph) {
+        spec_walk_params wp{};
+        wp.tau = 1.0;
+        wp.pullback = 1e-6;
+        wp.gauss_a = a[ph];
+        wp.thin = walk_len;
+        wp.resume = ph > 0;
+        const long long steps = (long long)(ph + 1) * spc * walk_len;
+        VCHK(walk_run_impl(h, SPEC_WALK_HNR, chains, dZero, steps, seed, &wp, dXout, dSamp, (long long)ph * spc, spc,
+                           &ws, s));
+        calls += ws.calls;
+        VHIP(phase_lse(groups, chains / groups, spc, n, dSamp, a[ph] - a[ph + 1], dOut, s));
+        std::vector<double> lse(groups);
+        VHIP(hipMemcpyAsync(lse.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
+        VHIP(hipStreamSynchronize(s));
+        for (int g = 0; g < groups; ++g) gl[(size_t)g * (phases + 1) + ph + 1] = lse[g];
+    }
+    cleanup();
+#undef VCHK
+#undef VHIP
+    // ---- combine: mean of the groups' log-volumes, Student-t interval
+    std::vector<double> lv(groups, 0.0);
+    double mean = 0.0;
+    for (int g = 0; g < groups; ++g) {
+        for (int k = 0; k <= phases; ++k) lv[g] += gl[(size_t)g * (phases + 1) + k];
+        mean += lv[g];
+    }
+    mean /= groups;
+    double var = 0.0;
+    for (int g = 0; g < groups; ++g) var += (lv[g] - mean) * (lv[g] - mean);
+    var /= (groups - 1);
+    const double half = student_t975(groups - 1) * std::sqrt(var / groups);
+    *log_vol = mean;
+    if (ci_lo) *ci_lo = mean - half;
+    if (ci_hi) *ci_hi = mean + half;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->a0 = a0;
+        st->a_end = a_end;
+        st->p_inside = hit_tot / ndraw;
+        st->oracle_calls = calls;
+        st->phases = phases;
+        for (int k = 0; k <= phases; ++k) {
+            double m = 0.0;
+            for (int g = 0; g < groups; ++g) m += gl[(size_t)g * (phases + 1) + k];
+            st->log_terms[k] = m / groups;
+        }
+    }
     return SPEC_OK;
 }
 

@@ -78,6 +78,81 @@ __global__ __launch_bounds__(256) void k_walk_init(WalkArgs a, const double* __r
     if (a.steps > 0) begin_step(a, c, 0, lane);
 }
 
+// Continue chains that finished an earlier call's steps: a.steps is larger now.
+__global__ __launch_bounds__(256) void k_walk_resume(WalkArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= a.chains) return;
+    const WalkState& S = a.st;
+    const long long k = S.step[c];
+    if (S.active[c] || k >= a.steps) return;
+    if (lane == 0) S.active[c] = 1;
+    begin_step(a, c, k, lane);
+}
+
+// Exact draws from N(0, sd^2 I): point q = g * per_group + k uses normals
+// 2d, 2d+1 of the stream (chain g, step k, tag TAG_GAUSS0).
+__global__ void k_gauss_points(int count, int per_group, int n, uint64_t seed, double sd, double* __restrict__ X) {
+    const int q = blockIdx.x;
+    if (q >= count) return;
+    const uint32_t g = (uint32_t)(q / per_group), k = (uint32_t)(q % per_group);
+    for (int d = threadIdx.x; 2 * d < n; d += blockDim.x) {
+        double g0, g1;
+        normal_pair(seed, g, k, (uint32_t)d, TAG_GAUSS0, g0, g1);
+        X[(size_t)q * n + 2 * d] = sd * g0;
+        if (2 * d + 1 < n) X[(size_t)q * n + 2 * d + 1] = sd * g1;
+    }
+}
+
+// Per group (block g): log of the mean of exp(da |x|^2) over the samples of
+// the group's chains (chains [g cpg, (g+1) cpg), nsamp samples each), and the
+// membership hit count of the exact draws of the group.
+__global__ __launch_bounds__(256) void k_phase_lse(int cpg, int nsamp, int n, const double* __restrict__ samples,
+                                                   double da, double* __restrict__ out) {
+    __shared__ double red[8];
+    const int g = blockIdx.x, t = threadIdx.x;
+    const int cnt = cpg * nsamp;
+    const double* base = samples + (size_t)g * cpg * nsamp * n;
+    double mx = -INFINITY;
+    for (int e = t; e < cnt; e += blockDim.x) {
+        const double* x = base + (size_t)e * n;
+        double r2 = 0.0;
+        for (int i = 0; i < n; ++i) r2 += x[i] * x[i];
+        mx = fmax(mx, da * r2);
+    }
+    mx = wave_max(mx);
+    if ((t & 63) == 0) red[t >> 6] = mx;
+    __syncthreads();
+    mx = -INFINITY;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, red[w]);
+    __syncthreads();
+    double sm = 0.0;
+    for (int e = t; e < cnt; e += blockDim.x) {
+        const double* x = base + (size_t)e * n;
+        double r2 = 0.0;
+        for (int i = 0; i < n; ++i) r2 += x[i] * x[i];
+        sm += exp(da * r2 - mx);
+    }
+    sm = block_sum(sm, red);
+    if (t == 0) out[g] = mx + log(sm) - log((double)cnt);
+}
+
+__global__ void k_count_groups(int groups, int per_group, const int8_t* __restrict__ flag, double* __restrict__ out) {
+    const int g = blockIdx.x;
+    if (g >= groups) return;
+    int c = 0;
+    for (int k = threadIdx.x; k < per_group; k += blockDim.x) c += flag[(size_t)g * per_group + k] != 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    __shared__ int red[16];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
+        out[g] = (double)tot;
+    }
+}
+
 // Truncated normal N(mu, sig^2) on [lo, hi] by inverting the CDF with u.
 __device__ inline double trunc_normal_at(double mu, double sig, double lo, double hi, double u) {
     const double al = (lo - mu) / sig, be = (hi - mu) / sig;
@@ -109,9 +184,11 @@ __device__ inline void end_step(const WalkArgs& a, int c, int lane) {
     for (int i = lane; i < n; i += 64) S.xs[(size_t)c * n + i] = S.x[(size_t)c * n + i];
     const long long k = S.step[c] + 1;
     if (a.samples && a.thin > 0 && k % a.thin == 0) {
-        const long long j = k / a.thin - 1;
-        double* dst = a.samples + ((size_t)c * a.nsamp + j) * n;
-        for (int i = lane; i < n; i += 64) dst[i] = S.x[(size_t)c * n + i];
+        const long long j = k / a.thin - 1 - a.samp_first;
+        if (j >= 0 && j < a.nsamp) {
+            double* dst = a.samples + ((size_t)c * a.nsamp + j) * n;
+            for (int i = lane; i < n; i += 64) dst[i] = S.x[(size_t)c * n + i];
+        }
     }
     if (lane == 0) {
         S.step[c] = k;
@@ -267,6 +344,24 @@ hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s) {
 }
 hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s) {
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, s, chains, active, out);
+    return hipGetLastError();
+}
+hipError_t walk_resume(const WalkArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_walk_resume, dim3((a.chains + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double sd, double* X, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gauss_points, dim3(count), dim3(64), 0, s, count, per_group, n, seed, sd, X);
+    return hipGetLastError();
+}
+hipError_t phase_lse(int groups, int cpg, int nsamp, int n, const double* samples, double da, double* out,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_phase_lse, dim3(groups), dim3(256), 0, s, cpg, nsamp, n, samples, da, out);
+    return hipGetLastError();
+}
+hipError_t count_groups(int groups, int per_group, const int8_t* flag, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_groups, dim3(groups), dim3(256), 0, s, groups, per_group, flag, out);
     return hipGetLastError();
 }
 hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStream_t s) {

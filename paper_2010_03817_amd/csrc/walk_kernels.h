@@ -36,8 +36,8 @@ struct WalkArgs {
     const double* Astk;
     int ldA, P;
     // samples and logging
-    double* samples;   // chains x nsamp x n (nullable)
-    long long nsamp;
+    double* samples;   // chains x nsamp x n (nullable): samples samp_first .. samp_first + nsamp - 1
+    long long nsamp, samp_first;
     int thin;
     double* log_buf;   // log_cap records of (x, v, t-, t+, chain, status)
     int32_t* log_count;
@@ -49,5 +49,12 @@ hipError_t walk_update(const WalkArgs& a, hipStream_t s);
 hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s);
 hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s);
 hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStream_t s);
+hipError_t walk_resume(const WalkArgs& a, hipStream_t s);
+// Volume helpers: exact Gaussian draws, per-group log-mean-exp of a phase,
+// per-group membership counts.
+hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double sd, double* X, hipStream_t s);
+hipError_t phase_lse(int groups, int cpg, int nsamp, int n, const double* samples, double da, double* out,
+                     hipStream_t s);
+hipError_t count_groups(int groups, int per_group, const int8_t* flag, double* out, hipStream_t s);
 
 }  // namespace spec

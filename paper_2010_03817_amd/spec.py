@@ -41,6 +41,16 @@ class WalkStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class VolumeParams(C.Structure):
+    _fields_ = [("phases", C.c_int), ("samples_per_phase", C.c_int), ("chains", C.c_int), ("walk_len", C.c_int),
+                ("groups", C.c_int), ("a0", C.c_double), ("a_end", C.c_double)]
+
+
+class VolumeStats(C.Structure):
+    _fields_ = [("a0", C.c_double), ("a_end", C.c_double), ("p_inside", C.c_double), ("oracle_calls", C.c_double),
+                ("phases", C.c_int), ("log_terms", C.c_double * 65)]
+
+
 class MlpTrainParams(C.Structure):
     _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("lr_final", C.c_double),
                 ("val_frac", C.c_double), ("quantile", C.c_double), ("seed", C.c_uint64)]
@@ -117,6 +127,8 @@ def lib():
                                      C.POINTER(MlpTrainStats), vp]
     L.spec_mlp_predict_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     L.spec_set_mlp.argtypes = [vp, vp, C.c_double, C.c_int]
+    L.spec_volume_estimate.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(VolumeStats), vp]
     L.spec_tune_mlp_delta_dev.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, C.POINTER(C.c_double),
                                           vp]
     for name in declared_symbols():
@@ -268,6 +280,19 @@ class Spectrahedron:
         out = np.zeros((batch, 16), dtype=np.int64)
         check(lib().spec_diag_phase_stamps(self._h, batch, out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def volume(self, phases=20, samples_per_phase=2000, chains=64, walk_len=10, groups=8, a0=0.0, a_end=0.0,
+               seed=1):
+        """Gaussian-cooling volume estimate: (log vol, ci_lo, ci_hi, stats)."""
+        p = VolumeParams(phases=phases, samples_per_phase=samples_per_phase, chains=chains, walk_len=walk_len,
+                         groups=groups, a0=a0, a_end=a_end)
+        lv, lo, hi = C.c_double(), C.c_double(), C.c_double()
+        st = VolumeStats()
+        check(lib().spec_volume_estimate(self._h, C.byref(p), int(seed), C.byref(lv), C.byref(lo), C.byref(hi),
+                                         C.byref(st), _stream()))
+        d = {"a0": st.a0, "a_end": st.a_end, "p_inside": st.p_inside, "oracle_calls": st.oracle_calls,
+             "log_terms": list(st.log_terms[:st.phases + 1])}
+        return lv.value, lo.value, hi.value, d
 
     def set_mlp(self, net, delta=0.0, mode=1):
         """Attach a trained Mlp (learned bracket for reflect and billiard walks);

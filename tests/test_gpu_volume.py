@@ -1,0 +1,76 @@
+"""GPU tests of the Gaussian-cooling volume estimate against known volumes and
+the oracle's own estimate, and of the walk's resume semantics it relies on."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2010_03817_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2010_03817_amd import spec
+    return spec
+
+
+def _check(lv, lo, hi, truth):
+    w = hi - lo
+    assert w > 0
+    assert lo - 0.5 * w <= truth <= hi + 0.5 * w, (lv, lo, hi, truth)
+
+
+def test_resume_continues_the_same_chains(S):
+    """Two calls (10 steps, then resumed to 20) equal one 20-step call: same
+    counter-based random streams, samples at the same indices."""
+    inst = I.gbase(10, 10, seed=101, scale=math.sqrt(10))
+    g = S.Spectrahedron(inst)
+    x0 = np.zeros((8, 10))
+    xa, sa, _, _ = g.walk(S.HNR, x0, 20, seed=5, gauss_a=0.3, thin=5)
+    g2 = S.Spectrahedron(inst)
+    g2.walk(S.HNR, x0, 10, seed=5, gauss_a=0.3, thin=5)
+    xb, sb, st, _ = g2.walk(S.HNR, x0, 20, seed=5, gauss_a=0.3, thin=5, resume=True)
+    assert st["calls"] == 8 * 10
+    assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+    assert np.array_equal(sa.cpu().numpy()[:, 2:], sb.cpu().numpy()[:, 2:])
+
+
+@pytest.mark.parametrize("which", ["ball10", "elliptope", "box5"])
+def test_volume_known_bodies(S, which):
+    if which == "ball10":
+        n = 10
+        inst = I.arrow_ball(n)
+        truth = 5 * math.log(math.pi) - math.log(120.0)
+    elif which == "elliptope":
+        inst = I.elliptope3()
+        truth = math.log(math.pi ** 2 / 2)
+    else:
+        inst = I.box(5, 1.0)
+        truth = 5 * math.log(2.0)
+    g = S.Spectrahedron(inst)
+    lv, lo, hi, st = g.volume(phases=20, samples_per_phase=2000, chains=64, walk_len=5, groups=8, seed=17)
+    print(which, lv, lo, hi, truth, st["a0"], st["a_end"], st["p_inside"])
+    assert 0.5 <= st["p_inside"] <= 0.9
+    _check(lv, lo, hi, truth)
+
+
+def test_volume_agrees_with_oracle(S):
+    n = 6
+    inst = I.arrow_ball(n)
+    truth = (n / 2) * math.log(math.pi) - math.lgamma(n / 2 + 1)
+    a0, a_end = 4.0 * n, 1.0 / 16.0
+    g = S.Spectrahedron(inst)
+    lv, lo, hi, st = g.volume(phases=20, samples_per_phase=1600, chains=32, walk_len=3, groups=8, a0=a0,
+                              a_end=a_end, seed=13)
+    o = O.Oracle(inst)
+    olv, olo, ohi, _ = o.volume(phases=20, samples_per_phase=1600, chains=32, walk_len=3, seed=13, a0=a0,
+                                a_end=a_end, groups=8)
+    print("gpu", lv, lo, hi, "oracle", olv, olo, ohi, "truth", truth)
+    # the exact-draw term is the same estimator on independent streams
+    assert abs(st["log_terms"][0] - (0.5 * n * math.log(math.pi / a0))) < 1.0
+    h1, h2 = 0.5 * (hi - lo), 0.5 * (ohi - olo)
+    assert abs(lv - olv) <= 1.5 * math.hypot(h1, h2) + 1e-3
+    _check(lv, lo, hi, truth)

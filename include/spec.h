@@ -123,6 +123,22 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
                              double* t_plus, double* s_out, double* w_out, int32_t* status,
                              void* stream);
 
+/* INTERSECTION for polynomial curves of degree 1 or 2 (Alg. INTERSECTION,
+ * Lemma "PEP and S cap C"): with Q_k = coef[e][k][0] A0 + sum_i
+ * coef[e][k][i] A_i (coef: batch x (degree+1) x (n+1), row-major), the first
+ * positive / negative roots of det(Q0 + t Q1 + t^2 Q2) within |t| <= horizon
+ * (+-INFINITY when there is none), i.e. the ends of the interval around 0 on
+ * which Q(t) stays positive definite.  Q0 must be positive definite
+ * (else NOT_INTERIOR, NaN outputs).  Dense blocks by certified Weyl steps:
+ * each step factors Q(tau) and bounds lambda_min of L^-1 Q'(tau) L^-T and of
+ * L^-1 Q2 L^-T from below (Lanczos Ritz value minus residual bound), so Q
+ * stays definite over the step; diagonal rows by their scalar quadratics.
+ * status[e]: OK, NOT_INTERIOR, NOCONV (an eigen solve did not converge). */
+spec_status spec_intersect_curve(spec_handle h, int batch, int degree, const double* coef, double horizon,
+                                 double* t_minus, double* t_plus, int32_t* status);
+spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const double* coef, double horizon,
+                                     double* t_minus, double* t_plus, int32_t* status, void* stream);
+
 /* Parameters of spec_walk_run (Section "Random walks").
  *  tau       billiard: step length ell = -tau ln(eta), eta ~ U(0,1) (Alg.
  *            Billiard; tau about the diameter); unused by Hit-and-Run
@@ -141,7 +157,8 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
  *            starting from x0; `steps` then counts from the original start
  *  log_chains, log_cap, log_buf, log_count   optional device log of the
  *            segments of chains c < log_chains: records of 2n+4 doubles
- *            (x, v, t-, t+, chain, status), log_count (device int32, zeroed
+ *            (x, v, t-, t+, chain, status) (HMC: (p, velocity, remaining travel time,
+ *            first root u+ of the segment's pencil, chain, status)), log_count (device int32, zeroed
  *            by the caller) counts the records attempted. */
 typedef struct {
     double tau;
@@ -173,7 +190,11 @@ typedef struct {
  * stats (nullable, host) the totals.  Device pointers; asynchronous on
  * `stream` except that it reads a device flag every 16 rounds to stop when
  * all chains are done (and synchronises at the end when stats is given).
- * Kinds HNR, CHNR, BILLIARD; SPEC_EINVAL for bad arguments. */
+ * Kinds HNR, CHNR, BILLIARD, HMC (Alg. HMC with reflections for the Gaussian
+ * target exp(-gauss_a |x|^2): travel time ell = tau eta, momentum N(0, I),
+ * exact elliptic flow, each segment a degree-2 curve solved as in
+ * spec_intersect_curve; gauss_a > 0 and tau > 0 required); SPEC_EINVAL for
+ * bad arguments. */
 spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps,
                               uint64_t seed, const spec_walk_params* p, double* x_out, double* samples,
                               spec_walk_stats* stats, void* stream);

@@ -48,7 +48,7 @@ struct spec_s {
     spec_mlp_s* net = nullptr;
     double mdelta = 0.0;
     int lmode = 0;
-    double *dShift = nullptr, *dShiftHi = nullptr, *dPred = nullptr;
+    double *dShift = nullptr, *dShiftHi = nullptr, *dPred = nullptr, *dHz = nullptr;
     // walk state
     int wcap = 0;
     double *wX = nullptr, *wXs = nullptr, *wV = nullptr, *wEll = nullptr, *wStats = nullptr, *wSum = nullptr;
@@ -58,7 +58,7 @@ struct spec_s {
     void free_work() {
         dfree(dZ); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
-        dfree(dShift); dfree(dShiftHi); dfree(dPred);
+        dfree(dShift); dfree(dShiftHi); dfree(dPred); dfree(dHz);
         cap = 0;
     }
     void free_walk() {
@@ -91,8 +91,8 @@ struct spec_s {
         if (batch <= cap) return SPEC_OK;
         free_work();
         const int c = round_up(batch, 64);
-        HIPCHK(dalloc(&dZ, (size_t)2 * c * Kpad));
-        HIPCHK(dalloc(&dFB, (size_t)2 * c * ldA, false));
+        HIPCHK(dalloc(&dZ, (size_t)3 * c * Kpad));
+        HIPCHK(dalloc(&dFB, (size_t)3 * c * ldA, false));
         HIPCHK(dalloc(&dQ, (size_t)c * ldq(), false));
         HIPCHK(dalloc(&dU, (size_t)c * m, false));
         HIPCHK(dalloc(&dU2, (size_t)c * ldA));
@@ -105,6 +105,7 @@ struct spec_s {
         HIPCHK(dalloc(&dShift, (size_t)c));
         HIPCHK(dalloc(&dShiftHi, (size_t)c));
         HIPCHK(dalloc(&dPred, (size_t)c));
+        HIPCHK(dalloc(&dHz, (size_t)c));
         cap = c;
         return SPEC_OK;
     }
@@ -193,6 +194,44 @@ spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, 
         if (h->lmode == 2) a.shift_hi = h->dShiftHi;
     }
     HIPCHK(launch_line_fused(a, batch, s));
+    mark(h, 3, s);
+    return SPEC_OK;
+}
+
+// Degree-2 curve round over `batch` curves whose coefficient rows (3 per curve)
+// are already in Z: assembly of Q0, Q1, Q2, then certified Weyl stepping.
+spec_status curve_oracle(spec_s* h, int batch, const double* horizon, double hscalar, double* tm, double* tp,
+                         int32_t* st, bool both, bool want_vec, int32_t* iters, hipStream_t s) {
+    const int bp = round_up(batch, 64);
+    mark(h, 0, s);
+    HIPCHK(gemm_f64(false, 3 * bp, h->ldA, h->Kpad, h->dZ, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA, s));
+    mark(h, 1, s);
+    mark(h, 2, s);
+    CurveArgs a{};
+    a.m = h->m;
+    a.md = h->md;
+    a.P = h->P;
+    a.kmax = h->kmax;
+    a.tol = h->tol;
+    a.FB = h->dFB;
+    a.ldfb = h->ldA;
+    a.brow0 = bp;
+    a.horizon = horizon;
+    a.hscalar = hscalar;
+    a.both = both ? 1 : 0;
+    a.want_vec = want_vec ? 1 : 0;
+    a.Q = h->dQ;
+    a.ldq = h->ldq();
+    a.status = st;
+    a.tm = tm;
+    a.tp = tp;
+    a.hit = h->dHit;
+    a.iters = iters;
+    a.u = h->dU;
+    a.ldu = h->m;
+    a.U2 = h->dU2;
+    a.ldu2 = h->ldA;
+    HIPCHK(launch_curve2(a, batch, s));
     mark(h, 3, s);
     return SPEC_OK;
 }
@@ -449,7 +488,40 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
     return reflect_tail(h, batch, v, t_plus, status, s_out, w_out, s);
 }
 
+spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const double* coef, double horizon,
+                                     double* t_minus, double* t_plus, int32_t* status, void* stream) {
+    if (!h || batch < 0 || (degree != 1 && degree != 2) || !(horizon > 0.0) ||
+        (batch && (!coef || !t_minus || !t_plus || !status)))
+        return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SPCHK(h->ensure(batch));
+    const int bp = round_up(batch, 64);
+    HIPCHK(launch_build_z_coef(batch, h->n, h->Kpad, degree + 1, coef, h->dZ, bp, s));
+    return curve_oracle(h, batch, nullptr, horizon, t_minus, t_plus, status, true, false, nullptr, s);
+}
+
 // ------------------------------------------------------------ host-pointer forms
+
+spec_status spec_intersect_curve(spec_handle h, int batch, int degree, const double* coef, double horizon,
+                                 double* t_minus, double* t_plus, int32_t* status) {
+    if (!h || batch < 0 || (degree != 1 && degree != 2) || (batch && (!coef || !t_minus || !t_plus || !status)))
+        return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    SPCHK(h->ensure_stage(batch));
+    const size_t nc = (size_t)batch * (degree + 1) * (h->n + 1);
+    double* dC = nullptr;
+    HIPCHK(dalloc(&dC, nc, false));
+    hipError_t e = hipMemcpy(dC, coef, sizeof(double) * nc, hipMemcpyHostToDevice);
+    spec_status rc = from_hip(e);
+    if (rc == SPEC_OK)
+        rc = spec_intersect_curve_dev(h, batch, degree, dC, horizon, h->sO1, h->sO2, h->sSt, nullptr);
+    if (rc == SPEC_OK) rc = from_hip(hipMemcpy(t_minus, h->sO1, sizeof(double) * batch, hipMemcpyDeviceToHost));
+    if (rc == SPEC_OK) rc = from_hip(hipMemcpy(t_plus, h->sO2, sizeof(double) * batch, hipMemcpyDeviceToHost));
+    if (rc == SPEC_OK) rc = from_hip(hipMemcpy(status, h->sSt, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
+    dfree(dC);
+    return rc;
+}
 
 spec_status spec_membership(spec_handle h, int batch, const double* x, int8_t* interior) {
     if (!h || batch < 0 || (batch && (!x || !interior))) return SPEC_EINVAL;
@@ -517,8 +589,10 @@ namespace {
 spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
                           const spec_walk_params* p, double* x_out, double* samples, long long samp_first,
                           long long nsamp, spec_walk_stats* stats, hipStream_t s) {
-    if (kind != SPEC_WALK_HNR && kind != SPEC_WALK_CHNR && kind != SPEC_WALK_BILLIARD) return SPEC_EINVAL;
-    if (kind == SPEC_WALK_BILLIARD && !(p->tau > 0.0)) return SPEC_EINVAL;
+    if (kind != SPEC_WALK_HNR && kind != SPEC_WALK_CHNR && kind != SPEC_WALK_BILLIARD && kind != SPEC_WALK_HMC)
+        return SPEC_EINVAL;
+    if ((kind == SPEC_WALK_BILLIARD || kind == SPEC_WALK_HMC) && !(p->tau > 0.0)) return SPEC_EINVAL;
+    if (kind == SPEC_WALK_HMC && !(p->gauss_a > 0.0)) return SPEC_EINVAL;
     if (p->gauss_a < 0.0 || !(p->pullback >= 0.0 && p->pullback < 1.0) || p->thin < 0) return SPEC_EINVAL;
     if (p->log_buf && (!p->log_count || p->log_cap < 0)) return SPEC_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -566,10 +640,16 @@ spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0,
     const bool billiard = kind == SPEC_WALK_BILLIARD;
     long long rounds = 0;
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
+    const bool hmc = kind == SPEC_WALK_HMC;
     while (rounds < max_rounds) {
-        SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard, billiard ? h->wEll : nullptr,
-                          s, billiard, billiard));
-        if (billiard) {
+        if (hmc) {
+            HIPCHK(walk_hmc_prep(a, h->dZ, round_up(chains, 64), h->Kpad, h->dHz, s));
+            SPCHK(curve_oracle(h, chains, h->dHz, INFINITY, h->dTm, h->dTp, h->dSt, false, true, nullptr, s));
+        } else {
+            SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard,
+                              billiard ? h->wEll : nullptr, s, billiard, billiard));
+        }
+        if (billiard || hmc) {
             const int bp = round_up(chains, 64);
             const int Kn = round_up(h->P, 16);
             if (h->m > 0)

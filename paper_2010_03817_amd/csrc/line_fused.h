@@ -31,6 +31,31 @@ struct FusedArgs {
     long long* prof;           // nullable: per chain 8 clock64 stamps of the phases
 };
 
+// Degree-2 curve oracle: first root of det Q(t), Q(t) = Q0 + t Q1 + t^2 Q2,
+// by certified Weyl stepping (internal launch interface).
+struct CurveArgs {
+    int m, md, P, kmax;
+    double tol;
+    const double* FB;          // rows c, brow0 + c, 2 brow0 + c: Q0, Q1, Q2 of chain c (packed + diagonal rows)
+    int ldfb, brow0;
+    const double* horizon;     // nullable: per-chain horizon (else hscalar)
+    double hscalar;
+    int both;                  // also the first negative root (t-)
+    int want_vec;              // form u and vec(u u^T) at a dense hit of the positive root
+    double* Q;                 // per chain Lanczos basis (kmax x m), ld ldq
+    size_t ldq;
+    int32_t* status;
+    double* tm;
+    double* tp;
+    int32_t* hit;              // HIT_DENSE, a diagonal row, or HIT_NONE
+    int32_t* iters;            // nullable: Weyl steps (both directions)
+    double* u;
+    int ldu;
+    double* U2;
+    int ldu2;
+};
+hipError_t launch_curve2(const CurveArgs& a, int nblocks, hipStream_t s);
+
 size_t fused_lds_bytes(int m, int kmax);
 int fused_threads(int m);
 hipError_t launch_line_fused(const FusedArgs& a, int nblocks, hipStream_t s);

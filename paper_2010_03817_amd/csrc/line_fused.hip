@@ -157,7 +157,9 @@ __device__ __forceinline__ void dense_trinv16(double* T, int lane) {
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
 __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* flag) {
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
+    const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int T = (m + 15) / 16;
     for (int K = 0; K < T; ++K) {
         if (wv == 0) {
@@ -203,7 +205,9 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
 // In-place triangular inverse W = L^{-1} of the packed lower factor: column
 // blocks from the last one, W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) L_JJ^{-1}.
 __device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
+    const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int T = (m + 15) / 16;
     for (int J = T - 1; J >= 0; --J) {
         if (wv == 0) {
@@ -444,6 +448,321 @@ __device__ __forceinline__ double w_row(const double* L, const double* x, int r,
     return s0 + s1;
 }
 
+// Scratch layout of the Lanczos phase (after the factor phase).
+struct LzLayout {
+    double *slot, *al, *be, *red, *sres;
+};
+__device__ __forceinline__ LzLayout lz_layout(double* scr, int kmax) {
+    LzLayout o;
+    o.slot = scr;                 // 2 MAXH (zero past m)
+    o.al = scr + 2 * MAXH;        // kmax
+    o.be = o.al + kmax;           // kmax + 1
+    o.red = o.be + kmax + 1;      // 8
+    o.sres = o.red + 8;           // 8: theta_min, r_min, theta_max, r_max, stop, k, total steps
+    return o;
+}
+
+// The pencil of one Lanczos run: C = W B W^T with W = L^{-1} in LDS and
+// B = b0 B0 + b1 B1 (packed rows in HBM, B1 nullable).
+struct LzCtx {
+    int m, kmax, min_only, first_check;
+    double tol;
+    const double* B0;
+    double b0;
+    const double* B1;
+    double b1;
+    double* Qg;        // this chain's basis (kmax x m)
+    long long* prof;   // nullable: per-part cycles of the steering wave (slots 8..13)
+};
+
+// Extreme eigenvalue(s) of C by Lanczos (lambda_min only when min_only),
+// restarted from the Ritz vector after kmax steps, NCYCLES cycles at most.
+// Every thread of the block calls it.  Results in sres (LDS): theta_min,
+// r_min, theta_max, r_max, stop (1 converged, 2 not), steps of the last
+// cycle, total steps; al / be hold T_k of the last cycle and Qg its basis.
+// Wave 0 steers (Ritz values, residual bounds, stop decision); waves 1..
+// hold B and run the matrix-vector products.  Both run the same sequence
+// of barriers.
+__device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, const LzCtx& c) {
+    // the thread index is made opaque here so that lane addressing is formed
+    // per call, not hoisted (and kept live) across a caller's loop
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int lane = t & 63, wv = t >> 6;
+    const int m = c.m;
+    const int hm = (m + 1) >> 1;
+    const int tw = t - 64;
+    const int r = tw >> 1, h = tw & 1;
+    const bool worker = wv >= 1;
+    const bool own = worker && r < m;
+    const int c0 = h * hm;
+    const int kmax = c.kmax;
+    double* slot = scr;            // 2 MAXH (zero past m)
+    double* al = scr + 2 * MAXH;   // kmax
+    double* be = al + kmax;        // kmax + 1
+    double* red = be + kmax + 1;   // 8
+    double* sres = red + 8;        // 8: theta_min, r_min, theta_max, r_max, stop, k
+    double* Qg = c.Qg;
+    for (int e = m + t; e < 2 * MAXH; e += blockDim.x) slot[e] = 0.0;
+    const int R0w = 32 * (wv - 1);  // first column of this worker wave in W^T x
+    // start vector (deterministic, positive)
+    double qr = 0.0;
+    if (own) {
+        u4 hsh = philox10(u4{(uint32_t)r, 0x5eedu, 0u, 0x51a7u}, 0x2010u, 0x3817u);
+        qr = 0.5 + (double)(hsh.x >> 11) * (1.0 / 2097152.0);
+    }
+    double nq = block_sum_lds((own && h == 0) ? qr * qr : 0.0, red);
+    qr *= 1.0 / sqrt(nq);
+    if (worker) {
+        double breg[MAXH];
+#pragma unroll
+        for (int k = 0; k < MAXH; ++k) {
+            const int cc = c0 + k;
+            double v = 0.0;
+            if (own && k < hm && cc < m) {
+                const int e = cc <= r ? pk(r, cc) : pk(cc, r);
+                v = c.b0 * c.B0[e];
+                if (c.B1) v += c.b1 * c.B1[e];
+            }
+            breg[k] = v;
+        }
+        for (int cyc = 0;; ++cyc) {
+        double qprev = 0.0, bprev = 0.0;
+        for (int j = 0; j < kmax; ++j) {
+            if (own && h == 0) {
+                Qg[(size_t)j * m + r] = qr;
+                slot[r] = qr;
+            }
+            lds_barrier();  // B1
+            // a = W^T q, lanes (c, h) over row halves of the wave's band
+            double av = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
+            av += __shfl_xor(av, 1, 64);
+            lds_barrier();  // B2
+            if (own && h == 0) slot[r] = av;
+            lds_barrier();  // B3
+            // b = B a from registers
+            double bv = 0.0;
+            {
+                const double* sv = slot + c0;
+#pragma unroll
+                for (int kk = 0; kk < MAXH; kk += 4) {
+                    bv += breg[kk] * sv[kk];
+                    bv += breg[kk + 1] * sv[kk + 1];
+                    bv += breg[kk + 2] * sv[kk + 2];
+                    bv += breg[kk + 3] * sv[kk + 3];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            bv += __shfl_xor(bv, 1, 64);
+            lds_barrier();  // B4
+            if (own && h == 0) slot[r] = bv;
+            lds_barrier();  // B5
+            // c = W b
+            double cv = own ? w_row(L, slot, r, h) : 0.0;
+            cv += __shfl_xor(cv, 1, 64);
+            const double alj = wave_uniform(block_sum_lds((own && h == 0) ? qr * cv : 0.0, red));  // B6, B7
+            cv -= alj * qr + bprev * qprev;
+            const double bn = wave_uniform(sqrt(block_sum_lds((own && h == 0) ? cv * cv : 0.0, red)));  // B8, B9
+            lds_barrier();  // B10 (control wave stores alpha, beta)
+            lds_barrier();  // B11 (control wave decides)
+            if (sres[4] != 0.0) break;
+            qprev = qr;
+            qr = cv * (1.0 / bn);
+            bprev = bn;
+        }
+        if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
+        // not converged within kmax steps: restart from the Ritz vector(s)
+        __syncthreads();  // basis rows in HBM are read across lanes
+        {
+            const int kk = (int)sres[5];
+            double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, r) : 0.0;
+            if (!c.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, r);
+            const double nz = block_sum_lds((own && h == 0) ? zr * zr : 0.0, red);
+            qr = zr * (1.0 / sqrt(nz));
+        }
+        lds_barrier();
+        }
+    } else {
+        long long ph[6] = {0, 0, 0, 0, 0, 0};
+        if (lane == 0) sres[6] = 0.0;
+        for (int cyc = 0;; ++cyc) {
+        int next_check = c.first_check > 0 ? c.first_check : 4;
+        double prev_q = -1.0;
+        int prev_k = 0;
+        long long tprev = clock64();
+#define PHASE(i)                          \
+    {                                     \
+const long long tn = clock64();   \
+ph[i] += tn - tprev;              \
+tprev = tn;                       \
+    }
+        for (int j = 0; j < kmax; ++j) {
+            lds_barrier();  // B1
+            PHASE(0)
+            lds_barrier();  // B2
+            PHASE(1)
+            lds_barrier();  // B3
+            lds_barrier();  // B4
+            PHASE(2)
+            lds_barrier();  // B5
+            const double alj = block_sum_lds(0.0, red);           // B6, B7
+            PHASE(3)
+            const double bn = sqrt(block_sum_lds(0.0, red));      // B8, B9
+            if (lane == 0) {
+                al[j] = alj;
+                be[j + 1] = bn;
+            }
+            lds_barrier();  // B10
+            PHASE(4)
+            const int k = j + 1;
+            const bool exhausted = bn <= 1e-14 * fmax(fabs(al[0]), 1e-300);
+            const bool check = exhausted || k == kmax || k >= next_check;
+            double stop = 0.0;
+            if (check) {
+                // T_k into registers
+                const double aA = lane < k ? al[lane] : 0.0, aB = lane + 64 < k ? al[lane + 64] : 0.0;
+                const double bA = lane < k ? be[lane] : 0.0, bB = lane + 64 < k ? be[lane + 64] : 0.0;
+                const double bA1 = lane + 1 < k ? be[lane + 1] : 0.0, bB1 = lane + 65 < k ? be[lane + 65] : 0.0;
+                const double b2A = bA * bA, b2B = bB * bB;
+                const double rbA = bA != 0.0 ? 1.0 / bA : 0.0, rbB = bB != 0.0 ? 1.0 / bB : 0.0;
+                // Gershgorin interval of T_k (rows spread over the lanes)
+                double glo = INFINITY, ghi = -INFINITY;
+                if (lane < k) {
+                    const double rad = (lane ? fabs(bA) : 0.0) + fabs(bA1);
+                    glo = aA - rad;
+                    ghi = aA + rad;
+                }
+                if (lane + 64 < k) {
+                    const double rad = fabs(bB) + fabs(bB1);
+                    glo = fmin(glo, aB - rad);
+                    ghi = fmax(ghi, aB + rad);
+                }
+                glo = wave_min(glo);
+                ghi = wave_max(ghi);
+                const double pad = 1e-14 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
+                glo -= pad;
+                ghi += pad;
+                // multisection: all lanes on lambda_min when only it is wanted, else
+                // lanes 0-31 on lambda_min and 32-63 on lambda_max
+                const int npts = c.min_only ? 64 : 32;
+                const bool want_min = c.min_only || lane < 32;
+                const int sub = c.min_only ? lane : (lane & 31);
+                double lo = glo, hi = ghi;
+#pragma nounroll
+                for (int it = 0; it < 12; ++it) {
+                    const double w = hi - lo;
+                    if (!(w > 2e-16 * fmax(fabs(lo), fabs(hi)))) break;
+                    const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
+                    const int cnt = sturm_reg(aA, aB, b2A, b2B, k, x);
+                    const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
+                    const unsigned long long mask = __ballot(hitp);
+                    unsigned long long hm;
+                    if (c.min_only) hm = mask;
+                    else hm = want_min ? (mask & 0xffffffffull) : (mask >> 32);
+                    const int first = hm ? __ffsll((long long)hm) - 1 : npts;
+                    const double nlo = lo + w * (double)first / (double)(npts + 1);
+                    const double nhi = first < npts ? lo + w * (double)(first + 1) / (double)(npts + 1) : hi;
+                    lo = nlo;
+                    hi = nhi;
+                }
+                const double th = 0.5 * (lo + hi);
+                const double res =
+                    exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
+                const int src_max = c.min_only ? 0 : 32;
+                if (lane == 0) {
+                    sres[0] = th;
+                    sres[1] = res;
+                }
+                if (lane == src_max) {
+                    sres[2] = c.min_only ? NAN : th;
+                    sres[3] = c.min_only ? 0.0 : res;
+                }
+                const double thmin = __shfl(th, 0, 64), thmax = __shfl(th, src_max, 64);
+                const double rmin = __shfl(res, 0, 64), rmax = __shfl(res, src_max, 64);
+                // residual bound below tol |theta|, or at the rounding level of C
+                // (scaled by the spectral radius: Gershgorin bound of T_k, which
+                // also covers lambda_max when only lambda_min is tracked)
+                const double rho = fmax(fmax(fabs(thmin), c.min_only ? 0.0 : fabs(thmax)),
+                                        fmax(fabs(glo), fabs(ghi)));
+                const double floor_r = 2.2e-14 * rho;
+                const double tmin = fmax(c.tol * fabs(thmin), floor_r);
+                const double tmax = fmax(c.tol * fabs(thmax), floor_r);
+                const bool cmin = rmin <= tmin;
+                const bool cmax = c.min_only || rmax <= tmax;
+                const bool conv_now = exhausted || (cmin && cmax);
+                if (conv_now) stop = 1.0;
+                else if (k == kmax) stop = 2.0;
+                // next test: where the residual decay since the last test predicts
+                // convergence (at least 2, at most 12 steps ahead)
+                double q = rmin / tmin;
+                if (!c.min_only) q = fmax(q, rmax / tmax);
+                int ahead = 4;
+                if (prev_q > 0.0 && q < prev_q && q > 1.0) {
+                    const double rate = log(q / prev_q) / (double)(k - prev_k);  // < 0
+                    ahead = (int)ceil(log(q) / -rate);
+                }
+                ahead = ahead < 2 ? 2 : (ahead > 12 ? 12 : ahead);
+                prev_q = q;
+                prev_k = k;
+                next_check = k + ahead;
+            } else if (k == kmax) {
+                stop = 2.0;
+            }
+            if (lane == 0) {
+                sres[4] = stop;
+                sres[5] = (double)k;
+                if (stop != 0.0) sres[6] += (double)k;
+            }
+            lds_barrier();  // B11
+            PHASE(5)
+            if (stop != 0.0) break;
+        }
+        if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
+        __syncthreads();
+        (void)block_sum_lds(0.0, red);
+        lds_barrier();
+        }
+#undef PHASE
+        if (c.prof && t == 0)
+            for (int i = 0; i < 6; ++i) c.prof[8 + i] = ph[i];
+    }
+}
+
+// Kernel vector of the pencil at its root: u = W^T z with z the Ritz vector
+// of lam from the last Lanczos run (k steps, basis Qg), written to u (m) and
+// the packed vec(u u^T) (off-diagonal entries doubled) to U2, the left
+// operand of the normal GEMM w_i = u^T A_i u.  Every thread calls it.
+__device__ __forceinline__ void ritz_u(const double* L, double* scr, int m, int kmax, int k, double lam,
+                                       const double* Qg, double* u, double* U2) {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
+    const int wv = t >> 6;
+    const int tw = t - 64;
+    const int r = tw >> 1, h = tw & 1;
+    const bool own = wv >= 1 && r < m;
+    const int R0w = 32 * (wv - 1);
+    const LzLayout lz = lz_layout(scr, kmax);
+    double* slot = lz.slot;
+    const double zr = own ? ritz_row(lz.al, lz.be, k, lam, Qg, m, r) : 0.0;
+    lds_barrier();
+    if (own && h == 0) slot[r] = zr;
+    lds_barrier();
+    double uv = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
+    uv += __shfl_xor(uv, 1, 64);
+    lds_barrier();
+    if (own && h == 0) {
+        u[r] = uv;
+        slot[r] = uv;
+    }
+    lds_barrier();
+    if (own) {
+        const double ur = slot[r];
+        const int half = (r + 2) >> 1;
+        const int kb = h == 0 ? 0 : half, ke = h == 0 ? half : r + 1;
+        for (int cc = kb; cc < ke; ++cc) U2[pk(r, cc)] = (cc == r ? 1.0 : 2.0) * ur * slot[cc];
+    }
+}
+
 __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
     extern __shared__ double lds[];
     const int m = a.m, P = a.P, md = a.md;
@@ -535,242 +854,33 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
         STAMP(3)
         if (!ok) st = SPEC_NOT_INTERIOR;
         if (ok && !a.membership_only) {
-            // Wave 0 steers (Ritz values, residual bounds, stop decision); waves
-            // 1.. hold B and run the matrix-vector products.  Both run the same
-            // sequence of barriers.
             const int hm = (m + 1) >> 1;
             const int tw = t - 64;
             const int r = tw >> 1, h = tw & 1;
-            const bool worker = wv >= 1;
-            const bool own = worker && r < m;
-            const int c0 = h * hm;
+            const bool own = wv >= 1 && r < m;
+            (void)hm;
             const int kmax = a.kmax;
-            double* slot = scr;            // 2 MAXH (zero past m)
-            double* al = scr + 2 * MAXH;   // kmax
-            double* be = al + kmax;        // kmax + 1
-            double* red = be + kmax + 1;   // 8
-            double* sres = red + 8;        // 8: theta_min, r_min, theta_max, r_max, stop, k
+            const LzLayout lz = lz_layout(scr, kmax);
+            double* slot = lz.slot;
+            double* al = lz.al;
+            double* be = lz.be;
+            double* sres = lz.sres;
             double* Qg = a.Q + (size_t)chain * a.ldq;
-            for (int e = m + t; e < 2 * MAXH; e += blockDim.x) slot[e] = 0.0;
             const int R0w = 32 * (wv - 1);  // first column of this worker wave in W^T x
-            // start vector (deterministic, positive)
-            double qr = 0.0;
-            if (own) {
-                u4 hsh = philox10(u4{(uint32_t)r, 0x5eedu, 0u, 0x51a7u}, 0x2010u, 0x3817u);
-                qr = 0.5 + (double)(hsh.x >> 11) * (1.0 / 2097152.0);
-            }
-            double nq = block_sum_lds((own && h == 0) ? qr * qr : 0.0, red);
-            qr *= 1.0 / sqrt(nq);
             STAMP(4)
-            if (worker) {
-                double breg[MAXH];
-#pragma unroll
-                for (int k = 0; k < MAXH; ++k) {
-                    const int c = c0 + k;
-                    double v = 0.0;
-                    if (own && k < hm && c < m) v = c <= r ? Br[pk(r, c)] : Br[pk(c, r)];
-                    breg[k] = v;
-                }
-                for (int cyc = 0;; ++cyc) {
-                double qprev = 0.0, bprev = 0.0;
-                for (int j = 0; j < kmax; ++j) {
-                    if (own && h == 0) {
-                        Qg[(size_t)j * m + r] = qr;
-                        slot[r] = qr;
-                    }
-                    lds_barrier();  // B1
-                    // a = W^T q, lanes (c, h) over row halves of the wave's band
-                    double av = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
-                    av += __shfl_xor(av, 1, 64);
-                    lds_barrier();  // B2
-                    if (own && h == 0) slot[r] = av;
-                    lds_barrier();  // B3
-                    // b = B a from registers
-                    double bv = 0.0;
-                    {
-                        const double* sv = slot + c0;
-#pragma unroll
-                        for (int kk = 0; kk < MAXH; kk += 4) {
-                            bv += breg[kk] * sv[kk];
-                            bv += breg[kk + 1] * sv[kk + 1];
-                            bv += breg[kk + 2] * sv[kk + 2];
-                            bv += breg[kk + 3] * sv[kk + 3];
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    }
-                    bv += __shfl_xor(bv, 1, 64);
-                    lds_barrier();  // B4
-                    if (own && h == 0) slot[r] = bv;
-                    lds_barrier();  // B5
-                    // c = W b
-                    double cv = own ? w_row(L, slot, r, h) : 0.0;
-                    cv += __shfl_xor(cv, 1, 64);
-                    const double alj = wave_uniform(block_sum_lds((own && h == 0) ? qr * cv : 0.0, red));  // B6, B7
-                    cv -= alj * qr + bprev * qprev;
-                    const double bn = wave_uniform(sqrt(block_sum_lds((own && h == 0) ? cv * cv : 0.0, red)));  // B8, B9
-                    lds_barrier();  // B10 (control wave stores alpha, beta)
-                    lds_barrier();  // B11 (control wave decides)
-                    if (sres[4] != 0.0) break;
-                    qprev = qr;
-                    qr = cv * (1.0 / bn);
-                    bprev = bn;
-                }
-                if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
-                // not converged within kmax steps: restart from the Ritz vector(s)
-                __syncthreads();  // basis rows in HBM are read across lanes
-                {
-                    const int kk = (int)sres[5];
-                    double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, r) : 0.0;
-                    if (!a.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, r);
-                    const double nz = block_sum_lds((own && h == 0) ? zr * zr : 0.0, red);
-                    qr = zr * (1.0 / sqrt(nz));
-                }
-                lds_barrier();
-                }
-            } else {
-                long long ph[6] = {0, 0, 0, 0, 0, 0};
-                if (lane == 0) sres[6] = 0.0;
-                for (int cyc = 0;; ++cyc) {
-                int next_check = a.first_check > 0 ? a.first_check : 4;
-                double prev_q = -1.0;
-                int prev_k = 0;
-                long long tprev = clock64();
-#define PHASE(i)                          \
-    {                                     \
-        const long long tn = clock64();   \
-        ph[i] += tn - tprev;              \
-        tprev = tn;                       \
-    }
-                for (int j = 0; j < kmax; ++j) {
-                    lds_barrier();  // B1
-                    PHASE(0)
-                    lds_barrier();  // B2
-                    PHASE(1)
-                    lds_barrier();  // B3
-                    lds_barrier();  // B4
-                    PHASE(2)
-                    lds_barrier();  // B5
-                    const double alj = block_sum_lds(0.0, red);           // B6, B7
-                    PHASE(3)
-                    const double bn = sqrt(block_sum_lds(0.0, red));      // B8, B9
-                    if (lane == 0) {
-                        al[j] = alj;
-                        be[j + 1] = bn;
-                    }
-                    lds_barrier();  // B10
-                    PHASE(4)
-                    const int k = j + 1;
-                    const bool exhausted = bn <= 1e-14 * fmax(fabs(al[0]), 1e-300);
-                    const bool check = exhausted || k == kmax || k >= next_check;
-                    double stop = 0.0;
-                    if (check) {
-                        // T_k into registers
-                        const double aA = lane < k ? al[lane] : 0.0, aB = lane + 64 < k ? al[lane + 64] : 0.0;
-                        const double bA = lane < k ? be[lane] : 0.0, bB = lane + 64 < k ? be[lane + 64] : 0.0;
-                        const double bA1 = lane + 1 < k ? be[lane + 1] : 0.0, bB1 = lane + 65 < k ? be[lane + 65] : 0.0;
-                        const double b2A = bA * bA, b2B = bB * bB;
-                        const double rbA = bA != 0.0 ? 1.0 / bA : 0.0, rbB = bB != 0.0 ? 1.0 / bB : 0.0;
-                        // Gershgorin interval of T_k (rows spread over the lanes)
-                        double glo = INFINITY, ghi = -INFINITY;
-                        if (lane < k) {
-                            const double rad = (lane ? fabs(bA) : 0.0) + fabs(bA1);
-                            glo = aA - rad;
-                            ghi = aA + rad;
-                        }
-                        if (lane + 64 < k) {
-                            const double rad = fabs(bB) + fabs(bB1);
-                            glo = fmin(glo, aB - rad);
-                            ghi = fmax(ghi, aB + rad);
-                        }
-                        glo = wave_min(glo);
-                        ghi = wave_max(ghi);
-                        const double pad = 1e-14 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
-                        glo -= pad;
-                        ghi += pad;
-                        // multisection: all lanes on lambda_min when only it is wanted, else
-                        // lanes 0-31 on lambda_min and 32-63 on lambda_max
-                        const int npts = a.min_only ? 64 : 32;
-                        const bool want_min = a.min_only || lane < 32;
-                        const int sub = a.min_only ? lane : (lane & 31);
-                        double lo = glo, hi = ghi;
-#pragma nounroll
-                        for (int it = 0; it < 12; ++it) {
-                            const double w = hi - lo;
-                            if (!(w > 2e-16 * fmax(fabs(lo), fabs(hi)))) break;
-                            const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
-                            const int cnt = sturm_reg(aA, aB, b2A, b2B, k, x);
-                            const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
-                            const unsigned long long mask = __ballot(hitp);
-                            unsigned long long hm;
-                            if (a.min_only) hm = mask;
-                            else hm = want_min ? (mask & 0xffffffffull) : (mask >> 32);
-                            const int first = hm ? __ffsll((long long)hm) - 1 : npts;
-                            const double nlo = lo + w * (double)first / (double)(npts + 1);
-                            const double nhi = first < npts ? lo + w * (double)(first + 1) / (double)(npts + 1) : hi;
-                            lo = nlo;
-                            hi = nhi;
-                        }
-                        const double th = 0.5 * (lo + hi);
-                        const double res =
-                            exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
-                        const int src_max = a.min_only ? 0 : 32;
-                        if (lane == 0) {
-                            sres[0] = th;
-                            sres[1] = res;
-                        }
-                        if (lane == src_max) {
-                            sres[2] = a.min_only ? NAN : th;
-                            sres[3] = a.min_only ? 0.0 : res;
-                        }
-                        const double thmin = __shfl(th, 0, 64), thmax = __shfl(th, src_max, 64);
-                        const double rmin = __shfl(res, 0, 64), rmax = __shfl(res, src_max, 64);
-                        // residual bound below tol |theta|, or at the rounding level of C
-                        // (scaled by the spectral radius: Gershgorin bound of T_k, which
-                        // also covers lambda_max when only lambda_min is tracked)
-                        const double rho = fmax(fmax(fabs(thmin), a.min_only ? 0.0 : fabs(thmax)),
-                                                fmax(fabs(glo), fabs(ghi)));
-                        const double floor_r = 2.2e-14 * rho;
-                        const double tmin = fmax(a.tol * fabs(thmin), floor_r);
-                        const double tmax = fmax(a.tol * fabs(thmax), floor_r);
-                        const bool cmin = rmin <= tmin;
-                        const bool cmax = a.min_only || rmax <= tmax;
-                        const bool conv_now = exhausted || (cmin && cmax);
-                        if (conv_now) stop = 1.0;
-                        else if (k == kmax) stop = 2.0;
-                        // next test: where the residual decay since the last test predicts
-                        // convergence (at least 2, at most 12 steps ahead)
-                        double q = rmin / tmin;
-                        if (!a.min_only) q = fmax(q, rmax / tmax);
-                        int ahead = 4;
-                        if (prev_q > 0.0 && q < prev_q && q > 1.0) {
-                            const double rate = log(q / prev_q) / (double)(k - prev_k);  // < 0
-                            ahead = (int)ceil(log(q) / -rate);
-                        }
-                        ahead = ahead < 2 ? 2 : (ahead > 12 ? 12 : ahead);
-                        prev_q = q;
-                        prev_k = k;
-                        next_check = k + ahead;
-                    } else if (k == kmax) {
-                        stop = 2.0;
-                    }
-                    if (lane == 0) {
-                        sres[4] = stop;
-                        sres[5] = (double)k;
-                        if (stop != 0.0) sres[6] += (double)k;
-                    }
-                    lds_barrier();  // B11
-                    PHASE(5)
-                    if (stop != 0.0) break;
-                }
-                if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
-                __syncthreads();
-                (void)block_sum_lds(0.0, red);
-                lds_barrier();
-                }
-#undef PHASE
-                if (prof && t == 0)
-                    for (int i = 0; i < 6; ++i) prof[8 + i] = ph[i];
-            }
+            LzCtx lc;
+            lc.m = m;
+            lc.kmax = kmax;
+            lc.min_only = a.min_only;
+            lc.first_check = a.first_check;
+            lc.tol = a.tol;
+            lc.B0 = Br;
+            lc.b0 = 1.0;
+            lc.B1 = nullptr;
+            lc.b1 = 0.0;
+            lc.Qg = Qg;
+            lc.prof = prof;
+            lanczos_extreme(L, scr, lc);
             __syncthreads();  // basis entries in HBM are read across lanes below
             STAMP(5)
             lmin = sres[0];
@@ -789,29 +899,8 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
                 hit = HIT_DENSE;
             }
             const bool need_vec = a.want_vec && hit == HIT_DENSE && isfinite(tp) && (a.ell == nullptr || tp < a.ell[chain]);
-            if (need_vec) {
-                // Ritz vector z = sum_j y_j q_j of lambda_min
-                const double zr = own ? ritz_row(al, be, k, lmin, Qg, m, r) : 0.0;
-                lds_barrier();
-                if (own && h == 0) slot[r] = zr;
-                lds_barrier();
-                // u = W^T z
-                double uv = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
-                uv += __shfl_xor(uv, 1, 64);
-                lds_barrier();
-                if (own && h == 0) {
-                    a.u[(size_t)chain * a.ldu + r] = uv;
-                    slot[r] = uv;
-                }
-                lds_barrier();
-                if (own) {
-                    double* U2 = a.U2 + (size_t)chain * a.ldu2;
-                    const double ur = slot[r];
-                    const int half = (r + 2) >> 1;
-                    const int kb = h == 0 ? 0 : half, ke = h == 0 ? half : r + 1;
-                    for (int cc = kb; cc < ke; ++cc) U2[pk(r, cc)] = (cc == r ? 1.0 : 2.0) * ur * slot[cc];
-                }
-            }
+            if (need_vec)
+                ritz_u(L, scr, m, kmax, k, lmin, Qg, a.u + (size_t)chain * a.ldu, a.U2 + (size_t)chain * a.ldu2);
         }
     }
     STAMP(6)
@@ -837,6 +926,197 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
         }
         a.status[chain] = st;
     }
+}
+
+// Smallest s > 0 with 1 + a s + b s^2 = 0 (+inf when there is none): the
+// root 2 / (-a + sqrt(a^2 - 4 b)) in the form without cancellation.
+__device__ __forceinline__ double first_root_q(double a, double b) {
+    if (b > 0.0 && !(a < 0.0)) return INFINITY;
+    const double disc = a * a - 4.0 * b;
+    if (disc < 0.0) return INFINITY;
+    const double den = -a + sqrt(disc);
+    return den > 0.0 ? 2.0 / den : INFINITY;
+}
+
+// One workgroup per chain, the thread and LDS shape of k_line_fused.  For the
+// dense block, certified Weyl stepping (the degree-2 case of Lemma "PEP and S
+// cap C"): at tau_k, L L^T = Q(tau_k), D1 = L^-1 (Q1 + 2 tau_k Q2) L^-T and
+// D2 = L^-1 Q2 L^-T; by Weyl's inequality lambda_min(Q(tau_k + s)) >= 0 while
+// 1 + d1 s + d2 s^2 > 0 with d1, d2 lower bounds of lambda_min(D1),
+// lambda_min(D2) (Ritz value minus residual bound), so tau_{k+1} = tau_k + s*
+// with s* that polynomial's first positive root.  Stop when the step falls
+// below 1e-15 tau, when the factor no longer exists (rounding level), or past
+// the horizon.  Diagonal rows: scalar quadratics.
+__global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
+    extern __shared__ double lds[];
+    const int m = a.m, P = a.P, md = a.md;
+    const int chain = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+    double* L = lds;
+    double* scr = lds + P;
+    int* sflag = (int*)(scr + 256);
+    double* rtp = scr + 264;
+    double* rtm = rtp + 8;
+    int* rj = (int*)(rtm + 8);
+    int* rbad = rj + 8;
+    const double* Q0 = a.FB + (size_t)chain * a.ldfb;
+    const double* Q1 = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
+    const double* Q2 = a.FB + (size_t)(2 * a.brow0 + chain) * a.ldfb;
+    const double hz = a.horizon ? a.horizon[chain] : a.hscalar;
+    int32_t st = SPEC_OK;
+
+    // ---- diagonal rows: first roots of q0 + q1 t + q2 t^2 on both sides
+    double dtp = INFINITY, dtm = INFINITY;  // dtm: distance on the negative side
+    int dj = -1, bad = 0;
+    for (int j = t; j < md; j += blockDim.x) {
+        const double q0 = Q0[P + j], q1 = Q1[P + j], q2 = Q2[P + j];
+        if (!(q0 > 0.0)) bad = 1;
+        const double sp = first_root_q(q1 / q0, q2 / q0);
+        if (sp <= hz && sp < dtp) { dtp = sp; dj = j; }
+        if (a.both) {
+            const double sm = first_root_q(-q1 / q0, q2 / q0);
+            if (sm <= hz) dtm = fmin(dtm, sm);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double otp = __shfl_xor(dtp, o, 64);
+        const int oj = __shfl_xor(dj, o, 64);
+        if (otp < dtp || (otp == dtp && oj >= 0 && (dj < 0 || oj < dj))) { dtp = otp; dj = oj; }
+        dtm = fmin(dtm, __shfl_xor(dtm, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if (lane == 0) { rtp[wv] = dtp; rtm[wv] = dtm; rj[wv] = dj; rbad[wv] = bad; }
+    lds_barrier();
+    dtp = INFINITY; dtm = INFINITY; dj = -1; bad = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (rtp[w] < dtp || (rtp[w] == dtp && rj[w] >= 0 && (dj < 0 || rj[w] < dj))) { dtp = rtp[w]; dj = rj[w]; }
+        dtm = fmin(dtm, rtm[w]);
+        bad |= rbad[w];
+    }
+    lds_barrier();
+    double tp = dtp, tmd = dtm;
+    int hit = dj >= 0 ? dj : HIT_NONE;
+    int iters = 0;
+    bool conv = true;
+
+    if (bad) st = SPEC_NOT_INTERIOR;
+    if (!bad && m > 0) {
+        const int kmax = a.kmax;
+        double* Qg = a.Q + (size_t)chain * a.ldq;
+        const LzLayout lz = lz_layout(scr, kmax);
+        for (int dir = 0; dir < (a.both ? 2 : 1) && st == SPEC_OK; ++dir) {
+            const double sg = dir == 0 ? 1.0 : -1.0;
+            const bool vec_dir = a.want_vec && dir == 0;
+            double tau = 0.0, tau_prev = 0.0, root = INFINITY;
+            bool vec_ok = false, backoff = false;
+            int rung = 0;
+            for (int it = 0; it < 210; ++it) {
+                ++iters;
+                for (int e = t; e < P; e += blockDim.x) L[e] = Q0[e] + tau * (sg * Q1[e] + tau * Q2[e]);
+                lds_barrier();
+                const bool ok = chol_blocked(L, m, scr, sflag);
+                lds_barrier();
+                if (!ok) {
+                    if (it == 0) {
+                        st = SPEC_NOT_INTERIOR;
+                        break;
+                    }
+                    // definiteness lost at the rounding level: the root is tau.  For the
+                    // kernel vector, factor just inside it: root (1 - delta) for delta =
+                    // 1e-12, 1e-10, 1e-8, 1e-6 (never below the last certified iterate)
+                    // until a factor exists; there the pencil's most negative
+                    // eigenvalue is isolated and its eigenvector is the kernel direction.
+                    if (!backoff) root = tau;
+                    if (!vec_dir || rung == 4) break;  // no factor next to the root: no kernel vector
+                    backoff = true;
+                    const double delta = rung == 0 ? 1e-12 : (rung == 1 ? 1e-10 : (rung == 2 ? 1e-8 : 1e-6));
+                    ++rung;
+                    tau = fmax(root * (1.0 - delta), tau_prev);
+                    continue;
+                }
+                tri_inverse(L, m, scr);
+                // lambda_min of D2, then of D1 (its basis stays for the kernel vector)
+                double d[2] = {0.0, 0.0};
+                for (int pass = backoff ? 1 : 0; pass < 2; ++pass) {
+                    LzCtx lc;
+                    lc.m = m;
+                    lc.kmax = kmax;
+                    lc.min_only = 1;
+                    lc.first_check = 0;
+                    lc.tol = a.tol;
+                    lc.B0 = pass == 0 ? Q2 : Q1;
+                    lc.b0 = pass == 0 ? 1.0 : sg;
+                    lc.B1 = pass == 0 ? nullptr : Q2;
+                    lc.b1 = pass == 0 ? 0.0 : 2.0 * tau;
+                    lc.Qg = Qg;
+                    lc.prof = nullptr;
+                    lanczos_extreme(L, scr, lc);
+                    __syncthreads();
+                    if (lz.sres[4] != 1.0) conv = false;
+                    d[pass] = lz.sres[0] - lz.sres[1];
+                    lds_barrier();
+                }
+                if (backoff) {
+                    vec_ok = true;
+                    break;
+                }
+                const double step = first_root_q(d[1], d[0]);
+                if (!(step < INFINITY)) break;
+                const double next = tau + step;
+                if (next > hz) break;
+                if (step <= 1e-15 * next) {
+                    root = next;
+                    vec_ok = true;
+                    break;
+                }
+                tau_prev = tau;
+                tau = next;
+            }
+            if (st != SPEC_OK) break;
+            if (dir == 0) {
+                if (root <= tp) {
+                    tp = root;
+                    hit = HIT_DENSE;
+                    if (a.want_vec && vec_ok) {
+                        __syncthreads();  // basis rows in HBM are read across lanes
+                        const double lam = lz.sres[0];
+                        ritz_u(L, scr, m, kmax, (int)lz.sres[5], lam, Qg, a.u + (size_t)chain * a.ldu,
+                               a.U2 + (size_t)chain * a.ldu2);
+                    } else if (a.want_vec) {
+                        // no factor at the last iterate: no kernel vector (zero normal)
+                        for (int e = t; e < P; e += blockDim.x) a.U2[(size_t)chain * a.ldu2 + e] = 0.0;
+                    }
+                }
+            } else {
+                tmd = fmin(tmd, root);
+            }
+            lds_barrier();
+        }
+    }
+    if (t == 0) {
+        double tm = -tmd;
+        if (st == SPEC_NOT_INTERIOR) {
+            tm = NAN;
+            tp = NAN;
+            hit = HIT_NONE;
+        } else if (!conv) {
+            st = SPEC_NOCONV;
+        }
+        if (!a.both && st != SPEC_NOT_INTERIOR) tm = NAN;
+        a.tm[chain] = tm;
+        a.tp[chain] = tp;
+        a.hit[chain] = isfinite(tp) ? hit : HIT_NONE;
+        a.status[chain] = st;
+        if (a.iters) a.iters[chain] = iters;
+    }
+}
+
+hipError_t launch_curve2(const CurveArgs& a, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    const size_t lds = fused_lds_bytes(a.m, a.kmax);
+    if (lds > 163840 || a.m > 2 * MAXH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_curve2, dim3(nblocks), dim3(fused_threads(a.m)), lds, s, a);
+    return hipGetLastError();
 }
 
 size_t fused_lds_bytes(int m, int kmax) {

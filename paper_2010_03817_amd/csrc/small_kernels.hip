@@ -31,6 +31,26 @@ hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const dou
     return hipGetLastError();
 }
 
+// Rows k * zrow0 + c (k < nrows) of Z from the coefficient rows
+// coef[c][k][0..n] of curve c, zero-padded to Kpad.
+__global__ void k_build_z_coef(int batch, int n, int Kpad, int nrows, const double* __restrict__ coef,
+                               double* __restrict__ Z, int zrow0) {
+    const int c = blockIdx.x;
+    if (c >= batch) return;
+    for (int k = 0; k < 3; ++k) {
+        double* z = Z + ((size_t)k * zrow0 + c) * Kpad;
+        for (int i = threadIdx.x; i < Kpad; i += blockDim.x)
+            z[i] = (k < nrows && i <= n) ? coef[((size_t)c * nrows + k) * (n + 1) + i] : 0.0;
+    }
+}
+
+hipError_t launch_build_z_coef(int batch, int n, int Kpad, int nrows, const double* coef, double* Z, int zrow0,
+                               hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_z_coef, dim3(batch), dim3(64), 0, s, batch, n, Kpad, nrows, coef, Z, zrow0);
+    return hipGetLastError();
+}
+
 // Reflection (Alg. REFLECTION): w from the normal GEMM (dense hit, Lemma
 // "Gradient of det F") or the hit row's coefficients (diagonal hit), oriented
 // outward, and s = v - 2 <v, w_hat> w_hat.  One wave per chain.

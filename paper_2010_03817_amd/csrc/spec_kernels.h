@@ -18,6 +18,10 @@ hipError_t mfma_probe(double* out, hipStream_t s);
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s);
 
+// Rows k * zrow0 + c, k = 0, 1, 2, of Z: coefficient rows of curve c
+// (nrows of them given, the rest zero), zero-padded to Kpad.
+hipError_t launch_build_z_coef(int batch, int n, int Kpad, int nrows, const double* coef, double* Z, int zrow0,
+                               hipStream_t s);
 struct ReflectArgs {
     int batch, n, m, P, md, ldA;
     const double* Astk;  // (rows) x ldA; row i+1 = A_i packed, diagonal part at column P

@@ -45,6 +45,9 @@ __device__ inline void begin_step(const WalkArgs& a, int c, long long step64, in
         int j = (int)floor(u0 * a.n);
         if (j >= a.n) j = a.n - 1;
         for (int i = lane; i < a.n; i += 64) v[i] = i == j ? 1.0 : 0.0;
+    } else if (a.kind == SPEC_WALK_HMC) {
+        // momentum v ~ N(0, I), not normalised (Alg. HMC with reflections)
+        for (int i = lane; i < a.n; i += 64) v[i] = dir_component(a.seed, (uint32_t)c, step, TAG_MOM, i);
     } else {
         random_unit_dir(a.seed, (uint32_t)c, step, TAG_DIR, a.n, v, lane);
     }
@@ -53,6 +56,10 @@ __device__ inline void begin_step(const WalkArgs& a, int c, long long step64, in
             double u0, u1;
             draw_u2(a.seed, (uint32_t)c, step, 0, TAG_LEN, u0, u1);
             S.ell[c] = -a.tau * log(u0);
+        } else if (a.kind == SPEC_WALK_HMC) {
+            double u0, u1;
+            draw_u2(a.seed, (uint32_t)c, step, 0, TAG_LEN, u0, u1);
+            S.ell[c] = a.tau * u0;  // travel time ell = tau eta, eta ~ U(0,1)
         } else {
             S.ell[c] = INFINITY;
         }
@@ -76,6 +83,47 @@ __global__ __launch_bounds__(256) void k_walk_init(WalkArgs a, const double* __r
         for (int k = 0; k < WALK_NSTAT; ++k) S.stats[(size_t)c * WALK_NSTAT + k] = 0.0;
     }
     if (a.steps > 0) begin_step(a, c, 0, lane);
+}
+
+// HMC-with-reflections trajectory for the Gaussian exp(-|x|^2 / (2 sigma^2)),
+// sigma^2 = 1 / (2 gauss_a): the Hamiltonian flow is the ellipse
+// Phi(theta) = p cos(theta) + sigma v sin(theta), theta = t / sigma, and with
+// u = tan(theta / 2),  (1 + u^2) F(Phi) = F(p) + u 2 sigma B(v) + u^2 F(-p),
+// a degree-2 pencil in u with the same roots.  A segment covers at most a
+// quarter turn (u <= 1).  This kernel writes the pencil's coefficient rows
+// [1, p], [0, 2 sigma v], [1, -p] and the horizon u_h = tan(theta_h / 2).
+__global__ __launch_bounds__(256) void k_hmc_prep(WalkArgs a, double* __restrict__ Z, int zrow0, int Kpad,
+                                                  double* __restrict__ horizon) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= a.chains) return;
+    const WalkState& S = a.st;
+    const int n = a.n;
+    const double sigma = 1.0 / sqrt(2.0 * a.gauss_a);
+    const double* x = S.x + (size_t)c * n;
+    const double* v = S.v + (size_t)c * n;
+    double* z0 = Z + (size_t)c * Kpad;
+    double* z1 = Z + (size_t)(zrow0 + c) * Kpad;
+    double* z2 = Z + (size_t)(2 * zrow0 + c) * Kpad;
+    for (int k = lane; k < Kpad; k += 64) {
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+        if (k == 0) {
+            r0 = 1.0;
+            r2 = 1.0;
+        } else if (k <= n) {
+            r0 = x[k - 1];
+            r1 = 2.0 * sigma * v[k - 1];
+            r2 = -x[k - 1];
+        }
+        z0[k] = r0;
+        z1[k] = r1;
+        z2[k] = r2;
+    }
+    if (lane == 0) {
+        const double half_pi = 1.5707963267948966;
+        const double th = fmin(S.ell[c] / sigma, half_pi);
+        horizon[c] = tan(0.5 * fmax(th, 0.0));
+    }
 }
 
 // Continue chains that finished an earlier call's steps: a.steps is larger now.
@@ -223,7 +271,8 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
                 rec[n + i] = v[i];
             }
             if (lane == 0) {
-                rec[2 * n] = tm;
+                // HMC segments log the remaining travel time in the t- slot
+                rec[2 * n] = a.kind == SPEC_WALK_HMC ? S.ell[c] : tm;
                 rec[2 * n + 1] = tp;
                 rec[2 * n + 2] = (double)c;
                 rec[2 * n + 3] = (double)status;
@@ -241,6 +290,68 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         if (lane == 0) st[3] += 1.0;
         for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
         end_step(a, c, lane);
+        return;
+    }
+    if (a.kind == SPEC_WALK_HMC) {
+        // one segment of the trajectory: up to the boundary (reflect) or the
+        // horizon (rotate), then continue while travel time is left
+        const double sigma = 1.0 / sqrt(2.0 * a.gauss_a);
+        const double half_pi = 1.5707963267948966;
+        const double ell = S.ell[c];
+        const double th_h = fmin(ell / sigma, half_pi);
+        const double us = tp;
+        double* xs_ = S.xs + (size_t)c * n;
+        (void)xs_;
+        if (!(us <= tan(0.5 * th_h)) || !isfinite(us)) {
+            const double cs = cos(th_h), sn = sin(th_h);
+            for (int i = lane; i < n; i += 64) {
+                const double pi_ = x[i], vi = v[i];
+                x[i] = pi_ * cs + sigma * vi * sn;
+                v[i] = -pi_ / sigma * sn + vi * cs;
+            }
+            const double rest = ell - sigma * th_h;
+            if (lane == 0) S.ell[c] = rest;
+            if (!(rest > 1e-13 * sigma)) end_step(a, c, lane);
+            return;
+        }
+        const double th = 2.0 * atan(us);
+        const double cs = cos(th), sn = sin(th);
+        // velocity at the hit point and the outward normal there
+        const int hit = a.hit[c];
+        double nn = 0.0, vw = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double vh = -x[i] / sigma * sn + v[i] * cs;
+            const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                               : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+            nn += wi * wi;
+            vw += wi * vh;
+        }
+        nn = wave_sum(nn);
+        vw = wave_sum(vw);
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        const double coef = 2.0 * vw * inv * inv;
+        const double thp = (1.0 - a.pullback) * th;
+        const double cp = cos(thp), sp = sin(thp);
+        for (int i = lane; i < n; i += 64) {
+            const double pi_ = x[i], vi = v[i];
+            const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                               : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+            const double vh = -pi_ / sigma * sn + vi * cs;
+            x[i] = pi_ * cp + sigma * vi * sp;
+            v[i] = vh - coef * wi;
+        }
+        const int nref = S.nref[c] + 1;
+        if (lane == 0) {
+            if (!(nn > 0.0) || status == SPEC_NONSMOOTH) st[4] += 1.0;
+            st[1] += 1.0;
+            S.ell[c] = ell - sigma * th;
+            S.nref[c] = nref;
+        }
+        if (nref > a.rho) {
+            if (lane == 0) st[2] += 1.0;
+            for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+            end_step(a, c, lane);
+        }
         return;
     }
     if (a.kind == SPEC_WALK_HNR || a.kind == SPEC_WALK_CHNR) {
@@ -344,6 +455,10 @@ hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s) {
 }
 hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s) {
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(1024), 0, s, chains, active, out);
+    return hipGetLastError();
+}
+hipError_t walk_hmc_prep(const WalkArgs& a, double* Z, int zrow0, int Kpad, double* horizon, hipStream_t s) {
+    hipLaunchKernelGGL(k_hmc_prep, dim3((a.chains + 3) / 4), dim3(256), 0, s, a, Z, zrow0, Kpad, horizon);
     return hipGetLastError();
 }
 hipError_t walk_resume(const WalkArgs& a, hipStream_t s) {

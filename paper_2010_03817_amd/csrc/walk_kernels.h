@@ -50,6 +50,8 @@ hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s);
 hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s);
 hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStream_t s);
 hipError_t walk_resume(const WalkArgs& a, hipStream_t s);
+// HMC: coefficient rows of the segment's degree-2 pencil into Z and horizons.
+hipError_t walk_hmc_prep(const WalkArgs& a, double* Z, int zrow0, int Kpad, double* horizon, hipStream_t s);
 // Volume helpers: exact Gaussian draws, per-group log-mean-exp of a phase,
 // per-group membership counts.
 hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double sd, double* X, hipStream_t s);

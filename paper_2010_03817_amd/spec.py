@@ -102,6 +102,8 @@ def lib():
     L.spec_reflect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.spec_membership.argtypes = [vp, C.c_int, vp, vp]
     L.spec_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+    L.spec_intersect_curve.argtypes = [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp, vp]
+    L.spec_intersect_curve_dev.argtypes = [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp, vp, vp]
     L.spec_reflect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
     L.spec_walk_run_dev.argtypes = [vp, C.c_int, C.c_int, vp, C.c_longlong, C.c_uint64, C.POINTER(WalkParams), vp,
                                     vp, C.POINTER(WalkStats), vp]
@@ -222,6 +224,19 @@ class Spectrahedron:
         tp = torch.empty_like(tm)
         st = torch.empty(B, dtype=torch.int32, device="cuda")
         check(lib().spec_intersect_dev(self._h, B, _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), _ptr(st), _stream()))
+        return tm, tp, st
+
+    def intersect_curve(self, coef, horizon=float("inf"), degree=2):
+        """First positive / negative roots of det(Q0 + t Q1 + t^2 Q2) within the
+        horizon; coef: batch x (degree+1) x (n+1)."""
+        torch = _torch()
+        coef = _f64(coef).reshape(-1, degree + 1, self.n + 1)
+        B = coef.shape[0]
+        tm = torch.empty(B, dtype=torch.float64, device="cuda")
+        tp = torch.empty_like(tm)
+        st = torch.empty(B, dtype=torch.int32, device="cuda")
+        check(lib().spec_intersect_curve_dev(self._h, B, degree, _ptr(coef), float(horizon), _ptr(tm), _ptr(tp),
+                                             _ptr(st), _stream()))
         return tm, tp, st
 
     def reflect(self, x, v):

@@ -238,6 +238,35 @@ spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uin
                                  double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Uneven batching: many spectrahedra (different n and m) whose chains run
+ * their oracle rounds together.  Each round assembles every instance's
+ * pencils, then runs the per-chain oracle of all instances by a launch
+ * strategy: 1 = one persistent launch whose workgroups take (instance, chain)
+ * items, largest dense blocks first, from an atomic counter (LDS sized for
+ * the largest m); 2 = one such launch per size class (m <= 64, m <= 128,
+ * larger), so that small instances run many workgroups per compute unit;
+ * 3 = one launch per instance.  0 = chosen by spec_batch_tune on first use.
+ * With use_graph, a round is captured once per walk phase into a HIP graph
+ * and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct spec_batch_s* spec_batch;
+
+/* A batch over `count` handles; they stay owned by the caller and must
+ * outlive the batch.  The batch has its own stream. */
+spec_status spec_batch_create(int count, const spec_handle* hs, spec_batch* out);
+spec_status spec_batch_destroy(spec_batch b);
+spec_status spec_batch_set_strategy(spec_batch b, int strategy, int use_graph);
+/* Time `rounds` uniform Hit-and-Run rounds of `chains` chains per instance
+ * with each strategy (ms per round into ms_out[3], nullable) and keep the
+ * fastest (*chosen, nullable).  The handles' walk state is overwritten. */
+spec_status spec_batch_tune(spec_batch b, int chains, int rounds, double* ms_out, int* chosen);
+/* spec_volume_estimate for every instance, all walks advancing together:
+ * log_vol, ci_lo, ci_hi: host arrays of `count`; oracle_calls (nullable):
+ * total over instances.  Synchronises. */
+spec_status spec_batch_volume(spec_batch b, const spec_volume_params* p, uint64_t seed, double* log_vol,
+                              double* ci_lo, double* ci_hi, double* oracle_calls);
+
+/* ------------------------------------------------------------------------
  * Learned boundary bracket.
  *
  * A small MLP maps (x, v) to predictions of (log t+, log(-t-)).  With a

@@ -571,6 +571,10 @@ namespace {
 spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
                           const spec_walk_params* p, double* x_out, double* samples, long long samp_first,
                           long long nsamp, spec_walk_stats* stats, hipStream_t s);
+WalkArgs make_walk_args(spec_handle h, int kind, int chains, long long steps, uint64_t seed,
+                        const spec_walk_params* p, double* samples, long long samp_first, long long nsamp);
+spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const spec_walk_params* p,
+                        double* x_out, spec_walk_stats* stats, hipStream_t s);
 
 }  // namespace
 
@@ -600,6 +604,14 @@ spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0,
     if (p->resume && chains > h->wcap) return SPEC_EINVAL;
     SPCHK(h->ensure(chains));
     SPCHK(h->ensure_walk(chains));
+    WalkArgs a = make_walk_args(h, kind, chains, steps, seed, p, samples, samp_first, nsamp);
+    if (!p->resume) HIPCHK(walk_init(a, x0, s));
+    else HIPCHK(walk_resume(a, s));
+    return walk_rounds(h, a, kind, chains, p, x_out, stats, s);
+}
+
+WalkArgs make_walk_args(spec_handle h, int kind, int chains, long long steps, uint64_t seed,
+                        const spec_walk_params* p, double* samples, long long samp_first, long long nsamp) {
     WalkArgs a{};
     a.kind = kind;
     a.chains = chains;
@@ -628,8 +640,11 @@ spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0,
     a.log_count = p->log_count;
     a.log_cap = p->log_cap;
     a.log_chains = p->log_chains;
-    if (!p->resume) HIPCHK(walk_init(a, x0, s));
-    else HIPCHK(walk_resume(a, s));
+    return a;
+}
+
+spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const spec_walk_params* p,
+                        double* x_out, spec_walk_stats* stats, hipStream_t s) {
     // totals at entry: a resumed call reports the counts of its own rounds
     double tot0[WALK_NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (stats && p->resume) {
@@ -746,6 +761,389 @@ double student_t975(int nu) {
 
 }  // namespace
 
+// A batch of spectrahedra whose oracle rounds run together (uneven n, m).
+struct spec_batch_s {
+    std::vector<spec_handle> hs;
+    hipStream_t stream = nullptr;
+    int strategy = 0;       // 0: tune on first use, 1: one persistent launch, 2: per size class, 3: per instance
+    bool use_graph = true;  // capture a round into a HIP graph and replay it
+    // plan for `chains` chains per instance
+    int chains = 0;
+    FusedArgs* dArgs = nullptr;
+    int2* dWork = nullptr;
+    int* dCounter = nullptr;
+    struct Cls { int off, count, max_m, kmax, nblocks; };
+    std::vector<Cls> all, classes;
+    void free_plan() {
+        dfree(dArgs);
+        dfree(dWork);
+        dfree(dCounter);
+        chains = 0;
+        all.clear();
+        classes.clear();
+    }
+};
+
+namespace {
+
+int persistent_blocks(int max_m, int kmax) {
+    const int per_cu = line_fused_multi_blocks_per_cu(max_m, kmax);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+
+// Work lists: every (instance, chain), the largest dense blocks first (the
+// longest items start first); classes split at m <= 64 and m <= 128.
+spec_status batch_plan(spec_batch_s* b, int chains) {
+    if (b->chains == chains) return SPEC_OK;
+    b->free_plan();
+    const int K = (int)b->hs.size();
+    std::vector<FusedArgs> args(K);
+    for (int i = 0; i < K; ++i) {
+        spec_handle h = b->hs[i];
+        SPCHK(h->ensure(chains));
+        SPCHK(h->ensure_walk(chains));
+        args[i] = fused_args(h, round_up(chains, 64), h->dSt, h->dTm, h->dTp, false, nullptr);
+    }
+    std::vector<int> order(K);
+    for (int i = 0; i < K; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->hs[x]->m > b->hs[y]->m; });
+    std::vector<int2> work;
+    work.reserve((size_t)K * chains);
+    auto cls_of = [&](int m) { return m <= 64 ? 2 : (m <= 128 ? 1 : 0); };
+    int off = 0;
+    for (int c = 0; c < 3; ++c) {
+        spec_batch_s::Cls k{off, 0, 0, 2, 0};
+        for (int i : order) {
+            spec_handle h = b->hs[i];
+            if (cls_of(h->m) != c) continue;
+            for (int ch = 0; ch < chains; ++ch) work.push_back(make_int2(i, ch));
+            k.count += chains;
+            k.max_m = std::max(k.max_m, h->m);
+            k.kmax = std::max(k.kmax, h->kmax);
+        }
+        if (k.count) {
+            k.nblocks = persistent_blocks(k.max_m, k.kmax);
+            b->classes.push_back(k);
+        }
+        off += k.count;
+    }
+    spec_batch_s::Cls a{0, (int)work.size(), 0, 2, 0};
+    for (auto& k : b->classes) {
+        a.max_m = std::max(a.max_m, k.max_m);
+        a.kmax = std::max(a.kmax, k.kmax);
+    }
+    a.nblocks = persistent_blocks(a.max_m, a.kmax);
+    b->all.push_back(a);
+    HIPCHK(dalloc(&b->dArgs, (size_t)K, false));
+    HIPCHK(dalloc(&b->dWork, work.size(), false));
+    HIPCHK(dalloc(&b->dCounter, 1));
+    HIPCHK(hipMemcpy(b->dArgs, args.data(), sizeof(FusedArgs) * K, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->dWork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
+    b->chains = chains;
+    return SPEC_OK;
+}
+
+// One oracle round of every instance's walk (line oracle, both ends) and the
+// walk update: per-instance assembly, the fused oracle by the batch's
+// strategy, per-instance update.
+spec_status batch_round(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, int strategy, hipStream_t s) {
+    const int K = (int)b->hs.size();
+    for (int i = 0; i < K; ++i) {
+        spec_handle h = b->hs[i];
+        int bp = 0;
+        SPCHK(assemble(h, chains, h->wX, h->wV, &bp, s));
+    }
+    if (strategy == 3 || K == 1) {
+        for (int i = 0; i < K; ++i) {
+            spec_handle h = b->hs[i];
+            FusedArgs a = fused_args(h, round_up(chains, 64), h->dSt, h->dTm, h->dTp, false, nullptr);
+            HIPCHK(launch_line_fused(a, chains, s));
+        }
+    } else {
+        const auto& list = strategy == 1 ? b->all : b->classes;
+        for (const auto& k : list)
+            HIPCHK(launch_line_fused_multi(b->dArgs, b->dWork + k.off, k.count, b->dCounter, k.max_m, k.kmax,
+                                           k.nblocks, s));
+    }
+    for (int i = 0; i < K; ++i) HIPCHK(walk_update(wa[i], s));
+    return SPEC_OK;
+}
+
+// `rounds` rounds, replayed from a captured graph when enabled.
+spec_status batch_rounds(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, int strategy, long long rounds,
+                         bool graph, hipStream_t s) {
+    if (rounds <= 0) return SPEC_OK;
+    if (!graph) {
+        for (long long r = 0; r < rounds; ++r) SPCHK(batch_round(b, wa, chains, strategy, s));
+        return SPEC_OK;
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    spec_status rc = batch_round(b, wa, chains, strategy, s);
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (rc != SPEC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    HIPCHK(ec);
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    for (long long r = 0; r < rounds && e == hipSuccess; ++r) e = hipGraphLaunch(ge, s);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    (void)hipGraphDestroy(g);
+    return from_hip(e);
+}
+
+spec_status batch_tune(spec_batch_s* b, int chains, int rounds, double* ms_out, int* chosen) {
+    hipStream_t s = b->stream;
+    SPCHK(batch_plan(b, chains));
+    const int K = (int)b->hs.size();
+    std::vector<WalkArgs> wa(K);
+    double* dZero = nullptr;
+    int nmax = 1;
+    for (auto h : b->hs) nmax = std::max(nmax, h->n);
+    HIPCHK(dalloc(&dZero, (size_t)chains * nmax));
+    spec_walk_params wp{};
+    wp.tau = 1.0;
+    wp.pullback = 1e-6;
+    for (int i = 0; i < K; ++i) {
+        wa[i] = make_walk_args(b->hs[i], SPEC_WALK_HNR, chains, (long long)1 << 40, 0x7E57ull, &wp, nullptr, 0, 0);
+        HIPCHK(walk_init(wa[i], dZero, s));
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = INFINITY;
+    int pick = 1;
+    spec_status rc = SPEC_OK;
+    for (int strat = 1; strat <= 3 && rc == SPEC_OK; ++strat) {
+        rc = batch_rounds(b, wa, chains, strat, 1, b->use_graph, s);  // warm-up
+        if (rc != SPEC_OK) break;
+        (void)hipEventRecord(e0, s);
+        rc = batch_rounds(b, wa, chains, strat, rounds, b->use_graph, s);
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (rc == SPEC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = SPEC_EDEVICE;
+        const double per = ms / rounds;
+        if (ms_out) ms_out[strat - 1] = per;
+        if (per < best) {
+            best = per;
+            pick = strat;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dfree(dZero);
+    if (rc != SPEC_OK) return rc;
+    b->strategy = pick;
+    if (chosen) *chosen = pick;
+    return SPEC_OK;
+}
+
+// Gaussian-cooling volume of K spectrahedra (see spec_volume_estimate), the
+// walks of all of them advancing together round by round.  b == nullptr:
+// plain per-instance rounds on `s` (K == 1).
+spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spec_volume_params* p, uint64_t seed,
+                        double* log_vol, double* ci_lo, double* ci_hi, spec_volume_stats* st, hipStream_t s) {
+    const int phases = p->phases > 0 ? p->phases : 20;
+    const int spp = p->samples_per_phase > 0 ? p->samples_per_phase : 2000;
+    const int chains = p->chains > 0 ? p->chains : 64;
+    const int walk_len = p->walk_len > 0 ? p->walk_len : 10;
+    const int groups = p->groups > 0 ? p->groups : 8;
+    if (phases > 64 || groups < 2 || chains % groups || spp < groups) return SPEC_EINVAL;
+    const double pi = 3.14159265358979323846;
+    const int spc = (spp + chains - 1) / chains;
+    const int ndraw = groups * spp;
+    const int prerun_chains = 64, prerun_steps = 20;
+    int nmax = 1;
+    for (int k = 0; k < K; ++k) nmax = std::max(nmax, hs[k]->n);
+    // shared scratch
+    double *dX = nullptr, *dOut = nullptr, *dZero = nullptr, *dXout = nullptr;
+    int8_t* dFlag = nullptr;
+    int32_t* dCnt = nullptr;
+    std::vector<double*> dSamp(K, nullptr);
+    auto cleanup = [&]() {
+        dfree(dX); dfree(dFlag); dfree(dOut); dfree(dZero); dfree(dXout); dfree(dCnt);
+        for (auto& q : dSamp) dfree(q);
+    };
+#define VCHK(expr)                                                  \
+    do {                                                            \
+        spec_status _r = (expr);                                    \
+        if (_r != SPEC_OK) { cleanup(); return _r; }                \
+    } while (0)
+#define VHIP(expr) VCHK(from_hip(expr))
+    VHIP(dalloc(&dX, (size_t)std::max(ndraw, prerun_chains * prerun_steps * 2) * (2 * nmax + 4), false));
+    VHIP(dalloc(&dFlag, (size_t)std::max(ndraw, 1024), false));
+    VHIP(dalloc(&dOut, (size_t)groups, false));
+    VHIP(dalloc(&dZero, (size_t)std::max(chains, prerun_chains) * nmax));
+    VHIP(dalloc(&dXout, (size_t)std::max(chains, prerun_chains) * nmax, false));
+    VHIP(dalloc(&dCnt, 1));
+    for (int k = 0; k < K; ++k) VHIP(dalloc(&dSamp[k], (size_t)chains * spc * hs[k]->n, false));
+    std::vector<double> a0v(K), aendv(K), pin(K), calls(K, 0.0);
+    std::vector<std::vector<double>> a(K, std::vector<double>(phases + 1));
+    std::vector<std::vector<double>> gl(K, std::vector<double>((size_t)groups * (phases + 1), 0.0));
+    // ---- per instance: schedule ends and the first integral
+    for (int k = 0; k < K; ++k) {
+        spec_handle h = hs[k];
+        const int n = h->n;
+        spec_walk_stats ws{};
+        double a_end = p->a_end;
+        if (!(a_end > 0.0)) {
+            spec_walk_params wp{};
+            wp.tau = 1.0;
+            wp.pullback = 1e-6;
+            wp.log_chains = prerun_chains;
+            wp.log_cap = prerun_chains * prerun_steps;
+            wp.log_buf = dX;
+            wp.log_count = dCnt;
+            VHIP(hipMemsetAsync(dCnt, 0, sizeof(int32_t), s));
+            VCHK(walk_run_impl(h, SPEC_WALK_HNR, prerun_chains, dZero, prerun_steps, seed ^ 0x5851F42D4C957F2Dull, &wp,
+                               dXout, nullptr, 0, 0, &ws, s));
+            calls[k] += ws.calls;
+            std::vector<double> lg((size_t)wp.log_cap * (2 * n + 4));
+            VHIP(hipMemcpyAsync(lg.data(), dX, sizeof(double) * lg.size(), hipMemcpyDeviceToHost, s));
+            VHIP(hipStreamSynchronize(s));
+            double d = 0.0;
+            for (int r = 0; r < wp.log_cap; ++r) {
+                const double tm = lg[(size_t)r * (2 * n + 4) + 2 * n], tp = lg[(size_t)r * (2 * n + 4) + 2 * n + 1];
+                if (std::isfinite(tm) && std::isfinite(tp)) d = std::max(d, tp - tm);
+            }
+            if (!(d > 0.0)) { cleanup(); return SPEC_UNBOUNDED; }
+            a_end = 1.0 / (4.0 * d * d);
+        }
+        auto inside = [&](double av, int cnt, uint64_t seed2, double* frac) -> spec_status {
+            const double sd = 1.0 / std::sqrt(2.0 * av);
+            HIPCHK(gauss_points(cnt, cnt, n, seed2, sd, dX, s));
+            SPCHK(spec_membership_dev(h, cnt, dX, dFlag, s));
+            double hits = 0.0;
+            HIPCHK(count_groups(1, cnt, dFlag, dOut, s));
+            HIPCHK(hipMemcpyAsync(&hits, dOut, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            *frac = hits / cnt;
+            return SPEC_OK;
+        };
+        double a0 = p->a0;
+        if (!(a0 > 0.0)) {
+            // the inside fraction grows with a0: bracket [lo, hi] with f(lo) < 0.5 and
+            // f(hi) > 0.9, then bisect in log a0 until 0.5 <= f <= 0.9
+            const uint64_t s2 = seed ^ 0xA0761D6478BD642Full;
+            double f = 0.0, lo = 0.0, hi = 0.0;
+            a0 = 64.0 * a_end;
+            for (int it = 0; it < 200; ++it) {
+                VCHK(inside(a0, 1024, s2, &f));
+                if (f >= 0.5 && f <= 0.9) break;
+                if (f < 0.5) lo = a0;
+                else hi = a0;
+                if (lo > 0.0 && hi > 0.0) a0 = std::sqrt(lo * hi);
+                else a0 = f < 0.5 ? 2.0 * a0 : 0.5 * a0;
+            }
+        }
+        if (!(a0 > a_end)) a0 = 2.0 * a_end;
+        a0v[k] = a0;
+        aendv[k] = a_end;
+        const double sd0 = 1.0 / std::sqrt(2.0 * a0);
+        VHIP(gauss_points(ndraw, spp, n, seed, sd0, dX, s));
+        VCHK(spec_membership_dev(h, ndraw, dX, dFlag, s));
+        VHIP(count_groups(groups, spp, dFlag, dOut, s));
+        std::vector<double> hits(groups);
+        VHIP(hipMemcpyAsync(hits.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
+        VHIP(hipStreamSynchronize(s));
+        double hit_tot = 0.0;
+        for (int g = 0; g < groups; ++g) {
+            if (!(hits[g] > 0.0)) { cleanup(); return SPEC_NOT_INTERIOR; }
+            hit_tot += hits[g];
+            gl[k][(size_t)g * (phases + 1)] = 0.5 * n * std::log(pi / a0) + std::log(hits[g] / spp);
+        }
+        pin[k] = hit_tot / ndraw;
+        for (int i = 0; i < phases; ++i)
+            a[k][i] = phases == 1 ? a0 : a0 * std::pow(a_end / a0, (double)i / (phases - 1));
+        a[k][phases] = 0.0;
+        VCHK(h->ensure(chains));
+        VCHK(h->ensure_walk(chains));
+    }
+    // ---- phases: Gaussian Hit-and-Run of every instance, rounds in lockstep
+    int strategy = 3;
+    bool graph = false;
+    if (b) {
+        VCHK(batch_plan(b, chains));
+        if (b->strategy == 0) VCHK(batch_tune(b, chains, 4, nullptr, nullptr));
+        strategy = b->strategy;
+        graph = b->use_graph;
+    }
+    std::vector<WalkArgs> wa(K);
+    for (int ph = 0; ph < phases; ++ph) {
+        const long long steps = (long long)(ph + 1) * spc * walk_len;
+        for (int k = 0; k < K; ++k) {
+            spec_walk_params wp{};
+            wp.tau = 1.0;
+            wp.pullback = 1e-6;
+            wp.gauss_a = a[k][ph];
+            wp.thin = walk_len;
+            wa[k] = make_walk_args(hs[k], SPEC_WALK_HNR, chains, steps, seed, &wp, dSamp[k], (long long)ph * spc, spc);
+            if (ph == 0) VHIP(walk_init(wa[k], dZero, s));
+            else VHIP(walk_resume(wa[k], s));
+        }
+        const long long rounds = (long long)spc * walk_len;  // Hit-and-Run: one step per round
+        if (b) {
+            VCHK(batch_rounds(b, wa, chains, strategy, rounds, graph, s));
+        } else {
+            spec_walk_params wp{};
+            wp.max_rounds = rounds;
+            spec_walk_stats ws{};
+            VCHK(walk_rounds(hs[0], wa[0], SPEC_WALK_HNR, chains, &wp, dXout, &ws, s));
+        }
+        for (int k = 0; k < K; ++k) {
+            calls[k] += (double)rounds * chains;
+            VHIP(phase_lse(groups, chains / groups, spc, hs[k]->n, dSamp[k], a[k][ph] - a[k][ph + 1], dOut, s));
+            std::vector<double> lse(groups);
+            VHIP(hipMemcpyAsync(lse.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
+            VHIP(hipStreamSynchronize(s));
+            for (int g = 0; g < groups; ++g) gl[k][(size_t)g * (phases + 1) + ph + 1] = lse[g];
+        }
+    }
+    cleanup();
+#undef VCHK
+#undef VHIP
+    // ---- combine per instance: mean of the groups' log-volumes, Student-t interval
+    const double tq = student_t975(groups - 1);
+    for (int k = 0; k < K; ++k) {
+        std::vector<double> lv(groups, 0.0);
+        double mean = 0.0;
+        for (int g = 0; g < groups; ++g) {
+            for (int i = 0; i <= phases; ++i) lv[g] += gl[k][(size_t)g * (phases + 1) + i];
+            mean += lv[g];
+        }
+        mean /= groups;
+        double var = 0.0;
+        for (int g = 0; g < groups; ++g) var += (lv[g] - mean) * (lv[g] - mean);
+        var /= (groups - 1);
+        const double half = tq * std::sqrt(var / groups);
+        log_vol[k] = mean;
+        if (ci_lo) ci_lo[k] = mean - half;
+        if (ci_hi) ci_hi[k] = mean + half;
+        if (st) {
+            spec_volume_stats& o = st[k];
+            std::memset(&o, 0, sizeof(o));
+            o.a0 = a0v[k];
+            o.a_end = aendv[k];
+            o.p_inside = pin[k];
+            o.oracle_calls = calls[k];
+            o.phases = phases;
+            for (int i = 0; i <= phases; ++i) {
+                double m = 0.0;
+                for (int g = 0; g < groups; ++g) m += gl[k][(size_t)g * (phases + 1) + i];
+                o.log_terms[i] = m / groups;
+            }
+        }
+    }
+    return SPEC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 // ------------------------------------------------------------ diagnostics
@@ -828,162 +1226,55 @@ spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out) {
 spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uint64_t seed, double* log_vol,
                                  double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream) {
     if (!h || !p || !log_vol) return SPEC_EINVAL;
-    const int phases = p->phases > 0 ? p->phases : 20;
-    const int spp = p->samples_per_phase > 0 ? p->samples_per_phase : 2000;
-    const int chains = p->chains > 0 ? p->chains : 64;
-    const int walk_len = p->walk_len > 0 ? p->walk_len : 10;
-    const int groups = p->groups > 0 ? p->groups : 8;
-    if (phases > 64 || groups < 2 || chains % groups || spp < groups) return SPEC_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    const int n = h->n;
-    const double pi = 3.14159265358979323846;
-    double* dX = nullptr;   // exact draws / pre-run log
-    int8_t* dFlag = nullptr;
-    double* dOut = nullptr;
-    double* dSamp = nullptr;
-    double* dZero = nullptr;
-    double* dXout = nullptr;
-    int32_t* dCnt = nullptr;
-    const int spc = (spp + chains - 1) / chains;
-    const int ndraw = groups * spp;
-    const int prerun_chains = 64, prerun_steps = 20;
-    auto cleanup = [&]() {
-        dfree(dX); dfree(dFlag); dfree(dOut); dfree(dSamp); dfree(dZero); dfree(dXout); dfree(dCnt);
-    };
-#define VCHK(expr)                                                  \
-    do {                                                            \
-        spec_status _r = (expr);                                    \
-        if (_r != SPEC_OK) { cleanup(); return _r; }                \
-    } while (0)
-#define VHIP(expr) VCHK(from_hip(expr))
-    VHIP(dalloc(&dX, (size_t)std::max(ndraw, prerun_chains * prerun_steps * 2) * (2 * n + 4), false));
-    VHIP(dalloc(&dFlag, (size_t)std::max(ndraw, 1024), false));
-    VHIP(dalloc(&dOut, (size_t)groups, false));
-    VHIP(dalloc(&dSamp, (size_t)chains * spc * n, false));
-    VHIP(dalloc(&dZero, (size_t)std::max(chains, prerun_chains) * n));
-    VHIP(dalloc(&dXout, (size_t)std::max(chains, prerun_chains) * n, false));
-    VHIP(dalloc(&dCnt, 1));
-    spec_walk_stats ws{};
-    double calls = 0.0;
-    // ---- schedule ends
-    double a_end = p->a_end;
-    if (!(a_end > 0.0)) {
-        spec_walk_params wp{};
-        wp.tau = 1.0;
-        wp.pullback = 1e-6;
-        wp.log_chains = prerun_chains;
-        wp.log_cap = prerun_chains * prerun_steps;
-        wp.log_buf = dX;
-        wp.log_count = dCnt;
-        VCHK(walk_run_impl(h, SPEC_WALK_HNR, prerun_chains, dZero, prerun_steps, seed ^ 0x5851F42D4C957F2Dull, &wp,
-                           dXout, nullptr, 0, 0, &ws, s));
-        calls += ws.calls;
-        std::vector<double> lg((size_t)wp.log_cap * (2 * n + 4));
-        VHIP(hipMemcpyAsync(lg.data(), dX, sizeof(double) * lg.size(), hipMemcpyDeviceToHost, s));
-        VHIP(hipStreamSynchronize(s));
-        double d = 0.0;
-        for (int r = 0; r < wp.log_cap; ++r) {
-            const double tm = lg[(size_t)r * (2 * n + 4) + 2 * n], tp = lg[(size_t)r * (2 * n + 4) + 2 * n + 1];
-            if (std::isfinite(tm) && std::isfinite(tp)) d = std::max(d, tp - tm);
-        }
-        if (!(d > 0.0)) { cleanup(); return SPEC_UNBOUNDED; }
-        a_end = 1.0 / (4.0 * d * d);
+    return volume_many(nullptr, &h, 1, p, seed, log_vol, ci_lo, ci_hi, st, (hipStream_t)stream);
+}
+
+spec_status spec_batch_create(int count, const spec_handle* hs, spec_batch* out) {
+    if (count < 1 || !hs || !out) return SPEC_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < count; ++i)
+        if (!hs[i]) return SPEC_EINVAL;
+    spec_batch_s* b = new spec_batch_s();
+    b->hs.assign(hs, hs + count);
+    if (hipStreamCreate(&b->stream) != hipSuccess) {
+        delete b;
+        return SPEC_EDEVICE;
     }
-    // fraction of N(0, I/(2a)) inside S from `cnt` exact draws (group 0 stream of seed2)
-    auto inside = [&](double a, int cnt, uint64_t seed2, double* frac) -> spec_status {
-        const double sd = 1.0 / std::sqrt(2.0 * a);
-        HIPCHK(gauss_points(cnt, cnt, n, seed2, sd, dX, s));
-        SPCHK(spec_membership_dev(h, cnt, dX, dFlag, s));
-        double hits = 0.0;
-        HIPCHK(count_groups(1, cnt, dFlag, dOut, s));
-        HIPCHK(hipMemcpyAsync(&hits, dOut, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        *frac = hits / cnt;
-        return SPEC_OK;
-    };
-    double a0 = p->a0;
-    if (!(a0 > 0.0)) {
-        // the inside fraction grows with a0: bracket [lo, hi] with f(lo) < 0.5 and
-        // f(hi) > 0.9, then bisect in log a0 until 0.5 <= f <= 0.9
-        const uint64_t s2 = seed ^ 0xA0761D6478BD642Full;
-        double f = 0.0, lo = 0.0, hi = 0.0;
-        a0 = 64.0 * a_end;
-        for (int it = 0; it < 200; ++it) {
-            VCHK(inside(a0, 1024, s2, &f));
-            if (f >= 0.5 && f <= 0.9) break;
-            if (f < 0.5) lo = a0;
-            else hi = a0;
-            if (lo > 0.0 && hi > 0.0) a0 = std::sqrt(lo * hi);
-            else a0 = f < 0.5 ? 2.0 * a0 : 0.5 * a0;
-        }
-    }
-    if (!(a0 > a_end)) a0 = 2.0 * a_end;
-    // ---- int_S f_0 per group: exact draws + membership
-    std::vector<double> gl((size_t)groups * (phases + 1), 0.0);
-    const double sd0 = 1.0 / std::sqrt(2.0 * a0);
-    VHIP(gauss_points(ndraw, spp, n, seed, sd0, dX, s));
-    VCHK(spec_membership_dev(h, ndraw, dX, dFlag, s));
-    VHIP(count_groups(groups, spp, dFlag, dOut, s));
-    std::vector<double> hits(groups);
-    VHIP(hipMemcpyAsync(hits.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
-    VHIP(hipStreamSynchronize(s));
-    double hit_tot = 0.0;
-    for (int g = 0; g < groups; ++g) {
-        if (!(hits[g] > 0.0)) { cleanup(); return SPEC_NOT_INTERIOR; }
-        hit_tot += hits[g];
-        gl[(size_t)g * (phases + 1)] = 0.5 * n * std::log(pi / a0) + std::log(hits[g] / spp);
-    }
-    // ---- phases: Gaussian Hit-and-Run targeting f_i, warm-started
-    std::vector<double> a(phases + 1);
-    for (int i = 0; i < phases; ++i) a[i] = phases == 1 ? a0 : a0 * std::pow(a_end / a0, (double)i / (phases - 1));
-    a[phases] = 0.0;
-    for (int ph = 0; ph < phases; ++ph) {
-        spec_walk_params wp{};
-        wp.tau = 1.0;
-        wp.pullback = 1e-6;
-        wp.gauss_a = a[ph];
-        wp.thin = walk_len;
-        wp.resume = ph > 0;
-        const long long steps = (long long)(ph + 1) * spc * walk_len;
-        VCHK(walk_run_impl(h, SPEC_WALK_HNR, chains, dZero, steps, seed, &wp, dXout, dSamp, (long long)ph * spc, spc,
-                           &ws, s));
-        calls += ws.calls;
-        VHIP(phase_lse(groups, chains / groups, spc, n, dSamp, a[ph] - a[ph + 1], dOut, s));
-        std::vector<double> lse(groups);
-        VHIP(hipMemcpyAsync(lse.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
-        VHIP(hipStreamSynchronize(s));
-        for (int g = 0; g < groups; ++g) gl[(size_t)g * (phases + 1) + ph + 1] = lse[g];
-    }
-    cleanup();
-#undef VCHK
-#undef VHIP
-    // ---- combine: mean of the groups' log-volumes, Student-t interval
-    std::vector<double> lv(groups, 0.0);
-    double mean = 0.0;
-    for (int g = 0; g < groups; ++g) {
-        for (int k = 0; k <= phases; ++k) lv[g] += gl[(size_t)g * (phases + 1) + k];
-        mean += lv[g];
-    }
-    mean /= groups;
-    double var = 0.0;
-    for (int g = 0; g < groups; ++g) var += (lv[g] - mean) * (lv[g] - mean);
-    var /= (groups - 1);
-    const double half = student_t975(groups - 1) * std::sqrt(var / groups);
-    *log_vol = mean;
-    if (ci_lo) *ci_lo = mean - half;
-    if (ci_hi) *ci_hi = mean + half;
-    if (st) {
-        std::memset(st, 0, sizeof(*st));
-        st->a0 = a0;
-        st->a_end = a_end;
-        st->p_inside = hit_tot / ndraw;
-        st->oracle_calls = calls;
-        st->phases = phases;
-        for (int k = 0; k <= phases; ++k) {
-            double m = 0.0;
-            for (int g = 0; g < groups; ++g) m += gl[(size_t)g * (phases + 1) + k];
-            st->log_terms[k] = m / groups;
-        }
+    *out = b;
+    return SPEC_OK;
+}
+
+spec_status spec_batch_destroy(spec_batch b) {
+    if (!b) return SPEC_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    b->free_plan();
+    (void)hipStreamDestroy(b->stream);
+    delete b;
+    return SPEC_OK;
+}
+
+spec_status spec_batch_set_strategy(spec_batch b, int strategy, int use_graph) {
+    if (!b || strategy < 0 || strategy > 3) return SPEC_EINVAL;
+    b->strategy = strategy;
+    b->use_graph = use_graph != 0;
+    return SPEC_OK;
+}
+
+spec_status spec_batch_tune(spec_batch b, int chains, int rounds, double* ms_out, int* chosen) {
+    if (!b || chains < 1 || rounds < 1) return SPEC_EINVAL;
+    return batch_tune(b, chains, rounds, ms_out, chosen);
+}
+
+spec_status spec_batch_volume(spec_batch b, const spec_volume_params* p, uint64_t seed, double* log_vol,
+                              double* ci_lo, double* ci_hi, double* oracle_calls) {
+    if (!b || !p || !log_vol) return SPEC_EINVAL;
+    const int K = (int)b->hs.size();
+    std::vector<spec_volume_stats> st(K);
+    SPCHK(volume_many(b, b->hs.data(), K, p, seed, log_vol, ci_lo, ci_hi, st.data(), b->stream));
+    if (oracle_calls) {
+        double c = 0.0;
+        for (auto& x : st) c += x.oracle_calls;
+        *oracle_calls = c;
     }
     return SPEC_OK;
 }

@@ -56,6 +56,16 @@ struct CurveArgs {
 };
 hipError_t launch_curve2(const CurveArgs& a, int nblocks, hipStream_t s);
 
+// Persistent launch over (instance, chain) items of several spectrahedra:
+// args[instance] as for launch_line_fused, work[i] = (instance, chain) in the
+// order items are to start, counter: one device int (reset by the launch),
+// LDS sized for max_m and kmax (the largest over the instances).
+hipError_t launch_line_fused_multi(const FusedArgs* args, const int2* work, int nwork, int* counter, int max_m,
+                                   int kmax, int nblocks, hipStream_t s);
+
+// Workgroups of the persistent launch resident per compute unit.
+int line_fused_multi_blocks_per_cu(int max_m, int kmax);
+
 size_t fused_lds_bytes(int m, int kmax);
 int fused_threads(int m);
 hipError_t launch_line_fused(const FusedArgs& a, int nblocks, hipStream_t s);

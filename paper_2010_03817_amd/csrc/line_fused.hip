@@ -763,10 +763,10 @@ __device__ __forceinline__ void ritz_u(const double* L, double* scr, int m, int 
     }
 }
 
-__global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
-    extern __shared__ double lds[];
+// One chain's line oracle (the body of k_line_fused); every thread of the
+// block calls it with the same arguments.
+__device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, double* lds) {
     const int m = a.m, P = a.P, md = a.md;
-    const int chain = a.idx ? a.idx[blockIdx.x] : (int)blockIdx.x;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     double* L = lds;
     double* scr = lds + P;  // scratch; layout depends on the phase
@@ -926,6 +926,57 @@ __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
         }
         a.status[chain] = st;
     }
+}
+
+__global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
+    extern __shared__ double lds[];
+    const int chain = a.idx ? a.idx[blockIdx.x] : (int)blockIdx.x;
+    line_fused_chain(a, chain, lds);
+}
+
+// Persistent form over many spectrahedra: workgroups take (instance, chain)
+// items from `work` in order (an atomic counter hands them out, so the
+// longest items, placed first, start first) until the list is exhausted.
+// The dynamic LDS is sized for the largest instance.
+__global__ __launch_bounds__(512) void k_line_fused_multi(const FusedArgs* __restrict__ args,
+                                                          const int2* __restrict__ work, int nwork,
+                                                          int* __restrict__ counter) {
+    extern __shared__ double lds[];
+    __shared__ int item;
+    for (;;) {
+        __syncthreads();  // the previous item is finished with LDS
+        if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = item;
+        if (it >= nwork) break;
+        const int2 w = work[it];
+        line_fused_chain(args[w.x], w.y, lds);
+    }
+}
+
+__global__ void k_zero_int(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+int line_fused_multi_blocks_per_cu(int max_m, int kmax) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_line_fused_multi),
+                                                     fused_threads(max_m), fused_lds_bytes(max_m, kmax)) !=
+        hipSuccess)
+        per_cu = 1;
+    return per_cu;
+}
+
+hipError_t launch_line_fused_multi(const FusedArgs* args, const int2* work, int nwork, int* counter, int max_m,
+                                   int kmax, int nblocks, hipStream_t s) {
+    if (nwork <= 0) return hipSuccess;
+    if (max_m > 2 * MAXH) return hipErrorInvalidValue;
+    const size_t lds = fused_lds_bytes(max_m, kmax);
+    if (lds > 163840 - 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, counter);
+    hipLaunchKernelGGL(k_line_fused_multi, dim3(nblocks), dim3(fused_threads(max_m)), lds, s, args, work, nwork,
+                       counter);
+    return hipGetLastError();
 }
 
 // Smallest s > 0 with 1 + a s + b s^2 = 0 (+inf when there is none): the

@@ -129,6 +129,11 @@ def lib():
                                      C.POINTER(MlpTrainStats), vp]
     L.spec_mlp_predict_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     L.spec_set_mlp.argtypes = [vp, vp, C.c_double, C.c_int]
+    L.spec_batch_create.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp)]
+    L.spec_batch_destroy.argtypes = [vp]
+    L.spec_batch_set_strategy.argtypes = [vp, C.c_int, C.c_int]
+    L.spec_batch_tune.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_int)]
+    L.spec_batch_volume.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, vp, vp, vp, C.POINTER(C.c_double)]
     L.spec_volume_estimate.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(VolumeStats), vp]
     L.spec_tune_mlp_delta_dev.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, C.POINTER(C.c_double),
@@ -336,6 +341,49 @@ class Spectrahedron:
         out = np.empty((batch, 4))
         check(lib().spec_diag_lanczos_info(self._h, batch, out.ctypes.data_as(C.c_void_p)))
         return out
+
+
+class Batch:
+    """Uneven batch of spectrahedra (include/spec.h, spec_batch_*)."""
+
+    def __init__(self, specs):
+        _torch()
+        self.specs = list(specs)
+        arr = (C.c_void_p * len(self.specs))(*[g._h.value for g in self.specs])
+        h = C.c_void_p()
+        check(lib().spec_batch_create(len(self.specs), arr, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spec_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_strategy(self, strategy, use_graph=True):
+        check(lib().spec_batch_set_strategy(self._h, int(strategy), int(bool(use_graph))))
+
+    def tune(self, chains=64, rounds=4):
+        ms = np.empty(3)
+        k = C.c_int()
+        check(lib().spec_batch_tune(self._h, int(chains), int(rounds), ms.ctypes.data_as(C.c_void_p), C.byref(k)))
+        return k.value, list(ms)
+
+    def volume(self, phases=20, samples_per_phase=2000, chains=64, walk_len=10, groups=8, a0=0.0, a_end=0.0,
+               seed=1):
+        K = len(self.specs)
+        p = VolumeParams(phases=phases, samples_per_phase=samples_per_phase, chains=chains, walk_len=walk_len,
+                         groups=groups, a0=a0, a_end=a_end)
+        lv, lo, hi = np.empty(K), np.empty(K), np.empty(K)
+        calls = C.c_double()
+        check(lib().spec_batch_volume(self._h, C.byref(p), int(seed), lv.ctypes.data_as(C.c_void_p),
+                                      lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p), C.byref(calls)))
+        return lv, lo, hi, calls.value
 
 
 class Mlp:

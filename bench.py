@@ -220,6 +220,51 @@ def train_learned(g, S, x0, tau, chains, rows_target, epochs, seed=77):
     return net, report
 
 
+def uneven_leg(S, I, samples_per_phase):
+    """256 spectrahedra, n and m log-uniform in [20, 200] (every 16th an arrow
+    ball of known volume), 64 chains each: launch strategy autotuned, oracle
+    round rate of the whole mixed batch, and a batched Gaussian-cooling
+    volume with the balls' errors against pi^(n/2) / Gamma(n/2 + 1)."""
+    rng = np.random.default_rng(104)
+    insts, balls = [], []
+    for k in range(256):
+        n = int(round(math.exp(rng.uniform(math.log(20), math.log(200)))))
+        m = int(round(math.exp(rng.uniform(math.log(20), math.log(200)))))
+        if k % 16 == 0:
+            m = min(n, 199) + 1
+            insts.append(I.arrow_ball(m - 1))
+            balls.append(k)
+        else:
+            insts.append(I.gbase(n, m, seed=1000 + k))
+    specs = [S.Spectrahedron(i) for i in insts]
+    b = S.Batch(specs)
+    chains = 64
+    chosen, ms = b.tune(chains=chains, rounds=10)
+    out = {"instances": len(insts), "chains_per_instance": chains,
+           "sum_m3": float(sum(g.m ** 3 for g in specs)),
+           "strategy_ms_per_round": {"persistent": ms[0], "size_classes": ms[1], "per_instance": ms[2]},
+           "chosen": ["persistent", "size_classes", "per_instance"][chosen - 1],
+           "oracle_calls_per_s": len(insts) * chains / (min(ms) * 1e-3)}
+    t0 = time.perf_counter()
+    lv, lo, hi, calls = b.volume(phases=20, samples_per_phase=samples_per_phase, chains=chains, walk_len=1,
+                                 groups=8, seed=404)
+    wall = time.perf_counter() - t0
+    errs, inside = [], 0
+    for k in balls:
+        nb = insts[k].n
+        truth = 0.5 * nb * math.log(math.pi) - math.lgamma(0.5 * nb + 1)
+        errs.append(lv[k] - truth)
+        w = hi[k] - lo[k]
+        inside += int(lo[k] - 0.5 * w <= truth <= hi[k] + 0.5 * w)
+    out["volume"] = {"phases": 20, "samples_per_phase": samples_per_phase, "walk_len": 1, "seconds": wall,
+                     "oracle_calls": calls, "oracle_calls_per_s": calls / wall,
+                     "ball_log_vol_err": {"max_abs": float(np.max(np.abs(errs))),
+                                          "mean": float(np.mean(errs))},
+                     "balls_within_ci": f"{inside}/{len(balls)}"}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +275,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-rows", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--uneven-samples", type=int, default=256,
+                    help="samples per cooling phase of the 256-spectrahedra volume (2000 for the full run)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -317,6 +365,9 @@ def main():
     if learned_sum is not None:
         out["learned"] = learned_sum
         out["learned_over_plain"] = learned_sum["oracle_calls_per_s"] / plain_sum["oracle_calls_per_s"]
+    if not args.no_uneven:
+        progress("uneven batch: 256 spectrahedra, autotune, batched volume")
+        out["uneven_batch"] = uneven_leg(S, I, args.uneven_samples)
     if not args.no_cpu:
         progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))

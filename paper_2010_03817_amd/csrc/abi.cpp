@@ -27,8 +27,10 @@ struct spec_s {
     // Lanczos settings
     int kmax = 80;
     double tol = 1e-8;
-    // workspace (capacity in chains, multiple of 64)
+    // workspace (capacity in chains, multiple of 64); work_gen changes whenever
+    // it is (re)allocated, so that cached device pointers can be revalidated
     int cap = 0;
+    unsigned work_gen = 0;
     double *dZ = nullptr, *dFB = nullptr, *dQ = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
     double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
     int32_t *dHit = nullptr, *dSt = nullptr;
@@ -60,6 +62,7 @@ struct spec_s {
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
         dfree(dShift); dfree(dShiftHi); dfree(dPred); dfree(dHz);
         cap = 0;
+        ++work_gen;
     }
     void free_walk() {
         dfree(wX); dfree(wXs); dfree(wV); dfree(wEll); dfree(wStats); dfree(wSum);
@@ -772,6 +775,7 @@ struct spec_batch_s {
     FusedArgs* dArgs = nullptr;
     int2* dWork = nullptr;
     int* dCounter = nullptr;
+    std::vector<unsigned> gens;  // handles' workspace generations the plan was built for
     struct Cls { int off, count, max_m, kmax, nblocks; };
     std::vector<Cls> all, classes;
     void free_plan() {
@@ -781,6 +785,7 @@ struct spec_batch_s {
         chains = 0;
         all.clear();
         classes.clear();
+        gens.clear();
     }
 };
 
@@ -796,15 +801,22 @@ int persistent_blocks(int max_m, int kmax) {
 // Work lists: every (instance, chain), the largest dense blocks first (the
 // longest items start first); classes split at m <= 64 and m <= 128.
 spec_status batch_plan(spec_batch_s* b, int chains) {
-    if (b->chains == chains) return SPEC_OK;
-    b->free_plan();
     const int K = (int)b->hs.size();
+    for (int i = 0; i < K; ++i) {
+        SPCHK(b->hs[i]->ensure(chains));
+        SPCHK(b->hs[i]->ensure_walk(chains));
+    }
+    // the plan holds the handles' workspace pointers: rebuild it whenever a
+    // workspace has been reallocated since
+    bool same = b->chains == chains && (int)b->gens.size() == K;
+    for (int i = 0; same && i < K; ++i) same = b->gens[i] == b->hs[i]->work_gen;
+    if (same) return SPEC_OK;
+    b->free_plan();
     std::vector<FusedArgs> args(K);
     for (int i = 0; i < K; ++i) {
         spec_handle h = b->hs[i];
-        SPCHK(h->ensure(chains));
-        SPCHK(h->ensure_walk(chains));
         args[i] = fused_args(h, round_up(chains, 64), h->dSt, h->dTm, h->dTp, false, nullptr);
+        b->gens.push_back(h->work_gen);
     }
     std::vector<int> order(K);
     for (int i = 0; i < K; ++i) order[i] = i;
@@ -1014,10 +1026,18 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
             if (!(d > 0.0)) { cleanup(); return SPEC_UNBOUNDED; }
             a_end = 1.0 / (4.0 * d * d);
         }
+        // membership of many points in chunks, so that the handle's workspace
+        // stays sized for the walks
+        auto member = [&](int cnt) -> spec_status {
+            const int chunk = std::max(chains, 256);
+            for (int q0 = 0; q0 < cnt; q0 += chunk)
+                SPCHK(spec_membership_dev(h, std::min(chunk, cnt - q0), dX + (size_t)q0 * n, dFlag + q0, s));
+            return SPEC_OK;
+        };
         auto inside = [&](double av, int cnt, uint64_t seed2, double* frac) -> spec_status {
             const double sd = 1.0 / std::sqrt(2.0 * av);
             HIPCHK(gauss_points(cnt, cnt, n, seed2, sd, dX, s));
-            SPCHK(spec_membership_dev(h, cnt, dX, dFlag, s));
+            SPCHK(member(cnt));
             double hits = 0.0;
             HIPCHK(count_groups(1, cnt, dFlag, dOut, s));
             HIPCHK(hipMemcpyAsync(&hits, dOut, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1046,7 +1066,7 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
         aendv[k] = a_end;
         const double sd0 = 1.0 / std::sqrt(2.0 * a0);
         VHIP(gauss_points(ndraw, spp, n, seed, sd0, dX, s));
-        VCHK(spec_membership_dev(h, ndraw, dX, dFlag, s));
+        VCHK(member(ndraw));
         VHIP(count_groups(groups, spp, dFlag, dOut, s));
         std::vector<double> hits(groups);
         VHIP(hipMemcpyAsync(hits.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));

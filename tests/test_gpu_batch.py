@@ -62,3 +62,18 @@ def test_batch_tune_picks_a_strategy(S):
     chosen, ms = b.tune(chains=64, rounds=3)
     assert chosen in (1, 2, 3)
     assert all(np.isfinite(ms)) and min(ms) == ms[chosen - 1]
+
+
+def test_tune_then_volume_revalidates_the_plan(S):
+    """The autotuner builds the batch plan for its chains; the volume's exact
+    draws then grow the handles' workspaces.  The plan must follow the new
+    workspaces (a stale plan would point at freed memory)."""
+    insts, truths = _mix()
+    specs = [S.Spectrahedron(i) for i in insts]
+    b = S.Batch(specs)
+    chosen, _ = b.tune(chains=32, rounds=2)
+    lv, lo, hi, _ = b.volume(**PARAMS)
+    b2 = S.Batch([S.Spectrahedron(i) for i in insts])
+    b2.set_strategy(chosen, True)
+    lv2, lo2, hi2, _ = b2.volume(**PARAMS)
+    assert np.array_equal(lv, lv2) and np.array_equal(lo, lo2)

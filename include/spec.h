@@ -208,13 +208,16 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
  *    Gaussian draws and the membership oracle;
  *  - each ratio is the sample mean of exp((a_i - a_{i+1}) |x|^2) over points
  *    of Gaussian Hit-and-Run chains targeting f_i restricted to S (chains
- *    start at the origin, which must be interior, and are warm-started from
- *    the previous phase);
+ *    start from exact draws of f_0 inside S, are warm-started from the
+ *    previous phase, and run burn_in steps after each change of target);
+ *    the origin must be interior;
  *  - chains are split into `groups` independent groups; the estimate is the
  *    mean of the groups' log-volumes with a Student-t 95 % interval.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int phases;             /* cooling phases (default 20) */
+    int phases;             /* cooling phases; <= 0: enough for a_{i+1} >= a_i (1 - 1/sqrt(n)), the
+                               cooling rate under which each ratio has bounded relative variance
+                               (at most 256; one count for a whole batch, the largest needed) */
     int samples_per_phase;  /* samples per phase over all chains; also exact draws per group for int f_0
                                (default 2000) */
     int chains;             /* chains, a multiple of groups (default 64) */
@@ -222,6 +225,9 @@ typedef struct {
     int groups;             /* independent groups for the interval (default 8) */
     double a0;              /* <= 0: chosen so that 50-90 % of N(0, I/(2 a0)) lies in S */
     double a_end;           /* <= 0: 1/(4 d^2), d the longest chord of a 64-chain Hit-and-Run pre-run */
+    int burn_in;            /* Hit-and-Run steps at the start of each phase before samples are kept
+                               (< 0: n, about one relaxation time of |x|^2 at rate 1/n per step; in a
+                               batch the largest n, since all walks advance in lockstep) */
 } spec_volume_params;
 
 typedef struct {
@@ -229,11 +235,11 @@ typedef struct {
     double p_inside;        /* fraction of the exact draws inside S */
     double oracle_calls;    /* line oracle calls of the walks */
     int phases;
-    double log_terms[65];   /* [0] = log int f_0, [i] = log of ratio i (group means) */
+    double log_terms[257];  /* [0] = log int f_0, [i] = log of ratio i (group means) */
 } spec_volume_stats;
 
 /* Estimate log vol(S); host outputs, asynchronous work on `stream`, synchronises.
- * EINVAL for bad parameters (phases 1..64, groups >= 2, chains % groups == 0). */
+ * EINVAL for bad parameters (phases <= 256, groups >= 2, chains % groups == 0). */
 spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uint64_t seed, double* log_vol,
                                  double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream);
 

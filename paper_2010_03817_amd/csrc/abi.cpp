@@ -960,12 +960,12 @@ spec_status batch_tune(spec_batch_s* b, int chains, int rounds, double* ms_out, 
 // plain per-instance rounds on `s` (K == 1).
 spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spec_volume_params* p, uint64_t seed,
                         double* log_vol, double* ci_lo, double* ci_hi, spec_volume_stats* st, hipStream_t s) {
-    const int phases = p->phases > 0 ? p->phases : 20;
+    int phases = p->phases > 0 ? p->phases : 0;  // 0: from the cooling rule once the schedule ends are known
     const int spp = p->samples_per_phase > 0 ? p->samples_per_phase : 2000;
     const int chains = p->chains > 0 ? p->chains : 64;
     const int walk_len = p->walk_len > 0 ? p->walk_len : 10;
     const int groups = p->groups > 0 ? p->groups : 8;
-    if (phases > 64 || groups < 2 || chains % groups || spp < groups) return SPEC_EINVAL;
+    if (phases > 256 || groups < 2 || chains % groups || spp < groups) return SPEC_EINVAL;
     const double pi = 3.14159265358979323846;
     const int spc = (spp + chains - 1) / chains;
     const int ndraw = groups * spp;
@@ -976,10 +976,11 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
     double *dX = nullptr, *dOut = nullptr, *dZero = nullptr, *dXout = nullptr;
     int8_t* dFlag = nullptr;
     int32_t* dCnt = nullptr;
-    std::vector<double*> dSamp(K, nullptr);
+    std::vector<double*> dSamp(K, nullptr), dStart(K, nullptr);
     auto cleanup = [&]() {
         dfree(dX); dfree(dFlag); dfree(dOut); dfree(dZero); dfree(dXout); dfree(dCnt);
         for (auto& q : dSamp) dfree(q);
+        for (auto& q : dStart) dfree(q);
     };
 #define VCHK(expr)                                                  \
     do {                                                            \
@@ -993,10 +994,13 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
     VHIP(dalloc(&dZero, (size_t)std::max(chains, prerun_chains) * nmax));
     VHIP(dalloc(&dXout, (size_t)std::max(chains, prerun_chains) * nmax, false));
     VHIP(dalloc(&dCnt, 1));
+    if (chains > 1024) { cleanup(); return SPEC_EINVAL; }
     for (int k = 0; k < K; ++k) VHIP(dalloc(&dSamp[k], (size_t)chains * spc * hs[k]->n, false));
+    for (int k = 0; k < K; ++k) VHIP(dalloc(&dStart[k], (size_t)chains * hs[k]->n));
     std::vector<double> a0v(K), aendv(K), pin(K), calls(K, 0.0);
-    std::vector<std::vector<double>> a(K, std::vector<double>(phases + 1));
-    std::vector<std::vector<double>> gl(K, std::vector<double>((size_t)groups * (phases + 1), 0.0));
+    std::vector<std::vector<double>> a(K);
+    std::vector<std::vector<double>> gl(K);
+    std::vector<std::vector<double>> g0(K, std::vector<double>(groups, 0.0));  // log int f_0 per group
     // ---- per instance: schedule ends and the first integral
     for (int k = 0; k < K; ++k) {
         spec_handle h = hs[k];
@@ -1068,6 +1072,8 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
         VHIP(gauss_points(ndraw, spp, n, seed, sd0, dX, s));
         VCHK(member(ndraw));
         VHIP(count_groups(groups, spp, dFlag, dOut, s));
+        // chains start from exact draws of f_0 inside S (the origin if too few)
+        VHIP(select_inside(ndraw, n, dX, dFlag, chains, dStart[k], dCnt, s));
         std::vector<double> hits(groups);
         VHIP(hipMemcpyAsync(hits.data(), dOut, sizeof(double) * groups, hipMemcpyDeviceToHost, s));
         VHIP(hipStreamSynchronize(s));
@@ -1075,14 +1081,27 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
         for (int g = 0; g < groups; ++g) {
             if (!(hits[g] > 0.0)) { cleanup(); return SPEC_NOT_INTERIOR; }
             hit_tot += hits[g];
-            gl[k][(size_t)g * (phases + 1)] = 0.5 * n * std::log(pi / a0) + std::log(hits[g] / spp);
+            g0[k][g] = 0.5 * n * std::log(pi / a0) + std::log(hits[g] / spp);
         }
         pin[k] = hit_tot / ndraw;
-        for (int i = 0; i < phases; ++i)
-            a[k][i] = phases == 1 ? a0 : a0 * std::pow(a_end / a0, (double)i / (phases - 1));
-        a[k][phases] = 0.0;
         VCHK(h->ensure(chains));
         VCHK(h->ensure_walk(chains));
+    }
+    if (phases == 0) {
+        // cooling rule a_{i+1} >= a_i (1 - 1/sqrt(n)) from a_0 down to a_end
+        for (int k = 0; k < K; ++k) {
+            const double rate = -std::log1p(-1.0 / std::sqrt((double)std::max(hs[k]->n, 2)));
+            phases = std::max(phases, 1 + (int)std::ceil(std::log(a0v[k] / aendv[k]) / rate));
+        }
+        phases = std::min(std::max(phases, 2), 256);
+    }
+    for (int k = 0; k < K; ++k) {
+        a[k].assign(phases + 1, 0.0);
+        for (int i = 0; i < phases; ++i)
+            a[k][i] = phases == 1 ? a0v[k] : a0v[k] * std::pow(aendv[k] / a0v[k], (double)i / (phases - 1));
+        a[k][phases] = 0.0;
+        gl[k].assign((size_t)groups * (phases + 1), 0.0);
+        for (int g = 0; g < groups; ++g) gl[k][(size_t)g * (phases + 1)] = g0[k][g];
     }
     // ---- phases: Gaussian Hit-and-Run of every instance, rounds in lockstep
     int strategy = 3;
@@ -1094,19 +1113,28 @@ spec_status volume_many(spec_batch_s* b, const spec_handle* hs, int K, const spe
         graph = b->use_graph;
     }
     std::vector<WalkArgs> wa(K);
+    int burn = p->burn_in;
+    if (burn < 0) {
+        burn = 0;
+        for (int k = 0; k < K; ++k) burn = std::max(burn, hs[k]->n);
+    }
+    const long long burn_r = ((long long)burn + walk_len - 1) / walk_len * walk_len;  // whole thinning intervals
+    const long long per_phase = burn_r + (long long)spc * walk_len;
     for (int ph = 0; ph < phases; ++ph) {
-        const long long steps = (long long)(ph + 1) * spc * walk_len;
+        const long long steps = (long long)(ph + 1) * per_phase;
+        // samples of this phase: steps ph * per_phase + burn_r + walk_len * (j + 1)
+        const long long first = ((long long)ph * per_phase + burn_r) / walk_len;
         for (int k = 0; k < K; ++k) {
             spec_walk_params wp{};
             wp.tau = 1.0;
             wp.pullback = 1e-6;
             wp.gauss_a = a[k][ph];
             wp.thin = walk_len;
-            wa[k] = make_walk_args(hs[k], SPEC_WALK_HNR, chains, steps, seed, &wp, dSamp[k], (long long)ph * spc, spc);
-            if (ph == 0) VHIP(walk_init(wa[k], dZero, s));
+            wa[k] = make_walk_args(hs[k], SPEC_WALK_HNR, chains, steps, seed, &wp, dSamp[k], first, spc);
+            if (ph == 0) VHIP(walk_init(wa[k], dStart[k], s));
             else VHIP(walk_resume(wa[k], s));
         }
-        const long long rounds = (long long)spc * walk_len;  // Hit-and-Run: one step per round
+        const long long rounds = per_phase;  // Hit-and-Run: one step per round
         if (b) {
             VCHK(batch_rounds(b, wa, chains, strategy, rounds, graph, s));
         } else {

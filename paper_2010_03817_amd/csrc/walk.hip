@@ -185,6 +185,23 @@ __global__ __launch_bounds__(256) void k_phase_lse(int cpg, int nsamp, int n, co
     if (t == 0) out[g] = mx + log(sm) - log((double)cnt);
 }
 
+// Starting points: the first `chains` of the `count` draws that are inside S
+// (flag set), in draw order; one workgroup, thread 0 selects.
+__global__ void k_select_inside(int count, int n, const double* __restrict__ X, const int8_t* __restrict__ flag,
+                                int chains, double* __restrict__ out, int* __restrict__ found) {
+    __shared__ int pick[1024];
+    __shared__ int np;
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int q = 0; q < count && c < chains && c < 1024; ++q)
+            if (flag[q]) pick[c++] = q;
+        np = c;
+        *found = c;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * n; e += blockDim.x) out[e] = X[(size_t)pick[e / n] * n + e % n];
+}
+
 __global__ void k_count_groups(int groups, int per_group, const int8_t* __restrict__ flag, double* __restrict__ out) {
     const int g = blockIdx.x;
     if (g >= groups) return;
@@ -473,6 +490,12 @@ hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double s
 hipError_t phase_lse(int groups, int cpg, int nsamp, int n, const double* samples, double da, double* out,
                      hipStream_t s) {
     hipLaunchKernelGGL(k_phase_lse, dim3(groups), dim3(256), 0, s, cpg, nsamp, n, samples, da, out);
+    return hipGetLastError();
+}
+hipError_t select_inside(int count, int n, const double* X, const int8_t* flag, int chains, double* out, int* found,
+                         hipStream_t s) {
+    if (chains > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_select_inside, dim3(1), dim3(256), 0, s, count, n, X, flag, chains, out, found);
     return hipGetLastError();
 }
 hipError_t count_groups(int groups, int per_group, const int8_t* flag, double* out, hipStream_t s) {

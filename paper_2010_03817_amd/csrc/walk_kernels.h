@@ -58,5 +58,8 @@ hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double s
 hipError_t phase_lse(int groups, int cpg, int nsamp, int n, const double* samples, double da, double* out,
                      hipStream_t s);
 hipError_t count_groups(int groups, int per_group, const int8_t* flag, double* out, hipStream_t s);
+// The first `chains` (<= 1024) draws inside S into out (chains x n); *found = how many there were.
+hipError_t select_inside(int count, int n, const double* X, const int8_t* flag, int chains, double* out, int* found,
+                         hipStream_t s);
 
 }  // namespace spec

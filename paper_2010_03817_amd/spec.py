@@ -43,12 +43,12 @@ class WalkStats(C.Structure):
 
 class VolumeParams(C.Structure):
     _fields_ = [("phases", C.c_int), ("samples_per_phase", C.c_int), ("chains", C.c_int), ("walk_len", C.c_int),
-                ("groups", C.c_int), ("a0", C.c_double), ("a_end", C.c_double)]
+                ("groups", C.c_int), ("a0", C.c_double), ("a_end", C.c_double), ("burn_in", C.c_int)]
 
 
 class VolumeStats(C.Structure):
     _fields_ = [("a0", C.c_double), ("a_end", C.c_double), ("p_inside", C.c_double), ("oracle_calls", C.c_double),
-                ("phases", C.c_int), ("log_terms", C.c_double * 65)]
+                ("phases", C.c_int), ("log_terms", C.c_double * 257)]
 
 
 class MlpTrainParams(C.Structure):
@@ -302,10 +302,10 @@ class Spectrahedron:
         return out
 
     def volume(self, phases=20, samples_per_phase=2000, chains=64, walk_len=10, groups=8, a0=0.0, a_end=0.0,
-               seed=1):
+               seed=1, burn_in=-1):
         """Gaussian-cooling volume estimate: (log vol, ci_lo, ci_hi, stats)."""
         p = VolumeParams(phases=phases, samples_per_phase=samples_per_phase, chains=chains, walk_len=walk_len,
-                         groups=groups, a0=a0, a_end=a_end)
+                         groups=groups, a0=a0, a_end=a_end, burn_in=burn_in)
         lv, lo, hi = C.c_double(), C.c_double(), C.c_double()
         st = VolumeStats()
         check(lib().spec_volume_estimate(self._h, C.byref(p), int(seed), C.byref(lv), C.byref(lo), C.byref(hi),
@@ -375,10 +375,10 @@ class Batch:
         return k.value, list(ms)
 
     def volume(self, phases=20, samples_per_phase=2000, chains=64, walk_len=10, groups=8, a0=0.0, a_end=0.0,
-               seed=1):
+               seed=1, burn_in=-1):
         K = len(self.specs)
         p = VolumeParams(phases=phases, samples_per_phase=samples_per_phase, chains=chains, walk_len=walk_len,
-                         groups=groups, a0=a0, a_end=a_end)
+                         groups=groups, a0=a0, a_end=a_end, burn_in=burn_in)
         lv, lo, hi = np.empty(K), np.empty(K), np.empty(K)
         calls = C.c_double()
         check(lib().spec_batch_volume(self._h, C.byref(p), int(seed), lv.ctypes.data_as(C.c_void_p),

@@ -25,7 +25,7 @@ def _mix():
     return insts, truths
 
 
-PARAMS = dict(phases=12, samples_per_phase=512, chains=32, walk_len=4, groups=8, seed=23)
+PARAMS = dict(phases=12, samples_per_phase=512, chains=32, walk_len=4, groups=8, seed=23, burn_in=8)
 
 
 def test_batch_strategies_and_graph_agree_with_single(S):

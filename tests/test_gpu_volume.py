@@ -74,3 +74,15 @@ def test_volume_agrees_with_oracle(S):
     h1, h2 = 0.5 * (hi - lo), 0.5 * (ohi - olo)
     assert abs(lv - olv) <= 1.5 * math.hypot(h1, h2) + 1e-3
     _check(lv, lo, hi, truth)
+
+
+def test_volume_cooling_rule_ball50(S):
+    """Phase count from the cooling rule a_{i+1} = a_i (1 - 1/sqrt(n)): the
+    50-dimensional ball within the interval."""
+    n = 50
+    g = S.Spectrahedron(I.arrow_ball(n))
+    truth = 0.5 * n * math.log(math.pi) - math.lgamma(0.5 * n + 1)
+    lv, lo, hi, st = g.volume(phases=0, samples_per_phase=1024, chains=64, walk_len=2, groups=8, seed=29)
+    print("ball50", lv, lo, hi, truth, len(st["log_terms"]) - 1)
+    assert len(st["log_terms"]) - 1 >= 30
+    _check(lv, lo, hi, truth)

@@ -275,6 +275,51 @@ def uneven_leg(S, I, samples_per_phase):
     return out
 
 
+def hmc_precision_leg(g, S, tau, chains, rounds):
+    """HMC with reflections for the Gaussian exp(-|x|^2 / 2) (sigma = 1) on the
+    n = m = 200 instance, travel time tau eta with tau = the diameter
+    estimate: segment (curve-oracle call) and step rates in FP64, and the
+    first-root error of the FP32 and BF16-pair pencil assemblies against FP64
+    on logged segments."""
+    import torch
+    n = N_DIM
+    sigma, a = 1.0, 0.5
+    x0 = torch.zeros((chains, n), dtype=torch.float64, device="cuda")
+    g.walk(S.HMC, x0, 1 << 40, seed=77, gauss_a=a, tau=tau, max_rounds=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st, log = g.walk(S.HMC, x0, 1 << 40, seed=77, gauss_a=a, tau=tau, max_rounds=rounds, resume=True,
+                           log_chains=chains, log_cap=chains * rounds)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"chains": chains, "sigma": sigma, "tau": tau, "rounds": rounds, "seconds": wall,
+           "curve_calls_per_s": st["calls"] / wall, "steps_in_window_per_s": st["steps"] / wall,
+           "reflections_per_call": st["reflections"] / max(st["calls"], 1), "not_interior": st["not_interior"],
+           "noconv": st["noconv"]}
+    # first roots of logged segments' pencils in each assembly precision
+    L = log[: min(log.shape[0], 4096)]
+    p, v = L[:, :n], L[:, n:2 * n]
+    coef = torch.zeros((L.shape[0], 3, n + 1), dtype=torch.float64, device="cuda")
+    coef[:, 0, 0], coef[:, 0, 1:] = 1.0, p
+    coef[:, 1, 1:] = 2 * sigma * v
+    coef[:, 2, 0], coef[:, 2, 1:] = 1.0, -p
+    roots = {}
+    for name, mode in (("fp64", S.PREC_FP64), ("fp32", S.PREC_FP32_ASM), ("bf16x2", S.PREC_BF16X2_ASM)):
+        g.set_precision(mode)
+        _, tp, stc = g.intersect_curve(coef, 1.0)
+        roots[name] = (tp.cpu().numpy(), stc.cpu().numpy())
+    g.set_precision(S.PREC_FP64)
+    ref, rst = roots["fp64"]
+    for name in ("fp32", "bf16x2"):
+        tp, stc = roots[name]
+        ok = np.isfinite(ref) & np.isfinite(tp) & (rst == 0) & (stc == 0)
+        rel = np.abs(tp[ok] - ref[ok]) / ref[ok]
+        out[f"{name}_vs_fp64_root_rel"] = {"segments": int(ok.sum()), "median": float(np.median(rel)),
+                                           "p99": float(np.quantile(rel, 0.99)), "max": float(rel.max()),
+                                           "hit_disagreements": int(np.sum(np.isfinite(ref) != np.isfinite(tp)))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +331,9 @@ def main():
     ap.add_argument("--train-rows", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-hmc", action="store_true")
+    ap.add_argument("--hmc-chains", type=int, default=8192)
+    ap.add_argument("--hmc-rounds", type=int, default=4)
     ap.add_argument("--uneven-samples", type=int, default=256,
                     help="samples per cooling phase of the 256-spectrahedra volume (2000 for the full run)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -375,6 +423,9 @@ def main():
     if learned_sum is not None:
         out["learned"] = learned_sum
         out["learned_over_plain"] = learned_sum["oracle_calls_per_s"] / plain_sum["oracle_calls_per_s"]
+    if not args.no_hmc:
+        progress("HMC with reflections, precision split")
+        out["hmc_precision"] = hmc_precision_leg(g, S, dhat, args.hmc_chains, args.hmc_rounds)
     if not args.no_uneven:
         progress("uneven batch: 256 spectrahedra, autotune, batched volume")
         out["uneven_batch"] = uneven_leg(S, I, args.uneven_samples)

@@ -59,6 +59,12 @@ typedef enum {
     SPEC_WALK_HMC = 3       /* HMC with reflections, Alg. HMC_w_reflection         */
 } spec_walk_kind;
 
+typedef enum {
+    SPEC_PREC_FP64 = 0,       /* FP64 pencil assembly                               */
+    SPEC_PREC_FP32_ASM = 1,   /* FP32 MFMA assembly, FP32 accumulation              */
+    SPEC_PREC_BF16X2_ASM = 2  /* bfloat16 hi+lo pairs on MFMA, FP32 accumulation    */
+} spec_precision;
+
 typedef struct spec_s* spec_handle;
 
 /* Largest merged dense block the device kernels handle (one workgroup holds
@@ -93,6 +99,16 @@ const char* spec_status_str(spec_status s);
  * about the square of the bound over the gap).  SPEC_ENOTSUP if the
  * tridiagonal would not fit in LDS for this handle's m. */
 spec_status spec_set_lanczos(spec_handle h, int kmax, double tol);
+
+/* Precision of the pencil assembly F(x), B(v) (and Q0, Q1, Q2 of curves):
+ * SPEC_PREC_FP64 (default, FP64 MFMA), SPEC_PREC_FP32_ASM (coefficients and
+ * the A-stack rounded to FP32, FP32 MFMA with FP32 accumulation),
+ * SPEC_PREC_BF16X2_ASM (each FP32 operand split into a bfloat16 pair
+ * hi + lo, products hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation).
+ * The factorisation, the eigen solve and the reflection normal stay FP64;
+ * the assembled pencils carry the reduced precision's rounding, so t+- move
+ * by about that relative error times the conditioning of F(x). */
+spec_status spec_set_precision(spec_handle h, int mode);
 
 /* MEMBERSHIP (Alg. MEMBERSHIP, read as strict definiteness): interior[e] = 1
  * iff F(x_e) is positive definite (Cholesky succeeds). */

@@ -24,6 +24,9 @@ struct spec_s {
     int device = 0;
     int n = 0, m = 0, md = 0, P = 0, Ptot = 0, K = 0, Kpad = 0, ldA = 0, Arows = 0, Nn = 0;
     double* dA = nullptr;  // Arows x ldA
+    // pencil assembly precision: 0 FP64, 1 FP32 MFMA, 2 BF16 hi+lo MFMA (FP32 accumulation)
+    int prec = 0;
+    float* dA32 = nullptr;  // FP32 copy of the A-stack when prec > 0
     // Lanczos settings
     int kmax = 80;
     double tol = 1e-8;
@@ -32,6 +35,7 @@ struct spec_s {
     int cap = 0;
     unsigned work_gen = 0;
     double *dZ = nullptr, *dFB = nullptr, *dQ = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
+    float* dZ32 = nullptr;
     double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
     int32_t *dHit = nullptr, *dSt = nullptr;
     // staging for the host-pointer entry points
@@ -58,7 +62,7 @@ struct spec_s {
     long long* wStep = nullptr;
 
     void free_work() {
-        dfree(dZ); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
+        dfree(dZ); dfree(dZ32); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
         dfree(dShift); dfree(dShiftHi); dfree(dPred); dfree(dHz);
         cap = 0;
@@ -95,6 +99,7 @@ struct spec_s {
         free_work();
         const int c = round_up(batch, 64);
         HIPCHK(dalloc(&dZ, (size_t)3 * c * Kpad));
+        HIPCHK(dalloc(&dZ32, (size_t)3 * c * Kpad));
         HIPCHK(dalloc(&dFB, (size_t)3 * c * ldA, false));
         HIPCHK(dalloc(&dQ, (size_t)c * ldq(), false));
         HIPCHK(dalloc(&dU, (size_t)c * m, false));
@@ -132,14 +137,24 @@ struct spec_s {
 
 namespace {
 
+// FB (M rows) = Z (M x Kpad) * A-stack in the handle's assembly precision.
+spec_status pencil_gemm(spec_s* h, int M, hipStream_t s) {
+    if (h->prec == 0) {
+        HIPCHK(gemm_f64(false, M, h->ldA, h->Kpad, h->dZ, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA, s));
+    } else {
+        HIPCHK(to_f32((size_t)M * h->Kpad, h->dZ, h->dZ32, s));
+        HIPCHK(gemm_asm(h->prec - 1, M, h->ldA, h->Kpad, h->dZ32, h->Kpad, h->dA32, h->ldA, h->dFB, h->ldA, s));
+    }
+    return SPEC_OK;
+}
+
 // [F; B] for `batch` chains: rows 0..batch-1 = F(x_c), rows bp + c = B(v_c).
 spec_status assemble(spec_s* h, int batch, const double* x, const double* v, int* bp_out, hipStream_t s) {
     const int bp = round_up(batch, 64);
     *bp_out = bp;
     HIPCHK(launch_build_z(batch, h->n, h->Kpad, x, v, h->dZ, bp, s));
     const int M = v ? 2 * bp : bp;
-    HIPCHK(gemm_f64(false, M, h->ldA, h->Kpad, h->dZ, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA, s));
-    return SPEC_OK;
+    return pencil_gemm(h, M, s);
 }
 
 inline void mark(spec_s* h, int i, hipStream_t s) {
@@ -207,7 +222,7 @@ spec_status curve_oracle(spec_s* h, int batch, const double* horizon, double hsc
                          int32_t* st, bool both, bool want_vec, int32_t* iters, hipStream_t s) {
     const int bp = round_up(batch, 64);
     mark(h, 0, s);
-    HIPCHK(gemm_f64(false, 3 * bp, h->ldA, h->Kpad, h->dZ, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA, s));
+    SPCHK(pencil_gemm(h, 3 * bp, s));
     mark(h, 1, s);
     mark(h, 2, s);
     CurveArgs a{};
@@ -380,6 +395,7 @@ spec_status spec_destroy(spec_handle h) {
     h->free_stage();
     h->free_walk();
     dfree(h->dA);
+    dfree(h->dA32);
     dfree(h->dLamSum);
     dfree(h->dProf);
     for (auto& e : h->ev)
@@ -448,6 +464,18 @@ spec_status spec_tune_mlp_delta_dev(spec_handle h, spec_mlp net, int batch, cons
     if (rc != SPEC_OK) return rc;
     *best = best_d;
     return spec_set_mlp(h, net, best_d, 1);
+}
+
+spec_status spec_set_precision(spec_handle h, int mode) {
+    if (!h || mode < SPEC_PREC_FP64 || mode > SPEC_PREC_BF16X2_ASM) return SPEC_EINVAL;
+    if (mode != SPEC_PREC_FP64 && !h->dA32) {
+        const size_t cnt = (size_t)h->Arows * h->ldA;
+        HIPCHK(dalloc(&h->dA32, cnt, false));
+        HIPCHK(to_f32(cnt, h->dA, h->dA32, nullptr));
+        HIPCHK(hipDeviceSynchronize());
+    }
+    h->prec = mode;
+    return SPEC_OK;
 }
 
 spec_status spec_set_lanczos(spec_handle h, int kmax, double tol) {

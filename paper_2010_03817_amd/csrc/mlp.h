@@ -26,6 +26,13 @@ enum GemmMode : int {
 hipError_t gemm_f32(bool ta, bool tb, bool bf16, int mode, int M, int N, int K, const float* A, int lda,
                     const float* B, int ldb, float* C, int ldc, float* aux, int ldaux, hipStream_t s);
 
+// Reduced-precision pencil assembly: C (FP64, M x N) = A (M x K) B (K x N),
+// FP32 row-major operands, FP32 accumulation; prec 0 FP32 MFMA, 1 BF16 hi+lo
+// pairs (three BF16 MFMA products).
+hipError_t gemm_asm(int prec, int M, int N, int K, const float* A, int lda, const float* B, int ldb, double* C, int ldc,
+                    hipStream_t s);
+hipError_t to_f32(size_t count, const double* x, float* y, hipStream_t s);
+
 // Features [(x - mu_x) * isd_x, (v - mu_v) * isd_v, 1] of rows (FP64 in, FP32 out, ldf >= 2n + 1).
 hipError_t mlp_features(int rows, int n, const double* x, int ldx, const double* v, int ldv, const float* mu,
                         const float* isd, float* F, int ldf, hipStream_t s);

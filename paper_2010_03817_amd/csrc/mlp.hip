@@ -104,6 +104,81 @@ __global__ __launch_bounds__(256) void k_gemm_f32(int M, int N, int K, const flo
             }
 }
 
+// Reduced-precision assembly of packed pencils: C (M x N, FP64 out) = A B with
+// A (M x K) and B (K x N) row-major FP32.  PREC 0: FP32 MFMA; PREC 1: BF16
+// hi+lo pairs, a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi (three BF16 MFMAs).
+// FP32 accumulation in both.  Same 64 x 64 tiling as k_gemm_f32.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm_asm(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                  const float* __restrict__ B, int ldb, double* __restrict__ C,
+                                                  int ldc) {
+    __shared__ float As[BM][LDS_K];
+    __shared__ float Bs[BN][LDS_K];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const int lr = lane & 15, lg = lane >> 4;
+    f4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        for (int e = t; e < BM * BK; e += 256) {
+            const int mm = e / BK, kk = e % BK, gm = m0 + mm, gk = k0 + kk;
+            As[mm][kk] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.f;
+        }
+        for (int e = t; e < BN * BK; e += 256) {
+            const int nn = e % BN, kk = e / BN, gn = n0 + nn, gk = k0 + kk;
+            Bs[nn][kk] = (gn < N && gk < K) ? B[(size_t)gk * ldb + gn] : 0.f;
+        }
+        __syncthreads();
+        if (PREC == 1) {
+            short8 ah[2], al[2], bh[2], bl[2];
+            for (int i = 0; i < 2; ++i)
+                for (int q = 0; q < 8; ++q) {
+                    const float av = As[wm + 16 * i + lr][8 * lg + q], bv = Bs[wn + 16 * i + lr][8 * lg + q];
+                    const short ahq = bf16_rne(av), bhq = bf16_rne(bv);
+                    ah[i][q] = ahq;
+                    bh[i][q] = bhq;
+                    al[i][q] = bf16_rne(av - __uint_as_float((uint32_t)(uint16_t)ahq << 16));
+                    bl[i][q] = bf16_rne(bv - __uint_as_float((uint32_t)(uint16_t)bhq << 16));
+                }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[i]),
+                                                                        __builtin_bit_cast(bf16x8, bh[j]),
+                                                                        acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                                        __builtin_bit_cast(bf16x8, bl[j]),
+                                                                        acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                                        __builtin_bit_cast(bf16x8, bh[j]),
+                                                                        acc[i][j], 0, 0, 0);
+                }
+        } else {
+            for (int kq = 0; kq < BK; kq += 4) {
+                const float a0 = As[wm + lr][kq + lg], a1 = As[wm + 16 + lr][kq + lg];
+                const float b0 = Bs[wn + lr][kq + lg], b1 = Bs[wn + 16 + lr][kq + lg];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + 4 * lg + r, gn = n0 + wn + 16 * j + lr;
+                if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = (double)acc[i][j][r];
+            }
+}
+
+__global__ void k_to_f32(size_t count, const double* __restrict__ x, float* __restrict__ y) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) y[e] = (float)x[e];
+}
+
 template <bool TA, bool TB, bool BF16>
 hipError_t gemm_mode(int mode, dim3 g, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
                      int ldc, float* aux, int ldaux, hipStream_t s) {
@@ -278,6 +353,21 @@ hipError_t gemm_f32(bool ta, bool tb, bool bf16, int mode, int M, int N, int K, 
         case 6: return gemm_mode<true, true, false>(mode, g, M, N, K, A, lda, B, ldb, C, ldc, aux, ldaux, s);
         default: return gemm_mode<true, true, true>(mode, g, M, N, K, A, lda, B, ldb, C, ldc, aux, ldaux, s);
     }
+}
+
+hipError_t gemm_asm(int prec, int M, int N, int K, const float* A, int lda, const float* B, int ldb, double* C, int ldc,
+                    hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const dim3 g((N + BN - 1) / BN, (M + BM - 1) / BM);
+    if (prec == 1) k_gemm_asm<1><<<g, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    else k_gemm_asm<0><<<g, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t to_f32(size_t count, const double* x, float* y, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    k_to_f32<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(count, x, y);
+    return hipGetLastError();
 }
 
 hipError_t mlp_features(int rows, int n, const double* x, int ldx, const double* v, int ldv, const float* mu,

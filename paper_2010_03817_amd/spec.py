@@ -20,6 +20,7 @@ HEADERS = [os.path.join(os.path.dirname(_HERE), "include", h) for h in ("spec.h"
 OK, EINVAL, ENOMEM, EDEVICE, NOT_INTERIOR, UNBOUNDED, NONSMOOTH, REFLECT_CAP, CERT_FALLBACK, NOCONV, ENOTSUP = range(11)
 DENSE, DIAG = 0, 1
 HNR, CHNR, BILLIARD, HMC = 0, 1, 2, 3
+PREC_FP64, PREC_FP32_ASM, PREC_BF16X2_ASM = 0, 1, 2
 
 
 class SpecError(RuntimeError):
@@ -97,6 +98,7 @@ def lib():
     L.spec_status_str.argtypes = [C.c_int]
     L.spec_status_str.restype = C.c_char_p
     L.spec_set_lanczos.argtypes = [vp, C.c_int, C.c_double]
+    L.spec_set_precision.argtypes = [vp, C.c_int]
     L.spec_membership_dev.argtypes = [vp, C.c_int, vp, vp, vp]
     L.spec_intersect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
     L.spec_reflect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
@@ -199,6 +201,10 @@ class Spectrahedron:
 
     def set_lanczos(self, kmax: int, tol: float):
         check(lib().spec_set_lanczos(self._h, int(kmax), float(tol)))
+
+    def set_precision(self, mode: int):
+        """Pencil assembly precision: PREC_FP64, PREC_FP32_ASM, PREC_BF16X2_ASM."""
+        check(lib().spec_set_precision(self._h, int(mode)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -149,7 +149,8 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
  * each step factors Q(tau) and bounds lambda_min of L^-1 Q'(tau) L^-T and of
  * L^-1 Q2 L^-T from below (Lanczos Ritz value minus residual bound), so Q
  * stays definite over the step; diagonal rows by their scalar quadratics.
- * status[e]: OK, NOT_INTERIOR, NOCONV (an eigen solve did not converge). */
+ * status[e]: OK, NOT_INTERIOR, NOCONV (the eigen solve of L^-1 Q'(tau) L^-T did
+ * not converge; the bounds stay certified, the step only shorter). */
 spec_status spec_intersect_curve(spec_handle h, int batch, int degree, const double* coef, double horizon,
                                  double* t_minus, double* t_plus, int32_t* status);
 spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const double* coef, double horizon,

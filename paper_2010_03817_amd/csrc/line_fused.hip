@@ -156,11 +156,20 @@ __device__ __forceinline__ void dense_trinv16(double* T, int lane) {
 
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
-__device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* flag) {
+// prof (nullable): thread 0 adds the cycles of the diagonal-tile, panel and
+// trailing-update stages to prof[0..2].
+__device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* flag, long long* prof = nullptr) {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int T = (m + 15) / 16;
+    long long c0 = 0, c1 = 0, c2 = 0, tc = prof ? clock64() : 0;
+#define CHOL_TICK(acc)                       \
+    if (prof) {                              \
+        const long long tn = clock64();      \
+        acc += tn - tc;                      \
+        tc = tn;                             \
+    }
     for (int K = 0; K < T; ++K) {
         if (wv == 0) {
             tile_to_dense(L, m, K, D, lane);
@@ -172,6 +181,7 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
             }
         }
         lds_barrier();
+        CHOL_TICK(c0)
         if (*flag == 0) return false;
         // panel: L_IK = A_IK D^T
         for (int I = K + 1 + wv; I < T; I += nw) {
@@ -185,6 +195,7 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
             acc_to_tile(L, m, I, K, acc, lane);
         }
         lds_barrier();
+        CHOL_TICK(c1)
         // trailing update A_IJ -= L_IK L_JK^T, K < J <= I
         const int R = T - K - 1;
         for (int e = wv; e < R * (R + 1) / 2; e += nw) {
@@ -198,6 +209,13 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
             acc_to_tile(L, m, I, J, acc, lane);
         }
         lds_barrier();
+        CHOL_TICK(c2)
+    }
+#undef CHOL_TICK
+    if (prof && t == 0) {
+        prof[0] += c0;
+        prof[1] += c1;
+        prof[2] += c2;
     }
     return true;
 }
@@ -351,19 +369,26 @@ __device__ __forceinline__ double tri_at(double vA, double vB, int i) { return i
 // (p_{i-1}, p_i) is rescaled by a power of two every 8 steps.  Exact zeros
 // count as positive (a measure-zero event for a multisection point).
 __device__ inline int sturm_reg(double aA, double aB, double b2A, double b2B, int k, double x) {
-    double pm = 1.0, pc = tri_at(aA, aB, 0) - x;
+    double pm = 1.0, pc = rl(aA, 0) - x;
     int cnt = pc < 0.0;
-    for (int i = 1; i < k; ++i) {
-        const double pn = (tri_at(aA, aB, i) - x) * pc - tri_at(b2A, b2B, i) * pm;
-        cnt += (pn < 0.0) != (pc < 0.0);
-        pm = pc;
-        pc = pn;
-        if ((i & 7) == 0) {
-            const int e = ilogb(fabs(pc) + fabs(pm) + 1e-300);
-            pc = ldexp(pc, -e);
-            pm = ldexp(pm, -e);
-        }
+    // rows 1..63 live in the A registers, rows 64.. in the B registers: two
+    // loops, so that no per-step select between them is needed
+#define STURM_STEP(av, b2v)                                \
+    {                                                      \
+        const double pn = ((av) - x) * pc - (b2v) * pm;    \
+        cnt += (pn < 0.0) != (pc < 0.0);                   \
+        pm = pc;                                           \
+        pc = pn;                                           \
+        if ((i & 7) == 0) {                                \
+            const int e = ilogb(fabs(pc) + fabs(pm) + 1e-300); \
+            pc = ldexp(pc, -e);                            \
+            pm = ldexp(pm, -e);                            \
+        }                                                  \
     }
+    const int k1 = k < 64 ? k : 64;
+    for (int i = 1; i < k1; ++i) STURM_STEP(rl(aA, i), rl(b2A, i))
+    for (int i = 64; i < k; ++i) STURM_STEP(rl(aB, i - 64), rl(b2B, i - 64))
+#undef STURM_STEP
     return cnt;
 }
 
@@ -589,6 +614,8 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
         int next_check = c.first_check > 0 ? c.first_check : 4;
         double prev_q = -1.0;
         int prev_k = 0;
+        // bracket of this lane's extreme Ritz value at the previous test (NaN: none)
+        double w_lo = NAN, w_hi = NAN, w_r = 0.0;
         long long tprev = clock64();
 #define PHASE(i)                          \
     {                                     \
@@ -648,6 +675,30 @@ tprev = tn;                       \
                 const bool want_min = c.min_only || lane < 32;
                 const int sub = c.min_only ? lane : (lane & 31);
                 double lo = glo, hi = ghi;
+                // warm start: T_k's leading submatrices are the earlier T's, so by
+                // interlacing theta_min can only fall and theta_max only rise since
+                // the last test.  Keep the previous inner end; take the outer end a
+                // little beyond the previous bracket if a Sturm count confirms no
+                // eigenvalue lies past it.
+                if (w_lo == w_lo) {
+                    const double span = 4.0 * w_r + 16.0 * (w_hi - w_lo) + 1e-12 * fmax(fabs(w_lo), fabs(w_hi));
+                    const double xw = want_min ? w_lo - span : w_hi + span;
+                    const int cw = sturm_reg(aA, aB, b2A, b2B, k, xw);
+                    const bool okw = want_min ? (cw == 0) : (cw >= k);
+                    if (okw) {
+                        if (want_min) {
+                            lo = fmax(glo, xw);
+                            hi = fmin(ghi, w_hi);
+                        } else {
+                            lo = fmax(glo, w_lo);
+                            hi = fmin(ghi, xw);
+                        }
+                        if (!(hi > lo)) {
+                            lo = glo;
+                            hi = ghi;
+                        }
+                    }
+                }
 #pragma nounroll
                 for (int it = 0; it < 12; ++it) {
                     const double w = hi - lo;
@@ -668,6 +719,9 @@ tprev = tn;                       \
                 const double th = 0.5 * (lo + hi);
                 const double res =
                     exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
+                w_lo = lo;
+                w_hi = hi;
+                w_r = res;
                 const int src_max = c.min_only ? 0 : 32;
                 if (lane == 0) {
                     sres[0] = th;
@@ -833,12 +887,13 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         // One loop so that the factorisation is instantiated once.
         int phase = a.shift_hi ? 0 : 1;
         bool ok = false;
+        long long cst[3] = {0, 0, 0};  // Cholesky stage cycles (profiling)
         STAMP(1)
         for (;;) {
             const double sh = phase == 0 ? a.shift_hi[chain] : t0;
             for (int e = t; e < P; e += blockDim.x) L[e] = a.membership_only ? Fr[e] : Fr[e] + sh * Br[e];
             lds_barrier();
-            ok = chol_blocked(L, m, scr, sflag);
+            ok = chol_blocked(L, m, scr, sflag, prof ? cst : nullptr);
             lds_barrier();
             if (phase == 0) {
                 if (ok) cert = 2;
@@ -850,6 +905,11 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             t0 = 0.0;
         }
         STAMP(2)
+        if (prof && t == 0) {
+            prof[7] = cst[0];
+            prof[14] = cst[1];
+            prof[15] = cst[2];
+        }
         if (ok && !a.membership_only) tri_inverse(L, m, scr);
         STAMP(3)
         if (!ok) st = SPEC_NOT_INTERIOR;
@@ -1094,7 +1154,10 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                     lc.kmax = kmax;
                     lc.min_only = 1;
                     lc.first_check = 0;
-                    lc.tol = a.tol;
+                    // only a lower bound of lambda_min enters the step: theta - r is a
+                    // bound at any tolerance, a looser one just shortens the step.  D1
+                    // fixes the root and the kernel vector, so it is solved more tightly.
+                    lc.tol = pass == 0 ? fmax(a.tol, 1e-3) : fmax(a.tol, 1e-6);
                     lc.B0 = pass == 0 ? Q2 : Q1;
                     lc.b0 = pass == 0 ? 1.0 : sg;
                     lc.B1 = pass == 0 ? nullptr : Q2;
@@ -1103,7 +1166,7 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                     lc.prof = nullptr;
                     lanczos_extreme(L, scr, lc);
                     __syncthreads();
-                    if (lz.sres[4] != 1.0) conv = false;
+                    if (pass == 1 && lz.sres[4] != 1.0) conv = false;
                     d[pass] = lz.sres[0] - lz.sres[1];
                     lds_barrier();
                 }

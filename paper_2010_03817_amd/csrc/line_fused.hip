@@ -473,6 +473,184 @@ __device__ __forceinline__ double w_row(const double* L, const double* x, int r,
     return s0 + s1;
 }
 
+// Balanced triangular products of the Lanczos step on the packed lower W in
+// LDS, by 16 x 16 tiles.  Worker wave g takes tile columns (W^T x) or tile
+// rows (W x) g and T-1-g, T tiles per side: T+1 tiles per wave (the middle
+// one alone when T is odd), against 2T for the first or last band of a
+// row/column split.  In a tile, lane l holds rows (l >> 4) + 4 s, s < 4, of
+// column l & 15, so that one load reads 16 consecutive entries of 4 rows.
+
+// Rows of a tile row past m are read as row m-1 (valid entries of W for every
+// column left of the diagonal tile) against x = 0, so only the diagonal
+// tile needs a mask; a diagonal entry right of the diagonal is replaced by 0
+// before use (its address is still inside the LDS allocation: at most 15
+// entries past the factor, where the scratch area lies).
+// Lane moves within rows of 16 lanes by DPP (no index registers, no LDS):
+// quad_perm [1,0,3,2] (lane ^ 1), [2,3,0,1] (lane ^ 2), row_ror:8
+// (lane ^ 8), row_half_mirror (lane ^ 7 within 8) and row_mirror (lane ^ 15).
+constexpr int DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_X8 = 0x128, DPP_HMIR = 0x141, DPP_MIR = 0x140;
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave: within rows by DPP, then the four row totals.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_mov<DPP_X1>(v);
+    v += dpp_mov<DPP_X2>(v);
+    v += dpp_mov<DPP_HMIR>(v);
+    v += dpp_mov<DPP_MIR>(v);
+    const long long b = __double_as_longlong(v);
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+        s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+    return s;
+}
+
+// block_sum_lds with the wave sums by DPP (same barriers).
+__device__ __forceinline__ double block_sum_dpp(double v, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum_dpp(v);
+    lds_barrier();
+    if (lane == 0) red[wid] = v;
+    lds_barrier();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+// Column sums of W^T x over tile column J (tiles I = J..T-1).  Lane l takes
+// column 16 J + (l >> 2) and rows 4 q + (l & 3) of each tile (one load still
+// reads 16 consecutive entries of 4 rows); the four lanes of a quad, which
+// share the column, return its sum.  The diagonal tile and a last tile row
+// that ends past m are masked; between them the byte addresses step by
+// pk(r + 16) - pk(r) = 16 r + 136 entries, with no masks.
+__device__ __forceinline__ double wt_col(const double* L, const double* x, int m, int T, int J, int lane) {
+    asm volatile("" : "+v"(lane));  // addressing formed per call, not kept live across the step loop
+    const int p = lane & 3, c = 16 * J + (lane >> 2);
+    const int Iend = (m & 15) ? T - 1 : T;  // tile rows with all 16 rows below m
+    double s = 0.0;
+    auto edge = [&](int I) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * I + 4 * q + p, rr = r < m ? r : m - 1;
+            const double xv = x[rr];
+            const double w = L[pk(rr, 0) + c];
+            s += (r < m && c <= r ? w : 0.0) * (r < m ? xv : 0.0);
+        }
+    };
+    edge(J);
+    if (J + 1 < Iend) {
+        const char* Lb = (const char*)L;
+        const char* xb = (const char*)(x + 16 * (J + 1) + p);
+        int ab[4], d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * (J + 1) + 4 * q + p;
+            ab[q] = 8 * (pk(r, 0) + c);
+            d[q] = 8 * (16 * r + 136);
+        }
+        for (int I = J + 1; I < Iend; ++I) {
+            double w[4], xs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w[q] = *(const double*)(Lb + ab[q]);
+                xs[q] = *(const double*)(xb + 32 * q);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s += w[q] * xs[q];
+                ab[q] += d[q];
+                d[q] += 8 * 256;
+            }
+            xb += 128;
+        }
+    }
+    if (Iend < T && J < T - 1) edge(T - 1);
+    s += dpp_mov<DPP_X1>(s);
+    s += dpp_mov<DPP_X2>(s);
+    return s;
+}
+
+// Column sums of W^T x for tile columns J1 = g (o1) and J2 = T-1-g (o2; zero
+// when J2 = J1), in the lanes that wt_col names.
+__device__ __forceinline__ void wt_tiles(const double* L, const double* x, int m, int T, int g, int lane,
+                                         double& o1, double& o2) {
+    o1 = wt_col(L, x, m, T, g, lane);
+    o2 = T - 1 - g != g ? wt_col(L, x, m, T, T - 1 - g, lane) : 0.0;
+}
+
+// Sum over the 16 lanes of each lane row of four per-row accumulators,
+// exchanging half of them at each of the first two levels (lane ^ 8, then
+// the mirror partner within 8, which differs in bit 2): lane l ends with the
+// total of a[s], s = 2 ((l >> 3) & 1) + ((l >> 2) & 1).
+__device__ __forceinline__ double red16x4(const double a[4], int lane) {
+    const bool b3 = lane & 8, b2 = lane & 4;
+    const double k0 = b3 ? a[2] : a[0], k1 = b3 ? a[3] : a[1];
+    const double s0 = b3 ? a[0] : a[2], s1 = b3 ? a[1] : a[3];
+    const double u0 = k0 + dpp_mov<DPP_X8>(s0), u1 = k1 + dpp_mov<DPP_X8>(s1);
+    double v = (b2 ? u1 : u0) + dpp_mov<DPP_HMIR>(b2 ? u0 : u1);
+    v += dpp_mov<DPP_X2>(v);
+    v += dpp_mov<DPP_X1>(v);
+    return v;
+}
+
+// Row of W x that red16x4 leaves in lane l, within its tile row.
+__device__ __forceinline__ int w_tiles_row(int lane) {
+    return (lane >> 4) + 4 * (2 * ((lane >> 3) & 1) + ((lane >> 2) & 1));
+}
+
+// Row sums of W x over tile row I (tiles J = 0..I): lane l returns the sum
+// of row 16 I + w_tiles_row(l).  The tiles left of the diagonal are read at
+// fixed offsets from four row bases.
+__device__ __forceinline__ double w_strip(const double* L, const double* x, int m, int I, int lane) {
+    asm volatile("" : "+v"(lane));  // addressing formed per call (as in wt_tiles)
+    const int i0 = lane >> 4, j = lane & 15;
+    const double* rp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 16 * I + i0 + 4 * q;
+        rp[q] = L + pk(r < m ? r : m - 1, 0) + j;
+    }
+    const double* xp = x + j;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int J = 0; J < I; ++J) {
+        const double xv = xp[16 * J];
+        double w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = rp[q][16 * J];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] += w[q] * xv;
+    }
+    {  // diagonal tile
+        const int c = 16 * I + j;
+        const double xr = x[c < m ? c : 0];
+        const double xv = c < m ? xr : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double w = rp[q][16 * I];
+            a[q] += (c <= 16 * I + i0 + 4 * q ? w : 0.0) * xv;
+        }
+    }
+    return red16x4(a, lane);
+}
+
+// Row sums of W x for tile rows I1 = g (o1) and I2 = T-1-g (o2; zero when
+// I2 = I1), in the lanes that w_strip names.
+__device__ __forceinline__ void w_tiles(const double* L, const double* x, int m, int T, int g, int lane,
+                                        double& o1, double& o2) {
+    o1 = w_strip(L, x, m, g, lane);
+    o2 = T - 1 - g != g ? w_strip(L, x, m, T - 1 - g, lane) : 0.0;
+}
+
 // Scratch layout of the Lanczos phase (after the factor phase).
 struct LzLayout {
     double *slot, *al, *be, *red, *sres;
@@ -529,7 +707,10 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     double* sres = red + 8;        // 8: theta_min, r_min, theta_max, r_max, stop, k
     double* Qg = c.Qg;
     for (int e = m + t; e < 2 * MAXH; e += blockDim.x) slot[e] = 0.0;
-    const int R0w = 32 * (wv - 1);  // first column of this worker wave in W^T x
+    // tile pair of this worker wave: ceil(T/2) pairs for ceil(m/32) worker waves
+    const int T = (m + 15) >> 4;
+    const int g = wv - 1, g2 = T - 1 - g;
+    const bool gact = worker && g <= g2;
     // start vector (deterministic, positive)
     double qr = 0.0;
     if (own) {
@@ -559,11 +740,16 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
                 slot[r] = qr;
             }
             lds_barrier();  // B1
-            // a = W^T q, lanes (c, h) over row halves of the wave's band
-            double av = own ? wt_column(L, slot, r, R0w, m, h) : 0.0;
-            av += __shfl_xor(av, 1, 64);
+            // a = W^T q over this wave's pair of tile columns
+            double a1 = 0.0, a2 = 0.0;
+            if (gact) wt_tiles(L, slot, m, T, g, lane, a1, a2);
             lds_barrier();  // B2
-            if (own && h == 0) slot[r] = av;
+            if (gact && (lane & 3) == 0) {
+                int l = lane >> 2;
+                asm volatile("" : "+v"(l));
+                if (16 * g + l < m) slot[16 * g + l] = a1;
+                if (g2 != g && 16 * g2 + l < m) slot[16 * g2 + l] = a2;
+            }
             lds_barrier();  // B3
             // b = B a from registers
             double bv = 0.0;
@@ -578,18 +764,30 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
-            bv += __shfl_xor(bv, 1, 64);
+            bv += dpp_mov<DPP_X1>(bv);
             lds_barrier();  // B4
             if (own && h == 0) slot[r] = bv;
             lds_barrier();  // B5
-            // c = W b
-            double cv = own ? w_row(L, slot, r, h) : 0.0;
-            cv += __shfl_xor(cv, 1, 64);
-            const double alj = wave_uniform(block_sum_lds((own && h == 0) ? qr * cv : 0.0, red));  // B6, B7
+            // c = W b over this wave's pair of tile rows
+            double cw1 = 0.0, cw2 = 0.0;
+            if (gact) w_tiles(L, slot, m, T, g, lane, cw1, cw2);
+            lds_barrier();  // B6
+            if (gact && (lane & 3) == 0) {
+                int l = lane;
+                asm volatile("" : "+v"(l));
+                const int rr = w_tiles_row(l);
+                if (16 * g + rr < m) slot[16 * g + rr] = cw1;
+                if (g2 != g && 16 * g2 + rr < m) slot[16 * g2 + rr] = cw2;
+            }
+            lds_barrier();  // B7
+            // alpha = q^T c from the computed c, so that the new residual is
+            // orthogonal to q to working precision whatever the conditioning of W
+            double cv = own ? slot[r] : 0.0;
+            const double alj = wave_uniform(block_sum_dpp((own && h == 0) ? qr * cv : 0.0, red));  // B8, B9
             cv -= alj * qr + bprev * qprev;
-            const double bn = wave_uniform(sqrt(block_sum_lds((own && h == 0) ? cv * cv : 0.0, red)));  // B8, B9
-            lds_barrier();  // B10 (control wave stores alpha, beta)
-            lds_barrier();  // B11 (control wave decides)
+            const double bn = wave_uniform(sqrt(block_sum_dpp((own && h == 0) ? cv * cv : 0.0, red)));  // B10, B11
+            lds_barrier();  // B12 (control wave stores alpha, beta)
+            lds_barrier();  // B13 (control wave decides)
             if (sres[4] != 0.0) break;
             qprev = qr;
             qr = cv * (1.0 / bn);
@@ -632,14 +830,16 @@ tprev = tn;                       \
             lds_barrier();  // B4
             PHASE(2)
             lds_barrier();  // B5
-            const double alj = block_sum_lds(0.0, red);           // B6, B7
+            lds_barrier();  // B6
+            lds_barrier();  // B7
+            const double alj = block_sum_lds(0.0, red);           // B8, B9
             PHASE(3)
-            const double bn = sqrt(block_sum_lds(0.0, red));      // B8, B9
+            const double bn = sqrt(block_sum_lds(0.0, red));      // B10, B11
             if (lane == 0) {
                 al[j] = alj;
                 be[j + 1] = bn;
             }
-            lds_barrier();  // B10
+            lds_barrier();  // B12
             PHASE(4)
             const int k = j + 1;
             const bool exhausted = bn <= 1e-14 * fmax(fabs(al[0]), 1e-300);
@@ -767,7 +967,7 @@ tprev = tn;                       \
                 sres[5] = (double)k;
                 if (stop != 0.0) sres[6] += (double)k;
             }
-            lds_barrier();  // B11
+            lds_barrier();  // B13
             PHASE(5)
             if (stop != 0.0) break;
         }
@@ -926,7 +1126,6 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             double* be = lz.be;
             double* sres = lz.sres;
             double* Qg = a.Q + (size_t)chain * a.ldq;
-            const int R0w = 32 * (wv - 1);  // first column of this worker wave in W^T x
             STAMP(4)
             LzCtx lc;
             lc.m = m;

@@ -154,6 +154,115 @@ __device__ __forceinline__ void dense_trinv16(double* T, int lane) {
     }
 }
 
+// Lane k of each 16-lane row broadcast to the whole row (DPP row_newbcast).
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x150 + K, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + K, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1 / sqrt(d) for a positive pivot: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - d y^2) / 2 (quadratic convergence from its
+// ~2^-23 relative error to the rounding level); tiny or huge d take the
+// correctly rounded library form.
+__device__ __forceinline__ double rsqrt_pivot(double d) {
+    if (!(d > 1e-280 && d < 1e280)) return 1.0 / sqrt(d);
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double r = fma(-d * y, y, 1.0);
+        y = fma(0.5 * y, r, y);
+    }
+    return y;
+}
+
+// Unrolled steps of the diagonal-tile factorisation (column J, then J + 1..).
+// Lane J keeps 1 / L_JJ in a[J]: its own diagonal entry is read only as that
+// reciprocal afterwards.
+template <int J>
+struct DiagSteps {
+    // trailing update of column K > J by column J: a_iK -= l_iJ l_KJ
+    template <int K, bool = (K < 16)>
+    struct Upd {
+        __device__ __forceinline__ static void run(double (&a)[16]) {
+            a[K] -= a[J] * row_bcast<K>(a[J]);
+            Upd<K + 1>::run(a);
+        }
+    };
+    template <int K>
+    struct Upd<K, false> {
+        __device__ __forceinline__ static void run(double (&)[16]) {}
+    };
+    __device__ __forceinline__ static bool run(double (&a)[16], int i) {
+        __builtin_amdgcn_sched_barrier(0);  // one column at a time (bounds the live broadcasts)
+        const double d = row_bcast<J>(a[J]);
+        if (!(d > 0.0)) return false;  // the same pivot in every lane
+        const double iv = rsqrt_pivot(d);
+        a[J] = i == J ? iv : a[J] * iv;
+        Upd<J + 1>::run(a);
+        return DiagSteps<J + 1>::run(a, i);
+    }
+};
+template <>
+struct DiagSteps<16> {
+    __device__ __forceinline__ static bool run(double (&)[16], int) { return true; }
+};
+
+// Unrolled rows I of the inverse of the factor, for the column c a lane holds:
+// W_Ic = (delta_Ic - sum_{k<I} L_Ik W_kc) / L_II.
+template <int I>
+struct InvSteps {
+    template <int K, bool = (K < I)>
+    struct Dot {
+        __device__ __forceinline__ static double run(const double (&a)[16], const double (&w)[16], double s) {
+            return Dot<K + 1>::run(a, w, s - row_bcast<I>(a[K]) * w[K]);
+        }
+    };
+    template <int K>
+    struct Dot<K, false> {
+        __device__ __forceinline__ static double run(const double (&)[16], const double (&)[16], double s) { return s; }
+    };
+    __device__ __forceinline__ static void run(const double (&a)[16], double (&w)[16], int c) {
+        __builtin_amdgcn_sched_barrier(0);
+        w[I] = Dot<0>::run(a, w, c == I ? 1.0 : 0.0) * row_bcast<I>(a[I]);
+        InvSteps<I + 1>::run(a, w, c);
+    }
+};
+template <>
+struct InvSteps<16> {
+    __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], int) {}
+};
+
+// Diagonal tile K of the blocked factorisation, in registers of one wave:
+// lane l holds row l & 15 of the tile (the four 16-lane rows of the wave hold
+// the same data), factors it by columns with row broadcasts, then forms the
+// inverse of the factor by columns (lane l computes column l & 15:
+// W_Ic = (delta_Ic - sum_{k<I} L_Ik W_kc) / L_II) and stores it in place of
+// the tile (lower part; rows past m are the identity and are not stored).
+// Returns false when a pivot is not positive (every lane agrees).
+__device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane) {
+    asm volatile("" : "+v"(lane));  // lane masks formed per call, not hoisted out of the tile loop
+    const int i = lane & 15, r = 16 * K + i;
+    const double* row = L + pk(r < m ? r : 16 * K, 16 * K);
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const double v = row[c];
+        a[c] = r < m ? (c <= i ? v : 0.0) : (c == i ? 1.0 : 0.0);
+    }
+    if (!DiagSteps<0>::run(a, i)) return false;
+    double w[16];
+    InvSteps<0>::run(a, w, i);
+    if (lane < 16) {
+#pragma unroll
+        for (int I = 0; I < 16; ++I)
+            if (I >= i && 16 * K + I < m) L[pk(16 * K + I, 16 * K) + i] = w[I];
+    }
+    return true;
+}
+
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
 // prof (nullable): thread 0 adds the cycles of the diagonal-tile, panel and
@@ -172,24 +281,19 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
     }
     for (int K = 0; K < T; ++K) {
         if (wv == 0) {
-            tile_to_dense(L, m, K, D, lane);
-            const bool ok = dense_chol16(D, lane);
+            const bool ok = diag_factor16(L, m, K, lane);
             if (lane == 0) *flag = ok ? 1 : 0;
-            if (ok) {
-                dense_to_tile(L, m, K, D, lane);
-                dense_trinv16(D, lane);
-            }
         }
         lds_barrier();
         CHOL_TICK(c0)
         if (*flag == 0) return false;
-        // panel: L_IK = A_IK D^T
+        // panel: L_IK = A_IK W_KK^T (W_KK = L_KK^{-1}, now in the diagonal tile)
         for (int I = K + 1 + wv; I < T; I += nw) {
             d4 acc{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const double a = tl(L, m, I, K, lane & 15, 4 * s + (lane >> 4));
-                const double b = D[sw(lane & 15, 4 * s + (lane >> 4))];
+                const double b = tl(L, m, K, K, lane & 15, 4 * s + (lane >> 4));
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
             acc_to_tile(L, m, I, K, acc, lane);
@@ -228,18 +332,14 @@ __device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int T = (m + 15) / 16;
     for (int J = T - 1; J >= 0; --J) {
-        if (wv == 0) {
-            tile_to_dense(L, m, J, D, lane);
-            dense_trinv16(D, lane);
-        }
-        lds_barrier();
-        // P_KJ = L_KJ D for K > J, in place
+        // P_KJ = L_KJ W_JJ for K > J, in place (W_JJ = L_JJ^{-1}, left in the
+        // diagonal tile by the factorisation)
         for (int K = J + 1 + wv; K < T; K += nw) {
             d4 acc{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const double a = tl(L, m, K, J, lane & 15, 4 * s + (lane >> 4));
-                const double b = D[sw(4 * s + (lane >> 4), lane & 15)];
+                const double b = tl(L, m, J, J, 4 * s + (lane >> 4), lane & 15);
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
             acc_to_tile(L, m, K, J, acc, lane);
@@ -268,12 +368,6 @@ __device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
         for (int q = 0; q < 4; ++q) {
             const int I = J + 1 + wv + q * nw;
             if (I < T) acc_to_tile(L, m, I, J, res[q], lane);
-        }
-        if (wv == 0) {
-            for (int e = lane; e < 256; e += 64) {
-                const int i = e >> 4, c = e & 15, r = 16 * J + i, cc = 16 * J + c;
-                if (r < m && c <= i) L[pk(r, cc)] = D[sw(i, c)];
-            }
         }
         lds_barrier();
     }
@@ -492,8 +586,8 @@ constexpr int DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_X8 = 0x128, DPP_HMIR = 0x141, DP
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

@@ -488,6 +488,40 @@ __device__ inline int sturm_reg(double aA, double aB, double b2A, double b2B, in
 
 // 1/|y| for the eigenvector y of T_k (backward recurrence, y_{k-1} = 1);
 // rbA/rbB hold 1/be_i.
+// Sturm count of T_k below this lane's x with T_k read from LDS (al, be; the
+// same address in every lane, a broadcast): blocks of 8 steps whose loads are
+// issued ahead of the recurrence, with a power-of-two rescaling after each
+// block (exact, so the count is that of the plain recurrence).
+__device__ inline int sturm_lds(const double* al, const double* be, int k, double x) {
+    k = __builtin_amdgcn_readfirstlane(k);
+    double pm = 1.0, pc = al[0] - x;
+    int cnt = pc < 0.0;
+#define STURM_STEP(av, bv)                                 \
+    {                                                      \
+        const double pn = ((av) - x) * pc - ((bv) * (bv)) * pm; \
+        cnt += (pn < 0.0) != (pc < 0.0);                   \
+        pm = pc;                                           \
+        pc = pn;                                           \
+    }
+    int i = 1;
+    for (; i + 8 <= k; i += 8) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            av[u] = al[i + u];
+            bv[u] = be[i + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) STURM_STEP(av[u], bv[u])
+        const int e = ilogb(fabs(pc) + fabs(pm) + 1e-300);
+        pc = ldexp(pc, -e);
+        pm = ldexp(pm, -e);
+    }
+    for (; i < k; ++i) STURM_STEP(al[i], be[i])
+#undef STURM_STEP
+    return cnt;
+}
+
 __device__ inline double backward_norm_reg(double aA, double aB, double bA, double bB, double rbA, double rbB, int k,
                                            double th) {
     double y1 = 1.0, y0 = 0.0, ss = 1.0;
@@ -977,7 +1011,7 @@ tprev = tn;                       \
                 if (w_lo == w_lo) {
                     const double span = 4.0 * w_r + 16.0 * (w_hi - w_lo) + 1e-12 * fmax(fabs(w_lo), fabs(w_hi));
                     const double xw = want_min ? w_lo - span : w_hi + span;
-                    const int cw = sturm_reg(aA, aB, b2A, b2B, k, xw);
+                    const int cw = sturm_lds(al, be, k, xw);
                     const bool okw = want_min ? (cw == 0) : (cw >= k);
                     if (okw) {
                         if (want_min) {
@@ -993,30 +1027,62 @@ tprev = tn;                       \
                         }
                     }
                 }
+                // multisection down to a relative width rel (at most 12 passes)
+                auto msect = [&](double rel) {
 #pragma nounroll
-                for (int it = 0; it < 12; ++it) {
-                    const double w = hi - lo;
-                    if (!(w > 2e-16 * fmax(fabs(lo), fabs(hi)))) break;
-                    const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
-                    const int cnt = sturm_reg(aA, aB, b2A, b2B, k, x);
-                    const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
-                    const unsigned long long mask = __ballot(hitp);
-                    unsigned long long hm;
-                    if (c.min_only) hm = mask;
-                    else hm = want_min ? (mask & 0xffffffffull) : (mask >> 32);
-                    const int first = hm ? __ffsll((long long)hm) - 1 : npts;
-                    const double nlo = lo + w * (double)first / (double)(npts + 1);
-                    const double nhi = first < npts ? lo + w * (double)(first + 1) / (double)(npts + 1) : hi;
-                    lo = nlo;
-                    hi = nhi;
+                    for (int it = 0; it < 12; ++it) {
+                        const double w = hi - lo;
+                        if (!(w > rel * fmax(fabs(lo), fabs(hi)))) break;
+                        const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
+                        const int cnt = sturm_lds(al, be, k, x);
+                        const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
+                        const unsigned long long mask = __ballot(hitp);
+                        unsigned long long hm;
+                        if (c.min_only) hm = mask;
+                        else hm = want_min ? (mask & 0xffffffffull) : (mask >> 32);
+                        const int first = hm ? __ffsll((long long)hm) - 1 : npts;
+                        const double nlo = lo + w * (double)first / (double)(npts + 1);
+                        const double nhi = first < npts ? lo + w * (double)(first + 1) / (double)(npts + 1) : hi;
+                        lo = nlo;
+                        hi = nhi;
+                    }
+                };
+                const int src_max = c.min_only ? 0 : 32;
+                double th = 0.0, res = 0.0, thmin = 0.0, thmax = 0.0, tmin = 0.0, tmax = 0.0;
+                bool conv_now = false;
+                // residual bound below tol |theta|, or at the rounding level of C
+                // (scaled by the spectral radius: Gershgorin bound of T_k, which
+                // also covers lambda_max when only lambda_min is tracked).  The
+                // bound hardly depends on theta once theta is far closer to the
+                // Ritz value than the gap, so the test runs with theta to 1e-10
+                // (relative) and a passing test (or the last step) is repeated
+                // with theta to the rounding level.
+                double rmin = 0.0, rmax = 0.0;
+                auto test = [&]() {
+                    th = 0.5 * (lo + hi);
+                    res = exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
+                    thmin = __shfl(th, 0, 64);
+                    thmax = __shfl(th, src_max, 64);
+                    rmin = __shfl(res, 0, 64);
+                    rmax = __shfl(res, src_max, 64);
+                    const double rho = fmax(fmax(fabs(thmin), c.min_only ? 0.0 : fabs(thmax)),
+                                            fmax(fabs(glo), fabs(ghi)));
+                    const double floor_r = 2.2e-14 * rho;
+                    tmin = fmax(c.tol * fabs(thmin), floor_r);
+                    tmax = fmax(c.tol * fabs(thmax), floor_r);
+                    const bool cmin = rmin <= tmin;
+                    const bool cmax = c.min_only || rmax <= tmax;
+                    conv_now = exhausted || (cmin && cmax);
+                };
+                msect(1e-10);
+                test();
+                if (conv_now || k == kmax) {
+                    msect(2e-16);
+                    test();
                 }
-                const double th = 0.5 * (lo + hi);
-                const double res =
-                    exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
                 w_lo = lo;
                 w_hi = hi;
                 w_r = res;
-                const int src_max = c.min_only ? 0 : 32;
                 if (lane == 0) {
                     sres[0] = th;
                     sres[1] = res;
@@ -1025,19 +1091,6 @@ tprev = tn;                       \
                     sres[2] = c.min_only ? NAN : th;
                     sres[3] = c.min_only ? 0.0 : res;
                 }
-                const double thmin = __shfl(th, 0, 64), thmax = __shfl(th, src_max, 64);
-                const double rmin = __shfl(res, 0, 64), rmax = __shfl(res, src_max, 64);
-                // residual bound below tol |theta|, or at the rounding level of C
-                // (scaled by the spectral radius: Gershgorin bound of T_k, which
-                // also covers lambda_max when only lambda_min is tracked)
-                const double rho = fmax(fmax(fabs(thmin), c.min_only ? 0.0 : fabs(thmax)),
-                                        fmax(fabs(glo), fabs(ghi)));
-                const double floor_r = 2.2e-14 * rho;
-                const double tmin = fmax(c.tol * fabs(thmin), floor_r);
-                const double tmax = fmax(c.tol * fabs(thmax), floor_r);
-                const bool cmin = rmin <= tmin;
-                const bool cmax = c.min_only || rmax <= tmax;
-                const bool conv_now = exhausted || (cmin && cmax);
                 if (conv_now) stop = 1.0;
                 else if (k == kmax) stop = 2.0;
                 // next test: where the residual decay since the last test predicts

@@ -879,19 +879,31 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
                 if (g2 != g && 16 * g2 + l < m) slot[16 * g2 + l] = a2;
             }
             lds_barrier();  // B3
-            // b = B a from registers
-            double bv = 0.0;
+            // b = B a from registers; the broadcast loads of a run one group of
+            // four ahead of the products (two groups in flight), the schedule
+            // pinned group by group so that the loads are not all hoisted
+            double bv = 0.0, bw = 0.0;
             {
                 const double* sv = slot + c0;
+                double cur[4], nxt[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cur[u] = sv[u];
 #pragma unroll
                 for (int kk = 0; kk < MAXH; kk += 4) {
-                    bv += breg[kk] * sv[kk];
-                    bv += breg[kk + 1] * sv[kk + 1];
-                    bv += breg[kk + 2] * sv[kk + 2];
-                    bv += breg[kk + 3] * sv[kk + 3];
+                    if (kk + 4 < MAXH) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) nxt[u] = sv[kk + 4 + u];
+                    }
+                    bv += breg[kk] * cur[0];
+                    bw += breg[kk + 1] * cur[1];
+                    bv += breg[kk + 2] * cur[2];
+                    bw += breg[kk + 3] * cur[3];
                     __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
                 }
             }
+            bv += bw;
             bv += dpp_mov<DPP_X1>(bv);
             lds_barrier();  // B4
             if (own && h == 0) slot[r] = bv;

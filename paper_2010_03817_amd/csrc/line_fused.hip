@@ -76,6 +76,13 @@ __device__ __forceinline__ void acc_to_tile(double* L, int m, int I, int J, d4 a
 // 16 i + (j ^ i), so that a column is spread over all banks.
 __device__ __forceinline__ int sw(int i, int j) { return 16 * i + (j ^ i); }
 
+// Packed offset of row r with rows past m read as row m - 1: a valid address
+// whose (garbage) entries only reach results that are not stored.
+__device__ __forceinline__ int rowb(int r, int m) {
+    const int rr = r < m ? r : m - 1;
+    return (rr * (rr + 1)) >> 1;
+}
+
 // Copy the lower part of diagonal tile K of the packed matrix into the dense
 // tile T (identity on rows past m, zeros above the diagonal).  One wave.
 __device__ __forceinline__ void tile_to_dense(const double* L, int m, int K, double* T, int lane) {
@@ -271,6 +278,7 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lh = lane >> 4;
     const int T = (m + 15) / 16;
     long long c0 = 0, c1 = 0, c2 = 0, tc = prof ? clock64() : 0;
 #define CHOL_TICK(acc)                       \
@@ -287,16 +295,31 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
         lds_barrier();
         CHOL_TICK(c0)
         if (*flag == 0) return false;
-        // panel: L_IK = A_IK W_KK^T (W_KK = L_KK^{-1}, now in the diagonal tile)
-        for (int I = K + 1 + wv; I < T; I += nw) {
-            d4 acc{0.0, 0.0, 0.0, 0.0};
+        // panel: L_IK = A_IK W_KK^T (W_KK = L_KK^{-1}, now in the diagonal tile).
+        // MFMA operands: lane l holds X[l & 15][4 s + (l >> 4)] of the left and
+        // Y[l & 15][4 s + (l >> 4)] of the right factor of X Y^T; results land
+        // in rows (l >> 4) + 4 r, column l & 15.
+        if (K + 1 < T) {
+            double wk[4];
+            {
+                const double* pw = L + rowb(16 * K + li, m) + 16 * K + lh;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const double a = tl(L, m, I, K, lane & 15, 4 * s + (lane >> 4));
-                const double b = tl(L, m, K, K, lane & 15, 4 * s + (lane >> 4));
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                for (int s = 0; s < 4; ++s) {
+                    const double w = pw[4 * s];
+                    wk[s] = 4 * s + lh <= li ? w : 0.0;
+                }
             }
-            acc_to_tile(L, m, I, K, acc, lane);
+            for (int I = K + 1 + wv; I < T; I += nw) {
+                const double* pa = L + rowb(16 * I + li, m) + 16 * K + lh;
+                d4 acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], wk[s], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * I + lh + 4 * r;
+                    if (row < m) L[rowb(row, m) + 16 * K + li] = acc[r];
+                }
+            }
         }
         lds_barrier();
         CHOL_TICK(c1)
@@ -308,9 +331,22 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
             while (ii * (ii + 1) / 2 > e) --ii;
             const int jj = e - ii * (ii + 1) / 2;
             const int I = K + 1 + ii, J = K + 1 + jj;
-            d4 acc = tile_to_acc(L, m, I, J, lane);
-            acc = mm_xyt(acc, L, m, I, K, J, K, -1.0, lane);
-            acc_to_tile(L, m, I, J, acc, lane);
+            const double* pa = L + rowb(16 * I + li, m) + 16 * K + lh;
+            const double* pb = L + rowb(16 * J + li, m) + 16 * K + lh;
+            int ab[4];
+            d4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ab[r] = rowb(16 * I + lh + 4 * r, m) + 16 * J + li;
+                acc[r] = L[ab[r]];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * s], pb[4 * s], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * I + lh + 4 * r, col = 16 * J + li;
+                if (row < m && col <= row) L[ab[r]] = acc[r];
+            }
         }
         lds_barrier();
         CHOL_TICK(c2)
@@ -330,33 +366,50 @@ __device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lh = lane >> 4;
     const int T = (m + 15) / 16;
     for (int J = T - 1; J >= 0; --J) {
         // P_KJ = L_KJ W_JJ for K > J, in place (W_JJ = L_JJ^{-1}, left in the
-        // diagonal tile by the factorisation)
-        for (int K = J + 1 + wv; K < T; K += nw) {
-            d4 acc{0.0, 0.0, 0.0, 0.0};
+        // diagonal tile by the factorisation; right operand W_JJ[4 s + (l >> 4)][l & 15])
+        if (J + 1 < T) {
+            double wj[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const double a = tl(L, m, K, J, lane & 15, 4 * s + (lane >> 4));
-                const double b = tl(L, m, J, J, 4 * s + (lane >> 4), lane & 15);
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                const double w = L[rowb(16 * J + 4 * s + lh, m) + 16 * J + li];
+                wj[s] = li <= 4 * s + lh ? w : 0.0;
             }
-            acc_to_tile(L, m, K, J, acc, lane);
+            for (int K = J + 1 + wv; K < T; K += nw) {
+                const double* pa = L + rowb(16 * K + li, m) + 16 * J + lh;
+                d4 acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], wj[s], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * K + lh + 4 * r;
+                    if (row < m) L[rowb(row, m) + 16 * J + li] = acc[r];
+                }
+            }
         }
         lds_barrier();
-        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ (tiles I = J+1+wv + q nw, q < 4)
+        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ (tiles I = J+1+wv + q nw, q < 4).  Right
+        // operand P_KJ[4 s + (l >> 4)][l & 15]; its rows past m are zeroed, since
+        // the matching columns of W_IK are zero and garbage there must not meet them.
         d4 res[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int I = J + 1 + wv + q * nw;
             d4 acc{0.0, 0.0, 0.0, 0.0};
             if (I < T) {
+                const int rbI = rowb(16 * I + li, m);
                 for (int K = J + 1; K <= I; ++K) {
+                    const double* pa = L + rbI + 16 * K + lh;
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        const double a = tl(L, m, I, K, lane & 15, 4 * s + (lane >> 4));
-                        const double b = tl(L, m, K, J, 4 * s + (lane >> 4), lane & 15);
+                        const int kr = 16 * K + 4 * s + lh;
+                        const double av = pa[4 * s];
+                        const double a = (K < I || 4 * s + lh <= li) ? av : 0.0;
+                        const double bv = L[rowb(kr, m) + 16 * J + li];
+                        const double b = kr < m ? bv : 0.0;
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                     }
                 }
@@ -367,7 +420,13 @@ __device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int I = J + 1 + wv + q * nw;
-            if (I < T) acc_to_tile(L, m, I, J, res[q], lane);
+            if (I < T) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * I + lh + 4 * r;
+                    if (row < m) L[rowb(row, m) + 16 * J + li] = res[q][r];
+                }
+            }
         }
         lds_barrier();
     }

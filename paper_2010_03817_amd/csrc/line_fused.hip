@@ -287,19 +287,39 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
         acc += tn - tc;                      \
         tc = tn;                             \
     }
-    for (int K = 0; K < T; ++K) {
-        if (wv == 0) {
-            const bool ok = diag_factor16(L, m, K, lane);
-            if (lane == 0) *flag = ok ? 1 : 0;
+    // A_IJ -= L_IK L_JK^T for one tile, K < J <= I
+    auto trail_tile = [&](int K, int I, int J) {
+        const double* pa = L + rowb(16 * I + li, m) + 16 * K + lh;
+        const double* pb = L + rowb(16 * J + li, m) + 16 * K + lh;
+        int ab[4];
+        d4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            ab[r] = rowb(16 * I + lh + 4 * r, m) + 16 * J + li;
+            acc[r] = L[ab[r]];
         }
-        lds_barrier();
-        CHOL_TICK(c0)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * s], pb[4 * s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * I + lh + 4 * r, col = 16 * J + li;
+            if (row < m && col <= row) L[ab[r]] = acc[r];
+        }
+    };
+    if (wv == 0) {
+        const bool ok = diag_factor16(L, m, 0, lane);
+        if (lane == 0) *flag = ok ? 1 : 0;
+    }
+    lds_barrier();
+    CHOL_TICK(c0)
+    for (int K = 0; K < T; ++K) {
         if (*flag == 0) return false;
+        if (K + 1 == T) break;
         // panel: L_IK = A_IK W_KK^T (W_KK = L_KK^{-1}, now in the diagonal tile).
         // MFMA operands: lane l holds X[l & 15][4 s + (l >> 4)] of the left and
         // Y[l & 15][4 s + (l >> 4)] of the right factor of X Y^T; results land
         // in rows (l >> 4) + 4 r, column l & 15.
-        if (K + 1 < T) {
+        {
             double wk[4];
             {
                 const double* pw = L + rowb(16 * K + li, m) + 16 * K + lh;
@@ -323,29 +343,21 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
         }
         lds_barrier();
         CHOL_TICK(c1)
-        // trailing update A_IJ -= L_IK L_JK^T, K < J <= I
+        // trailing update, K < J <= I, with look-ahead: wave 0 updates the next
+        // diagonal tile and factors it (its own LDS writes are seen by its later
+        // reads) while the other waves update the remaining tiles
         const int R = T - K - 1;
-        for (int e = wv; e < R * (R + 1) / 2; e += nw) {
-            int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-            while (ii * (ii + 1) / 2 > e) --ii;
-            const int jj = e - ii * (ii + 1) / 2;
-            const int I = K + 1 + ii, J = K + 1 + jj;
-            const double* pa = L + rowb(16 * I + li, m) + 16 * K + lh;
-            const double* pb = L + rowb(16 * J + li, m) + 16 * K + lh;
-            int ab[4];
-            d4 acc;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                ab[r] = rowb(16 * I + lh + 4 * r, m) + 16 * J + li;
-                acc[r] = L[ab[r]];
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * s], pb[4 * s], acc, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * I + lh + 4 * r, col = 16 * J + li;
-                if (row < m && col <= row) L[ab[r]] = acc[r];
+        if (wv == 0) {
+            trail_tile(K, K + 1, K + 1);
+            const bool ok = diag_factor16(L, m, K + 1, lane);
+            if (lane == 0) *flag = ok ? 1 : 0;
+        } else {
+            for (int e = wv; e < R * (R + 1) / 2; e += nw - 1) {
+                int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+                while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+                while (ii * (ii + 1) / 2 > e) --ii;
+                const int jj = e - ii * (ii + 1) / 2;
+                trail_tile(K, K + 1 + ii, K + 1 + jj);
             }
         }
         lds_barrier();

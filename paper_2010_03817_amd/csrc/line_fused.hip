@@ -217,29 +217,31 @@ struct DiagSteps<16> {
     __device__ __forceinline__ static bool run(double (&)[16], int) { return true; }
 };
 
-// Unrolled rows I of the inverse of the factor, for the column c a lane holds:
-// W_Ic = (delta_Ic - sum_{k<I} L_Ik W_kc) / L_II.
+// Unrolled rows I of the inverse of the factor, for the column c a lane holds,
+// right-looking: W_Ic = s_I / L_II, then s_I' -= L_I'I W_Ic for every I' > I
+// (s starts as the unit vector e_c), so that each row waits on one product.
 template <int I>
 struct InvSteps {
-    template <int K, bool = (K < I)>
-    struct Dot {
-        __device__ __forceinline__ static double run(const double (&a)[16], const double (&w)[16], double s) {
-            return Dot<K + 1>::run(a, w, s - row_bcast<I>(a[K]) * w[K]);
+    template <int J, bool = (J < 16)>
+    struct Upd {
+        __device__ __forceinline__ static void run(const double (&a)[16], double (&sv)[16], double w) {
+            sv[J] -= row_bcast<J>(a[I]) * w;
+            Upd<J + 1>::run(a, sv, w);
         }
     };
-    template <int K>
-    struct Dot<K, false> {
-        __device__ __forceinline__ static double run(const double (&)[16], const double (&)[16], double s) { return s; }
+    template <int J>
+    struct Upd<J, false> {
+        __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double) {}
     };
-    __device__ __forceinline__ static void run(const double (&a)[16], double (&w)[16], int c) {
-        __builtin_amdgcn_sched_barrier(0);
-        w[I] = Dot<0>::run(a, w, c == I ? 1.0 : 0.0) * row_bcast<I>(a[I]);
-        InvSteps<I + 1>::run(a, w, c);
+    __device__ __forceinline__ static void run(const double (&a)[16], double (&sv)[16], double (&w)[16]) {
+        w[I] = sv[I] * row_bcast<I>(a[I]);
+        Upd<I + 1>::run(a, sv, w[I]);
+        InvSteps<I + 1>::run(a, sv, w);
     }
 };
 template <>
 struct InvSteps<16> {
-    __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], int) {}
+    __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double (&)[16]) {}
 };
 
 // Diagonal tile K of the blocked factorisation, in registers of one wave:
@@ -260,8 +262,10 @@ __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane)
         a[c] = r < m ? (c <= i ? v : 0.0) : (c == i ? 1.0 : 0.0);
     }
     if (!DiagSteps<0>::run(a, i)) return false;
-    double w[16];
-    InvSteps<0>::run(a, w, i);
+    double w[16], sv[16];
+#pragma unroll
+    for (int I = 0; I < 16; ++I) sv[I] = I == i ? 1.0 : 0.0;
+    InvSteps<0>::run(a, sv, w);
     if (lane < 16) {
 #pragma unroll
         for (int I = 0; I < 16; ++I)

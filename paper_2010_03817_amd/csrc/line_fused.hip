@@ -782,14 +782,6 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
     return s;
 }
 
-// Column sums of W^T x for tile columns J1 = g (o1) and J2 = T-1-g (o2; zero
-// when J2 = J1), in the lanes that wt_col names.
-__device__ __forceinline__ void wt_tiles(const double* L, const double* x, int m, int T, int g, int lane,
-                                         double& o1, double& o2) {
-    o1 = wt_col(L, x, m, T, g, lane);
-    o2 = T - 1 - g != g ? wt_col(L, x, m, T, T - 1 - g, lane) : 0.0;
-}
-
 // Sum over the 16 lanes of each lane row of four per-row accumulators,
 // exchanging half of them at each of the first two levels (lane ^ 8, then
 // the mirror partner within 8, which differs in bit 2): lane l ends with the
@@ -814,7 +806,7 @@ __device__ __forceinline__ int w_tiles_row(int lane) {
 // of row 16 I + w_tiles_row(l).  The tiles left of the diagonal are read at
 // fixed offsets from four row bases.
 __device__ __forceinline__ double w_strip(const double* L, const double* x, int m, int I, int lane) {
-    asm volatile("" : "+v"(lane));  // addressing formed per call (as in wt_tiles)
+    asm volatile("" : "+v"(lane));  // addressing formed per call (as in wt_col)
     const int i0 = lane >> 4, j = lane & 15;
     const double* rp[4];
 #pragma unroll
@@ -846,12 +838,41 @@ __device__ __forceinline__ double w_strip(const double* L, const double* x, int 
     return red16x4(a, lane);
 }
 
-// Row sums of W x for tile rows I1 = g (o1) and I2 = T-1-g (o2; zero when
-// I2 = I1), in the lanes that w_strip names.
-__device__ __forceinline__ void w_tiles(const double* L, const double* x, int m, int T, int g, int lane,
-                                        double& o1, double& o2) {
-    o1 = w_strip(L, x, m, g, lane);
-    o2 = T - 1 - g != g ? w_strip(L, x, m, T - 1 - g, lane) : 0.0;
+// Work of wave w (of nw, the steering wave included) in the two triangular
+// products: the T tile columns (W^T x) or tile rows (W x) ordered by size,
+// T - s tiles for item s, are dealt in pairs {w, 2 nw - 1 - w} (an item past
+// T is absent; T <= 2 nw - 2 for every m).  The sizes then total at most T
+// per wave, and the waves sharing a SIMD (w and w + 4) carry nearly equal
+// work.  Column item s is tile column s; row item s is tile row T - 1 - s.
+__device__ __forceinline__ void mv_wt(const double* L, const double* x, int m, int T, int w, int nw, int lane,
+                                      double& o1, double& o2) {
+    const int s2 = 2 * nw - 1 - w;
+    o1 = w < T ? wt_col(L, x, m, T, w, lane) : 0.0;
+    o2 = s2 < T ? wt_col(L, x, m, T, s2, lane) : 0.0;
+}
+__device__ __forceinline__ void mv_wt_store(double* y, int m, int T, int w, int nw, int lane, double o1, double o2) {
+    if ((lane & 3) == 0) {
+        int l = lane >> 2;
+        asm volatile("" : "+v"(l));
+        const int s2 = 2 * nw - 1 - w;
+        if (w < T && 16 * w + l < m) y[16 * w + l] = o1;
+        if (s2 < T && 16 * s2 + l < m) y[16 * s2 + l] = o2;
+    }
+}
+__device__ __forceinline__ void mv_w(const double* L, const double* x, int m, int T, int w, int nw, int lane,
+                                     double& o1, double& o2) {
+    const int i2 = T - 2 * nw + w;
+    o1 = w < T ? w_strip(L, x, m, T - 1 - w, lane) : 0.0;
+    o2 = i2 >= 0 ? w_strip(L, x, m, i2, lane) : 0.0;
+}
+__device__ __forceinline__ void mv_w_store(double* y, int m, int T, int w, int nw, int lane, double o1, double o2) {
+    if ((lane & 3) == 0) {
+        int l = lane;
+        asm volatile("" : "+v"(l));
+        const int rr = w_tiles_row(l), i1 = T - 1 - w, i2 = T - 2 * nw + w;
+        if (w < T && 16 * i1 + rr < m) y[16 * i1 + rr] = o1;
+        if (i2 >= 0 && 16 * i2 + rr < m) y[16 * i2 + rr] = o2;
+    }
 }
 
 // Scratch layout of the Lanczos phase (after the factor phase).
@@ -910,10 +931,8 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     double* sres = red + 8;        // 8: theta_min, r_min, theta_max, r_max, stop, k
     double* Qg = c.Qg;
     for (int e = m + t; e < 2 * MAXH; e += blockDim.x) slot[e] = 0.0;
-    // tile pair of this worker wave: ceil(T/2) pairs for ceil(m/32) worker waves
-    const int T = (m + 15) >> 4;
-    const int g = wv - 1, g2 = T - 1 - g;
-    const bool gact = worker && g <= g2;
+    // tile items of the triangular products (every wave, see mv_wt)
+    const int T = (m + 15) >> 4, nwv = blockDim.x >> 6;
     // start vector (deterministic, positive)
     double qr = 0.0;
     if (own) {
@@ -943,16 +962,11 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
                 slot[r] = qr;
             }
             lds_barrier();  // B1
-            // a = W^T q over this wave's pair of tile columns
-            double a1 = 0.0, a2 = 0.0;
-            if (gact) wt_tiles(L, slot, m, T, g, lane, a1, a2);
+            // a = W^T q over this wave's tile columns
+            double a1, a2;
+            mv_wt(L, slot, m, T, wv, nwv, lane, a1, a2);
             lds_barrier();  // B2
-            if (gact && (lane & 3) == 0) {
-                int l = lane >> 2;
-                asm volatile("" : "+v"(l));
-                if (16 * g + l < m) slot[16 * g + l] = a1;
-                if (g2 != g && 16 * g2 + l < m) slot[16 * g2 + l] = a2;
-            }
+            mv_wt_store(slot, m, T, wv, nwv, lane, a1, a2);
             lds_barrier();  // B3
             // b = B a from registers; the broadcast loads of a run one group of
             // four ahead of the products (two groups in flight), the schedule
@@ -983,17 +997,11 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
             lds_barrier();  // B4
             if (own && h == 0) slot[r] = bv;
             lds_barrier();  // B5
-            // c = W b over this wave's pair of tile rows
-            double cw1 = 0.0, cw2 = 0.0;
-            if (gact) w_tiles(L, slot, m, T, g, lane, cw1, cw2);
+            // c = W b over this wave's tile rows
+            double cw1, cw2;
+            mv_w(L, slot, m, T, wv, nwv, lane, cw1, cw2);
             lds_barrier();  // B6
-            if (gact && (lane & 3) == 0) {
-                int l = lane;
-                asm volatile("" : "+v"(l));
-                const int rr = w_tiles_row(l);
-                if (16 * g + rr < m) slot[16 * g + rr] = cw1;
-                if (g2 != g && 16 * g2 + rr < m) slot[16 * g2 + rr] = cw2;
-            }
+            mv_w_store(slot, m, T, wv, nwv, lane, cw1, cw2);
             lds_barrier();  // B7
             // alpha = q^T c from the computed c, so that the new residual is
             // orthogonal to q to working precision whatever the conditioning of W
@@ -1001,8 +1009,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
             const double alj = wave_uniform(block_sum_dpp((own && h == 0) ? qr * cv : 0.0, red));  // B8, B9
             cv -= alj * qr + bprev * qprev;
             const double bn = wave_uniform(sqrt(block_sum_dpp((own && h == 0) ? cv * cv : 0.0, red)));  // B10, B11
-            lds_barrier();  // B12 (control wave stores alpha, beta)
-            lds_barrier();  // B13 (control wave decides)
+            lds_barrier();  // B12 (control wave stores alpha and beta and decides)
             if (sres[4] != 0.0) break;
             qprev = qr;
             qr = cv * (1.0 / bn);
@@ -1039,22 +1046,32 @@ tprev = tn;                       \
         for (int j = 0; j < kmax; ++j) {
             lds_barrier();  // B1
             PHASE(0)
-            lds_barrier();  // B2
+            {
+                double a1, a2;
+                mv_wt(L, slot, m, T, 0, nwv, lane, a1, a2);
+                lds_barrier();  // B2
+                mv_wt_store(slot, m, T, 0, nwv, lane, a1, a2);
+            }
             PHASE(1)
             lds_barrier();  // B3
             lds_barrier();  // B4
             PHASE(2)
             lds_barrier();  // B5
-            lds_barrier();  // B6
+            {
+                double c1, c2;
+                mv_w(L, slot, m, T, 0, nwv, lane, c1, c2);
+                lds_barrier();  // B6
+                mv_w_store(slot, m, T, 0, nwv, lane, c1, c2);
+            }
             lds_barrier();  // B7
             const double alj = block_sum_lds(0.0, red);           // B8, B9
             PHASE(3)
             const double bn = sqrt(block_sum_lds(0.0, red));      // B10, B11
+            // T_k in LDS (this wave's own writes precede its reads below)
             if (lane == 0) {
                 al[j] = alj;
                 be[j + 1] = bn;
             }
-            lds_barrier();  // B12
             PHASE(4)
             const int k = j + 1;
             const bool exhausted = bn <= 1e-14 * fmax(fabs(al[0]), 1e-300);
@@ -1201,7 +1218,7 @@ tprev = tn;                       \
                 sres[5] = (double)k;
                 if (stop != 0.0) sres[6] += (double)k;
             }
-            lds_barrier();  // B13
+            lds_barrier();  // B12
             PHASE(5)
             if (stop != 0.0) break;
         }

@@ -35,13 +35,18 @@ spec_status spec_diag_timing(spec_handle h, int on);
 spec_status spec_diag_stage_times(spec_handle h, double* ms_and_counts, double* lanczos_steps);
 
 /* Phase stamps of the per-chain kernel: spec_diag_phase_profile(h, c)
- * records, for the next calls on chains < c, the shader clock (clock64) of
- * thread 0 at 7 phase boundaries (start, F loaded, Cholesky, inverse,
- * Lanczos start, Lanczos end, done) and, in slots 8..13, the clock cycles
- * the steering wave spent in each part of the Lanczos steps (W^T q, B a,
- * W b + alpha, beta, stop test, barrier wait); 0 turns it off.
- * spec_diag_phase_stamps copies batch x 16 values to the host.  Calls must
- * use batch <= c. */
+ * records, for the next calls on chains < c, SPEC_DIAG_PHASE_SLOTS values
+ * per chain: the shader clock (clock64) of thread 0 at 7 phase boundaries
+ * (slots 0..6: start, F loaded, Cholesky, inverse, Lanczos start, Lanczos
+ * end, done); the Cholesky's diagonal-tile, panel and trailing-update cycles
+ * (slots 7, 14, 15); the cycles the steering wave spent in the parts of the
+ * Lanczos steps (slots 8..13: q stored, W^T q, B a, W b and alpha, beta, stop
+ * test and the closing barrier); the stop tests run and the Sturm passes
+ * they made (slots 16, 17), and the cycles of their multisection and of
+ * their residual bounds and decisions (slots 18, 19).  0 turns it off.  spec_diag_phase_stamps copies
+ * batch x SPEC_DIAG_PHASE_SLOTS values to the host.  Calls must use
+ * batch <= c. */
+#define SPEC_DIAG_PHASE_SLOTS 24
 spec_status spec_diag_phase_profile(spec_handle h, int max_chains);
 spec_status spec_diag_phase_stamps(spec_handle h, int batch, long long* out);
 

@@ -1269,7 +1269,7 @@ spec_status spec_diag_phase_profile(spec_handle h, int max_chains) {
     dfree(h->dProf);
     h->prof_cap = 0;
     if (max_chains > 0) {
-        HIPCHK(dalloc(&h->dProf, (size_t)max_chains * 16));
+        HIPCHK(dalloc(&h->dProf, (size_t)max_chains * SPEC_DIAG_PHASE_SLOTS));
         h->prof_cap = max_chains;
     }
     return SPEC_OK;
@@ -1278,7 +1278,7 @@ spec_status spec_diag_phase_profile(spec_handle h, int max_chains) {
 spec_status spec_diag_phase_stamps(spec_handle h, int batch, long long* out) {
     if (!h || !out || batch < 0 || batch > h->prof_cap) return SPEC_EINVAL;
     HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(out, h->dProf, sizeof(long long) * 16 * batch, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(out, h->dProf, sizeof(long long) * SPEC_DIAG_PHASE_SLOTS * batch, hipMemcpyDeviceToHost));
     return SPEC_OK;
 }
 

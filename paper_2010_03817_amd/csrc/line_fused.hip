@@ -28,6 +28,7 @@
 // LDS at m = 200: 20100 doubles of the factor + 380 of scratch = 160 KiB.
 #include "common.h"
 #include "line_fused.h"
+#include "spec_diag.h"
 
 namespace spec {
 
@@ -597,6 +598,45 @@ __device__ inline int sturm_lds(const double* al, const double* be, int k, doubl
     return cnt;
 }
 
+// |s_k| of the eigenvector s of T_k for this lane's theta (normalised, last
+// component), from the backward recurrence
+//   y_{i-1} = ((theta - alpha_i) y_i - beta_{i+1} y_{i+1}) / beta_i,
+// y_{k-1} = 1, with T_k read from LDS (a broadcast) and 1/beta_i from the
+// hardware reciprocal with one Newton step (a stopping bound needs no more).
+// y is rescaled every 4 steps once ss > 1e150; should ss still overflow (a run
+// of tiny beta_i), the result is NaN, which no stop test accepts, rather than
+// the 0 that 1/sqrt(inf) would give.
+__device__ inline double backward_norm_lds(const double* al, const double* be, int k, double th) {
+    k = __builtin_amdgcn_readfirstlane(k);
+    double y1 = 1.0, y0 = 0.0, ss = 1.0, bn = 0.0;
+    int i = k - 1;
+    auto step = [&]() {
+        const double ai = al[i], bi = be[i];
+        double r = __builtin_amdgcn_rcp(bi);
+        r = fma(r, fma(-bi, r, 1.0), r);
+        r = bi != 0.0 ? r : 0.0;
+        const double ym = ((th - ai) * y1 - bn * y0) * r;
+        y0 = y1;
+        y1 = ym;
+        ss = fma(ym, ym, ss);
+        bn = bi;
+        --i;
+    };
+    for (; i >= 4; ) {
+        step();
+        step();
+        step();
+        step();
+        if (ss > 1e150) {
+            y0 *= 1e-75;
+            y1 *= 1e-75;
+            ss *= 1e-150;
+        }
+    }
+    while (i >= 1) step();
+    return ss < INFINITY ? 1.0 / sqrt(ss) : NAN;
+}
+
 __device__ inline double backward_norm_reg(double aA, double aB, double bA, double bB, double rbA, double rbB, int k,
                                            double th) {
     double y1 = 1.0, y0 = 0.0, ss = 1.0;
@@ -899,7 +939,7 @@ struct LzCtx {
     const double* B1;
     double b1;
     double* Qg;        // this chain's basis (kmax x m)
-    long long* prof;   // nullable: per-part cycles of the steering wave (slots 8..13)
+    long long* prof;   // nullable: per-part cycles of the steering wave (slots 8..13), tests and passes (16, 17)
 };
 
 // Extreme eigenvalue(s) of C by Lanczos (lambda_min only when min_only),
@@ -1029,6 +1069,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
         }
     } else {
         long long ph[6] = {0, 0, 0, 0, 0, 0};
+        long long n_tests = 0, n_passes = 0, c_sect = 0, c_res = 0;
         if (lane == 0) sres[6] = 0.0;
         for (int cyc = 0;; ++cyc) {
         int next_check = c.first_check > 0 ? c.first_check : 4;
@@ -1078,6 +1119,7 @@ tprev = tn;                       \
             const bool check = exhausted || k == kmax || k >= next_check;
             double stop = 0.0;
             if (check) {
+                ++n_tests;
                 // T_k into registers
                 const double aA = lane < k ? al[lane] : 0.0, aB = lane + 64 < k ? al[lane + 64] : 0.0;
                 const double bA = lane < k ? be[lane] : 0.0, bB = lane + 64 < k ? be[lane + 64] : 0.0;
@@ -1116,6 +1158,7 @@ tprev = tn;                       \
                     const double span = 4.0 * w_r + 16.0 * (w_hi - w_lo) + 1e-12 * fmax(fabs(w_lo), fabs(w_hi));
                     const double xw = want_min ? w_lo - span : w_hi + span;
                     const int cw = sturm_lds(al, be, k, xw);
+                    ++n_passes;
                     const bool okw = want_min ? (cw == 0) : (cw >= k);
                     if (okw) {
                         if (want_min) {
@@ -1139,6 +1182,7 @@ tprev = tn;                       \
                         if (!(w > rel * fmax(fabs(lo), fabs(hi)))) break;
                         const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
                         const int cnt = sturm_lds(al, be, k, x);
+                        ++n_passes;
                         const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
                         const unsigned long long mask = __ballot(hitp);
                         unsigned long long hm;
@@ -1164,7 +1208,7 @@ tprev = tn;                       \
                 double rmin = 0.0, rmax = 0.0;
                 auto test = [&]() {
                     th = 0.5 * (lo + hi);
-                    res = exhausted ? 0.0 : fabs(bn) * backward_norm_reg(aA, aB, bA, bB, rbA, rbB, k, th);
+                    res = exhausted ? 0.0 : fabs(bn) * backward_norm_lds(al, be, k, th);
                     thmin = __shfl(th, 0, 64);
                     thmax = __shfl(th, src_max, 64);
                     rmin = __shfl(res, 0, 64);
@@ -1178,11 +1222,19 @@ tprev = tn;                       \
                     const bool cmax = c.min_only || rmax <= tmax;
                     conv_now = exhausted || (cmin && cmax);
                 };
+                long long tq = clock64();
                 msect(1e-10);
+                long long tr = clock64();
+                c_sect += tr - tq;
                 test();
+                tq = clock64();
+                c_res += tq - tr;
                 if (conv_now || k == kmax) {
                     msect(2e-16);
+                    tr = clock64();
+                    c_sect += tr - tq;
                     test();
+                    c_res += clock64() - tr;
                 }
                 w_lo = lo;
                 w_hi = hi;
@@ -1228,8 +1280,13 @@ tprev = tn;                       \
         lds_barrier();
         }
 #undef PHASE
-        if (c.prof && t == 0)
+        if (c.prof && t == 0) {
             for (int i = 0; i < 6; ++i) c.prof[8 + i] = ph[i];
+            c.prof[16] = n_tests;
+            c.prof[17] = n_passes;
+            c.prof[18] = c_sect;
+            c.prof[19] = c_res;
+        }
     }
 }
 
@@ -1287,7 +1344,7 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     double t0 = a.shift ? a.shift[chain] : 0.0;
     if (!(t0 > 0.0) || !isfinite(t0)) t0 = 0.0;  // no usable bracket: plain origin
     int32_t st = SPEC_OK;
-    long long* prof = a.prof ? a.prof + (size_t)chain * 16 : nullptr;
+    long long* prof = a.prof ? a.prof + (size_t)chain * SPEC_DIAG_PHASE_SLOTS : nullptr;
 #define STAMP(i) \
     if (prof && t == 0) prof[i] = clock64();
     STAMP(0)

@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, NOT_INTERIOR, UNBOUNDED, NONSMOOTH, REFLECT_CAP, CE
 DENSE, DIAG = 0, 1
 HNR, CHNR, BILLIARD, HMC = 0, 1, 2, 3
 PREC_FP64, PREC_FP32_ASM, PREC_BF16X2_ASM = 0, 1, 2
+PHASE_SLOTS = 24  # SPEC_DIAG_PHASE_SLOTS
 
 
 class SpecError(RuntimeError):
@@ -303,7 +304,7 @@ class Spectrahedron:
         check(lib().spec_diag_phase_profile(self._h, int(max_chains)))
 
     def phase_stamps(self, batch):
-        out = np.zeros((batch, 16), dtype=np.int64)
+        out = np.zeros((batch, PHASE_SLOTS), dtype=np.int64)
         check(lib().spec_diag_phase_stamps(self._h, batch, out.ctypes.data_as(C.c_void_p)))
         return out
 

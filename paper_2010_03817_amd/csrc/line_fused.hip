@@ -379,12 +379,21 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
 
 // In-place triangular inverse W = L^{-1} of the packed lower factor: column
 // blocks from the last one, W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) L_JJ^{-1}.
-__device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
+// prof (nullable): thread 0 adds the cycles of the three parts (P products,
+// W P sums, stores) to prof[0..2].
+__device__ __forceinline__ void tri_inverse(double* L, int m, double* D, long long* prof = nullptr) {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lh = lane >> 4;
     const int T = (m + 15) / 16;
+    long long c0 = 0, c1 = 0, c2 = 0, tc = prof ? clock64() : 0;
+#define INV_TICK(acc)                        \
+    if (prof) {                              \
+        const long long tn = clock64();      \
+        acc += tn - tc;                      \
+        tc = tn;                             \
+    }
     for (int J = T - 1; J >= 0; --J) {
         // P_KJ = L_KJ W_JJ for K > J, in place (W_JJ = L_JJ^{-1}, left in the
         // diagonal tile by the factorisation; right operand W_JJ[4 s + (l >> 4)][l & 15])
@@ -408,44 +417,69 @@ __device__ __forceinline__ void tri_inverse(double* L, int m, double* D) {
             }
         }
         lds_barrier();
-        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ (tiles I = J+1+wv + q nw, q < 4).  Right
-        // operand P_KJ[4 s + (l >> 4)][l & 15]; its rows past m are zeroed, since
-        // the matching columns of W_IK are zero and garbage there must not meet them.
-        d4 res[4];
+        INV_TICK(c0)
+        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ for the tile rows I > J.  Row I takes
+        // I - J products; rows are dealt by size in pairs {w, 2 nw - 1 - w} (row
+        // item s is I = T - 1 - s; at most two per wave since T - 1 - J <= 2 nw - 3),
+        // and a wave runs its two rows in one K loop: they share the loads of
+        // P_KJ and give two independent MFMA chains.  Right operand
+        // P_KJ[4 s + (l >> 4)][l & 15]; its rows past m are zeroed, since the
+        // matching columns of W_IK are zero and garbage there must not meet them.
+        {
+            const int n = T - 1 - J, s2 = 2 * nw - 1 - wv;
+            const int I1 = wv < n ? T - 1 - wv : -1, I2 = s2 < n ? T - 1 - s2 : -1;
+            d4 acc1{0.0, 0.0, 0.0, 0.0}, acc2{0.0, 0.0, 0.0, 0.0};
+            if (I1 >= 0) {
+                const int rb1 = rowb(16 * I1 + li, m), rb2 = rowb(16 * (I2 >= 0 ? I2 : I1) + li, m);
+                for (int K = J + 1; K <= I1; ++K) {
+                    double bq[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int I = J + 1 + wv + q * nw;
-            d4 acc{0.0, 0.0, 0.0, 0.0};
-            if (I < T) {
-                const int rbI = rowb(16 * I + li, m);
-                for (int K = J + 1; K <= I; ++K) {
-                    const double* pa = L + rbI + 16 * K + lh;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int kr = 16 * K + 4 * s + lh;
-                        const double av = pa[4 * s];
-                        const double a = (K < I || 4 * s + lh <= li) ? av : 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        const int kr = 16 * K + 4 * q + lh;
                         const double bv = L[rowb(kr, m) + 16 * J + li];
-                        const double b = kr < m ? bv : 0.0;
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                        bq[q] = kr < m ? bv : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double av = L[rb1 + 16 * K + 4 * q + lh];
+                        const double a1 = (K < I1 || 4 * q + lh <= li) ? av : 0.0;
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bq[q], acc1, 0, 0, 0);
+                    }
+                    if (K <= I2) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double av = L[rb2 + 16 * K + 4 * q + lh];
+                            const double a2 = (K < I2 || 4 * q + lh <= li) ? av : 0.0;
+                            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bq[q], acc2, 0, 0, 0);
+                        }
                     }
                 }
             }
-            res[q] = -acc;
-        }
-        lds_barrier();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int I = J + 1 + wv + q * nw;
-            if (I < T) {
+            lds_barrier();
+            INV_TICK(c1)
+            if (I1 >= 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * I + lh + 4 * r;
-                    if (row < m) L[rowb(row, m) + 16 * J + li] = res[q][r];
+                    const int row = 16 * I1 + lh + 4 * r;
+                    if (row < m) L[rowb(row, m) + 16 * J + li] = -acc1[r];
+                }
+            }
+            if (I2 >= 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * I2 + lh + 4 * r;
+                    if (row < m) L[rowb(row, m) + 16 * J + li] = -acc2[r];
                 }
             }
         }
         lds_barrier();
+        INV_TICK(c2)
+    }
+#undef INV_TICK
+    if (prof && t == 0) {
+        prof[0] += c0;
+        prof[1] += c1;
+        prof[2] += c2;
     }
 }
 
@@ -1418,7 +1452,13 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             prof[14] = cst[1];
             prof[15] = cst[2];
         }
-        if (ok && !a.membership_only) tri_inverse(L, m, scr);
+        long long ist[3] = {0, 0, 0};  // triangular-inverse part cycles (profiling)
+        if (ok && !a.membership_only) tri_inverse(L, m, scr, prof ? ist : nullptr);
+        if (prof && t == 0) {
+            prof[20] = ist[0];
+            prof[21] = ist[1];
+            prof[22] = ist[2];
+        }
         STAMP(3)
         if (!ok) st = SPEC_NOT_INTERIOR;
         if (ok && !a.membership_only) {

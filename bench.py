@@ -378,7 +378,7 @@ def main():
     asm_launches = max(plain["stages"]["assemble"][1], 1)
     asm_ms = plain["stages"]["assemble"][0] / asm_launches
     asm_flops = 2.0 * (2 * plain["stats"]["calls"] / asm_launches) * (N_DIM + 1) * (P + 2 * N_DIM)
-    assembly = {"kernel": "k_gemm_f64<false>", "achieved": asm_flops / (asm_ms * 1e-3) / 1e12,
+    assembly = {"kernel": "k_gemm_f64_128<false>", "achieved": asm_flops / (asm_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "ms_per_launch": asm_ms}
     assembly["frac"] = assembly["achieved"] / assembly["peak"]
     plain_sum = summary(plain, chains)

@@ -352,7 +352,7 @@ spec_status spec_create(int n, int nblocks, const int* block_size, const int* ki
     h->Ptot = h->P + md;
     h->K = n + 1;
     h->Kpad = round_up(h->K, 16);
-    h->ldA = round_up(h->Ptot, 64);
+    h->ldA = round_up(h->Ptot, 128);  // 128-wide GEMM tiles for the assembly
     h->Nn = round_up(n, 64);
     h->Arows = std::max(h->Kpad, 1 + h->Nn);
     while (h->kmax > 2 && fused_lds_bytes(h->m, h->kmax) > 163840) --h->kmax;

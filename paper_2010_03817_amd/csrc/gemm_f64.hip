@@ -5,10 +5,11 @@
 // (paper: construction of the pencil in O(n m^2), Lemma "intersection cost";
 //  normal (u^T A_i u)_i in O(n m^2), Lemma "reflection cost").
 //
-// Tiling: a 256-thread workgroup computes a 64x64 tile of C; each of its four
-// waves a 32x32 quarter as 2x2 MFMA 16x16 blocks.  K advances 16 at a time
-// through LDS.  M, N, K must be multiples of 64, 64, 16 (callers pad with
-// zeros).  Workgroups are ordered so that the eight XCDs each walk their own
+// Tiling: a 256-thread workgroup computes a 128x128 tile of C when M and N
+// allow it (see k_gemm_f64_128), else a 64x64 tile, each of its four waves a
+// 32x32 quarter as 2x2 MFMA 16x16 blocks.  K advances 16 at a time through
+// LDS.  M, N, K must be multiples of 64, 64, 16 (callers pad with zeros).
+// Workgroups are ordered so that the eight XCDs each walk their own
 // contiguous range of N tiles: a B panel is then fetched into one XCD's L2
 // and reused there by every M tile.
 #include "common.h"
@@ -100,10 +101,125 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, const dou
             }
 }
 
+// 128 x 128 tiles for shapes that allow them: each wave computes a 64 x 64
+// quarter as 4 x 4 MFMA blocks (half the operand traffic per flop of the
+// 64 x 64 tiling), the LDS stage is double-buffered and the next K slice is
+// read from global memory into registers while the current one is multiplied,
+// so that one barrier per K step suffices: buffer (s+1) mod 2 is written at
+// step s only after the barrier that ends step s-1, the last reads of it.
+constexpr int BT = 128, BK = 16;
+constexpr int LAS = BK + 1;   // padded LDS rows (bank spread)
+constexpr int LBS = BT + 2;
+
+template <bool TRANS_B>
+__global__ __launch_bounds__(256) void k_gemm_f64_128(int M, int N, int K, const double* __restrict__ A,
+                                                      int lda, const double* __restrict__ B, int ldb,
+                                                      double* __restrict__ C, int ldc) {
+    __shared__ double As[2][BT * LAS];
+    __shared__ double Bs[2][BK * LBS];
+
+    const int tilesM = M / BT, tilesN = N / BT;
+    const int total = tilesM * tilesN;
+    const int g = blockIdx.x;
+    int lin;
+    if (total % 8 == 0) {
+        const int per = total / 8;
+        lin = (g % 8) * per + g / 8;  // XCD g % 8 walks its own range, M fastest
+    } else {
+        lin = g;
+    }
+    const int tm = lin % tilesM, tn = lin / tilesM;
+    const int row0 = tm * BT, col0 = tn * BT;
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;
+    // global -> LDS mapping of one K slice: 8 consecutive doubles per thread
+    const int ar = t >> 1, ac = (t & 1) * 8;                          // A: row ar, columns ac..ac+7
+    const int br = TRANS_B ? (t & 1) * 8 : t >> 4, bc = TRANS_B ? t >> 1 : (t & 15) * 8;
+    double ra[8], rb[8];
+    auto fetch = [&](int k0) {
+        const double* pa = A + (size_t)(row0 + ar) * lda + k0 + ac;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ra[q] = pa[q];
+        if (!TRANS_B) {
+            const double* pb = B + (size_t)(k0 + br) * ldb + col0 + bc;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rb[q] = pb[q];
+        } else {
+            // B is N x K row-major: row col0 + bc, columns k0 + br ..
+            const double* pb = B + (size_t)(col0 + bc) * ldb + k0 + br;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rb[q] = pb[q];
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[buf][ar * LAS + ac + q] = ra[q];
+        if (!TRANS_B) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Bs[buf][br * LBS + bc + q] = rb[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Bs[buf][(br + q) * LBS + bc] = rb[q];
+        }
+    };
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int k0 = 0, s = 0; k0 < K; k0 += BK, ++s) {
+        const int cur = s & 1;
+        const bool more = k0 + BK < K;
+        if (more) fetch(k0 + BK);
+        const double* as = As[cur];
+        const double* bs = Bs[cur];
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = as[(wr + i * 16 + (lane & 15)) * LAS + ks + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = bs[(ks + (lane >> 4)) * LBS + wc + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) stash(cur ^ 1);
+        __syncthreads();
+    }
+    // accumulator r of lane l holds D[l/16 + 4 r][l % 16] of its 16x16 block
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
+                const int cc = col0 + wc + j * 16 + (lane & 15);
+                C[(size_t)rr * ldc + cc] = acc[i][j][r];
+            }
+}
+
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                     double* C, int ldc, hipStream_t s) {
     if (M % GT_M || N % GT_N || K % GT_K) return hipErrorInvalidValue;
     if (M == 0 || N == 0) return hipSuccess;
+    if (M % BT == 0 && N % BT == 0) {
+        const int tiles = (M / BT) * (N / BT);
+        if (transB)
+            hipLaunchKernelGGL(k_gemm_f64_128<true>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+        else
+            hipLaunchKernelGGL(k_gemm_f64_128<false>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+        return hipGetLastError();
+    }
     const int tiles = (M / GT_M) * (N / GT_N);
     if (transB)
         hipLaunchKernelGGL(k_gemm_f64<true>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);

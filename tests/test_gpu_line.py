@@ -44,9 +44,12 @@ def test_mfma_f64_lane_layout():
 
 
 @pytest.mark.parametrize("transB", [False, True])
-def test_gemm_f64(transB):
+@pytest.mark.parametrize("shape", [(128, 192, 48), (256, 384, 80), (128, 128, 16), (384, 256, 208)])
+def test_gemm_f64(transB, shape):
+    """64- and 128-wide tilings (the latter when M and N are multiples of 128),
+    odd and even numbers of K slices, against numpy."""
     rng = np.random.default_rng(1)
-    M, N, K = 128, 192, 48
+    M, N, K = shape
     A = rng.standard_normal((M, K))
     B = rng.standard_normal((N, K)) if transB else rng.standard_normal((K, N))
     Cg = _spec().gemm_f64(A, B, transB)

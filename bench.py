@@ -138,7 +138,7 @@ def roofline(run, chains, extra_chol=0.0):
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["traffic_unit"] = "bytes per launch"
-    roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64<false>", "normal": "k_gemm_f64<true>",
+    roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64_128<false>", "normal": "k_gemm_f64_128<true>",
                       "predict": "k_gemm_f32", "update": "k_walk_update"}[dom]
     roof["ms_per_launch"] = ms_dom
     return roof

@@ -806,9 +806,10 @@ __device__ __forceinline__ double block_sum_dpp(double v, double* red) {
 // Column sums of W^T x over tile column J (tiles I = J..T-1).  Lane l takes
 // column 16 J + (l >> 2) and rows 4 q + (l & 3) of each tile (one load still
 // reads 16 consecutive entries of 4 rows); the four lanes of a quad, which
-// share the column, return its sum.  The diagonal tile and a last tile row
-// that ends past m are masked; between them the byte addresses step by
-// pk(r + 16) - pk(r) = 16 r + 136 entries, with no masks.
+// share the column, return its sum.  The byte addresses step by
+// pk(r + 16) - pk(r) = 16 r + 136 entries from the diagonal tile on (which
+// masks the entries right of the diagonal); a last tile row that ends past m
+// takes the clamped form.
 __device__ __forceinline__ double wt_col(const double* L, const double* x, int m, int T, int J, int lane) {
     asm volatile("" : "+v"(lane));  // addressing formed per call, not kept live across the step loop
     const int p = lane & 3, c = 16 * J + (lane >> 2);
@@ -823,16 +824,33 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
             s += (r < m && c <= r ? w : 0.0) * (r < m ? xv : 0.0);
         }
     };
-    edge(J);
-    if (J + 1 < Iend) {
+    if (J < Iend) {
+        // from the diagonal tile on: incremental row bases; the diagonal tile
+        // masks the entries right of the diagonal (their addresses stay inside
+        // the allocation: at most 15 entries past the factor)
         const char* Lb = (const char*)L;
-        const char* xb = (const char*)(x + 16 * (J + 1) + p);
+        const char* xb = (const char*)(x + 16 * J + p);
         int ab[4], d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = 16 * (J + 1) + 4 * q + p;
+            const int r = 16 * J + 4 * q + p;
             ab[q] = 8 * (pk(r, 0) + c);
             d[q] = 8 * (16 * r + 136);
+        }
+        {
+            double w[4], xs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w[q] = *(const double*)(Lb + ab[q]);
+                xs[q] = *(const double*)(xb + 32 * q);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s += (c <= 16 * J + 4 * q + p ? w[q] : 0.0) * xs[q];
+                ab[q] += d[q];
+                d[q] += 8 * 256;
+            }
+            xb += 128;
         }
         for (int I = J + 1; I < Iend; ++I) {
             double w[4], xs[4];
@@ -849,6 +867,8 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
             }
             xb += 128;
         }
+    } else {
+        edge(J);  // the last tile row, ending past m
     }
     if (Iend < T && J < T - 1) edge(T - 1);
     s += dpp_mov<DPP_X1>(s);

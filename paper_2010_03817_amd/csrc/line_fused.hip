@@ -808,8 +808,8 @@ __device__ __forceinline__ double block_sum_dpp(double v, double* red) {
 // reads 16 consecutive entries of 4 rows); the four lanes of a quad, which
 // share the column, return its sum.  The byte addresses step by
 // pk(r + 16) - pk(r) = 16 r + 136 entries from the diagonal tile on (which
-// masks the entries right of the diagonal); a last tile row that ends past m
-// takes the clamped form.
+// masks the entries right of the diagonal); in a last tile row that ends past
+// m the rows past m read row m - 1 against x = 0.
 __device__ __forceinline__ double wt_col(const double* L, const double* x, int m, int T, int J, int lane) {
     asm volatile("" : "+v"(lane));  // addressing formed per call, not kept live across the step loop
     const int p = lane & 3, c = 16 * J + (lane >> 2);
@@ -867,10 +867,24 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
             }
             xb += 128;
         }
+        if (Iend < T) {
+            // the last tile row ends past m: its rows past m read row m - 1 (a
+            // valid, finite entry, since c < 16 (T - 1) <= m - 1 here) against x = 0
+            const int abmax = 8 * (pk(m - 1, 0) + c);
+            double w[4], xs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int a = ab[q] < abmax ? ab[q] : abmax;
+                w[q] = *(const double*)(Lb + a);
+                const double xv = *(const double*)(xb + 32 * q);
+                xs[q] = 16 * (T - 1) + 4 * q + p < m ? xv : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s += w[q] * xs[q];
+        }
     } else {
-        edge(J);  // the last tile row, ending past m
+        edge(J);  // the last tile row, ending past m, is the diagonal tile
     }
-    if (Iend < T && J < T - 1) edge(T - 1);
     s += dpp_mov<DPP_X1>(s);
     s += dpp_mov<DPP_X2>(s);
     return s;

@@ -186,6 +186,20 @@ __device__ __forceinline__ double rsqrt_pivot(double d) {
     return y;
 }
 
+// Row broadcasts bc[K] = lane K's v for K = K0..15, issued back to back so that
+// their latencies overlap (each feeds an independent product afterwards).
+template <int K, bool = (K < 16)>
+struct Bcast {
+    __device__ __forceinline__ static void run(double v, double (&bc)[16]) {
+        bc[K] = row_bcast<K>(v);
+        Bcast<K + 1>::run(v, bc);
+    }
+};
+template <int K>
+struct Bcast<K, false> {
+    __device__ __forceinline__ static void run(double, double (&)[16]) {}
+};
+
 // Unrolled steps of the diagonal-tile factorisation (column J, then J + 1..).
 // Lane J keeps 1 / L_JJ in a[J]: its own diagonal entry is read only as that
 // reciprocal afterwards.
@@ -194,14 +208,14 @@ struct DiagSteps {
     // trailing update of column K > J by column J: a_iK -= l_iJ l_KJ
     template <int K, bool = (K < 16)>
     struct Upd {
-        __device__ __forceinline__ static void run(double (&a)[16]) {
-            a[K] -= a[J] * row_bcast<K>(a[J]);
-            Upd<K + 1>::run(a);
+        __device__ __forceinline__ static void run(double (&a)[16], const double (&bc)[16]) {
+            a[K] -= a[J] * bc[K];
+            Upd<K + 1>::run(a, bc);
         }
     };
     template <int K>
     struct Upd<K, false> {
-        __device__ __forceinline__ static void run(double (&)[16]) {}
+        __device__ __forceinline__ static void run(double (&)[16], const double (&)[16]) {}
     };
     __device__ __forceinline__ static bool run(double (&a)[16], int i) {
         __builtin_amdgcn_sched_barrier(0);  // one column at a time (bounds the live broadcasts)
@@ -209,7 +223,10 @@ struct DiagSteps {
         if (!(d > 0.0)) return false;  // the same pivot in every lane
         const double iv = rsqrt_pivot(d);
         a[J] = i == J ? iv : a[J] * iv;
-        Upd<J + 1>::run(a);
+        double bc[16];
+        Bcast<J + 1>::run(a[J], bc);
+        __builtin_amdgcn_sched_barrier(0);
+        Upd<J + 1>::run(a, bc);
         return DiagSteps<J + 1>::run(a, i);
     }
 };
@@ -225,9 +242,9 @@ template <int I>
 struct InvSteps {
     template <int J, bool = (J < 16)>
     struct Upd {
-        __device__ __forceinline__ static void run(const double (&a)[16], double (&sv)[16], double w) {
-            sv[J] -= row_bcast<J>(a[I]) * w;
-            Upd<J + 1>::run(a, sv, w);
+        __device__ __forceinline__ static void run(const double (&bc)[16], double (&sv)[16], double w) {
+            sv[J] -= bc[J] * w;
+            Upd<J + 1>::run(bc, sv, w);
         }
     };
     template <int J>
@@ -235,8 +252,12 @@ struct InvSteps {
         __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double) {}
     };
     __device__ __forceinline__ static void run(const double (&a)[16], double (&sv)[16], double (&w)[16]) {
-        w[I] = sv[I] * row_bcast<I>(a[I]);
-        Upd<I + 1>::run(a, sv, w[I]);
+        __builtin_amdgcn_sched_barrier(0);
+        double bc[16];
+        Bcast<I>::run(a[I], bc);  // bc[I] = 1 / L_II, bc[J] = L_JI below
+        __builtin_amdgcn_sched_barrier(0);
+        w[I] = sv[I] * bc[I];
+        Upd<I + 1>::run(bc, sv, w[I]);
         InvSteps<I + 1>::run(a, sv, w);
     }
 };

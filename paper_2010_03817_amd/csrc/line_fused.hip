@@ -34,7 +34,8 @@ namespace spec {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int MAXH = 100;  // half-row length held in registers (m <= 200)
+constexpr int MAXH = 100;  // entries of B held in registers per worker thread (m <= 200)
+constexpr int BR = 4, BC = 25;  // block of B per worker thread: BR rows x BC columns (8 BC = 2 MAXH)
 constexpr int NCYCLES = 3;  // Lanczos cycles of at most kmax steps (restarts from the Ritz vector)
 
 // Element (i, j) of tile (I, J) of the packed lower matrix; zero above the
@@ -163,12 +164,11 @@ __device__ __forceinline__ void dense_trinv16(double* T, int lane) {
 }
 
 // Lane k of each 16-lane row broadcast to the whole row (DPP row_newbcast).
+// The 64-bit form is one v_mov_b64 with DPP (row_newbcast is the one DPP
+// control that 64-bit moves take).
 template <int K>
 __device__ __forceinline__ double row_bcast(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x150 + K, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + K, 0xf, 0xf, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xf, 0xf, true);
 }
 
 // 1 / sqrt(d) for a positive pivot: the hardware estimate refined by two
@@ -911,6 +911,20 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
     return s;
 }
 
+// Sum over each group of eight lanes of four per-lane accumulators, half of
+// them exchanged at the first two levels (the mirrored partner within the
+// eight, which differs in bit 2, then lane ^ 2): lane l ends with the total
+// of a[s], s = 2 ((l >> 2) & 1) + ((l >> 1) & 1), as does lane l ^ 1.
+__device__ __forceinline__ double red8x4(const double a[4], int lane) {
+    const bool b2 = lane & 4, b1 = lane & 2;
+    const double k0 = b2 ? a[2] : a[0], k1 = b2 ? a[3] : a[1];
+    const double s0 = b2 ? a[0] : a[2], s1 = b2 ? a[1] : a[3];
+    const double u0 = k0 + dpp_mov<DPP_HMIR>(s0), u1 = k1 + dpp_mov<DPP_HMIR>(s1);
+    double v = (b1 ? u1 : u0) + dpp_mov<DPP_X2>(b1 ? u0 : u1);
+    v += dpp_mov<DPP_X1>(v);
+    return v;
+}
+
 // Sum over the 16 lanes of each lane row of four per-row accumulators,
 // exchanging half of them at each of the first two levels (lane ^ 8, then
 // the mirror partner within 8, which differs in bit 2): lane l ends with the
@@ -975,6 +989,7 @@ __device__ __forceinline__ double w_strip(const double* L, const double* x, int 
 // work.  Column item s is tile column s; row item s is tile row T - 1 - s.
 __device__ __forceinline__ void mv_wt(const double* L, const double* x, int m, int T, int w, int nw, int lane,
                                       double& o1, double& o2) {
+    w = __builtin_amdgcn_readfirstlane(w);  // the wave index is uniform: scalar tile loops
     const int s2 = 2 * nw - 1 - w;
     o1 = w < T ? wt_col(L, x, m, T, w, lane) : 0.0;
     o2 = s2 < T ? wt_col(L, x, m, T, s2, lane) : 0.0;
@@ -990,6 +1005,7 @@ __device__ __forceinline__ void mv_wt_store(double* y, int m, int T, int w, int 
 }
 __device__ __forceinline__ void mv_w(const double* L, const double* x, int m, int T, int w, int nw, int lane,
                                      double& o1, double& o2) {
+    w = __builtin_amdgcn_readfirstlane(w);
     const int i2 = T - 2 * nw + w;
     o1 = w < T ? w_strip(L, x, m, T - 1 - w, lane) : 0.0;
     o2 = i2 >= 0 ? w_strip(L, x, m, i2, lane) : 0.0;
@@ -1046,12 +1062,10 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     asm volatile("" : "+v"(t));
     const int lane = t & 63, wv = t >> 6;
     const int m = c.m;
-    const int hm = (m + 1) >> 1;
     const int tw = t - 64;
-    const int r = tw >> 1, h = tw & 1;
+    const int r = tw >> 1, h = tw & 1;  // vector entries: thread pair (r, h) owns entry r
     const bool worker = wv >= 1;
     const bool own = worker && r < m;
-    const int c0 = h * hm;
     const int kmax = c.kmax;
     double* slot = scr;            // 2 MAXH (zero past m)
     double* al = scr + 2 * MAXH;   // kmax
@@ -1071,17 +1085,24 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     double nq = block_sum_lds((own && h == 0) ? qr * qr : 0.0, red);
     qr *= 1.0 / sqrt(nq);
     if (worker) {
+        // B in registers: worker thread tw holds the block of rows 4 g .. 4 g + 3
+        // (g = tw >> 3) and columns BC k8 .. BC k8 + BC - 1 (k8 = tw & 7), zero
+        // past m, so that it reads only BC entries of a per product
+        const int g = tw >> 3, k8 = tw & 7;
         double breg[MAXH];
 #pragma unroll
-        for (int k = 0; k < MAXH; ++k) {
-            const int cc = c0 + k;
-            double v = 0.0;
-            if (own && k < hm && cc < m) {
-                const int e = cc <= r ? pk(r, cc) : pk(cc, r);
-                v = c.b0 * c.B0[e];
-                if (c.B1) v += c.b1 * c.B1[e];
+        for (int i = 0; i < BR; ++i) {
+#pragma unroll
+            for (int k = 0; k < BC; ++k) {
+                const int rr = BR * g + i, cc = BC * k8 + k;
+                double v = 0.0;
+                if (rr < m && cc < m) {
+                    const int e = cc <= rr ? pk(rr, cc) : pk(cc, rr);
+                    v = c.b0 * c.B0[e];
+                    if (c.B1) v += c.b1 * c.B1[e];
+                }
+                breg[BC * i + k] = v;
             }
-            breg[k] = v;
         }
         for (int cyc = 0;; ++cyc) {
         double qprev = 0.0, bprev = 0.0;
@@ -1097,34 +1118,43 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
             lds_barrier();  // B2
             mv_wt_store(slot, m, T, wv, nwv, lane, a1, a2);
             lds_barrier();  // B3
-            // b = B a from registers; the broadcast loads of a run one group of
-            // four ahead of the products (two groups in flight), the schedule
-            // pinned group by group so that the loads are not all hoisted
-            double bv = 0.0, bw = 0.0;
+            // b = B a from registers: four row sums over this thread's BC
+            // columns, the loads of a one group of four ahead of the products
+            // (the schedule pinned group by group so that the loads are not all
+            // hoisted), then summed over the eight threads of the row block
+            double bv;
             {
-                const double* sv = slot + c0;
+                double acc[BR] = {0.0, 0.0, 0.0, 0.0};
+                const double* sv = slot + BC * k8;
                 double cur[4], nxt[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) cur[u] = sv[u];
 #pragma unroll
-                for (int kk = 0; kk < MAXH; kk += 4) {
-                    if (kk + 4 < MAXH) {
+                for (int kk = 0; kk < BC; kk += 4) {
+                    if (kk + 4 < BC) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) nxt[u] = sv[kk + 4 + u];
+                        for (int u = 0; u < 4; ++u)
+                            if (kk + 4 + u < BC) nxt[u] = sv[kk + 4 + u];
                     }
-                    bv += breg[kk] * cur[0];
-                    bw += breg[kk + 1] * cur[1];
-                    bv += breg[kk + 2] * cur[2];
-                    bw += breg[kk + 3] * cur[3];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (kk + u < BC) {
+#pragma unroll
+                            for (int i = 0; i < BR; ++i) acc[i] += breg[BC * i + kk + u] * cur[u];
+                        }
+                    }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
                 }
+                bv = red8x4(acc, lane);
             }
-            bv += bw;
-            bv += dpp_mov<DPP_X1>(bv);
             lds_barrier();  // B4
-            if (own && h == 0) slot[r] = bv;
+            {
+                // lanes 2 s and 2 s + 1 of the eight hold row 4 g + s
+                const int rb = BR * g + ((lane >> 1) & 3);
+                if ((lane & 1) == 0 && rb < m) slot[rb] = bv;
+            }
             lds_barrier();  // B5
             // c = W b over this wave's tile rows
             double cw1, cw2;

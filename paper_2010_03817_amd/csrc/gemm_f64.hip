@@ -97,7 +97,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, const dou
             for (int r = 0; r < 4; ++r) {
                 const int rr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
                 const int cc = col0 + wc + j * 16 + (lane & 15);
-                C[(size_t)rr * ldc + cc] = acc[i][j][r];
+                // streaming store: the output is not read again by this kernel
+                __builtin_nontemporal_store(acc[i][j][r], &C[(size_t)rr * ldc + cc]);
             }
 }
 
@@ -112,24 +113,57 @@ constexpr int LAS = BK + 1;   // padded LDS rows (bank spread)
 constexpr int LBS = BT + 2;
 
 template <bool TRANS_B>
+// Work items: every output tile once (ksplit = 1), or twice, for the two
+// halves of the K slices (ksplit = 2), each half adding its partial tile into
+// C, which the caller has zeroed: two additions onto zero give fl(a + b) in
+// either order, so the result does not depend on which half lands first.
+// Persistent: the gridDim.x workgroups (about two per CU) walk the items;
+// when the items divide into eight ranges, workgroup g stays in range g % 8
+// (its XCD under round-robin dispatch), and within a range the tiles go in
+// groups of GROUP_M tile rows, the rows of a group fastest, so that the tiles
+// in flight on one XCD share a few A row panels and B column panels (a
+// working set that stays in that XCD's L2).  The first K slice of a
+// workgroup's next item is read while the current tile is stored.
 __global__ __launch_bounds__(256) void k_gemm_f64_128(int M, int N, int K, const double* __restrict__ A,
                                                       int lda, const double* __restrict__ B, int ldb,
-                                                      double* __restrict__ C, int ldc) {
+                                                      double* __restrict__ C, int ldc, int ksplit) {
     __shared__ double As[2][BT * LAS];
     __shared__ double Bs[2][BK * LBS];
 
     const int tilesM = M / BT, tilesN = N / BT;
     const int total = tilesM * tilesN;
-    const int g = blockIdx.x;
-    int lin;
-    if (total % 8 == 0) {
-        const int per = total / 8;
-        lin = (g % 8) * per + g / 8;  // XCD g % 8 walks its own range, M fastest
-    } else {
-        lin = g;
-    }
-    const int tm = lin % tilesM, tn = lin / tilesM;
-    const int row0 = tm * BT, col0 = tn * BT;
+    const int items = total * ksplit;
+    const int G = gridDim.x, g = blockIdx.x;
+    const bool ranges = items % 8 == 0 && G % 8 == 0;
+    const int per = items / 8, GX = G / 8;
+    const int nks = K / BK, kmid = (nks / 2) * BK;
+    constexpr int GROUP_M = 8;
+    const int gsz = GROUP_M * tilesN;
+    // the i-th item of this workgroup (-1 past the end)
+    auto item_at = [&](int i) -> int {
+        if (ranges) {
+            const int j = g / 8 + GX * i;
+            return j < per ? (g % 8) * per + j : -1;
+        }
+        const int it = g + G * i;
+        return it < items ? it : -1;
+    };
+    struct Job {
+        int row0, col0, kbeg, kend;
+    };
+    auto job_of = [&](int it) -> Job {
+        const int part = it / total;  // K half (ksplit = 2), else 0
+        const int lin = it - part * total;
+        const int first_m = (lin / gsz) * GROUP_M;
+        const int gm = tilesM - first_m < GROUP_M ? tilesM - first_m : GROUP_M;
+        const int in_g = lin % gsz;
+        Job jb;
+        jb.row0 = (first_m + in_g % gm) * BT;
+        jb.col0 = (in_g / gm) * BT;
+        jb.kbeg = ksplit == 2 && part == 1 ? kmid : 0;
+        jb.kend = ksplit == 2 && part == 0 ? kmid : K;
+        return jb;
+    };
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;
@@ -137,7 +171,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64_128(int M, int N, int K, const
     const int ar = t >> 1, ac = (t & 1) * 8;                          // A: row ar, columns ac..ac+7
     const int br = TRANS_B ? (t & 1) * 8 : t >> 4, bc = TRANS_B ? t >> 1 : (t & 15) * 8;
     double ra[8], rb[8];
-    auto fetch = [&](int k0) {
+    auto fetch = [&](int row0, int col0, int k0) {
         const double* pa = A + (size_t)(row0 + ar) * lda + k0 + ac;
 #pragma unroll
         for (int q = 0; q < 8; ++q) ra[q] = pa[q];
@@ -164,48 +198,73 @@ __global__ __launch_bounds__(256) void k_gemm_f64_128(int M, int N, int K, const
         }
     };
 
-    d4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-    fetch(0);
+    int it = item_at(0);
+    if (it < 0) return;  // uniform over the workgroup
+    Job jb = job_of(it);
+    fetch(jb.row0, jb.col0, jb.kbeg);
     stash(0);
     __syncthreads();
-    for (int k0 = 0, s = 0; k0 < K; k0 += BK, ++s) {
-        const int cur = s & 1;
-        const bool more = k0 + BK < K;
-        if (more) fetch(k0 + BK);
-        const double* as = As[cur];
-        const double* bs = Bs[cur];
+    for (int i = 1;; ++i) {
+        d4 acc[4][4];
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            double a[4], b[4];
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = as[(wr + i * 16 + (lane & 15)) * LAS + ks + (lane >> 4)];
+            for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        // slice s of this item is in LDS buffer s & 1 (slice 0 stashed above)
+        for (int k0 = jb.kbeg, s = 0; k0 < jb.kend; k0 += BK, ++s) {
+            const int cur = s & 1;
+            const bool more = k0 + BK < jb.kend;
+            if (more) fetch(jb.row0, jb.col0, k0 + BK);
+            const double* as = As[cur];
+            const double* bs = Bs[cur];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = bs[(ks + (lane >> 4)) * LBS + wc + j * 16 + (lane & 15)];
+            for (int ks = 0; ks < BK; ks += 4) {
+                double a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int q = 0; q < 4; ++q) a[q] = as[(wr + q * 16 + (lane & 15)) * LAS + ks + (lane >> 4)];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        if (more) stash(cur ^ 1);
-        __syncthreads();
-    }
-    // accumulator r of lane l holds D[l/16 + 4 r][l % 16] of its 16x16 block
+                for (int q = 0; q < 4; ++q) b[q] = bs[(ks + (lane >> 4)) * LBS + wc + q * 16 + (lane & 15)];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+                for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rr = row0 + wr + i * 16 + (lane >> 4) + 4 * r;
-                const int cc = col0 + wc + j * 16 + (lane & 15);
-                C[(size_t)rr * ldc + cc] = acc[i][j][r];
+                    for (int q = 0; q < 4; ++q)
+                        acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p][q], 0, 0, 0);
             }
+            if (more) stash(cur ^ 1);
+            __syncthreads();  // (the last one: every wave is done with both buffers)
+        }
+        // the next item's first slice, read while this tile is stored
+        const int nit = item_at(i);
+        Job nj{0, 0, 0, 0};
+        if (nit >= 0) {
+            nj = job_of(nit);
+            fetch(nj.row0, nj.col0, nj.kbeg);
+        }
+        // accumulator r of lane l holds D[l/16 + 4 r][l % 16] of its 16x16 block
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = jb.row0 + wr + p * 16 + (lane >> 4) + 4 * r;
+                    const int cc = jb.col0 + wc + q * 16 + (lane & 15);
+                    double* pc = &C[(size_t)rr * ldc + cc];
+                    if (ksplit == 2) unsafeAtomicAdd(pc, acc[p][q][r]);
+                    // streaming store: the output is not read again by this kernel
+                    else __builtin_nontemporal_store(acc[p][q][r], pc);
+                }
+        if (nit < 0) break;
+        stash(0);
+        __syncthreads();
+        jb = nj;
+    }
+}
+
+// C = 0 by a kernel (no memset node when the launch is captured into a graph).
+__global__ void k_zero_f64(double* __restrict__ C, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) C[i] = 0.0;
 }
 
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
@@ -214,10 +273,32 @@ hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, 
     if (M == 0 || N == 0) return hipSuccess;
     if (M % BT == 0 && N % BT == 0) {
         const int tiles = (M / BT) * (N / BT);
+        // fewer tiles than two per CU and a long K: two K halves per tile, so
+        // that two workgroups share each CU (the output is zeroed first)
+        const int ksplit = tiles < 512 && K >= 4096 ? 2 : 1;
+        if (ksplit == 2) {
+            const size_t n = (size_t)M * N;
+            if (ldc != N) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, n);
+        }
+        // persistent grid: two workgroups per CU (LDS 68 KB each), at most one per item
+        static int cus = 0;
+        if (cus == 0) {
+            int dev = 0, v = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                cus = v;
+            else
+                cus = 256;
+        }
+        const int items = tiles * ksplit;
+        const int grid = items < 2 * cus ? items : 2 * cus;
         if (transB)
-            hipLaunchKernelGGL(k_gemm_f64_128<true>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+            hipLaunchKernelGGL(k_gemm_f64_128<true>, dim3(grid), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc,
+                               ksplit);
         else
-            hipLaunchKernelGGL(k_gemm_f64_128<false>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+            hipLaunchKernelGGL(k_gemm_f64_128<false>, dim3(grid), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc,
+                               ksplit);
         return hipGetLastError();
     }
     const int tiles = (M / GT_M) * (N / GT_N);

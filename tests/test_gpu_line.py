@@ -44,10 +44,12 @@ def test_mfma_f64_lane_layout():
 
 
 @pytest.mark.parametrize("transB", [False, True])
-@pytest.mark.parametrize("shape", [(128, 192, 48), (256, 384, 80), (128, 128, 16), (384, 256, 208)])
+@pytest.mark.parametrize("shape", [(128, 192, 48), (256, 384, 80), (128, 128, 16), (384, 256, 208),
+                                   (256, 256, 8192), (128, 256, 4112)])
 def test_gemm_f64(transB, shape):
     """64- and 128-wide tilings (the latter when M and N are multiples of 128),
-    odd and even numbers of K slices, against numpy."""
+    odd and even numbers of K slices, and the split into two K halves added
+    into a zeroed output (few tiles, long K), against numpy."""
     rng = np.random.default_rng(1)
     M, N, K = shape
     A = rng.standard_normal((M, K))

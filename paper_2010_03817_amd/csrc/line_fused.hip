@@ -251,13 +251,31 @@ struct InvSteps {
     struct Upd<J, false> {
         __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double) {}
     };
+    // keeps sv[J], J > I, in registers at this point of the program: with the
+    // empty volatile statements in program order, the updates of a step are
+    // not sunk to their uses and the broadcasts of the next step are not
+    // hoisted above them (which kept all 136 broadcasts live at once)
+    template <int J, bool = (J < 16)>
+    struct Pin {
+        __device__ __forceinline__ static void run(double (&sv)[16]) {
+            asm volatile("" : "+v"(sv[J]));
+            Pin<J + 1>::run(sv);
+        }
+    };
+    template <int J>
+    struct Pin<J, false> {
+        __device__ __forceinline__ static void run(double (&)[16]) {}
+    };
     __device__ __forceinline__ static void run(const double (&a)[16], double (&sv)[16], double (&w)[16]) {
         __builtin_amdgcn_sched_barrier(0);
+        double aI = a[I];
+        asm volatile("" : "+v"(aI));  // this step's broadcasts start here
         double bc[16];
-        Bcast<I>::run(a[I], bc);  // bc[I] = 1 / L_II, bc[J] = L_JI below
+        Bcast<I>::run(aI, bc);  // bc[I] = 1 / L_II, bc[J] = L_JI below
         __builtin_amdgcn_sched_barrier(0);
         w[I] = sv[I] * bc[I];
         Upd<I + 1>::run(bc, sv, w[I]);
+        Pin<I + 1>::run(sv);
         InvSteps<I + 1>::run(a, sv, w);
     }
 };
@@ -995,6 +1013,7 @@ __device__ __forceinline__ void mv_wt(const double* L, const double* x, int m, i
     o2 = s2 < T ? wt_col(L, x, m, T, s2, lane) : 0.0;
 }
 __device__ __forceinline__ void mv_wt_store(double* y, int m, int T, int w, int nw, int lane, double o1, double o2) {
+    w = __builtin_amdgcn_readfirstlane(w);  // scalar offsets (nothing per lane to keep across the step loop)
     if ((lane & 3) == 0) {
         int l = lane >> 2;
         asm volatile("" : "+v"(l));
@@ -1011,6 +1030,7 @@ __device__ __forceinline__ void mv_w(const double* L, const double* x, int m, in
     o2 = i2 >= 0 ? w_strip(L, x, m, i2, lane) : 0.0;
 }
 __device__ __forceinline__ void mv_w_store(double* y, int m, int T, int w, int nw, int lane, double o1, double o2) {
+    w = __builtin_amdgcn_readfirstlane(w);
     if ((lane & 3) == 0) {
         int l = lane;
         asm volatile("" : "+v"(l));

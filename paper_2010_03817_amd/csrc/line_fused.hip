@@ -200,9 +200,14 @@ struct Bcast<K, false> {
     __device__ __forceinline__ static void run(double, double (&)[16]) {}
 };
 
-// Unrolled steps of the diagonal-tile factorisation (column J, then J + 1..).
-// Lane J keeps 1 / L_JJ in a[J]: its own diagonal entry is read only as that
-// reciprocal afterwards.
+// Unrolled steps of the diagonal-tile factorisation (column J, then J + 1..),
+// each followed by the same step of the inverse of the factor, which needs
+// exactly the values that step has just broadcast.  Factor: lane l holds row
+// i = l & 15 in a[]; lane J keeps 1 / L_JJ in a[J] (its own diagonal entry is
+// read only as that reciprocal afterwards).  Inverse, right-looking, for the
+// column c = i a lane holds: W_Jc = s_J / L_JJ, then s_K -= L_KJ W_Jc for
+// every K > J (s starts as the unit vector e_c), with L_KJ the broadcast bc[K]
+// and 1 / L_JJ the reciprocal every lane has formed from the broadcast pivot.
 template <int J>
 struct DiagSteps {
     // trailing update of column K > J by column J: a_iK -= l_iJ l_KJ
@@ -217,79 +222,60 @@ struct DiagSteps {
     struct Upd<K, false> {
         __device__ __forceinline__ static void run(double (&)[16], const double (&)[16]) {}
     };
-    __device__ __forceinline__ static bool run(double (&a)[16], int i) {
+    // inverse update of s_K, K > J, by W_Jc
+    template <int K, bool = (K < 16)>
+    struct InvUpd {
+        __device__ __forceinline__ static void run(const double (&bc)[16], double (&sv)[16], double w) {
+            sv[K] -= bc[K] * w;
+            InvUpd<K + 1>::run(bc, sv, w);
+        }
+    };
+    template <int K>
+    struct InvUpd<K, false> {
+        __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double) {}
+    };
+    // keeps s_K, K > J, in registers at this point of the program: with the
+    // empty volatile statements in program order, the updates of a step are
+    // not sunk to their uses and the broadcasts of the next step are not
+    // hoisted above them (which kept all the broadcasts live at once)
+    template <int K, bool = (K < 16)>
+    struct Pin {
+        __device__ __forceinline__ static void run(double (&sv)[16]) {
+            asm volatile("" : "+v"(sv[K]));
+            Pin<K + 1>::run(sv);
+        }
+    };
+    template <int K>
+    struct Pin<K, false> {
+        __device__ __forceinline__ static void run(double (&)[16]) {}
+    };
+    __device__ __forceinline__ static bool run(double (&a)[16], double (&sv)[16], double (&w)[16], int i) {
         __builtin_amdgcn_sched_barrier(0);  // one column at a time (bounds the live broadcasts)
         const double d = row_bcast<J>(a[J]);
         if (!(d > 0.0)) return false;  // the same pivot in every lane
         const double iv = rsqrt_pivot(d);
         a[J] = i == J ? iv : a[J] * iv;
         double bc[16];
-        Bcast<J + 1>::run(a[J], bc);
+        Bcast<J + 1>::run(a[J], bc);  // bc[K] = L_KJ
         __builtin_amdgcn_sched_barrier(0);
         Upd<J + 1>::run(a, bc);
-        return DiagSteps<J + 1>::run(a, i);
+        w[J] = sv[J] * iv;
+        InvUpd<J + 1>::run(bc, sv, w[J]);
+        Pin<J + 1>::run(sv);
+        return DiagSteps<J + 1>::run(a, sv, w, i);
     }
 };
 template <>
 struct DiagSteps<16> {
-    __device__ __forceinline__ static bool run(double (&)[16], int) { return true; }
-};
-
-// Unrolled rows I of the inverse of the factor, for the column c a lane holds,
-// right-looking: W_Ic = s_I / L_II, then s_I' -= L_I'I W_Ic for every I' > I
-// (s starts as the unit vector e_c), so that each row waits on one product.
-template <int I>
-struct InvSteps {
-    template <int J, bool = (J < 16)>
-    struct Upd {
-        __device__ __forceinline__ static void run(const double (&bc)[16], double (&sv)[16], double w) {
-            sv[J] -= bc[J] * w;
-            Upd<J + 1>::run(bc, sv, w);
-        }
-    };
-    template <int J>
-    struct Upd<J, false> {
-        __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double) {}
-    };
-    // keeps sv[J], J > I, in registers at this point of the program: with the
-    // empty volatile statements in program order, the updates of a step are
-    // not sunk to their uses and the broadcasts of the next step are not
-    // hoisted above them (which kept all 136 broadcasts live at once)
-    template <int J, bool = (J < 16)>
-    struct Pin {
-        __device__ __forceinline__ static void run(double (&sv)[16]) {
-            asm volatile("" : "+v"(sv[J]));
-            Pin<J + 1>::run(sv);
-        }
-    };
-    template <int J>
-    struct Pin<J, false> {
-        __device__ __forceinline__ static void run(double (&)[16]) {}
-    };
-    __device__ __forceinline__ static void run(const double (&a)[16], double (&sv)[16], double (&w)[16]) {
-        __builtin_amdgcn_sched_barrier(0);
-        double aI = a[I];
-        asm volatile("" : "+v"(aI));  // this step's broadcasts start here
-        double bc[16];
-        Bcast<I>::run(aI, bc);  // bc[I] = 1 / L_II, bc[J] = L_JI below
-        __builtin_amdgcn_sched_barrier(0);
-        w[I] = sv[I] * bc[I];
-        Upd<I + 1>::run(bc, sv, w[I]);
-        Pin<I + 1>::run(sv);
-        InvSteps<I + 1>::run(a, sv, w);
-    }
-};
-template <>
-struct InvSteps<16> {
-    __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double (&)[16]) {}
+    __device__ __forceinline__ static bool run(double (&)[16], double (&)[16], double (&)[16], int) { return true; }
 };
 
 // Diagonal tile K of the blocked factorisation, in registers of one wave:
 // lane l holds row l & 15 of the tile (the four 16-lane rows of the wave hold
-// the same data), factors it by columns with row broadcasts, then forms the
-// inverse of the factor by columns (lane l computes column l & 15:
-// W_Ic = (delta_Ic - sum_{k<I} L_Ik W_kc) / L_II) and stores it in place of
-// the tile (lower part; rows past m are the identity and are not stored).
+// the same data), factors it by columns with row broadcasts and forms the
+// inverse of the factor alongside (lane l computes column l & 15:
+// W_Ic = (delta_Ic - sum_{k<I} L_Ik W_kc) / L_II), which it stores in place
+// of the tile (lower part; rows past m are the identity and are not stored).
 // Returns false when a pivot is not positive (every lane agrees).
 __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane) {
     asm volatile("" : "+v"(lane));  // lane masks formed per call, not hoisted out of the tile loop
@@ -301,11 +287,10 @@ __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane)
         const double v = row[c];
         a[c] = r < m ? (c <= i ? v : 0.0) : (c == i ? 1.0 : 0.0);
     }
-    if (!DiagSteps<0>::run(a, i)) return false;
     double w[16], sv[16];
 #pragma unroll
     for (int I = 0; I < 16; ++I) sv[I] = I == i ? 1.0 : 0.0;
-    InvSteps<0>::run(a, sv, w);
+    if (!DiagSteps<0>::run(a, sv, w, i)) return false;
     if (lane < 16) {
 #pragma unroll
         for (int I = 0; I < 16; ++I)

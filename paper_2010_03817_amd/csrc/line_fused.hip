@@ -1014,15 +1014,32 @@ __device__ __forceinline__ void mv_w(const double* L, const double* x, int m, in
     o1 = w < T ? w_strip(L, x, m, T - 1 - w, lane) : 0.0;
     o2 = i2 >= 0 ? w_strip(L, x, m, i2, lane) : 0.0;
 }
-__device__ __forceinline__ void mv_w_store(double* y, int m, int T, int w, int nw, int lane, double o1, double o2) {
+
+// Entry of the Lanczos vectors that lane `lane` of wave w owns: the row of
+// its W b output (w_strip leaves row 16 I + w_tiles_row(l) of tile row I in
+// the four lanes l of a quad), lane & 3 == 0 for the wave's first tile row,
+// lane & 3 == 1 for its second; -1 if none.  Every row below m has exactly
+// one owner, which keeps q_j, q_{j-1} and the residual of that row.
+__device__ __forceinline__ int owned_row(int m, int T, int w, int nw, int lane) {
     w = __builtin_amdgcn_readfirstlane(w);
-    if ((lane & 3) == 0) {
-        int l = lane;
-        asm volatile("" : "+v"(l));
-        const int rr = w_tiles_row(l), i1 = T - 1 - w, i2 = T - 2 * nw + w;
-        if (w < T && 16 * i1 + rr < m) y[16 * i1 + rr] = o1;
-        if (i2 >= 0 && 16 * i2 + rr < m) y[16 * i2 + rr] = o2;
-    }
+    const int sel = lane & 3, rr = w_tiles_row(lane);
+    const int I = sel == 0 ? T - 1 - w : T - 2 * nw + w;
+    const bool has = sel == 0 ? w < T : (sel == 1 && I >= 0);
+    const int r = 16 * I + rr;
+    return has && r < m ? r : -1;
+}
+
+// Block sum with one barrier: the wave sums go to buf[0 .. nw - 1], which
+// no thread reads or writes between the caller's previous barrier and this
+// one, nor again before every thread has read the sum (a later barrier).
+__device__ __forceinline__ double block_sum_once(double v, double* buf) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum_dpp(v);
+    if (lane == 0) buf[wid] = v;
+    lds_barrier();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += buf[i];
+    return s;
 }
 
 // Scratch layout of the Lanczos phase (after the factor phase).
@@ -1068,9 +1085,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     const int lane = t & 63, wv = t >> 6;
     const int m = c.m;
     const int tw = t - 64;
-    const int r = tw >> 1, h = tw & 1;  // vector entries: thread pair (r, h) owns entry r
     const bool worker = wv >= 1;
-    const bool own = worker && r < m;
     const int kmax = c.kmax;
     double* slot = scr;            // 2 MAXH (zero past m)
     double* al = scr + 2 * MAXH;   // kmax
@@ -1081,13 +1096,18 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     for (int e = m + t; e < 2 * MAXH; e += blockDim.x) slot[e] = 0.0;
     // tile items of the triangular products (every wave, see mv_wt)
     const int T = (m + 15) >> 4, nwv = blockDim.x >> 6;
+    // this lane's entry of the Lanczos vectors (see owned_row): q_j, q_{j-1}
+    // and the residual of row orow stay in its registers, and alpha, beta and
+    // the next vector are formed where W b leaves c
+    const int orow = owned_row(m, T, wv, nwv, lane);
+    const bool own = orow >= 0;
     // start vector (deterministic, positive)
     double qr = 0.0;
     if (own) {
-        u4 hsh = philox10(u4{(uint32_t)r, 0x5eedu, 0u, 0x51a7u}, 0x2010u, 0x3817u);
+        u4 hsh = philox10(u4{(uint32_t)orow, 0x5eedu, 0u, 0x51a7u}, 0x2010u, 0x3817u);
         qr = 0.5 + (double)(hsh.x >> 11) * (1.0 / 2097152.0);
     }
-    double nq = block_sum_lds((own && h == 0) ? qr * qr : 0.0, red);
+    double nq = block_sum_lds(own ? qr * qr : 0.0, red);
     qr *= 1.0 / sqrt(nq);
     if (worker) {
         // B in registers: worker thread tw holds the block of rows 4 g .. 4 g + 3
@@ -1112,9 +1132,9 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
         for (int cyc = 0;; ++cyc) {
         double qprev = 0.0, bprev = 0.0;
         for (int j = 0; j < kmax; ++j) {
-            if (own && h == 0) {
-                Qg[(size_t)j * m + r] = qr;
-                slot[r] = qr;
+            if (own) {
+                Qg[(size_t)j * m + orow] = qr;
+                slot[orow] = qr;
             }
             lds_barrier();  // B1
             // a = W^T q over this wave's tile columns
@@ -1161,19 +1181,19 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
                 if ((lane & 1) == 0 && rb < m) slot[rb] = bv;
             }
             lds_barrier();  // B5
-            // c = W b over this wave's tile rows
+            // c = W b over this wave's tile rows; the owner lanes keep their row
             double cw1, cw2;
             mv_w(L, slot, m, T, wv, nwv, lane, cw1, cw2);
-            lds_barrier();  // B6
-            mv_w_store(slot, m, T, wv, nwv, lane, cw1, cw2);
-            lds_barrier();  // B7
+            double cv = (lane & 3) == 0 ? cw1 : cw2;
             // alpha = q^T c from the computed c, so that the new residual is
-            // orthogonal to q to working precision whatever the conditioning of W
-            double cv = own ? slot[r] : 0.0;
-            const double alj = wave_uniform(block_sum_dpp((own && h == 0) ? qr * cv : 0.0, red));  // B8, B9
+            // orthogonal to q to working precision whatever the conditioning of
+            // W; the wave sums go to red (last read before the previous B7)
+            const double alj = wave_uniform(block_sum_once(own ? qr * cv : 0.0, red));  // B6
             cv -= alj * qr + bprev * qprev;
-            const double bn = wave_uniform(sqrt(block_sum_dpp((own && h == 0) ? cv * cv : 0.0, red)));  // B10, B11
-            lds_barrier();  // B12 (control wave stores alpha and beta and decides)
+            // beta: the wave sums go to the vector slot, which every wave has
+            // finished reading (b) before B6
+            const double bn = wave_uniform(sqrt(block_sum_once(own ? cv * cv : 0.0, slot)));  // B7
+            lds_barrier();  // B8 (control wave stores alpha and beta and decides)
             if (sres[4] != 0.0) break;
             qprev = qr;
             qr = cv * (1.0 / bn);
@@ -1184,9 +1204,9 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
         __syncthreads();  // basis rows in HBM are read across lanes
         {
             const int kk = (int)sres[5];
-            double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, r) : 0.0;
-            if (!c.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, r);
-            const double nz = block_sum_lds((own && h == 0) ? zr * zr : 0.0, red);
+            double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, orow) : 0.0;
+            if (!c.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, orow);
+            const double nz = block_sum_lds(own ? zr * zr : 0.0, red);
             qr = zr * (1.0 / sqrt(nz));
         }
         lds_barrier();
@@ -1199,6 +1219,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
         int next_check = c.first_check > 0 ? c.first_check : 4;
         double prev_q = -1.0;
         int prev_k = 0;
+        double qprev = 0.0, bprev = 0.0;  // this wave's own rows (as the workers')
         // bracket of this lane's extreme Ritz value at the previous test (NaN: none)
         double w_lo = NAN, w_hi = NAN, w_r = 0.0;
         long long tprev = clock64();
@@ -1209,6 +1230,10 @@ ph[i] += tn - tprev;              \
 tprev = tn;                       \
     }
         for (int j = 0; j < kmax; ++j) {
+            if (own) {
+                Qg[(size_t)j * m + orow] = qr;
+                slot[orow] = qr;
+            }
             lds_barrier();  // B1
             PHASE(0)
             {
@@ -1222,16 +1247,13 @@ tprev = tn;                       \
             lds_barrier();  // B4
             PHASE(2)
             lds_barrier();  // B5
-            {
-                double c1, c2;
-                mv_w(L, slot, m, T, 0, nwv, lane, c1, c2);
-                lds_barrier();  // B6
-                mv_w_store(slot, m, T, 0, nwv, lane, c1, c2);
-            }
-            lds_barrier();  // B7
-            const double alj = block_sum_lds(0.0, red);           // B8, B9
+            double c1, c2;
+            mv_w(L, slot, m, T, 0, nwv, lane, c1, c2);
+            double cv = (lane & 3) == 0 ? c1 : c2;
+            const double alj = wave_uniform(block_sum_once(own ? qr * cv : 0.0, red));  // B6
             PHASE(3)
-            const double bn = sqrt(block_sum_lds(0.0, red));      // B10, B11
+            cv -= alj * qr + bprev * qprev;
+            const double bn = wave_uniform(sqrt(block_sum_once(own ? cv * cv : 0.0, slot)));  // B7
             // T_k in LDS (this wave's own writes precede its reads below)
             if (lane == 0) {
                 al[j] = alj;
@@ -1394,13 +1416,22 @@ tprev = tn;                       \
                 sres[5] = (double)k;
                 if (stop != 0.0) sres[6] += (double)k;
             }
-            lds_barrier();  // B12
+            lds_barrier();  // B8
             PHASE(5)
             if (stop != 0.0) break;
+            qprev = qr;
+            qr = cv * (1.0 / bn);
+            bprev = bn;
         }
         if (!(sres[4] == 2.0 && cyc + 1 < NCYCLES)) break;
-        __syncthreads();
-        (void)block_sum_lds(0.0, red);
+        __syncthreads();  // basis rows in HBM are read across lanes
+        {
+            const int kk = (int)sres[5];
+            double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, orow) : 0.0;
+            if (!c.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, orow);
+            const double nz = block_sum_lds(own ? zr * zr : 0.0, red);
+            qr = zr * (1.0 / sqrt(nz));
+        }
         lds_barrier();
         }
 #undef PHASE

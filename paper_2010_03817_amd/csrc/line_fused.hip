@@ -1320,13 +1320,16 @@ tprev = tn;                       \
                         }
                     }
                 }
-                // multisection down to a relative width rel (at most 12 passes)
+                // multisection down to a relative width rel (at most 12 passes);
+                // the points lo + w (i / (npts + 1)) and the new ends use the one
+                // expression, so each new end is exactly a point that was counted
+                const double inv = 1.0 / (double)(npts + 1);
                 auto msect = [&](double rel) {
 #pragma nounroll
                     for (int it = 0; it < 12; ++it) {
                         const double w = hi - lo;
                         if (!(w > rel * fmax(fabs(lo), fabs(hi)))) break;
-                        const double x = lo + w * (double)(sub + 1) / (double)(npts + 1);
+                        const double x = lo + w * ((double)(sub + 1) * inv);
                         const int cnt = sturm_lds(al, be, k, x);
                         ++n_passes;
                         const bool hitp = want_min ? (cnt >= 1) : (cnt >= k);
@@ -1335,8 +1338,8 @@ tprev = tn;                       \
                         if (c.min_only) hm = mask;
                         else hm = want_min ? (mask & 0xffffffffull) : (mask >> 32);
                         const int first = hm ? __ffsll((long long)hm) - 1 : npts;
-                        const double nlo = lo + w * (double)first / (double)(npts + 1);
-                        const double nhi = first < npts ? lo + w * (double)(first + 1) / (double)(npts + 1) : hi;
+                        const double nlo = lo + w * ((double)first * inv);
+                        const double nhi = first < npts ? lo + w * ((double)(first + 1) * inv) : hi;
                         lo = nlo;
                         hi = nhi;
                     }

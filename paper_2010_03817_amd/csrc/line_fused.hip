@@ -1,18 +1,22 @@
 // Fused per-chain line oracle (paper: Alg. INTERSECTION for Phi(t) = x + t v,
 // Lemma "PEP and S cap C"; Alg. REFLECTION, Lemma "Gradient of det F").
 //
-// One workgroup per chain, 2m threads rounded up to whole waves.
+// One workgroup per chain: a steering wave plus 2m threads rounded up to
+// whole waves.
 //
 //  1. F0 = F(x) + t0 B(v) (t0 = 0 on the plain path; the certified lower end of
 //     the learned bracket otherwise) is read into LDS, packed by rows.
 //  2. Blocked Cholesky F0 = L L^T and in-place triangular inverse W = L^{-1}
 //     on 16x16 tiles with the FP64 matrix cores (v_mfma_f64_16x16x4f64);
 //     the diagonal tiles are factored / inverted by one wave.
-//  3. B(v) is held in registers: lane (r, h) keeps half h of the full
-//     symmetric row r, so B a needs no cross-lane reduction.
+//  3. B(v) is held in registers: worker thread t keeps the 4 x 25 block of
+//     the full symmetric B at rows 4 (t / 8).. and columns 25 (t % 8).., and
+//     B a sums each row block's four partial rows over eight lanes by DPP.
 //  4. Lanczos on C = W B W^T (W^T q from LDS, B a from registers, W b from
-//     LDS) without reorthogonalisation; the basis goes to HBM for the Ritz
-//     vector.  Every few steps the extreme Ritz values of T_k are bracketed by
+//     LDS) without reorthogonalisation; each vector entry belongs to the lane
+//     that W b leaves holding that row, so c, alpha, beta and the next q are
+//     formed in registers; the basis goes to HBM for the Ritz vector.  Every
+//     few steps the extreme Ritz values of T_k are bracketed by
 //     multisection of Sturm counts and the residual bound beta_{k+1}|s_k| is
 //     formed from the backward three-term recurrence of the eigenvector of
 //     T_k; stop when it is below max(tol |theta|, 100 eps rho), rho the
@@ -1075,8 +1079,9 @@ struct LzCtx {
 // r_min, theta_max, r_max, stop (1 converged, 2 not), steps of the last
 // cycle, total steps; al / be hold T_k of the last cycle and Qg its basis.
 // Wave 0 steers (Ritz values, residual bounds, stop decision); waves 1..
-// hold B and run the matrix-vector products.  Both run the same sequence
-// of barriers.
+// hold B and run B a.  Every wave runs its share of the triangular products
+// and owns the vector entries of its W b rows.  Both paths run the same
+// sequence of barriers (eight per step).
 __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, const LzCtx& c) {
     // the thread index is made opaque here so that lane addressing is formed
     // per call, not hoisted (and kept live) across a caller's loop

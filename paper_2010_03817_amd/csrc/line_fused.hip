@@ -303,7 +303,35 @@ __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane)
     return true;
 }
 
+// P_KJ = L_KJ W_JJ for the tiles K > J of column J, in place (W_JJ = L_JJ^{-1},
+// left in the diagonal tile by the factorisation), tiles dealt over waves
+// w = 0..nw-1 of the caller's choice.  MFMA right operand W_JJ[4 s + (l >> 4)][l & 15].
+__device__ __forceinline__ void inv_p_column(double* L, int m, int T, int J, int w, int nw, int lane) {
+    const int li = lane & 15, lh = lane >> 4;
+    if (J + 1 + w >= T) return;
+    double wj[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double v = L[rowb(16 * J + 4 * s + lh, m) + 16 * J + li];
+        wj[s] = li <= 4 * s + lh ? v : 0.0;
+    }
+    for (int K = J + 1 + w; K < T; K += nw) {
+        const double* pa = L + rowb(16 * K + li, m) + 16 * J + lh;
+        d4 acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], wj[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * K + lh + 4 * r;
+            if (row < m) L[rowb(row, m) + 16 * J + li] = acc[r];
+        }
+    }
+}
+
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
+// On success the columns J < T - 2 below the diagonal hold P_KJ = L_KJ W_JJ,
+// the first step of tri_inverse, formed by the waves that would otherwise
+// wait for the next diagonal tile.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
 // prof (nullable): thread 0 adds the cycles of the diagonal-tile, panel and
 // trailing-update stages to prof[0..2].
@@ -392,6 +420,10 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
                 const int jj = e - ii * (ii + 1) / 2;
                 trail_tile(K, K + 1 + ii, K + 1 + jj);
             }
+            // the first step of the triangular inverse for column K - 1, whose
+            // panel no later update reads: P_I,K-1 = L_I,K-1 W_K-1,K-1 in place
+            // (these waves would otherwise wait for the diagonal factor)
+            if (K >= 1) inv_p_column(L, m, T, K - 1, wv - 1, nw - 1, lane);
         }
         lds_barrier();
         CHOL_TICK(c2)
@@ -407,6 +439,8 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
 
 // In-place triangular inverse W = L^{-1} of the packed lower factor: column
 // blocks from the last one, W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) L_JJ^{-1}.
+// Expects the factor as chol_blocked leaves it: the products
+// P_KJ = L_KJ L_JJ^{-1} of the columns J < T - 2 already in place.
 // prof (nullable): thread 0 adds the cycles of the three parts (P products,
 // W P sums, stores) to prof[0..2].
 __device__ __forceinline__ void tri_inverse(double* L, int m, double* D, long long* prof = nullptr) {
@@ -422,29 +456,12 @@ __device__ __forceinline__ void tri_inverse(double* L, int m, double* D, long lo
         acc += tn - tc;                      \
         tc = tn;                             \
     }
+    // chol_blocked has formed P_KJ = L_KJ W_JJ (K > J) for the columns J < T - 2
     for (int J = T - 1; J >= 0; --J) {
-        // P_KJ = L_KJ W_JJ for K > J, in place (W_JJ = L_JJ^{-1}, left in the
-        // diagonal tile by the factorisation; right operand W_JJ[4 s + (l >> 4)][l & 15])
-        if (J + 1 < T) {
-            double wj[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const double w = L[rowb(16 * J + 4 * s + lh, m) + 16 * J + li];
-                wj[s] = li <= 4 * s + lh ? w : 0.0;
-            }
-            for (int K = J + 1 + wv; K < T; K += nw) {
-                const double* pa = L + rowb(16 * K + li, m) + 16 * J + lh;
-                d4 acc{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], wj[s], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * K + lh + 4 * r;
-                    if (row < m) L[rowb(row, m) + 16 * J + li] = acc[r];
-                }
-            }
+        if (J >= T - 2) {
+            inv_p_column(L, m, T, J, wv, nw, lane);
+            lds_barrier();
         }
-        lds_barrier();
         INV_TICK(c0)
         // W_IJ = - sum_{K=J+1..I} W_IK P_KJ for the tile rows I > J.  Row I takes
         // I - J products; rows are dealt by size in pairs {w, 2 nw - 1 - w} (row

@@ -303,35 +303,50 @@ __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane)
     return true;
 }
 
-// P_KJ = L_KJ W_JJ for the tiles K > J of column J, in place (W_JJ = L_JJ^{-1},
-// left in the diagonal tile by the factorisation), tiles dealt over waves
-// w = 0..nw-1 of the caller's choice.  MFMA right operand W_JJ[4 s + (l >> 4)][l & 15].
-__device__ __forceinline__ void inv_p_column(double* L, int m, int T, int J, int w, int nw, int lane) {
+// Tile (I, J), J < I, of the inverse W = L^{-1} by rows:
+// W_IJ = -W_II sum_{K=J..I-1} L_IK W_KJ, with row I of L, the rows K < I of W
+// (W_JJ the diagonal tile, lower part) and W_II in place.  Returned in the
+// accumulator layout (lane l: rows (l >> 4) + 4 r, column l & 15), which is
+// also the right-operand layout of the second product.  Rows of tile row I
+// past m read row m - 1 (finite; their results are never stored).
+__device__ __forceinline__ d4 inv_row_tile(const double* L, int m, int I, int J, int lane) {
     const int li = lane & 15, lh = lane >> 4;
-    if (J + 1 + w >= T) return;
-    double wj[4];
+    const double* pa = L + rowb(16 * I + li, m) + lh;  // L_IK[li][4 s + lh] at 16 K + 4 s
+    d4 acc{0.0, 0.0, 0.0, 0.0};
+    for (int K = J; K < I; ++K) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kr = 16 * K + 4 * s + lh;  // < m: K <= T - 2
+            const double b = L[rowb(kr, m) + 16 * J + li];
+            const double bv = (K > J || li <= 4 * s + lh) ? b : 0.0;  // W_JJ: lower part
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[16 * K + 4 * s], bv, acc, 0, 0, 0);
+        }
+    }
+    const double* pw = L + rowb(16 * I + li, m) + 16 * I + lh;  // W_II[li][4 s + lh]
+    d4 out{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const double v = L[rowb(16 * J + 4 * s + lh, m) + 16 * J + li];
-        wj[s] = li <= 4 * s + lh ? v : 0.0;
+        const double a = 4 * s + lh <= li ? pw[4 * s] : 0.0;
+        out = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc[s], out, 0, 0, 0);
     }
-    for (int K = J + 1 + w; K < T; K += nw) {
-        const double* pa = L + rowb(16 * K + li, m) + 16 * J + lh;
-        d4 acc{0.0, 0.0, 0.0, 0.0};
+    return -out;
+}
+__device__ __forceinline__ void store_tile(double* L, int m, int I, int J, d4 v, int lane) {
+    const int li = lane & 15, lh = lane >> 4;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], wj[s], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * K + lh + 4 * r;
-            if (row < m) L[rowb(row, m) + 16 * J + li] = acc[r];
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + lh + 4 * r;
+        if (row < m) L[rowb(row, m) + 16 * J + li] = v[r];
     }
 }
 
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
-// On success the columns J < T - 2 below the diagonal hold P_KJ = L_KJ W_JJ,
-// the first step of tri_inverse, formed by the waves that would otherwise
-// wait for the next diagonal tile.
+// It also forms the inverse W = L^{-1} by rows, row I in the trailing phase
+// of step I on the waves that would otherwise wait for the next diagonal
+// tile (row I of L is final after the panel of column I - 1, W_II after the
+// previous trailing phase), kept in registers and stored in the next panel
+// phase, when no update reads row I of L any more.  On success the tile rows
+// I <= T - 2 hold W; tri_inverse forms the last one.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
 // prof (nullable): thread 0 adds the cycles of the diagonal-tile, panel and
 // trailing-update stages to prof[0..2].
@@ -373,9 +388,21 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
     }
     lds_barrier();
     CHOL_TICK(c0)
+    // row wrow of W computed in the last trailing phase by waves 1.. (tiles
+    // j1 = wv - 1 and j2 = 2 (nw - 1) - wv, paired by size), not yet stored
+    int wrow = 0;
+    d4 wt1{0.0, 0.0, 0.0, 0.0}, wt2{0.0, 0.0, 0.0, 0.0};
+    const int j1 = wv - 1, j2 = 2 * (nw - 1) - wv;
+    auto store_wrow = [&]() {
+        if (wv >= 1 && wrow >= 1) {
+            if (j1 < wrow) store_tile(L, m, wrow, j1, wt1, lane);
+            if (j2 < wrow) store_tile(L, m, wrow, j2, wt2, lane);
+        }
+    };
     for (int K = 0; K < T; ++K) {
         if (*flag == 0) return false;
         if (K + 1 == T) break;
+        store_wrow();  // row K - 1 of W (no update of this step reads it)
         // panel: L_IK = A_IK W_KK^T (W_KK = L_KK^{-1}, now in the diagonal tile).
         // MFMA operands: lane l holds X[l & 15][4 s + (l >> 4)] of the left and
         // Y[l & 15][4 s + (l >> 4)] of the right factor of X Y^T; results land
@@ -420,14 +447,16 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
                 const int jj = e - ii * (ii + 1) / 2;
                 trail_tile(K, K + 1 + ii, K + 1 + jj);
             }
-            // the first step of the triangular inverse for column K - 1, whose
-            // panel no later update reads: P_I,K-1 = L_I,K-1 W_K-1,K-1 in place
-            // (these waves would otherwise wait for the diagonal factor)
-            if (K >= 1) inv_p_column(L, m, T, K - 1, wv - 1, nw - 1, lane);
+            // row K of W (these waves would otherwise wait for the diagonal factor)
+            wrow = K;
+            if (j1 < K) wt1 = inv_row_tile(L, m, K, j1, lane);
+            if (j2 < K) wt2 = inv_row_tile(L, m, K, j2, lane);
         }
         lds_barrier();
         CHOL_TICK(c2)
     }
+    store_wrow();  // row T - 2 of W
+    lds_barrier();
 #undef CHOL_TICK
     if (prof && t == 0) {
         prof[0] += c0;
@@ -437,92 +466,35 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
     return true;
 }
 
-// In-place triangular inverse W = L^{-1} of the packed lower factor: column
-// blocks from the last one, W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) L_JJ^{-1}.
-// Expects the factor as chol_blocked leaves it: the products
-// P_KJ = L_KJ L_JJ^{-1} of the columns J < T - 2 already in place.
-// prof (nullable): thread 0 adds the cycles of the three parts (P products,
-// W P sums, stores) to prof[0..2].
+// Last tile row of the inverse W = L^{-1} (chol_blocked has formed the rows
+// above it in place): W_T-1,J for J < T - 1 over all waves, paired by size,
+// then stored once every wave has read row T - 1 of L.
+// prof (nullable): thread 0 adds the cycles of its products and stores to
+// prof[1], prof[2] (prof[0], the earlier P products, stays 0).
 __device__ __forceinline__ void tri_inverse(double* L, int m, double* D, long long* prof = nullptr) {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
-    const int li = lane & 15, lh = lane >> 4;
     const int T = (m + 15) / 16;
-    long long c0 = 0, c1 = 0, c2 = 0, tc = prof ? clock64() : 0;
-#define INV_TICK(acc)                        \
-    if (prof) {                              \
-        const long long tn = clock64();      \
-        acc += tn - tc;                      \
-        tc = tn;                             \
-    }
-    // chol_blocked has formed P_KJ = L_KJ W_JJ (K > J) for the columns J < T - 2
-    for (int J = T - 1; J >= 0; --J) {
-        if (J >= T - 2) {
-            inv_p_column(L, m, T, J, wv, nw, lane);
-            lds_barrier();
-        }
-        INV_TICK(c0)
-        // W_IJ = - sum_{K=J+1..I} W_IK P_KJ for the tile rows I > J.  Row I takes
-        // I - J products; rows are dealt by size in pairs {w, 2 nw - 1 - w} (row
-        // item s is I = T - 1 - s; at most two per wave since T - 1 - J <= 2 nw - 3),
-        // and a wave runs its two rows in one K loop: they share the loads of
-        // P_KJ and give two independent MFMA chains.  Right operand
-        // P_KJ[4 s + (l >> 4)][l & 15]; its rows past m are zeroed, since the
-        // matching columns of W_IK are zero and garbage there must not meet them.
-        {
-            const int n = T - 1 - J, s2 = 2 * nw - 1 - wv;
-            const int I1 = wv < n ? T - 1 - wv : -1, I2 = s2 < n ? T - 1 - s2 : -1;
-            d4 acc1{0.0, 0.0, 0.0, 0.0}, acc2{0.0, 0.0, 0.0, 0.0};
-            if (I1 >= 0) {
-                const int rb1 = rowb(16 * I1 + li, m), rb2 = rowb(16 * (I2 >= 0 ? I2 : I1) + li, m);
-                for (int K = J + 1; K <= I1; ++K) {
-                    double bq[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int kr = 16 * K + 4 * q + lh;
-                        const double bv = L[rowb(kr, m) + 16 * J + li];
-                        bq[q] = kr < m ? bv : 0.0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double av = L[rb1 + 16 * K + 4 * q + lh];
-                        const double a1 = (K < I1 || 4 * q + lh <= li) ? av : 0.0;
-                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bq[q], acc1, 0, 0, 0);
-                    }
-                    if (K <= I2) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const double av = L[rb2 + 16 * K + 4 * q + lh];
-                            const double a2 = (K < I2 || 4 * q + lh <= li) ? av : 0.0;
-                            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bq[q], acc2, 0, 0, 0);
-                        }
-                    }
-                }
-            }
-            lds_barrier();
-            INV_TICK(c1)
-            if (I1 >= 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * I1 + lh + 4 * r;
-                    if (row < m) L[rowb(row, m) + 16 * J + li] = -acc1[r];
-                }
-            }
-            if (I2 >= 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * I2 + lh + 4 * r;
-                    if (row < m) L[rowb(row, m) + 16 * J + li] = -acc2[r];
-                }
-            }
-        }
+    long long tc = prof ? clock64() : 0, c1 = 0, c2 = 0;
+    (void)D;
+    if (T >= 2) {
+        const int I = T - 1, ja = wv, jb = 2 * nw - 1 - wv;
+        d4 va{0.0, 0.0, 0.0, 0.0}, vb{0.0, 0.0, 0.0, 0.0};
+        if (ja < I) va = inv_row_tile(L, m, I, ja, lane);
+        if (jb < I) vb = inv_row_tile(L, m, I, jb, lane);
         lds_barrier();
-        INV_TICK(c2)
+        if (prof) {
+            const long long tn = clock64();
+            c1 = tn - tc;
+            tc = tn;
+        }
+        if (ja < I) store_tile(L, m, I, ja, va, lane);
+        if (jb < I) store_tile(L, m, I, jb, vb, lane);
+        lds_barrier();
+        if (prof) c2 = clock64() - tc;
     }
-#undef INV_TICK
     if (prof && t == 0) {
-        prof[0] += c0;
         prof[1] += c1;
         prof[2] += c2;
     }

@@ -179,8 +179,7 @@ __device__ __forceinline__ double row_bcast(double v) {
 // Newton steps y <- y + y (1 - d y^2) / 2 (quadratic convergence from its
 // ~2^-23 relative error to the rounding level); tiny or huge d take the
 // correctly rounded library form.
-__device__ __forceinline__ double rsqrt_pivot(double d) {
-    if (!(d > 1e-280 && d < 1e280)) return 1.0 / sqrt(d);
+__device__ __forceinline__ double rsqrt_newton(double d) {  // d in (1e-280, 1e280)
     double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -188,6 +187,10 @@ __device__ __forceinline__ double rsqrt_pivot(double d) {
         y = fma(0.5 * y, r, y);
     }
     return y;
+}
+__device__ __forceinline__ double rsqrt_pivot(double d) {
+    if (!(d > 1e-280 && d < 1e280)) return 1.0 / sqrt(d);
+    return rsqrt_newton(d);
 }
 
 // Row broadcasts bc[K] = lane K's v for K = K0..15, issued back to back so that
@@ -274,12 +277,102 @@ struct DiagSteps<16> {
     __device__ __forceinline__ static bool run(double (&)[16], double (&)[16], double (&)[16], int) { return true; }
 };
 
+// y[K] -= s x[K] for K = K0..15
+template <int K0, int K = K0, bool = (K < 16)>
+struct SubScaled {
+    __device__ __forceinline__ static void run(double (&y)[16], const double (&x)[16], double s) {
+        y[K] = fma(-s, x[K], y[K]);
+        SubScaled<K0, K + 1>::run(y, x, s);
+    }
+};
+template <int K0, int K>
+struct SubScaled<K0, K, false> {
+    __device__ __forceinline__ static void run(double (&)[16], const double (&)[16], double) {}
+};
+template <int K0, int K = K0, bool = (K < 16)>
+struct PinFrom {  // empty volatile statements on x[K0..15]: values formed before this point
+    __device__ __forceinline__ static void run(double (&x)[16]) {
+        asm volatile("" : "+v"(x[K]));
+        PinFrom<K0, K + 1>::run(x);
+    }
+};
+template <int K0, int K>
+struct PinFrom<K0, K, false> {
+    __device__ __forceinline__ static void run(double (&)[16]) {}
+};
+
+// The same factorisation and inverse without square roots on the dependency
+// chain (elimination on the unscaled columns, as in L D L^T): with d_J the
+// pivot and r_J = 1 / d_J, column J updates a_iK -= (a_iJ r_J) a_KJ and the
+// inverse s_K -= a_KJ (s_J r_J) for K > J, where a_KJ is broadcast unscaled
+// and so does not wait for r_J; L_KJ = a_KJ / sqrt(d_J) and W_Jc = s_J /
+// sqrt(d_J) follow from one square root per lane after the last column (lane
+// i keeps its own pivot d_i).  The chain of a column is then the pivot
+// broadcast, the reciprocal (hardware estimate and two Newton steps) and the
+// update of the next pivot; the rest of column J - 1's updates and column J's
+// broadcasts are issued while the reciprocal is in flight.  `bad` is set when
+// a pivot is not in (1e-280, 1e280) (not positive, NaN or extreme): the caller
+// then repeats the tile with DiagSteps, which decides.
+template <int J>
+struct FastCol {
+    __device__ __forceinline__ static void run(double (&a)[16], double (&sv)[16], double (&bp)[16], double mp, double tp,
+                                               double& piv, bool& bad, int i) {
+        __builtin_amdgcn_sched_barrier(0);
+        const double d = row_bcast<J>(a[J]);  // a[J] of lane J: last updated by column J - 1's leading update
+        double y = __builtin_amdgcn_rcp(d);
+        bad |= !(d > 1e-280 && d < 1e280);
+        piv = i == J ? d : piv;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (J > 0) {  // the rest of column J - 1 (its update of column J was the leading one)
+            SubScaled<J + 1>::run(a, bp, mp);
+            SubScaled<J>::run(sv, bp, tp);
+            PinFrom<J + 1>::run(a);
+            PinFrom<J>::run(sv);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        double bc[16];
+        Bcast<J + 1>::run(a[J], bc);  // bc[K] = a_KJ, K > J
+        PinFrom<J + 1>::run(bc);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const double e = fma(-d, y, 1.0);
+            y = fma(y, e, y);
+        }
+        const double mJ = a[J] * y, tJ = sv[J] * y;
+        if constexpr (J + 1 < 16) {
+            a[J + 1] = fma(-mJ, bc[J + 1], a[J + 1]);  // leading update: the next pivot's column
+            asm volatile("" : "+v"(a[J + 1]));
+        }
+        FastCol<J + 1>::run(a, sv, bc, mJ, tJ, piv, bad, i);
+    }
+};
+template <>
+struct FastCol<16> {
+    __device__ __forceinline__ static void run(double (&)[16], double (&)[16], double (&)[16], double, double, double&,
+                                               bool&, int) {}
+};
+// w[J] = sv[J] s_J with s_J broadcast from lane J
+template <int J, bool = (J < 16)>
+struct ScaleRows {
+    __device__ __forceinline__ static void run(const double (&sv)[16], double (&w)[16], double s) {
+        w[J] = sv[J] * row_bcast<J>(s);
+        ScaleRows<J + 1>::run(sv, w, s);
+    }
+};
+template <int J>
+struct ScaleRows<J, false> {
+    __device__ __forceinline__ static void run(const double (&)[16], double (&)[16], double) {}
+};
+
 // Diagonal tile K of the blocked factorisation, in registers of one wave:
 // lane l holds row l & 15 of the tile (the four 16-lane rows of the wave hold
 // the same data), factors it by columns with row broadcasts and forms the
 // inverse of the factor alongside (lane l computes column l & 15:
 // W_Ic = (delta_Ic - sum_{k<I} L_Ik W_kc) / L_II), which it stores in place
 // of the tile (lower part; rows past m are the identity and are not stored).
+// FastCol does the work; a tile with a pivot outside its range is repeated by
+// DiagSteps (square root per column, library form for extreme pivots).
 // Returns false when a pivot is not positive (every lane agrees).
 __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane) {
     asm volatile("" : "+v"(lane));  // lane masks formed per call, not hoisted out of the tile loop
@@ -294,7 +387,21 @@ __device__ __forceinline__ bool diag_factor16(double* L, int m, int K, int lane)
     double w[16], sv[16];
 #pragma unroll
     for (int I = 0; I < 16; ++I) sv[I] = I == i ? 1.0 : 0.0;
-    if (!DiagSteps<0>::run(a, sv, w, i)) return false;
+    double bp[16], piv = 1.0;
+    bool bad = false;
+    FastCol<0>::run(a, sv, bp, 0.0, 0.0, piv, bad, i);
+    if (!bad) {
+        ScaleRows<0>::run(sv, w, rsqrt_newton(piv));  // piv in range: no pivot was flagged
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const double v = row[c];
+            a[c] = r < m ? (c <= i ? v : 0.0) : (c == i ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int I = 0; I < 16; ++I) sv[I] = I == i ? 1.0 : 0.0;
+        if (!DiagSteps<0>::run(a, sv, w, i)) return false;
+    }
     if (lane < 16) {
 #pragma unroll
         for (int I = 0; I < 16; ++I)
@@ -808,6 +915,27 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
     return s;
 }
 
+// Minimum and maximum over the wave by the same DPP steps (no lane-address
+// registers, unlike shuffles), the four row results read from lanes 0, 16, 32, 48.
+template <bool MAX>
+__device__ __forceinline__ double wave_ext_dpp(double v) {
+    auto op = [](double x, double y) { return MAX ? fmax(x, y) : fmin(x, y); };
+    v = op(v, dpp_mov<DPP_X1>(v));
+    v = op(v, dpp_mov<DPP_X2>(v));
+    v = op(v, dpp_mov<DPP_HMIR>(v));
+    v = op(v, dpp_mov<DPP_MIR>(v));
+    const long long b = __double_as_longlong(v);
+    double s = v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+        const double x = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        s = r == 0 ? x : op(s, x);
+    }
+    return s;
+}
+
 // block_sum_lds with the wave sums by DPP (same barriers).
 __device__ __forceinline__ double block_sum_dpp(double v, double* red) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1101,7 +1229,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
         u4 hsh = philox10(u4{(uint32_t)orow, 0x5eedu, 0u, 0x51a7u}, 0x2010u, 0x3817u);
         qr = 0.5 + (double)(hsh.x >> 11) * (1.0 / 2097152.0);
     }
-    double nq = block_sum_lds(own ? qr * qr : 0.0, red);
+    double nq = block_sum_dpp(own ? qr * qr : 0.0, red);
     qr *= 1.0 / sqrt(nq);
     if (worker) {
         // B in registers: worker thread tw holds the block of rows 4 g .. 4 g + 3
@@ -1200,7 +1328,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
             const int kk = (int)sres[5];
             double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, orow) : 0.0;
             if (!c.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, orow);
-            const double nz = block_sum_lds(own ? zr * zr : 0.0, red);
+            const double nz = block_sum_dpp(own ? zr * zr : 0.0, red);
             qr = zr * (1.0 / sqrt(nz));
         }
         lds_barrier();
@@ -1278,8 +1406,8 @@ tprev = tn;                       \
                     glo = fmin(glo, aB - rad);
                     ghi = fmax(ghi, aB + rad);
                 }
-                glo = wave_min(glo);
-                ghi = wave_max(ghi);
+                glo = wave_ext_dpp<false>(glo);
+                ghi = wave_ext_dpp<true>(ghi);
                 const double pad = 1e-14 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
                 glo -= pad;
                 ghi += pad;
@@ -1426,7 +1554,7 @@ tprev = tn;                       \
             const int kk = (int)sres[5];
             double zr = own ? ritz_row(al, be, kk, sres[0], Qg, m, orow) : 0.0;
             if (!c.min_only && own) zr += ritz_row(al, be, kk, sres[2], Qg, m, orow);
-            const double nz = block_sum_lds(own ? zr * zr : 0.0, red);
+            const double nz = block_sum_dpp(own ? zr * zr : 0.0, red);
             qr = zr * (1.0 / sqrt(nz));
         }
         lds_barrier();

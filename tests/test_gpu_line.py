@@ -106,6 +106,32 @@ def test_intersect_special_bodies():
     assert _np(tm)[0] == pytest.approx(tm_r[0], rel=T_REL)
 
 
+def test_extreme_scale_pivots():
+    """F and B scaled by 1e285 and by 1e-285: pivots outside (1e-280, 1e280)
+    send the diagonal tiles to the square-root-per-column factorisation; t+-
+    and membership are invariant under the scaling, so the oracle of the
+    unscaled instance is the reference."""
+    S = _spec()
+    inst = I.gbase(30, 40, seed=9)
+    o = O.Oracle(inst)
+    rng = np.random.default_rng(9)
+    x, v = _points(o, inst, rng, 24)
+    tm_r, tp_r, st_r = o.intersect(x, v)
+    dm = I.random_directions(rng, 64, inst.n)
+    xm = (rng.uniform(0.0, 1.5, 64) * o.intersect(np.zeros((64, inst.n)), dm)[1])[:, None] * dm
+    mem_r = o.membership(xm)
+    assert 0 < mem_r.sum() < len(mem_r)
+    for c in (1e285, 1e-285):
+        blocks = [I.Block(b.kind, b.A * c) for b in inst.blocks]
+        g = S.Spectrahedron(I.Instance(inst.n, blocks))
+        tm, tp, st = [_np(a) for a in g.intersect(x, v)]
+        assert np.array_equal(st, st_r), (c, st, st_r)
+        ok = st_r == O.OK
+        assert np.allclose(tp[ok], tp_r[ok], rtol=T_REL, atol=0), c
+        assert np.allclose(tm[ok], tm_r[ok], rtol=T_REL, atol=0), c
+        assert np.array_equal(_np(g.membership(xm)), mem_r), c
+
+
 def test_intersect_near_boundary():
     """Points pulled back from the boundary by 1e-6 (the post-reflection
     starts of the billiard walk), bucketed by the conditioning of F."""

@@ -43,8 +43,10 @@ spec_status spec_diag_stage_times(spec_handle h, double* ms_and_counts, double* 
  * Lanczos steps (slots 8..13: q stored, W^T q, B a, W b and alpha, beta, stop
  * test and the closing barrier); the stop tests run and the Sturm passes
  * they made (slots 16, 17), and the cycles of their multisection and of
- * their residual bounds and decisions (slots 18, 19); the triangular
- * inverse's product, sum and store cycles (slots 20..22).  0 turns it off.  spec_diag_phase_stamps copies
+ * their residual bounds and decisions (slots 18, 19); the busy cycles of
+ * wave 1 (trailing tiles and inverse rows) and of wave 0 (next diagonal
+ * tile) in the Cholesky's trailing phases (slots 20, 23); the last inverse
+ * row's product and store cycles (slots 21, 22).  0 turns it off.  spec_diag_phase_stamps copies
  * batch x SPEC_DIAG_PHASE_SLOTS values to the host.  Calls must use
  * batch <= c. */
 #define SPEC_DIAG_PHASE_SLOTS 24

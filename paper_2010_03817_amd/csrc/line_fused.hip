@@ -447,6 +447,33 @@ __device__ __forceinline__ void store_tile(double* L, int m, int I, int J, d4 v,
     }
 }
 
+// L[e] = F[e] + sh B[e] for e < P (B null: F alone) by the bd threads of the
+// block, each with 8 loads per array issued before their first use, so that
+// a thread's reads from global memory are in flight together rather than one
+// round trip at a time.
+__device__ __forceinline__ void fill_pencil(double* L, const double* F, const double* B, double sh, int P, int t,
+                                            int bd) {
+    constexpr int U = 8;
+    for (int e0 = t; e0 < P; e0 += U * bd) {
+        double f[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bd;
+            f[u] = e < P ? F[e] : 0.0;
+            b[u] = B && e < P ? B[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bd;
+            if (e < P) L[e] = B ? fma(sh, b[u], f[u]) : f[u];
+        }
+    }
+}
+
+#ifndef CHOL_RHO_X2
+#define CHOL_RHO_X2 4  // twice the cost of a trailing tile in inverse product steps
+#endif
+
 // Blocked Cholesky in LDS.  Returns false if F0 is not positive definite.
 // It also forms the inverse W = L^{-1} by rows, row I in the trailing phase
 // of step I on the waves that would otherwise wait for the next diagonal
@@ -455,15 +482,16 @@ __device__ __forceinline__ void store_tile(double* L, int m, int I, int J, d4 v,
 // phase, when no update reads row I of L any more.  On success the tile rows
 // I <= T - 2 hold W; tri_inverse forms the last one.
 // `flag` is an LDS int; `D` 256 doubles of LDS scratch.
-// prof (nullable): thread 0 adds the cycles of the diagonal-tile, panel and
-// trailing-update stages to prof[0..2].
+// prof (nullable): each thread adds the cycles of the diagonal-tile, panel and
+// trailing-update stages to prof[0..2] and its wave's busy cycles in the
+// trailing phases (up to its barrier arrival) to prof[3].
 __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* flag, long long* prof = nullptr) {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
     const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lh = lane >> 4;
     const int T = (m + 15) / 16;
-    long long c0 = 0, c1 = 0, c2 = 0, tc = prof ? clock64() : 0;
+    long long c0 = 0, c1 = 0, c2 = 0, cb = 0, tc = prof ? clock64() : 0;
 #define CHOL_TICK(acc)                       \
     if (prof) {                              \
         const long long tn = clock64();      \
@@ -542,33 +570,60 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
         // diagonal tile and factors it (its own LDS writes are seen by its later
         // reads) while the other waves update the remaining tiles
         const int R = T - K - 1;
+        const long long tb = prof ? clock64() : 0;
         if (wv == 0) {
             trail_tile(K, K + 1, K + 1);
             const bool ok = diag_factor16(L, m, K + 1, lane);
             if (lane == 0) *flag = ok ? 1 : 0;
         } else {
-            for (int e = wv; e < R * (R + 1) / 2; e += nw - 1) {
-                int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-                while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-                while (ii * (ii + 1) / 2 > e) --ii;
-                const int jj = e - ii * (ii + 1) / 2;
-                trail_tile(K, K + 1 + ii, K + 1 + jj);
+            // tiles e = 1..N of the trailing triangle (row-major; e = 0 is wave 0's),
+            // dealt in contiguous runs so that each worker's run plus its inverse
+            // chains below comes out even, a tile counting CHOL_RHO_X2 / 2 product
+            // steps of a chain (water level over the workers, integer arithmetic on
+            // scalar registers)
+            const int N = R * (R + 1) / 2 - 1;
+            if (N > 0) {
+                const int ws = __builtin_amdgcn_readfirstlane(wv), nwk = nw - 1;
+                auto chains = [&](int v) { return max(K - (v - 1), 0) + max(K - (2 * (nw - 1) - v), 0); };
+                int suml = 0;
+                for (int v = 1; v < nw; ++v) suml += chains(v);
+                const int lvl = 2 * suml + CHOL_RHO_X2 * N;
+                int pre = 0, tot = 0, own = 0;
+                for (int v = 1; v < nw; ++v) {
+                    const int cap = max(lvl - 2 * nwk * chains(v), 0);
+                    pre += v < ws ? cap : 0;
+                    own = v == ws ? cap : own;
+                    tot += cap;
+                }
+                const int e0 = 1 + N * pre / tot, e1 = 1 + N * (pre + own) / tot;
+                int ii = 0;
+                while ((ii + 1) * (ii + 2) / 2 <= e0) ++ii;
+                int jj = e0 - ii * (ii + 1) / 2;
+                for (int e = e0; e < e1; ++e) {
+                    trail_tile(K, K + 1 + ii, K + 1 + jj);
+                    if (++jj > ii) {
+                        ++ii;
+                        jj = 0;
+                    }
+                }
             }
             // row K of W (these waves would otherwise wait for the diagonal factor)
             wrow = K;
             if (j1 < K) wt1 = inv_row_tile(L, m, K, j1, lane);
             if (j2 < K) wt2 = inv_row_tile(L, m, K, j2, lane);
         }
+        if (prof) cb += clock64() - tb;
         lds_barrier();
         CHOL_TICK(c2)
     }
     store_wrow();  // row T - 2 of W
     lds_barrier();
 #undef CHOL_TICK
-    if (prof && t == 0) {
+    if (prof) {
         prof[0] += c0;
         prof[1] += c1;
         prof[2] += c2;
+        prof[3] += cb;
     }
     return true;
 }
@@ -577,7 +632,7 @@ __device__ __forceinline__ bool chol_blocked(double* L, int m, double* D, int* f
 // above it in place): W_T-1,J for J < T - 1 over all waves, paired by size,
 // then stored once every wave has read row T - 1 of L.
 // prof (nullable): thread 0 adds the cycles of its products and stores to
-// prof[1], prof[2] (prof[0], the earlier P products, stays 0).
+// prof[1], prof[2].
 __device__ __forceinline__ void tri_inverse(double* L, int m, double* D, long long* prof = nullptr) {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));  // per-call lane addressing (see lanczos_extreme)
@@ -817,24 +872,35 @@ __device__ inline double backward_norm_reg(double aA, double aB, double bA, doub
 
 // Row r of the Ritz vector z = sum_i y_i q_i of T_k for the Ritz value th,
 // with y from the backward three-term recurrence (y_{k-1} = 1) and the
-// stored basis rows Qg[i m + r]; normalised in y.
+// stored basis rows Qg[i m + r]; normalised in y.  The rows are read from
+// global memory 8 at a time ahead of the recurrence (which runs in the same
+// order either way), so that their loads are in flight together.
 __device__ inline double ritz_row(const double* al, const double* be, int k, double th, const double* Qg, int m,
                                   int r) {
+    constexpr int U = 8;
     double zr = 0.0, y1 = 1.0, y0 = 0.0, ss = 0.0;
-    for (int i = k - 1; i >= 0; --i) {
-        zr += y1 * Qg[(size_t)i * m + r];
-        ss += y1 * y1;
-        if (i >= 1) {
-            const double ym = ((th - al[i]) * y1 - (i + 1 < k ? be[i + 1] * y0 : 0.0)) / be[i];
-            y0 = y1;
-            y1 = ym;
-        }
-        if (ss > 1e280) {
-            const double sc = 1e-140;
-            y0 *= sc;
-            y1 *= sc;
-            ss *= sc * sc;
-            zr *= sc;
+    for (int i0 = k - 1; i0 >= 0; i0 -= U) {
+        double qv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) qv[u] = i0 - u >= 0 ? Qg[(size_t)(i0 - u) * m + r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 - u;
+            if (i < 0) break;
+            zr += y1 * qv[u];
+            ss += y1 * y1;
+            if (i >= 1) {
+                const double ym = ((th - al[i]) * y1 - (i + 1 < k ? be[i + 1] * y0 : 0.0)) / be[i];
+                y0 = y1;
+                y1 = ym;
+            }
+            if (ss > 1e280) {
+                const double sc = 1e-140;
+                y0 *= sc;
+                y1 *= sc;
+                ss *= sc * sc;
+                zr *= sc;
+            }
         }
     }
     return zr * (1.0 / sqrt(ss));
@@ -961,12 +1027,18 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
     const int Iend = (m & 15) ? T - 1 : T;  // tile rows with all 16 rows below m
     double s = 0.0;
     auto edge = [&](int I) {
+        double w[4], xs[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = 16 * I + 4 * q + p, rr = r < m ? r : m - 1;
-            const double xv = x[rr];
-            const double w = L[pk(rr, 0) + c];
-            s += (r < m && c <= r ? w : 0.0) * (r < m ? xv : 0.0);
+            xs[q] = x[rr];
+            w[q] = L[pk(rr, 0) + c];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // the loads in flight together
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * I + 4 * q + p;
+            s += (r < m && c <= r ? w[q] : 0.0) * (r < m ? xs[q] : 0.0);
         }
     };
     if (J < Iend) {
@@ -989,6 +1061,7 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
                 w[q] = *(const double*)(Lb + ab[q]);
                 xs[q] = *(const double*)(xb + 32 * q);
             }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 s += (c <= 16 * J + 4 * q + p ? w[q] : 0.0) * xs[q];
@@ -1004,6 +1077,7 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
                 w[q] = *(const double*)(Lb + ab[q]);
                 xs[q] = *(const double*)(xb + 32 * q);
             }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 s += w[q] * xs[q];
@@ -1021,11 +1095,11 @@ __device__ __forceinline__ double wt_col(const double* L, const double* x, int m
             for (int q = 0; q < 4; ++q) {
                 const int a = ab[q] < abmax ? ab[q] : abmax;
                 w[q] = *(const double*)(Lb + a);
-                const double xv = *(const double*)(xb + 32 * q);
-                xs[q] = 16 * (T - 1) + 4 * q + p < m ? xv : 0.0;
+                xs[q] = *(const double*)(xb + 32 * q);
             }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s += w[q] * xs[q];
+            for (int q = 0; q < 4; ++q) s += w[q] * (16 * (T - 1) + 4 * q + p < m ? xs[q] : 0.0);
         }
     } else {
         edge(J);  // the last tile row, ending past m, is the diagonal tile
@@ -1089,18 +1163,20 @@ __device__ __forceinline__ double w_strip(const double* L, const double* x, int 
         double w[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] = rp[q][16 * J];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] += w[q] * xv;
     }
-    {  // diagonal tile
+    {  // diagonal tile: its five loads issued together, then masked
         const int c = 16 * I + j;
         const double xr = x[c < m ? c : 0];
+        double w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = rp[q][16 * I];
+        __builtin_amdgcn_sched_barrier(0);
         const double xv = c < m ? xr : 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double w = rp[q][16 * I];
-            a[q] += (c <= 16 * I + i0 + 4 * q ? w : 0.0) * xv;
-        }
+        for (int q = 0; q < 4; ++q) a[q] += (c <= 16 * I + i0 + 4 * q ? w[q] : 0.0) * xv;
     }
     return red16x4(a, lane);
 }
@@ -1597,11 +1673,17 @@ __device__ __forceinline__ void ritz_u(const double* L, double* scr, int m, int 
         slot[r] = uv;
     }
     lds_barrier();
-    if (own) {
-        const double ur = slot[r];
-        const int half = (r + 2) >> 1;
-        const int kb = h == 0 ? 0 : half, ke = h == 0 ? half : r + 1;
-        for (int cc = kb; cc < ke; ++cc) U2[pk(r, cc)] = (cc == r ? 1.0 : 2.0) * ur * slot[cc];
+    // packed u u^T with the off-diagonal entries doubled, consecutive packed
+    // indices on consecutive threads (coalesced stores)
+    if (wv >= 1) {
+        const int nt = blockDim.x - 64, P = m * (m + 1) / 2;
+        for (int e = tw; e < P; e += nt) {
+            int rr = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+            while (rr * (rr + 1) / 2 > e) --rr;
+            while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
+            const int cc = e - rr * (rr + 1) / 2;
+            U2[e] = (cc == rr ? 1.0 : 2.0) * slot[rr] * slot[cc];
+        }
     }
 }
 
@@ -1675,11 +1757,11 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         // One loop so that the factorisation is instantiated once.
         int phase = a.shift_hi ? 0 : 1;
         bool ok = false;
-        long long cst[3] = {0, 0, 0};  // Cholesky stage cycles (profiling)
+        long long cst[4] = {0, 0, 0, 0};  // Cholesky stage cycles (profiling)
         STAMP(1)
         for (;;) {
             const double sh = phase == 0 ? a.shift_hi[chain] : t0;
-            for (int e = t; e < P; e += blockDim.x) L[e] = a.membership_only ? Fr[e] : Fr[e] + sh * Br[e];
+            fill_pencil(L, Fr, a.membership_only || sh == 0.0 ? nullptr : Br, sh, P, t, blockDim.x);
             lds_barrier();
             ok = chol_blocked(L, m, scr, sflag, prof ? cst : nullptr);
             lds_barrier();
@@ -1697,11 +1779,12 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             prof[7] = cst[0];
             prof[14] = cst[1];
             prof[15] = cst[2];
+            prof[23] = cst[3];
         }
+        if (prof && t == 64) prof[20] = cst[3];
         long long ist[3] = {0, 0, 0};  // triangular-inverse part cycles (profiling)
         if (ok && !a.membership_only) tri_inverse(L, m, scr, prof ? ist : nullptr);
         if (prof && t == 0) {
-            prof[20] = ist[0];
             prof[21] = ist[1];
             prof[22] = ist[2];
         }

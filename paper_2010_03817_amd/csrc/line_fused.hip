@@ -470,6 +470,28 @@ __device__ __forceinline__ void fill_pencil(double* L, const double* F, const do
     }
 }
 
+// L[e] = Q0[e] + tau (sg Q1[e] + tau Q2[e]) for e < P, loads batched as in
+// fill_pencil.
+__device__ __forceinline__ void fill_quadratic(double* L, const double* Q0, const double* Q1, const double* Q2,
+                                               double tau, double sg, int P, int t, int bd) {
+    constexpr int U = 8;
+    for (int e0 = t; e0 < P; e0 += U * bd) {
+        double q0[U], q1[U], q2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bd;
+            q0[u] = e < P ? Q0[e] : 0.0;
+            q1[u] = e < P ? Q1[e] : 0.0;
+            q2[u] = e < P ? Q2[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bd;
+            if (e < P) L[e] = q0[u] + tau * (sg * q1[u] + tau * q2[u]);
+        }
+    }
+}
+
 #ifndef CHOL_RHO_X2
 #define CHOL_RHO_X2 4  // twice the cost of a trailing tile in inverse product steps
 #endif
@@ -1999,7 +2021,7 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
             int rung = 0;
             for (int it = 0; it < 210; ++it) {
                 ++iters;
-                for (int e = t; e < P; e += blockDim.x) L[e] = Q0[e] + tau * (sg * Q1[e] + tau * Q2[e]);
+                fill_quadratic(L, Q0, Q1, Q2, tau, sg, P, t, blockDim.x);
                 lds_barrier();
                 const bool ok = chol_blocked(L, m, scr, sflag);
                 lds_barrier();

@@ -197,6 +197,33 @@ def test_bisection_tiny_instances():
             assert -tm[0] == pytest.approx(bisect_boundary(inst, x, v, -1.0), rel=1e-12)
 
 
+def test_paper_generator_structure_and_bisection():
+    """The random spectrahedra of the paper's experiments (Section 4):
+    A0 = Z Z^T + I is positive definite (the origin is interior), each A_i is
+    blkdiag(Qt, -Qt) with Qt symmetric, so B(v) has trace zero and eigenvalues
+    of both signs and every line leaves S on both sides (t+- finite).  The
+    oracle's t+- agree with bisection on LAPACK membership."""
+    rng = np.random.default_rng(8)
+    for n, m in [(3, 4), (5, 6), (8, 10)]:
+        inst = I.paper_random(n, m, seed=40 + m)
+        A = inst.blocks[0].A
+        h = m // 2
+        assert np.linalg.eigvalsh(A[0]).min() >= 1.0 - 1e-12
+        for i in range(1, n + 1):
+            assert np.array_equal(A[i], A[i].T)
+            assert np.array_equal(A[i][h:, h:], -A[i][:h, :h])
+            assert not A[i][:h, h:].any()
+        o = O.Oracle(inst)
+        for _ in range(3):
+            d = I.random_directions(rng, 1, n)[0]
+            v = I.random_directions(rng, 1, n)[0]
+            x = 0.4 * d * o.intersect(np.zeros(n), d)[1][0]
+            tm, tp, st = o.intersect(x, v)
+            assert st[0] == O.OK and np.isfinite(tm[0]) and np.isfinite(tp[0])
+            assert tp[0] == pytest.approx(bisect_boundary(inst, x, v), rel=1e-12)
+            assert -tm[0] == pytest.approx(bisect_boundary(inst, x, v, -1.0), rel=1e-12)
+
+
 @pytest.mark.parametrize("m", [7, 30])
 def test_generalized_eigen_special_case(m):
     inst = I.gbase(9, m, seed=m)

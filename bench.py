@@ -34,9 +34,10 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def _fused_traffic(chains):
-    """HBM bytes per launch of the fused kernel, from the committed counter
-    summary, while the kernel sources are those that were profiled."""
+def _fused_traffic(chains, leg):
+    """HBM bytes per launch of the fused kernel over the timed rounds of one
+    leg ("plain" or "learned"), from the committed counter summary, while the
+    kernel sources are those that were profiled."""
     import hashlib
     import re
     src = os.path.join(ROOT, "paper_2010_03817_amd", "csrc")
@@ -47,10 +48,11 @@ def _fused_traffic(chains):
         txt = open(os.path.join(ROOT, "profiles", "k_line_fused_billiard_n200_m200.md")).read()
     except OSError:
         return None
-    m = re.search(r"^traffic: (\d+) bytes/launch at (\d+) chains, sources ([0-9a-f]+)", txt, re.M)
-    if not m or m.group(3) != digest or int(m.group(2)) != chains:
-        return None
-    return float(m.group(1))
+    for m in re.finditer(r"^traffic: (\d+) bytes/launch at (\d+) chains, leg (\w+), sources ([0-9a-f]+)",
+                         txt, re.M):
+        if m.group(3) == leg and m.group(4) == digest and int(m.group(2)) == chains:
+            return float(m.group(1))
+    return None
 
 
 def _cpu_worker(args):
@@ -372,7 +374,7 @@ def main():
     plain = timed_rounds(g, S, x0, tau, args.steps, chains)
     roof = roofline(plain, chains)
     if roof["kernel"] == "k_line_fused":
-        roof["traffic"] = _fused_traffic(chains)
+        roof["traffic"] = _fused_traffic(chains, "plain")
     # assembly GEMM (F(x) and B(v) rows of every chain): FP64 MFMA utilisation
     P = M_DIM * (M_DIM + 1) // 2
     asm_launches = max(plain["stages"]["assemble"][1], 1)
@@ -395,6 +397,8 @@ def main():
         learned_sum = summary(learned, chains, cps)
         plain_sum.update({k: v for k, v in summary(plain, chains, cps).items() if k != "stage_ms_per_round"})
         learned_sum["roofline"] = roofline(learned, chains, extra_chol=learned["stats"]["cert_fallback"])
+        if learned_sum["roofline"]["kernel"] == "k_line_fused":
+            learned_sum["roofline"]["traffic"] = _fused_traffic(chains, "learned")
         learned_sum["training"] = report
         g.set_mlp(None)
 

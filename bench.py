@@ -110,7 +110,7 @@ def timed_rounds(g, S, x0, tau, rounds, chains):
 
 
 def roofline(run, chains, extra_chol=0.0):
-    """FP64 roofline of the dominant kernel of a timed run (see DESIGN.md)."""
+    """FP64 roofline of the dominant kernel of a timed run."""
     stages, lz_steps, calls = run["stages"], run["lz_steps"], run["stats"]["calls"]
     dom = max(stages, key=lambda k: stages[k][0])
     launches = max(stages[dom][1], 1)
@@ -322,6 +322,41 @@ def hmc_precision_leg(g, S, tau, chains, rounds):
     return out
 
 
+def paper_workload_leg(S, I, chains, rounds, warmup):
+    """Billiard walk on the paper's own random spectrahedra (Section 4: A0 =
+    Z Z^T + I, A_i = blkdiag(Qt, -Qt), no box block) at n = m = 100 and 200, the
+    sizes of its walk-length table.  Calls per completed step come from a
+    two-step walk of every chain; the rate from timed rounds as on the main
+    leg.  The paper's own average time per point (one sequential CPU walk) is
+    quoted beside it as context."""
+    import torch
+    out = {}
+    paper_ms = {100: 0.3, 200: 7.2}
+    for n in (100, 200):
+        inst = I.paper_random(n, n, seed=1000 + n)
+        g = S.Spectrahedron(inst)
+        pre = 64
+        _, _, _, log = g.walk(S.HNR, np.zeros((pre, n)), 20, seed=11, log_chains=pre, log_cap=pre * 20)
+        lg = log.cpu().numpy()
+        tau = 2.0 * float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+        x0 = torch.zeros((chains, n), dtype=torch.float64, device="cuda")
+        _, _, st2, _ = g.walk(S.BILLIARD, x0, 2, seed=77, tau=tau)
+        cps = st2["calls"] / max(st2["steps"], 1)
+        g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(warmup, 1))
+        run = timed_rounds(g, S, x0, tau, rounds, chains)
+        calls_s = run["stats"]["calls"] / run["wall"]
+        out[f"S-{n}-{n}"] = {
+            "chains": chains, "tau": tau, "instance_seed": 1000 + n,
+            "oracle_calls_per_s": calls_s, "calls_per_step": cps,
+            "billiard_steps_per_s": calls_s / cps,
+            "lanczos_steps_per_call": run["lz_steps"] / max(run["stats"]["calls"], 1),
+            "paper_ms_per_point": paper_ms[n],
+            "paper_hardware": "Intel Core i7-6700 @3.4 GHz, one sequential walk (context, not the target)",
+        }
+        del g, x0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +369,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-hmc", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--hmc-chains", type=int, default=8192)
     ap.add_argument("--hmc-rounds", type=int, default=4)
     ap.add_argument("--uneven-samples", type=int, default=256,
@@ -433,6 +469,9 @@ def main():
     if not args.no_uneven:
         progress("uneven batch: 256 spectrahedra, autotune, batched volume")
         out["uneven_batch"] = uneven_leg(S, I, args.uneven_samples)
+    if not args.no_paper:
+        progress("paper workload: billiard on S-100-100 and S-200-200")
+        out["paper_workload"] = paper_workload_leg(S, I, chains, args.steps, args.warmup)
     if not args.no_cpu:
         progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))

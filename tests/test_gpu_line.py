@@ -219,3 +219,23 @@ def test_empty_batch_and_repeat_calls():
     b = _np(g.intersect(x[:7], v[:7])[1])  # smaller call after a larger one
     c = _np(g.intersect(x, v)[1])
     assert np.array_equal(a[:7], b) and np.array_equal(a, c)  # deterministic
+
+
+def test_paper_generator_intersect_and_reflect():
+    """The random spectrahedra of the paper's experiments (Section 4):
+    A0 = Z Z^T + I, A_i = blkdiag(Qt, -Qt), with no box block; kappa(A0) grows
+    like m^2, which the interior pairs keep far below the 1e-9 bar."""
+    S = _spec()
+    for (n, m, b, seed) in [(20, 30, 40, 21), (60, 80, 24, 22), (100, 100, 8, 23)]:
+        inst = I.paper_random(n, m, seed=seed)
+        _check_intersect(inst, b, seed)
+        o, g = O.Oracle(inst), S.Spectrahedron(inst)
+        rng = np.random.default_rng(seed + 100)
+        x, v = _points(o, inst, rng, b)
+        tp_r, s_r, w_r, st_r = o.reflect(x, v)
+        tp, s, w, st = [_np(a) for a in g.reflect(x, v)]
+        ok = st_r == O.OK
+        assert ok.all() and np.array_equal(st, st_r)
+        assert np.allclose(tp, tp_r, rtol=T_REL, atol=0)
+        assert np.allclose(w, w_r, atol=1e-7 * max(1.0, np.abs(w_r).max()))
+        assert np.allclose(s, s_r, atol=2e-7)

@@ -381,6 +381,98 @@ int orc_intersect(const orc_lmi* h, int batch, const double* x, const double* v,
     return ORC_OK;
 }
 
+/* Membership of the pencil point F(x) + t B(v) = F(x + t v) over every block
+ * (strict definiteness, as orc_membership).  Fx, Bv hold the blocks of F(x)
+ * and B(v) back to back (block b at offset off[b]); P is scratch. */
+static int pencil_member(const orc_lmi* h, const double* Fx, const double* Bv, const size_t* off,
+                         double t, double* P, double* L) {
+    for (int b = 0; b < h->nb; b++) {
+        int m = h->m[b];
+        size_t sz = h->kind[b] == ORC_DENSE ? (size_t)m * m : (size_t)m;
+        for (size_t k = 0; k < sz; k++) P[k] = Fx[off[b] + k] + t * Bv[off[b] + k];
+        if (h->kind[b] == ORC_DENSE) {
+            if (cholesky(m, P, L) != 0) return 0;
+        } else {
+            for (int j = 0; j < m; j++) if (!(P[j] > 0.0)) return 0;
+        }
+    }
+    return 1;
+}
+
+/* End of the feasible interval along +v from membership alone: the definition
+ * t+ = sup{t >= 0 : F(x + s v) > 0 for all s in [0, t]} of Lemma "PEP and S
+ * cap C".  S is convex, so the feasible t form one interval and bisection on
+ * membership finds its end: from the guess g (1 if g is not a positive
+ * finite number) the bracket [lo, hi] is grown by doubling or shrunk by
+ * halving until lo is a member and hi is not, then halved until its midpoint
+ * equals an end (lo and hi adjacent doubles); returns lo, the last member.
+ * INFINITY when every t up to 1e300 is a member. */
+static double bisect_end(const orc_lmi* h, const double* Fx, const double* Bv, const size_t* off, double g,
+                         double* P, double* L) {
+    double lo = 0.0, hi = (g > 0.0 && isfinite(g)) ? g : 1.0;
+    if (pencil_member(h, Fx, Bv, off, hi, P, L)) {
+        do {
+            lo = hi;
+            hi = 2.0 * hi;
+            if (hi > 1e300) return INFINITY;
+        } while (pencil_member(h, Fx, Bv, off, hi, P, L));
+    } else {
+        for (;;) {
+            double half = 0.5 * hi;
+            if (!(half > 0.0)) return 0.0;
+            if (pencil_member(h, Fx, Bv, off, half, P, L)) { lo = half; break; }
+            hi = half;
+        }
+    }
+    for (;;) {
+        double mid = lo + 0.5 * (hi - lo);
+        if (!(mid > lo && mid < hi)) break;
+        if (pencil_member(h, Fx, Bv, off, mid, P, L)) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+int orc_line_bisect(const orc_lmi* h, int batch, const double* x, const double* v, const double* guess,
+                    double* tm, double* tp, int32_t* st) {
+    if (!h || batch < 0 || (batch && (!x || !v || !tm || !tp || !st))) return ORC_EINVAL;
+    size_t* off = (size_t*)malloc(sizeof(size_t) * (size_t)h->nb);
+    size_t tot = 0;
+    for (int b = 0; b < h->nb; b++) {
+        off[b] = tot;
+        tot += h->kind[b] == ORC_DENSE ? (size_t)h->m[b] * h->m[b] : (size_t)h->m[b];
+    }
+    size_t mm = (size_t)max_block(h);
+    double* Fx = (double*)malloc(sizeof(double) * tot);
+    double* Bv = (double*)malloc(sizeof(double) * tot);
+    double* Bn = (double*)malloc(sizeof(double) * tot);
+    double* P = (double*)malloc(sizeof(double) * mm * mm);
+    double* L = (double*)malloc(sizeof(double) * mm * mm);
+    if (!off || !Fx || !Bv || !Bn || !P || !L) {
+        free(off); free(Fx); free(Bv); free(Bn); free(P); free(L);
+        return ORC_ENOMEM;
+    }
+    for (int e = 0; e < batch; e++) {
+        const double* xe = x + (size_t)e * h->n;
+        const double* ve = v + (size_t)e * h->n;
+        for (int b = 0; b < h->nb; b++) {
+            combine(h, b, 1.0, xe, Fx + off[b]);
+            combine(h, b, 0.0, ve, Bv + off[b]);
+        }
+        for (size_t k = 0; k < tot; k++) Bn[k] = -Bv[k];
+        if (!pencil_member(h, Fx, Bv, off, 0.0, P, L)) {
+            tm[e] = NAN; tp[e] = NAN; st[e] = ORC_NOT_INTERIOR;
+            continue;
+        }
+        double gp = guess ? guess[2 * e + 1] : 1.0, gm = guess ? -guess[2 * e] : 1.0;
+        tp[e] = bisect_end(h, Fx, Bv, off, gp, P, L);
+        tm[e] = -bisect_end(h, Fx, Bn, off, gm, P, L);
+        st[e] = (isinf(tp[e]) || isinf(tm[e])) ? ORC_UNBOUNDED : ORC_OK;
+    }
+    free(off); free(Fx); free(Bv); free(Bn); free(P); free(L);
+    return ORC_OK;
+}
+
 /* Normal at the hit point from Lemma "Gradient of det F": grad det F(p) is a
  * multiple of (u^T A_1 u, ..., u^T A_n u), u in ker F(p); the scale and
  * orientation are dropped (the vector is normalised). For a diagonal entry j

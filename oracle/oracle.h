@@ -44,6 +44,15 @@ int orc_membership(const orc_lmi* h, int batch, const double* x, int8_t* interio
 int orc_intersect(const orc_lmi* h, int batch, const double* x, const double* v,
                   double* t_minus, double* t_plus, int32_t* status);
 
+/* The same t- <= 0 <= t+ from membership alone: bisection on the convex
+ * feasible interval {t : F(x + t v) > 0} with the Cholesky test of
+ * orc_membership applied to F(x) + t B(v), down to adjacent doubles (the
+ * definition of Lemma "PEP and S cap C"; no eigen solve, so the result does
+ * not depend on the conditioning of F(x)).  guess (nullable, batch x 2:
+ * t-, t+) only shortens the bracket search. */
+int orc_line_bisect(const orc_lmi* h, int batch, const double* x, const double* v, const double* guess,
+                    double* t_minus, double* t_plus, int32_t* status);
+
 /* Reflection (Alg. REFLECTION, eq. (reflection), Lemma "Gradient of det F"):
  * t+, reflected direction s, unit outward normal w_hat (sign: <v,w> >= 0). */
 int orc_reflect(const orc_lmi* h, int batch, const double* x, const double* v,

@@ -43,6 +43,7 @@ def lib():
         L.orc_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_membership.argtypes = [vp, C.c_int, dp, i8p]
         L.orc_intersect.argtypes = [vp, C.c_int, dp, dp, dp, dp, i32p]
+        L.orc_line_bisect.argtypes = [vp, C.c_int, dp, dp, dp, dp, dp, i32p]
         L.orc_reflect.argtypes = [vp, C.c_int, dp, dp, dp, dp, dp, i32p]
         L.orc_intersect_curve2.argtypes = [vp, C.c_int, dp, C.c_double, dp, dp, i32p, i32p]
         L.orc_walk.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int64, C.c_uint64, C.c_double, C.c_int,
@@ -117,6 +118,18 @@ class Oracle:
         tm, tp = np.empty(B), np.empty(B)
         st = np.empty(B, dtype=np.int32)
         lib().orc_intersect(self._h, B, _p(x), _p(v), _p(tm), _p(tp), _p(st, C.c_int32))
+        return tm, tp, st
+
+    def line_bisect(self, x, v, guess=None):
+        """(t-, t+, status) by bisection on membership (no eigen solve)."""
+        x = _d(x).reshape(-1, self.n)
+        v = _d(v).reshape(-1, self.n)
+        B = x.shape[0]
+        tm, tp = np.empty(B), np.empty(B)
+        st = np.empty(B, dtype=np.int32)
+        g = None if guess is None else _d(guess).reshape(B, 2)
+        lib().orc_line_bisect(self._h, B, _p(x), _p(v), None if g is None else _p(g), _p(tm), _p(tp),
+                              _p(st, C.c_int32))
         return tm, tp, st
 
     def reflect(self, x, v):

@@ -142,6 +142,8 @@ def roofline(run, chains, extra_chol=0.0):
     roof["traffic_unit"] = "bytes per launch"
     roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64_128<false>", "normal": "k_gemm_f64_128<true>",
                       "predict": "k_gemm_f32", "update": "k_walk_update"}[dom]
+    if dom == "fused":
+        roof["launches"] = "k_line_fused and its refining pass k_line_refine<false> per round (one stage)"
     roof["ms_per_launch"] = ms_dom
     return roof
 
@@ -165,22 +167,32 @@ def summary(run, chains, calls_per_step=None):
         "noconv": st["noconv"],
         "not_interior": st["not_interior"],
         "cert_fallback_rate": st["cert_fallback"] / max(calls, 1),
+        "refined_rate": st["refined"] / max(calls, 1),
+        "refine_failed": st["refine_failed"],
         "stage_ms_per_round": {k: v[0] / max(v[1], 1) for k, v in run["stages"].items()},
     }
 
 
 def train_learned(g, S, x0, tau, chains, rows_target, epochs, seed=77):
-    """Walk-generated (x, v, t-, t+) triples -> trained network -> autotuned
-    bracket half-width (attached to g).  Returns the network and a report."""
+    """Walk-generated (x, v, t-, t+) triples -> trained network, and the
+    constant-prediction control (the same network with zero weights predicts
+    the training mean of log t+ for every pair).  Rows of one chain in ten are
+    held out whole: half of them tune each bracket half-width through the real
+    learned kernel, the other half measure errors and Lanczos steps.  Returns
+    the network with its half-width, the control with its half-width, and a
+    report."""
     import torch
     n = N_DIM
     t0 = time.perf_counter()
     rounds = max(1, -(-rows_target // chains))
-    _, _, wst, log = g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=rounds, resume=True,
+    _, _, wst, log = g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=rounds,
                             log_chains=chains, log_cap=rounds * chains)
     calls_per_step = wst["calls"] / max(wst["steps"], 1)
-    x = log[:, :n].contiguous()
-    v = log[:, n:2 * n].contiguous()
+    held = (log[:, 2 * n + 2].to(torch.int64) % 10) == 9  # whole chains held out
+    order = torch.cat([torch.nonzero(~held).flatten(), torch.nonzero(held).flatten()])
+    x = log[order, :n].contiguous()
+    v = log[order, n:2 * n].contiguous()
+    nheld = int(held.sum())
     del log
     tm = torch.empty(x.shape[0], dtype=torch.float64, device="cuda")
     tp = torch.empty_like(tm)
@@ -189,37 +201,72 @@ def train_learned(g, S, x0, tau, chains, rows_target, epochs, seed=77):
         a, b, st = g.intersect(x[r0:r0 + chains], v[r0:r0 + chains])
         tm[r0:r0 + chains], tp[r0:r0 + chains] = a, b
         ok[r0:r0 + chains] = (st == S.OK) & torch.isfinite(a) & torch.isfinite(b) & (a < 0) & (b > 0)
+    nval = int(ok[x.shape[0] - nheld:].sum())
     x, v, tm, tp = x[ok], v[ok], tm[ok], tp[ok]
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    rows = x.shape[0]
+    vf = (nval + 0.25) / rows  # the trainer holds out the last round(vf rows) rows: exactly the held chains
     net = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed)
     t1 = time.perf_counter()
-    progress(f"training on {x.shape[0]} triples ({t0 and time.perf_counter() - t0:.1f} s to generate)")
-    tr = net.train(x, v, tm, tp, epochs=epochs, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=0.1, seed=seed)
+    progress(f"training on {rows - nval} triples, {nval} held out ({t_data:.1f} s to generate)")
+    tr = net.train(x, v, tm, tp, epochs=epochs, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf, seed=seed)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    # autotune the half-width on held-out pairs through the real learned kernel
-    nval = int(tr["val_rows"])
-    xv, vv = x[-nval:][:chains], v[-nval:][:chains]
+    xv, vv, tpv = x[rows - nval:], v[rows - nval:], tp[rows - nval:]
+    half = min(nval // 2, chains)
+    xa, va = xv[:half], vv[:half]                      # half-width tuning
+    xb, vb, tpb = xv[half:half + chains], vv[half:half + chains], tpv[half:half + chains]  # evaluation
+    ltpa = torch.log(tpv[:half]).cpu().numpy()
     levels = (0.5, 0.7, 0.8, 0.9, 0.95, 0.99)
-    cands = [tr["err_q"][q] for q in levels]
-    best, ms = g.tune_mlp_delta(net, xv, vv, cands, reps=2)
-    # learned against plain t+ on the held-out pairs (same device, same inputs)
-    tpl, _, _, stl = g.reflect(xv, vv)
-    g.set_mlp(None)
-    tpp, _, _, stp = g.reflect(xv, vv)
-    g.set_mlp(net, best, 1)
-    rel = (torch.abs(tpl - tpp) / tpp).cpu().numpy()
+    # the network: candidates from its errors on the tuning rows
+    lpa = net.predict(xa, va)[0].cpu().numpy()
+    cands = [float(np.quantile(np.abs(lpa - ltpa), q)) for q in levels]
+    best, ms = g.tune_mlp_delta(net, xa, va, cands, reps=2)
+    # the control: constant log t+ prediction (training mean), tuned the same way
+    ctl = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed + 1)
+    ctl.train(x, v, tm, tp, epochs=1, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf, seed=seed)
+    ctl.set_params(np.zeros(ctl.nparams, dtype=np.float32))
+    lca = ctl.predict(xa, va)[0].cpu().numpy()
+    ccands = [float(np.quantile(np.abs(lca - ltpa), q)) for q in levels]
+    cbest, cms = g.tune_mlp_delta(ctl, xa, va, ccands, reps=2)
+    # evaluation rows: t+ of learned, control and plain against each other, Lanczos steps
+    def reflect_eval(model, delta):
+        g.set_mlp(model, delta, 1) if model is not None else g.set_mlp(None)
+        tpx = g.reflect(xb, vb)[0]
+        info = g.lanczos_info(xb.shape[0])
+        return tpx, float(info[:, 3].mean()), float(np.mean(info[:, 2] == 1))
+    tpl, steps_l, fb_l = reflect_eval(net, best)
+    tpc, steps_c, fb_c = reflect_eval(ctl, cbest)
+    tpp, steps_p, _ = reflect_eval(None, 0.0)
+    ltpb = torch.log(tpb).cpu().numpy()
+    err_net = np.abs(net.predict(xb, vb)[0].cpu().numpy() - ltpb)
+    err_ctl = np.abs(ctl.predict(xb, vb)[0].cpu().numpy() - ltpb)
+
+    def relstats(a, b):
+        r = (torch.abs(a - b) / b).cpu().numpy()
+        return {"median": float(np.median(r)), "p99": float(np.quantile(r, 0.99)), "max": float(r.max())}
+
     report = {
         "calls_per_step": calls_per_step, "walk_calls": wst["calls"], "walk_steps": wst["steps"],
-        "rows": int(x.shape[0]), "data_seconds": t_data, "train_seconds": t_train,
+        "rows": rows, "held_out_rows": nval, "holdout": "whole chains (chain index % 10 == 9)",
+        "data_seconds": t_data, "train_seconds": t_train,
         "epochs": epochs, "adam_steps": tr["steps"], "train_loss": tr["train_loss"], "val_loss": tr["val_loss"],
+        "val_loss_constant_predictor": tr.get("val_loss_const"),
         "val_logtp_err": {str(k): v for k, v in tr["err_q"].items()},
         "delta_candidates": dict(zip([str(q) for q in levels], cands)), "tune_ms": ms, "delta": best,
-        "learned_vs_plain_tp_rel": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
-                                    "max": float(rel.max())},
+        "control": {"kind": "constant log t+ (training mean), zero-weight network",
+                    "delta_candidates": dict(zip([str(q) for q in levels], ccands)), "tune_ms": cms,
+                    "delta": cbest},
+        "eval_rows": int(xb.shape[0]),
+        "eval_logtp_err_median": {"network": float(np.median(err_net)), "control": float(np.median(err_ctl))},
+        "eval_lanczos_steps_per_call": {"learned": steps_l, "control": steps_c, "plain": steps_p},
+        "eval_fallback_rate": {"learned": fb_l, "control": fb_c},
+        "learned_vs_plain_tp_rel": relstats(tpl, tpp),
+        "control_vs_plain_tp_rel": relstats(tpc, tpp),
     }
-    return net, report
+    g.set_mlp(None)
+    return net, best, ctl, cbest, report
 
 
 def uneven_leg(S, I, samples_per_phase):
@@ -369,6 +416,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--state-rounds", type=int, default=30,
+                    help="rounds walked from the centre before the chain state shared by the legs is saved")
     ap.add_argument("--chains", type=int, default=CHAINS)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
@@ -411,11 +460,28 @@ def main():
 
     chains = args.chains
     x0 = torch.zeros((chains, N_DIM), dtype=torch.float64, device="cuda")
-    # warm-up rounds (also initialise the chains), then the plain timed rounds
-    g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.warmup, 1))
-    progress("plain path: timed rounds")
-    plain = timed_rounds(g, S, x0, tau, args.steps, chains)
-    roof = roofline(plain, chains)
+    net = ctl = report = None
+    if not args.no_learned:
+        progress("learned path: training data, training, half-width tuning")
+        net, delta, ctl, cdelta, report = train_learned(g, S, x0, tau, chains, args.train_rows, args.epochs)
+    # one chain state for every leg: fresh chains walked state_rounds rounds and
+    # saved; each leg restores it, runs the warm-up rounds and then the timed
+    # rounds with the same seed, so the legs see the same walk states
+    g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.state_rounds, 1))
+    g.save_walk_state()
+
+    def leg(name, model, d):
+        g.restore_walk_state()
+        g.set_mlp(model, d, 1) if model is not None else g.set_mlp(None)
+        g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.warmup, 1), resume=True)
+        progress(f"{name}: timed rounds")
+        run = timed_rounds(g, S, x0, tau, args.steps, chains)
+        g.set_mlp(None)
+        return run
+
+    cps = report["calls_per_step"] if report else None
+    plain = leg("plain path", None, 0.0)
+    roof = roofline(plain, chains, extra_chol=plain["stats"]["refined"])
     if roof["kernel"] == "k_line_fused":
         roof["traffic"] = _fused_traffic(chains, "plain")
     # assembly GEMM (F(x) and B(v) rows of every chain): FP64 MFMA utilisation
@@ -426,24 +492,20 @@ def main():
     assembly = {"kernel": "k_gemm_f64_128<false>", "achieved": asm_flops / (asm_ms * 1e-3) / 1e12,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "ms_per_launch": asm_ms}
     assembly["frac"] = assembly["achieved"] / assembly["peak"]
-    plain_sum = summary(plain, chains)
+    plain_sum = summary(plain, chains, cps)
     plain_sum["roofline"] = roof
 
-    learned_sum = None
-    if not args.no_learned:
-        progress("learned path: training data, training, half-width tuning")
-        net, report = train_learned(g, S, x0, tau, chains, args.train_rows, args.epochs)
-        progress(f"learned path: timed rounds (delta {report['delta']:.3f})")
-        g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.warmup, 1), resume=True)
-        learned = timed_rounds(g, S, x0, tau, args.steps, chains)
-        cps = report["calls_per_step"]
+    learned_sum = control_sum = None
+    if net is not None:
+        learned = leg(f"learned path (delta {delta:.3f})", net, delta)
         learned_sum = summary(learned, chains, cps)
-        plain_sum.update({k: v for k, v in summary(plain, chains, cps).items() if k != "stage_ms_per_round"})
-        learned_sum["roofline"] = roofline(learned, chains, extra_chol=learned["stats"]["cert_fallback"])
+        learned_sum["roofline"] = roofline(learned, chains,
+                                           extra_chol=learned["stats"]["cert_fallback"] + learned["stats"]["refined"])
         if learned_sum["roofline"]["kernel"] == "k_line_fused":
             learned_sum["roofline"]["traffic"] = _fused_traffic(chains, "learned")
         learned_sum["training"] = report
-        g.set_mlp(None)
+        control = leg(f"constant-shift control (delta {cdelta:.3f})", ctl, cdelta)
+        control_sum = summary(control, chains, cps)
 
     head = learned_sum if learned_sum is not None else plain_sum
     out = {
@@ -469,7 +531,11 @@ def main():
     }
     if learned_sum is not None:
         out["learned"] = learned_sum
+        out["control"] = control_sum
         out["learned_over_plain"] = learned_sum["oracle_calls_per_s"] / plain_sum["oracle_calls_per_s"]
+        out["learned_over_control"] = learned_sum["oracle_calls_per_s"] / control_sum["oracle_calls_per_s"]
+        out["comparison"] = ("plain, learned and control legs continue the same saved chain state with the same "
+                             "seed (warm-up rounds, then the timed rounds)")
     if not args.no_hmc:
         progress("HMC with reflections, precision split")
         out["hmc_precision"] = hmc_precision_leg(g, S, dhat, args.hmc_chains, args.hmc_rounds)

@@ -87,6 +87,45 @@ spec_status spec_create(int n, int nblocks, const int* block_size, const int* ki
                         const double* A, spec_handle* out);
 spec_status spec_destroy(spec_handle h);
 
+/* Settings of a handle.  Start from spec_options_default (zeroed fields are
+ * not the defaults).
+ *  precision     spec_precision of the pencil assembly (spec_set_precision)
+ *  kmax, tol     Lanczos steps per cycle and residual tolerance
+ *                (spec_set_lanczos; defaults 80 and 1e-8)
+ *  refine_ratio  far-root refinement.  The rounding error of C = L^-1 B L^-T
+ *                is about eps times its spectral radius rho, so from a start
+ *                next to the boundary (rho = 1/|t-| large) the far root
+ *                t+ = -1/lambda_min carries a relative error near
+ *                eps rho / |lambda_min|.  When the run from x ends with
+ *                rho > refine_ratio |lambda| for the eigenvalue of a root
+ *                that decides the result, that root is recomputed from the
+ *                shifted origin t0 = t1 (1 - 2^-10), t1 the first value: a
+ *                Cholesky factor of F(x + t0 v) (certifying t0 inside) and a
+ *                Lanczos run on which that root's eigenvalue dominates the
+ *                spectrum (the pencil identity of Lemma "PEP and S cap C" with
+ *                F(x) replaced by F(x + t0 v)).  Default 1e3; 0 disables.
+ *  tol_loose     tolerance of the run from x on such a side: its value only
+ *                places the origin of the refining run (default 1e-3).
+ * When the factor does not exist at t0 (t1 was too far out) the origin backs
+ * off to t1 (1 - 2^-5) and then t1 / 2; only if those fail too is the plain
+ * solve repeated at the full tolerance (counted as refine_failed in
+ * spec_walk_stats, beside the refined calls). */
+typedef struct {
+    int precision;
+    int kmax;
+    double tol;
+    double refine_ratio;
+    double tol_loose;
+} spec_options;
+
+spec_status spec_options_default(spec_options* opt);
+/* spec_create followed by spec_set_options (opt NULL: defaults); on an
+ * options error the handle is destroyed and *out is NULL. */
+spec_status spec_create_ex(int n, int nblocks, const int* block_size, const int* kind, const double* A,
+                           const spec_options* opt, spec_handle* out);
+spec_status spec_set_options(spec_handle h, const spec_options* opt);
+spec_status spec_get_options(spec_handle h, spec_options* opt);
+
 /* Sizes of a handle: n, merged dense size m, merged diagonal size md. */
 spec_status spec_dims(spec_handle h, int* n, int* m, int* md);
 
@@ -195,9 +234,13 @@ typedef struct {
  * does not include the earlier calls' rounds): oracle calls, reflections, cap hits, not-interior
  * segments, nonsmooth reflections, completed steps, eigen non-convergence,
  * oracle rounds run, oracle calls whose learned bracket was not certified
- * (they fell back to the plain origin). */
+ * (they fell back to the plain origin), oracle calls whose far root was
+ * refined from a shifted origin (spec_options.refine_ratio), and refinements
+ * whose factor at the shifted origin did not exist (the call then repeated the
+ * plain solve at the full tolerance). */
 typedef struct {
     double calls, reflections, cap_hits, not_interior, nonsmooth, steps, noconv, rounds, cert_fallback;
+    double refined, refine_failed;
 } spec_walk_stats;
 
 /* Run `chains` independent chains of the walk `kind` from x0 (chains x n,
@@ -215,6 +258,15 @@ typedef struct {
 spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps,
                               uint64_t seed, const spec_walk_params* p, double* x_out, double* samples,
                               spec_walk_stats* stats, void* stream);
+
+/* Save (restore = 0) or restore (restore = 1) the state of the chains of the
+ * handle's last walk (points, step starts, directions, remaining lengths,
+ * reflection and step counters, per-chain statistics) in device memory the
+ * handle owns, so that a later resumed spec_walk_run_dev (same kind, chains
+ * and seed) continues the same chains from the same state, e.g. under other
+ * oracle settings.  Synchronises the device.  SPEC_EINVAL without a walk
+ * state, or on restore when nothing was saved for the current state. */
+spec_status spec_walk_state(spec_handle h, int restore);
 
 /* ------------------------------------------------------------------------
  * Volume by Gaussian cooling (the Gaussian variant of multiphase Monte Carlo
@@ -334,6 +386,7 @@ typedef struct {
     double val_rows;
     double err_q[8];     /* |log t+_hat - log t+| on validation at the levels
                             0.5, 0.7, 0.8, 0.9, 0.95, 0.99, 0.995, 0.999 */
+    double val_loss_const; /* the same loss of the constant prediction (the training means) */
 } spec_mlp_train_stats;
 
 /* New network for n coordinates; parameters from Philox (key seed):

@@ -21,8 +21,16 @@ spec_status spec_diag_mfma_layout(double* host_out);
 spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A, const double* B, double* C);
 
 /* After an intersect/reflect call of `batch` elements: per element
- * (lambda_min(C), lambda_max(C), second smallest Ritz value, Lanczos steps). */
+ * (lambda_min(C), lambda_max(C) of the last Lanczos run, learned-bracket code
+ * (0: none or certified, 1: lower end not certified, plain origin used,
+ * 2: upper end definite in mode 2), Lanczos steps over every run). */
 spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out);
+
+/* After an intersect/reflect call of `batch` elements: per element the bits
+ * 1 (learned bracket not certified), 4 (a far root refined from a shifted
+ * origin), 8 (the factor at that origin did not exist; plain solve at the
+ * full tolerance). */
+spec_status spec_diag_call_flags(spec_handle h, int batch, int32_t* flags_out);
 
 /* Stage timing of the walk rounds, measured with HIP events recorded on the
  * walk's stream around each stage.  spec_diag_timing(h, 1) resets and turns

@@ -19,121 +19,7 @@
 using namespace spec;
 
 #include "abi_util.h"
-
-struct spec_s {
-    int device = 0;
-    int n = 0, m = 0, md = 0, P = 0, Ptot = 0, K = 0, Kpad = 0, ldA = 0, Arows = 0, Nn = 0;
-    double* dA = nullptr;  // Arows x ldA
-    // pencil assembly precision: 0 FP64, 1 FP32 MFMA, 2 BF16 hi+lo MFMA (FP32 accumulation)
-    int prec = 0;
-    float* dA32 = nullptr;  // FP32 copy of the A-stack when prec > 0
-    // Lanczos settings
-    int kmax = 80;
-    double tol = 1e-8;
-    // workspace (capacity in chains, multiple of 64); work_gen changes whenever
-    // it is (re)allocated, so that cached device pointers can be revalidated
-    int cap = 0;
-    unsigned work_gen = 0;
-    double *dZ = nullptr, *dFB = nullptr, *dQ = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
-    float* dZ32 = nullptr;
-    double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
-    int32_t *dHit = nullptr, *dSt = nullptr;
-    // staging for the host-pointer entry points
-    int scap = 0;
-    double *sX = nullptr, *sV = nullptr, *sO1 = nullptr, *sO2 = nullptr, *sS = nullptr, *sW = nullptr;
-    int32_t* sSt = nullptr;
-    int8_t* sI = nullptr;
-    // stage timing
-    bool timing = false;
-    hipEvent_t ev[6] = {};
-    double stage_ms[5] = {0, 0, 0, 0, 0}, stage_n[5] = {0, 0, 0, 0, 0}, lanczos_steps = 0;
-    double* dLamSum = nullptr;
-    long long* dProf = nullptr;
-    int prof_cap = 0;
-    // learned bracket (attached network, half-width, mode) and its per-chain shifts
-    spec_mlp_s* net = nullptr;
-    double mdelta = 0.0;
-    int lmode = 0;
-    double *dShift = nullptr, *dShiftHi = nullptr, *dPred = nullptr, *dHz = nullptr;
-    // walk state
-    int wcap = 0;
-    double *wX = nullptr, *wXs = nullptr, *wV = nullptr, *wEll = nullptr, *wStats = nullptr, *wSum = nullptr;
-    int32_t *wNref = nullptr, *wActive = nullptr, *wCount = nullptr;
-    long long* wStep = nullptr;
-
-    void free_work() {
-        dfree(dZ); dfree(dZ32); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
-        dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt);
-        dfree(dShift); dfree(dShiftHi); dfree(dPred); dfree(dHz);
-        cap = 0;
-        ++work_gen;
-    }
-    void free_walk() {
-        dfree(wX); dfree(wXs); dfree(wV); dfree(wEll); dfree(wStats); dfree(wSum);
-        dfree(wNref); dfree(wActive); dfree(wCount); dfree(wStep);
-        wcap = 0;
-    }
-    spec_status ensure_walk(int chains) {
-        if (chains <= wcap) return SPEC_OK;
-        free_walk();
-        const int c = round_up(chains, 64);
-        HIPCHK(dalloc(&wX, (size_t)c * n, false));
-        HIPCHK(dalloc(&wXs, (size_t)c * n, false));
-        HIPCHK(dalloc(&wV, (size_t)c * n, false));
-        HIPCHK(dalloc(&wEll, (size_t)c, false));
-        HIPCHK(dalloc(&wStats, (size_t)c * WALK_NSTAT, false));
-        HIPCHK(dalloc(&wSum, (size_t)WALK_NSTAT, false));
-        HIPCHK(dalloc(&wNref, (size_t)c, false));
-        HIPCHK(dalloc(&wActive, (size_t)c, false));
-        HIPCHK(dalloc(&wCount, (size_t)1, false));
-        HIPCHK(dalloc(&wStep, (size_t)c, false));
-        wcap = c;
-        return SPEC_OK;
-    }
-    void free_stage() {
-        dfree(sX); dfree(sV); dfree(sO1); dfree(sO2); dfree(sS); dfree(sW); dfree(sSt); dfree(sI);
-        scap = 0;
-    }
-    spec_status ensure(int batch) {
-        if (batch <= cap) return SPEC_OK;
-        free_work();
-        const int c = round_up(batch, 64);
-        HIPCHK(dalloc(&dZ, (size_t)3 * c * Kpad));
-        HIPCHK(dalloc(&dZ32, (size_t)3 * c * Kpad));
-        HIPCHK(dalloc(&dFB, (size_t)3 * c * ldA, false));
-        HIPCHK(dalloc(&dQ, (size_t)c * ldq(), false));
-        HIPCHK(dalloc(&dU, (size_t)c * m, false));
-        HIPCHK(dalloc(&dU2, (size_t)c * ldA));
-        HIPCHK(dalloc(&dWn, (size_t)c * Nn, false));
-        HIPCHK(dalloc(&dLam, (size_t)c * 4));
-        HIPCHK(dalloc(&dTm, (size_t)c));
-        HIPCHK(dalloc(&dTp, (size_t)c));
-        HIPCHK(dalloc(&dHit, (size_t)c));
-        HIPCHK(dalloc(&dSt, (size_t)c));
-        HIPCHK(dalloc(&dShift, (size_t)c));
-        HIPCHK(dalloc(&dShiftHi, (size_t)c));
-        HIPCHK(dalloc(&dPred, (size_t)c));
-        HIPCHK(dalloc(&dHz, (size_t)c));
-        cap = c;
-        return SPEC_OK;
-    }
-    size_t ldq() const { return (size_t)kmax * std::max(m, 1); }
-    spec_status ensure_stage(int batch) {
-        if (batch <= scap) return SPEC_OK;
-        free_stage();
-        const int c = round_up(batch, 64);
-        HIPCHK(dalloc(&sX, (size_t)c * n, false));
-        HIPCHK(dalloc(&sV, (size_t)c * n, false));
-        HIPCHK(dalloc(&sO1, (size_t)c, false));
-        HIPCHK(dalloc(&sO2, (size_t)c, false));
-        HIPCHK(dalloc(&sS, (size_t)c * n, false));
-        HIPCHK(dalloc(&sW, (size_t)c * n, false));
-        HIPCHK(dalloc(&sSt, (size_t)c, false));
-        HIPCHK(dalloc(&sI, (size_t)c, false));
-        scap = c;
-        return SPEC_OK;
-    }
-};
+#include "abi_handle.h"
 
 namespace {
 
@@ -185,7 +71,39 @@ FusedArgs fused_args(spec_s* h, int bp, int32_t* st, double* tm, double* tp, boo
     a.U2 = h->dU2;
     a.ldu2 = h->ldA;
     a.prof = h->prof_cap > 0 ? h->dProf : nullptr;
+    a.refine_ratio = h->refine_ratio;
+    a.tol_loose = h->tol_loose;
+    a.rlist = h->dRList;
+    a.rcount = h->dRCnt;
+    a.rshift = h->dRShift;
+    a.inst_id = 0;
+    a.flags = h->dFlags;
     return a;
+}
+
+// The line oracle over `batch` chains: the first pass, then the REFINE pass
+// over the chains it queued (far roots refined from a shifted origin; none
+// when refinement is off or only membership is asked).  The queue count
+// stays on the device, so the second launch is persistent and needs no
+// host synchronisation (the sequence can be captured in a graph).
+spec_status run_fused(spec_s* h, FusedArgs a, int batch, hipStream_t s) {
+    const bool refine = a.rlist && a.refine_ratio > 0.0 && !a.membership_only && h->m > 0;
+    if (!refine) {
+        a.rlist = nullptr;
+        HIPCHK(launch_line_fused(a, batch, s));
+        return SPEC_OK;
+    }
+    HIPCHK(launch_zero_ints(h->dRCnt, 2, s));
+    HIPCHK(launch_line_fused(a, batch, s));
+    FusedArgs r = a;
+    r.shift = h->dRShift;
+    r.shift_hi = nullptr;
+    r.idx = nullptr;
+    r.rlist = nullptr;
+    if (h->refine_bpc == 0) h->refine_bpc = line_refine_blocks_per_cu(h->m, h->kmax);
+    const int nb = std::min(batch, h->refine_bpc * h->cus);
+    HIPCHK(launch_line_refine(r, nullptr, h->dRList, h->dRCnt, h->dRCnt + 1, h->m, h->kmax, nb, s));
+    return SPEC_OK;
 }
 
 // One oracle round over `batch` chains.  min_only: only t+ (and its
@@ -211,7 +129,7 @@ spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, 
         a.shift = h->dShift;
         if (h->lmode == 2) a.shift_hi = h->dShiftHi;
     }
-    HIPCHK(launch_line_fused(a, batch, s));
+    SPCHK(run_fused(h, a, batch, s));
     mark(h, 3, s);
     return SPEC_OK;
 }
@@ -345,6 +263,8 @@ spec_status spec_create(int n, int nblocks, const int* block_size, const int* ki
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SPEC_EDEVICE;
     spec_s* h = new spec_s();
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return SPEC_EDEVICE; }
+    if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || h->cus < 1)
+        h->cus = 256;
     h->n = n;
     h->m = m;
     h->md = md;
@@ -484,7 +404,52 @@ spec_status spec_set_lanczos(spec_handle h, int kmax, double tol) {
     if (h->cap) h->free_work();  // the basis buffer is sized by kmax
     h->kmax = kmax;
     h->tol = tol;
+    h->refine_bpc = 0;  // occupancy depends on kmax through the LDS size
     return SPEC_OK;
+}
+
+spec_status spec_options_default(spec_options* o) {
+    if (!o) return SPEC_EINVAL;
+    o->precision = SPEC_PREC_FP64;
+    o->kmax = 80;
+    o->tol = 1e-8;
+    o->refine_ratio = 1e3;
+    o->tol_loose = 1e-3;
+    return SPEC_OK;
+}
+
+spec_status spec_get_options(spec_handle h, spec_options* o) {
+    if (!h || !o) return SPEC_EINVAL;
+    o->precision = h->prec;
+    o->kmax = h->kmax;
+    o->tol = h->tol;
+    o->refine_ratio = h->refine_ratio;
+    o->tol_loose = h->tol_loose;
+    return SPEC_OK;
+}
+
+spec_status spec_set_options(spec_handle h, const spec_options* o) {
+    if (!h || !o) return SPEC_EINVAL;
+    if (!(o->refine_ratio >= 0.0) || !std::isfinite(o->refine_ratio)) return SPEC_EINVAL;
+    if (!(o->tol_loose > 0.0 && o->tol_loose < 1.0)) return SPEC_EINVAL;
+    if (o->precision < SPEC_PREC_FP64 || o->precision > SPEC_PREC_BF16X2_ASM) return SPEC_EINVAL;
+    if (o->kmax != h->kmax || o->tol != h->tol) SPCHK(spec_set_lanczos(h, o->kmax, o->tol));
+    SPCHK(spec_set_precision(h, o->precision));
+    h->refine_ratio = o->refine_ratio;
+    h->tol_loose = o->tol_loose;
+    return SPEC_OK;
+}
+
+spec_status spec_create_ex(int n, int nblocks, const int* block_size, const int* kind, const double* A,
+                           const spec_options* opt, spec_handle* out) {
+    SPCHK(spec_create(n, nblocks, block_size, kind, A, out));
+    if (!opt) return SPEC_OK;
+    const spec_status rc = spec_set_options(*out, opt);
+    if (rc != SPEC_OK) {
+        spec_destroy(*out);
+        *out = nullptr;
+    }
+    return rc;
 }
 
 spec_status spec_membership_dev(spec_handle h, int batch, const double* x, int8_t* interior, void* stream) {
@@ -609,6 +574,39 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
 
 }  // namespace
 
+spec_status spec_walk_state(spec_handle h, int restore) {
+    if (!h || restore < 0 || restore > 1 || h->wcap == 0) return SPEC_EINVAL;
+    const size_t c = (size_t)h->wcap, n = (size_t)h->n;
+    if (!restore && h->scap_w != h->wcap) {
+        h->free_saved();
+        HIPCHK(dalloc(&h->vX, c * n, false));
+        HIPCHK(dalloc(&h->vXs, c * n, false));
+        HIPCHK(dalloc(&h->vV, c * n, false));
+        HIPCHK(dalloc(&h->vEll, c, false));
+        HIPCHK(dalloc(&h->vStats, c * WALK_NSTAT, false));
+        HIPCHK(dalloc(&h->vNref, c, false));
+        HIPCHK(dalloc(&h->vActive, c, false));
+        HIPCHK(dalloc(&h->vStep, c, false));
+        h->scap_w = h->wcap;
+    }
+    if (restore && h->scap_w != h->wcap) return SPEC_EINVAL;  // nothing saved for this state
+    auto cp = [&](void* dst_w, void* dst_v, size_t bytes) {
+        return restore ? hipMemcpy(dst_w, dst_v, bytes, hipMemcpyDeviceToDevice)
+                       : hipMemcpy(dst_v, dst_w, bytes, hipMemcpyDeviceToDevice);
+    };
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(cp(h->wX, h->vX, sizeof(double) * c * n));
+    HIPCHK(cp(h->wXs, h->vXs, sizeof(double) * c * n));
+    HIPCHK(cp(h->wV, h->vV, sizeof(double) * c * n));
+    HIPCHK(cp(h->wEll, h->vEll, sizeof(double) * c));
+    HIPCHK(cp(h->wStats, h->vStats, sizeof(double) * c * WALK_NSTAT));
+    HIPCHK(cp(h->wNref, h->vNref, sizeof(int32_t) * c));
+    HIPCHK(cp(h->wActive, h->vActive, sizeof(int32_t) * c));
+    HIPCHK(cp(h->wStep, h->vStep, sizeof(long long) * c));
+    HIPCHK(hipDeviceSynchronize());
+    return SPEC_OK;
+}
+
 spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
                               const spec_walk_params* p, double* x_out, double* samples, spec_walk_stats* stats,
                               void* stream) {
@@ -655,6 +653,7 @@ WalkArgs make_walk_args(spec_handle h, int kind, int chains, long long steps, ui
     a.rho = p->rho > 0 ? p->rho : 10 * h->n;
     a.st = WalkState{h->wX, h->wXs, h->wV, h->wEll, h->wNref, h->wStep, h->wActive, h->wStats};
     a.status = h->dSt;
+    a.flags = h->dFlags;
     a.tm = h->dTm;
     a.tp = h->dTp;
     a.hit = h->dHit;
@@ -677,13 +676,14 @@ WalkArgs make_walk_args(spec_handle h, int kind, int chains, long long steps, ui
 spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const spec_walk_params* p,
                         double* x_out, spec_walk_stats* stats, hipStream_t s) {
     // totals at entry: a resumed call reports the counts of its own rounds
-    double tot0[WALK_NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double tot0[WALK_NSTAT] = {};
     if (stats && p->resume) {
         HIPCHK(walk_sum_stats(chains, h->wStats, h->wSum, s));
         HIPCHK(hipMemcpyAsync(tot0, h->wSum, sizeof(tot0), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
     const bool billiard = kind == SPEC_WALK_BILLIARD;
+    if (kind == SPEC_WALK_HMC) a.flags = nullptr;  // the curve oracle writes no call flags
     long long rounds = 0;
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
     const bool hmc = kind == SPEC_WALK_HMC;
@@ -743,6 +743,8 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
         stats->noconv = tot[6];
         stats->rounds = (double)rounds;
         stats->cert_fallback = tot[7];
+        stats->refined = tot[8];
+        stats->refine_failed = tot[9];
     }
     return SPEC_OK;
 }
@@ -801,15 +803,21 @@ struct spec_batch_s {
     // plan for `chains` chains per instance
     int chains = 0;
     FusedArgs* dArgs = nullptr;
+    FusedArgs* dArgsRef = nullptr;  // the REFINE pass's arguments per instance
     int2* dWork = nullptr;
     int* dCounter = nullptr;
+    int2* dRList = nullptr;         // refinement queue shared by the instances
+    int* dRCnt = nullptr;
     std::vector<unsigned> gens;  // handles' workspace generations the plan was built for
     struct Cls { int off, count, max_m, kmax, nblocks; };
     std::vector<Cls> all, classes;
     void free_plan() {
         dfree(dArgs);
+        dfree(dArgsRef);
         dfree(dWork);
         dfree(dCounter);
+        dfree(dRList);
+        dfree(dRCnt);
         chains = 0;
         all.clear();
         classes.clear();
@@ -840,10 +848,18 @@ spec_status batch_plan(spec_batch_s* b, int chains) {
     for (int i = 0; same && i < K; ++i) same = b->gens[i] == b->hs[i]->work_gen;
     if (same) return SPEC_OK;
     b->free_plan();
-    std::vector<FusedArgs> args(K);
+    HIPCHK(dalloc(&b->dRList, (size_t)K * chains, false));
+    HIPCHK(dalloc(&b->dRCnt, (size_t)2));
+    std::vector<FusedArgs> args(K), argsRef(K);
     for (int i = 0; i < K; ++i) {
         spec_handle h = b->hs[i];
         args[i] = fused_args(h, round_up(chains, 64), h->dSt, h->dTm, h->dTp, false, nullptr);
+        args[i].rlist = b->dRList;
+        args[i].rcount = b->dRCnt;
+        args[i].inst_id = i;
+        argsRef[i] = args[i];
+        argsRef[i].shift = h->dRShift;
+        argsRef[i].rlist = nullptr;
         b->gens.push_back(h->work_gen);
     }
     std::vector<int> order(K);
@@ -877,9 +893,11 @@ spec_status batch_plan(spec_batch_s* b, int chains) {
     a.nblocks = persistent_blocks(a.max_m, a.kmax);
     b->all.push_back(a);
     HIPCHK(dalloc(&b->dArgs, (size_t)K, false));
+    HIPCHK(dalloc(&b->dArgsRef, (size_t)K, false));
     HIPCHK(dalloc(&b->dWork, work.size(), false));
     HIPCHK(dalloc(&b->dCounter, 1));
     HIPCHK(hipMemcpy(b->dArgs, args.data(), sizeof(FusedArgs) * K, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->dArgsRef, argsRef.data(), sizeof(FusedArgs) * K, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->dWork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
     b->chains = chains;
     return SPEC_OK;
@@ -899,13 +917,20 @@ spec_status batch_round(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, 
         for (int i = 0; i < K; ++i) {
             spec_handle h = b->hs[i];
             FusedArgs a = fused_args(h, round_up(chains, 64), h->dSt, h->dTm, h->dTp, false, nullptr);
-            HIPCHK(launch_line_fused(a, chains, s));
+            SPCHK(run_fused(h, a, chains, s));
         }
     } else {
+        // first pass by the strategy, then one REFINE pass over the queue of
+        // every instance (LDS for the largest m)
+        HIPCHK(launch_zero_ints(b->dRCnt, 2, s));
         const auto& list = strategy == 1 ? b->all : b->classes;
         for (const auto& k : list)
             HIPCHK(launch_line_fused_multi(b->dArgs, b->dWork + k.off, k.count, b->dCounter, k.max_m, k.kmax,
                                            k.nblocks, s));
+        const auto& a = b->all[0];
+        FusedArgs none{};
+        HIPCHK(launch_line_refine(none, b->dArgsRef, b->dRList, b->dRCnt, b->dRCnt + 1, a.max_m, a.kmax,
+                                  persistent_blocks(a.max_m, a.kmax), s));
     }
     for (int i = 0; i < K; ++i) HIPCHK(walk_update(wa[i], s));
     return SPEC_OK;
@@ -1295,6 +1320,12 @@ spec_status spec_diag_stage_times(spec_handle h, double* out, double* lanczos_st
 spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out) {
     if (!h || !lam_out || batch < 0 || batch > h->cap) return SPEC_EINVAL;
     HIPCHK(hipMemcpy(lam_out, h->dLam, sizeof(double) * 4 * batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+spec_status spec_diag_call_flags(spec_handle h, int batch, int32_t* flags_out) {
+    if (!h || !flags_out || batch < 0 || batch > h->cap) return SPEC_EINVAL;
+    HIPCHK(hipMemcpy(flags_out, h->dFlags, sizeof(int32_t) * batch, hipMemcpyDeviceToHost));
     return SPEC_OK;
 }
 

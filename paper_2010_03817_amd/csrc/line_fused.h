@@ -29,6 +29,18 @@ struct FusedArgs {
     double* U2;
     int ldu2;
     long long* prof;           // nullable: per chain 8 clock64 stamps of the phases
+    // far-root refinement (see line_fused_chain): a first-pass run from the
+    // plain origin with rho > refine_ratio |lambda| for a deciding root stops
+    // that side at tol_loose and queues (inst_id, chain) in rlist (count in
+    // *rcount) with the origin rshift[chain] for the REFINE pass, whose
+    // FusedArgs have shift = rshift
+    double refine_ratio;       // 0: off
+    double tol_loose;
+    int2* rlist;               // nullable: no refinement
+    int* rcount;
+    double* rshift;
+    int inst_id;
+    int32_t* flags;            // nullable: per chain SPEC_FLAG_* bits
 };
 
 // Degree-2 curve oracle: first root of det Q(t), Q(t) = Q0 + t Q1 + t^2 Q2,
@@ -65,6 +77,14 @@ hipError_t launch_line_fused_multi(const FusedArgs* args, const int2* work, int 
 
 // Workgroups of the persistent launch resident per compute unit.
 int line_fused_multi_blocks_per_cu(int max_m, int kmax);
+
+// The REFINE pass: persistent workgroups over the queued items (count read
+// on the device); args (per instance) or `one` when args is null.
+hipError_t launch_line_refine(const FusedArgs& one, const FusedArgs* args, const int2* work, const int* nwork,
+                              int* counter, int max_m, int kmax, int nblocks, hipStream_t s);
+int line_refine_blocks_per_cu(int max_m, int kmax);
+// p[0 .. count) = 0 by a kernel (no memset node in a captured graph); count <= 64.
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 
 size_t fused_lds_bytes(int m, int kmax);
 int fused_threads(int m);

@@ -1271,7 +1271,7 @@ __device__ __forceinline__ LzLayout lz_layout(double* scr, int kmax) {
     o.al = scr + 2 * MAXH;        // kmax
     o.be = o.al + kmax;           // kmax + 1
     o.red = o.be + kmax + 1;      // 8
-    o.sres = o.red + 8;           // 8: theta_min, r_min, theta_max, r_max, stop, k, total steps
+    o.sres = o.red + 8;           // 8: theta_min, r_min, theta_max, r_max, stop, k, total steps, rho
     return o;
 }
 
@@ -1280,6 +1280,10 @@ __device__ __forceinline__ LzLayout lz_layout(double* scr, int kmax) {
 struct LzCtx {
     int m, kmax, min_only, first_check;
     double tol;
+    // a side whose Ritz value is below rho / loose_ratio in magnitude (rho the
+    // spectral radius estimate) stops at the looser tol_loose: its value only
+    // places the origin of a refining run (loose_ratio 0: off)
+    double loose_ratio, tol_loose;
     const double* B0;
     double b0;
     const double* B1;
@@ -1292,7 +1296,8 @@ struct LzCtx {
 // restarted from the Ritz vector after kmax steps, NCYCLES cycles at most.
 // Every thread of the block calls it.  Results in sres (LDS): theta_min,
 // r_min, theta_max, r_max, stop (1 converged, 2 not), steps of the last
-// cycle, total steps; al / be hold T_k of the last cycle and Qg its basis.
+// cycle, total steps, the spectral radius estimate of the last test; al / be
+// hold T_k of the last cycle and Qg its basis.
 // Wave 0 steers (Ritz values, residual bounds, stop decision); waves 1..
 // hold B and run B a.  Every wave runs its share of the triangular products
 // and owns the vector entries of its W b rows.  Both paths run the same
@@ -1311,7 +1316,7 @@ __device__ __forceinline__ void lanczos_extreme(const double* L, double* scr, co
     double* al = scr + 2 * MAXH;   // kmax
     double* be = al + kmax;        // kmax + 1
     double* red = be + kmax + 1;   // 8
-    double* sres = red + 8;        // 8: theta_min, r_min, theta_max, r_max, stop, k
+    double* sres = red + 8;        // 8: theta_min, r_min, theta_max, r_max, stop, k, total, rho
     double* Qg = c.Qg;
     for (int e = m + t; e < 2 * MAXH; e += blockDim.x) slot[e] = 0.0;
     // tile items of the triangular products (every wave, see mv_wt)
@@ -1574,7 +1579,7 @@ tprev = tn;                       \
                 // Ritz value than the gap, so the test runs with theta to 1e-10
                 // (relative) and a passing test (or the last step) is repeated
                 // with theta to the rounding level.
-                double rmin = 0.0, rmax = 0.0;
+                double rmin = 0.0, rmax = 0.0, rho_last = 0.0;
                 auto test = [&]() {
                     th = 0.5 * (lo + hi);
                     res = exhausted ? 0.0 : fabs(bn) * backward_norm_lds(al, be, k, th);
@@ -1587,6 +1592,12 @@ tprev = tn;                       \
                     const double floor_r = 2.2e-14 * rho;
                     tmin = fmax(c.tol * fabs(thmin), floor_r);
                     tmax = fmax(c.tol * fabs(thmax), floor_r);
+                    if (c.loose_ratio > 0.0) {
+                        if (rho > c.loose_ratio * fabs(thmin)) tmin = fmax(tmin, c.tol_loose * fabs(thmin));
+                        if (!c.min_only && rho > c.loose_ratio * fabs(thmax))
+                            tmax = fmax(tmax, c.tol_loose * fabs(thmax));
+                    }
+                    rho_last = rho;
                     const bool cmin = rmin <= tmin;
                     const bool cmax = c.min_only || rmax <= tmax;
                     conv_now = exhausted || (cmin && cmax);
@@ -1611,6 +1622,7 @@ tprev = tn;                       \
                 if (lane == 0) {
                     sres[0] = th;
                     sres[1] = res;
+                    sres[7] = rho_last;
                 }
                 if (lane == src_max) {
                     sres[2] = c.min_only ? NAN : th;
@@ -1711,6 +1723,22 @@ __device__ __forceinline__ void ritz_u(const double* L, double* scr, int m, int 
 
 // One chain's line oracle (the body of k_line_fused); every thread of the
 // block calls it with the same arguments.
+//
+// Far-root refinement.  The rounding error of C = L^-1 B L^-T is about eps
+// times its spectral radius rho, so the root whose eigenvalue is small
+// against rho (the far root of a start next to the boundary, rho ~ 1/|t-|)
+// comes out of the run from x with a relative error near eps rho / |lambda|.
+// When a run from the plain origin ends with rho > refine_ratio |lambda| for
+// a root that decides the result, that side's Lanczos test uses the loose
+// tolerance, the chain is queued (rlist) with the new origin
+// t0 = t1 (1 - 2^-10) (t1 the root found; negative for t-), and a second,
+// REFINE, pass factors F(x + t0 v) (which certifies t0 inside) and runs
+// Lanczos on the shifted pencil, where that root's eigenvalue
+// -1/(t1 - t0) dominates the spectrum (lambda_min only; lambda_max as
+// -lambda_min of -C).  If the factor at t0 does not exist, the origin backs
+// off (see below) before the REFINE pass repeats the plain solve from x at
+// the full tolerance (REFINE_FAILED).
+template <bool REFINE>
 __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, double* lds) {
     const int m = a.m, P = a.P, md = a.md;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
@@ -1726,7 +1754,13 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     const double* Fr = a.FB + (size_t)chain * a.ldfb;
     const double* Br = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
     double t0 = a.shift ? a.shift[chain] : 0.0;
-    if (!(t0 > 0.0) || !isfinite(t0)) t0 = 0.0;  // no usable bracket: plain origin
+    if (REFINE) {
+        if (!isfinite(t0)) t0 = 0.0;
+    } else if (!(t0 > 0.0) || !isfinite(t0)) {
+        t0 = 0.0;  // no usable bracket: plain origin
+    }
+    const int side = t0 < 0.0 ? 2 : 1;  // REFINE: the root refined from t0
+    int flags = 0;
     int32_t st = SPEC_OK;
     long long* prof = a.prof ? a.prof + (size_t)chain * SPEC_DIAG_PHASE_SLOTS : nullptr;
 #define STAMP(i) \
@@ -1777,8 +1811,13 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         // an upper end t_hi, F(x + t_hi v) is tested first (a definite F there
         // means the bracket missed t+ on the high side: counted, harmless).
         // One loop so that the factorisation is instantiated once.
+        // REFINE: t0 = t1 (1 - 2^-10); should the factor not exist there (t1 too
+        // far out: the first pass stopped at the loose tolerance), the origin
+        // backs off to t1 (1 - 2^-5), then t1 / 2, before the plain solve
         int phase = a.shift_hi ? 0 : 1;
         bool ok = false;
+        int tries = 0;
+        const double t1r = t0 / (1.0 - 0.0009765625);
         long long cst[4] = {0, 0, 0, 0};  // Cholesky stage cycles (profiling)
         STAMP(1)
         for (;;) {
@@ -1793,7 +1832,16 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
                 continue;
             }
             if (ok || t0 == 0.0) break;
-            cert = 1;
+            if (REFINE) {
+                if (tries < 2) {
+                    ++tries;
+                    t0 = t1r * (tries == 1 ? 1.0 - 0.03125 : 0.5);
+                    continue;
+                }
+                flags |= SPEC_FLAG_REFINE_FAILED;
+            } else {
+                cert = 1;
+            }
             t0 = 0.0;
         }
         STAMP(2)
@@ -1826,14 +1874,18 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             double* sres = lz.sres;
             double* Qg = a.Q + (size_t)chain * a.ldq;
             STAMP(4)
+            // REFINE from a shifted origin: one side (lambda_max(C) = -lambda_min(-C))
+            const bool shifted = REFINE && t0 != 0.0;
             LzCtx lc;
             lc.m = m;
             lc.kmax = kmax;
-            lc.min_only = a.min_only;
+            lc.min_only = shifted ? 1 : a.min_only;
             lc.first_check = a.first_check;
             lc.tol = a.tol;
+            lc.loose_ratio = (!REFINE && t0 == 0.0) ? a.refine_ratio : 0.0;
+            lc.tol_loose = a.tol_loose;
             lc.B0 = Br;
-            lc.b0 = 1.0;
+            lc.b0 = (shifted && side == 2) ? -1.0 : 1.0;
             lc.B1 = nullptr;
             lc.b1 = 0.0;
             lc.Qg = Qg;
@@ -1846,19 +1898,58 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             conv = sres[4] == 1.0;
             const int k = (int)sres[5];
             iters = (int)sres[6];
-            // dense block: roots measured from the shifted origin t0
+            if (REFINE && a.lam) iters += (int)a.lam[4 * chain + 3];  // steps of the first pass
+            // dense block: roots measured from the origin t0
             double dtpd = INFINITY, dtmd = -INFINITY;
-            if (lmax > 0.0) dtmd = t0 - 1.0 / lmax;
-            if (lmin < 0.0) dtpd = t0 - 1.0 / lmin;
-            if (a.min_only) dtmd = NAN;  // lambda_max is not converged by design
-            tm = isnan(dtmd) ? dtmd : fmax(tm, dtmd);
-            if (dtpd <= tp) {
-                tp = dtpd;
-                hit = HIT_DENSE;
+            if (!shifted) {
+                if (lmax > 0.0) dtmd = t0 - 1.0 / lmax;
+                if (lmin < 0.0) dtpd = t0 - 1.0 / lmin;
+                if (a.min_only) dtmd = NAN;  // lambda_max is not converged by design
             }
-            const bool need_vec = a.want_vec && hit == HIT_DENSE && isfinite(tp) && (a.ell == nullptr || tp < a.ell[chain]);
+            int rside = 0;  // first pass: the root to refine (1 t+, 2 t-)
+            if (!REFINE && t0 == 0.0 && a.refine_ratio > 0.0 && conv && a.rlist) {
+                const double rho = sres[7];
+                if (lmin < 0.0 && rho > a.refine_ratio * fabs(lmin) && dtpd <= dtp * (1.0 + 1e-6))
+                    rside = 1;
+                else if (!a.min_only && !a.want_vec && lmax > 0.0 && rho > a.refine_ratio * lmax &&
+                         dtmd >= dtm * (1.0 + 1e-6))
+                    rside = 2;
+                if (rside && t == 0) {
+                    const double t1 = rside == 1 ? dtpd : dtmd;
+                    a.rshift[chain] = t1 * (1.0 - 0.0009765625);
+                    const int slot = atomicAdd(a.rcount, 1);
+                    a.rlist[slot] = make_int2(a.inst_id, chain);
+                }
+            }
+            if (shifted) {
+                // the refined root from t0; the other one stays that of the first pass
+                if (side == 1) {
+                    if (lmin < 0.0) dtpd = t0 - 1.0 / lmin;
+                    tm = a.tm[chain];
+                    if (dtpd <= tp) {
+                        tp = dtpd;
+                        hit = HIT_DENSE;
+                    }
+                } else {
+                    if (lmin < 0.0) dtmd = t0 + 1.0 / lmin;  // lambda_max(C) = -lmin
+                    lmax = -lmin;
+                    tm = fmax(tm, dtmd);
+                    tp = a.tp[chain];
+                    hit = a.hit[chain];
+                }
+            } else {
+                tm = isnan(dtmd) ? dtmd : fmax(tm, dtmd);
+                if (dtpd <= tp) {
+                    tp = dtpd;
+                    hit = HIT_DENSE;
+                }
+            }
+            // the kernel vector of a t+ hit comes from the run that fixes t+
+            const bool need_vec = a.want_vec && rside != 1 && !(shifted && side == 2) && hit == HIT_DENSE &&
+                                  isfinite(tp) && (a.ell == nullptr || tp < a.ell[chain]);
             if (need_vec)
                 ritz_u(L, scr, m, kmax, k, lmin, Qg, a.u + (size_t)chain * a.ldu, a.U2 + (size_t)chain * a.ldu2);
+            if (rside) flags |= SPEC_FLAG_REFINED;
         }
     }
     STAMP(6)
@@ -1872,7 +1963,10 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             if (!conv) st = SPEC_NOCONV;
             else if (isinf(tp) || isinf(tm)) st = SPEC_UNBOUNDED;
         }
+        if (REFINE && a.flags) flags |= a.flags[chain] & ~SPEC_FLAG_REFINE_FAILED;
+        if (REFINE && (flags & SPEC_FLAG_CERT_FALLBACK)) cert = 1;  // from the first pass
         if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;  // informational: values are final
+        if (a.flags) a.flags[chain] = flags | (cert == 1 ? SPEC_FLAG_CERT_FALLBACK : 0);
         a.tm[chain] = tm;
         a.tp[chain] = tp;
         a.hit[chain] = hit;
@@ -1889,7 +1983,33 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
 __global__ __launch_bounds__(512) void k_line_fused(FusedArgs a) {
     extern __shared__ double lds[];
     const int chain = a.idx ? a.idx[blockIdx.x] : (int)blockIdx.x;
-    line_fused_chain(a, chain, lds);
+    line_fused_chain<false>(a, chain, lds);
+}
+
+// The REFINE pass over the chains the first pass queued: persistent
+// workgroups take items (instance, chain) of `work` from an atomic counter
+// until *nwork (written by the first pass) is reached.  MULTI: args holds one
+// FusedArgs per instance (the REFINE pass's: shift = the queued origins);
+// otherwise `one` serves every item.
+template <bool MULTI>
+__global__ __launch_bounds__(512) void k_line_refine(FusedArgs one, const FusedArgs* __restrict__ args,
+                                                     const int2* __restrict__ work, const int* __restrict__ nwork,
+                                                     int* __restrict__ counter) {
+    extern __shared__ double lds[];
+    const int total = *nwork;
+    for (;;) {
+        // the item goes through the first LDS word, between chains (no static
+        // LDS: a chain of the largest size uses all of it)
+        __syncthreads();  // the previous item is finished with LDS
+        if (threadIdx.x == 0) ((int*)lds)[0] = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = ((int*)lds)[0];
+        __syncthreads();  // every thread has read it before the chain writes LDS
+        if (it >= total) break;
+        const int2 w = work[it];
+        if (MULTI) line_fused_chain<true>(args[w.x], w.y, lds);
+        else line_fused_chain<true>(one, w.y, lds);
+    }
 }
 
 // Persistent form over many spectrahedra: workgroups take (instance, chain)
@@ -1900,20 +2020,26 @@ __global__ __launch_bounds__(512) void k_line_fused_multi(const FusedArgs* __res
                                                           const int2* __restrict__ work, int nwork,
                                                           int* __restrict__ counter) {
     extern __shared__ double lds[];
-    __shared__ int item;
     for (;;) {
+        // the item goes through the first LDS word, between chains (no static
+        // LDS: a chain of the largest size uses all of it)
         __syncthreads();  // the previous item is finished with LDS
-        if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) ((int*)lds)[0] = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = item;
+        const int it = ((int*)lds)[0];
+        __syncthreads();  // every thread has read it before the chain writes LDS
         if (it >= nwork) break;
         const int2 w = work[it];
-        line_fused_chain(args[w.x], w.y, lds);
+        line_fused_chain<false>(args[w.x], w.y, lds);
     }
 }
 
 __global__ void k_zero_int(int* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+__global__ void k_zero_ints(int* p, int count) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < count) p[threadIdx.x] = 0;
 }
 
 int line_fused_multi_blocks_per_cu(int max_m, int kmax) {
@@ -1930,7 +2056,7 @@ hipError_t launch_line_fused_multi(const FusedArgs* args, const int2* work, int 
     if (nwork <= 0) return hipSuccess;
     if (max_m > 2 * MAXH) return hipErrorInvalidValue;
     const size_t lds = fused_lds_bytes(max_m, kmax);
-    if (lds > 163840 - 64) return hipErrorInvalidValue;
+    if (lds > 163840) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, counter);
     hipLaunchKernelGGL(k_line_fused_multi, dim3(nblocks), dim3(fused_threads(max_m)), lds, s, args, work, nwork,
                        counter);
@@ -2056,6 +2182,8 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                     // bound at any tolerance, a looser one just shortens the step.  D1
                     // fixes the root and the kernel vector, so it is solved more tightly.
                     lc.tol = pass == 0 ? fmax(a.tol, 1e-3) : fmax(a.tol, 1e-6);
+                    lc.loose_ratio = 0.0;
+                    lc.tol_loose = 0.0;
                     lc.B0 = pass == 0 ? Q2 : Q1;
                     lc.b0 = pass == 0 ? 1.0 : sg;
                     lc.B1 = pass == 0 ? nullptr : Q2;
@@ -2143,6 +2271,37 @@ int fused_threads(int m) {
     int t = 64 + ((2 * m + 63) / 64) * 64;
     if (t < 128) t = 128;
     return t;
+}
+
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
+    if (count <= 0 || count > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, p, count);
+    return hipGetLastError();
+}
+
+int line_refine_blocks_per_cu(int max_m, int kmax) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_line_refine<false>),
+                                                     fused_threads(max_m), fused_lds_bytes(max_m, kmax)) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+hipError_t launch_line_refine(const FusedArgs& one, const FusedArgs* args, const int2* work, const int* nwork,
+                              int* counter, int max_m, int kmax, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    if (max_m > 2 * MAXH) return hipErrorInvalidValue;
+    const size_t lds = fused_lds_bytes(max_m, kmax);
+    if (lds > 163840) return hipErrorInvalidValue;
+    if (args)
+        hipLaunchKernelGGL(k_line_refine<true>, dim3(nblocks), dim3(fused_threads(max_m)), lds, s, one, args, work,
+                           nwork, counter);
+    else
+        hipLaunchKernelGGL(k_line_refine<false>, dim3(nblocks), dim3(fused_threads(max_m)), lds, s, one, args, work,
+                           nwork, counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_line_fused(const FusedArgs& a, int nblocks, hipStream_t s) {

@@ -321,10 +321,11 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
     dfree(dTall);
     dfree(dTm);
     std::vector<double> err(nval);
-    double vl = 0.0;
+    double vl = 0.0, vc = 0.0;
     for (int r = 0; r < nval; ++r) {
         const double d0 = (double)yv[2 * r] - tv[2 * r], d1 = (double)yv[2 * r + 1] - tv[2 * r + 1];
         vl += d0 * d0 + d1 * d1;
+        vc += (double)tv[2 * r] * tv[2 * r] + (double)tv[2 * r + 1] * tv[2 * r + 1];
         const double pred = (double)yv[2 * r] * net->tsd[0] + net->tmu[0];
         err[r] = std::fabs(pred - std::log(hp[ntrain + r]));
     }
@@ -332,6 +333,7 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
         std::memset(st, 0, sizeof(*st));
         st->train_loss = train_loss;
         st->val_loss = vl / (2.0 * nval);
+        st->val_loss_const = vc / (2.0 * nval);
         st->delta = quantile(err, qq);
         st->err_median = quantile(err, 0.5);
         st->err_p99 = quantile(err, 0.99);

@@ -5,15 +5,19 @@
 
 namespace spec {
 
+// Rows c < batch as above; rows batch <= c < zrow0 of both halves are zero
+// (the padding rows of the GEMM: defined whatever the buffer held before).
 __global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__ x, const double* __restrict__ v,
                           double* __restrict__ Z, int zrow0) {
     const int c = blockIdx.x;
-    if (c >= batch) return;
+    if (c >= zrow0) return;
     double* zf = Z + (size_t)c * Kpad;
     double* zb = Z + (size_t)(zrow0 + c) * Kpad;
+    const bool live = c < batch;
     for (int k = threadIdx.x; k < Kpad; k += blockDim.x) {
         double fx = 0.0, bv = 0.0;
-        if (k == 0) {
+        if (!live) {
+        } else if (k == 0) {
             fx = 1.0;
         } else if (k <= n) {
             if (x) fx = x[(size_t)c * n + k - 1];
@@ -27,7 +31,8 @@ __global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s) {
     if (batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_z, dim3(batch), dim3(64), 0, s, batch, n, Kpad, x, v, Z, zrow0);
+    if (zrow0 < batch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_build_z, dim3(zrow0), dim3(64), 0, s, batch, n, Kpad, x, v, Z, zrow0);
     return hipGetLastError();
 }
 

@@ -10,11 +10,18 @@ namespace spec {
 // Which block attains t+ : a diagonal row index (>= 0), the dense block, or none.
 enum : int { HIT_DENSE = -1, HIT_NONE = -3 };
 
+// Per-call bits of the line oracle: the learned bracket was not certified
+// (plain origin used), a far root was refined from a shifted origin, a
+// refining factor did not exist (the run from 0 was repeated at the full
+// tolerance).
+enum : int { SPEC_FLAG_CERT_FALLBACK = 1, SPEC_FLAG_REFINED = 4, SPEC_FLAG_REFINE_FAILED = 8 };
+
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                     double* C, int ldc, hipStream_t s);
 hipError_t mfma_probe(double* out, hipStream_t s);
 
-// Assembly rows: Z[c] = [1, x_c] (F) and Z[zrow0 + c] = [0, v_c] (B), padded with zeros.
+// Assembly rows: Z[c] = [1, x_c] (F) and Z[zrow0 + c] = [0, v_c] (B), padded with zeros;
+// rows batch <= c < zrow0 of both halves are zero (zrow0 >= batch).
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s);
 

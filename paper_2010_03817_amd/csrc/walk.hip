@@ -300,6 +300,11 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         st[0] += 1.0;
         if (status == SPEC_NOCONV) st[6] += 1.0;
         if (status == SPEC_CERT_FALLBACK) st[7] += 1.0;
+        if (a.flags) {
+            const int f = a.flags[c];
+            if (f & SPEC_FLAG_REFINED) st[8] += 1.0;
+            if (f & SPEC_FLAG_REFINE_FAILED) st[9] += 1.0;
+        }
     }
     if (status == SPEC_NOT_INTERIOR) {
         // cannot happen from an interior start; count it and restart the

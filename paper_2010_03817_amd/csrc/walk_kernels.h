@@ -5,8 +5,9 @@
 namespace spec {
 
 // Per-chain statistics: oracle calls, reflections, cap hits, not-interior,
-// nonsmooth, completed steps, eigen non-convergence, learned-bracket fallbacks.
-constexpr int WALK_NSTAT = 8;
+// nonsmooth, completed steps, eigen non-convergence, learned-bracket fallbacks,
+// far roots refined from a shifted origin, refinements whose factor failed.
+constexpr int WALK_NSTAT = 10;
 
 struct WalkState {
     double* x;        // chains x n: current point
@@ -28,6 +29,7 @@ struct WalkArgs {
     WalkState st;
     // oracle results of the current round
     const int32_t* status;
+    const int32_t* flags;  // nullable: SPEC_FLAG_* bits of the oracle call
     const double* tm;
     const double* tp;
     const int32_t* hit;

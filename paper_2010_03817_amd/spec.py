@@ -37,7 +37,15 @@ class WalkParams(C.Structure):
 
 class WalkStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("calls", "reflections", "cap_hits", "not_interior", "nonsmooth", "steps",
-                                          "noconv", "rounds", "cert_fallback")]
+                                          "noconv", "rounds", "cert_fallback", "refined", "refine_failed")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("kmax", C.c_int), ("tol", C.c_double), ("refine_ratio", C.c_double),
+                ("tol_loose", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -60,7 +68,8 @@ class MlpTrainParams(C.Structure):
 
 class MlpTrainStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("train_loss", "val_loss", "delta", "err_median", "err_p99", "err_max",
-                                          "steps", "val_rows")] + [("err_q", C.c_double * 8)]
+                                          "steps", "val_rows")] + [("err_q", C.c_double * 8),
+                                                                   ("val_loss_const", C.c_double)]
     QUANTILE_LEVELS = (0.5, 0.7, 0.8, 0.9, 0.95, 0.99, 0.995, 0.999)
 
     def as_dict(self):
@@ -99,6 +108,11 @@ def lib():
     L.spec_status_str.argtypes = [C.c_int]
     L.spec_status_str.restype = C.c_char_p
     L.spec_set_lanczos.argtypes = [vp, C.c_int, C.c_double]
+    L.spec_walk_state.argtypes = [vp, C.c_int]
+    L.spec_options_default.argtypes = [C.POINTER(Options)]
+    L.spec_create_ex.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.POINTER(Options), C.POINTER(vp)]
+    L.spec_set_options.argtypes = [vp, C.POINTER(Options)]
+    L.spec_get_options.argtypes = [vp, C.POINTER(Options)]
     L.spec_set_precision.argtypes = [vp, C.c_int]
     L.spec_membership_dev.argtypes = [vp, C.c_int, vp, vp, vp]
     L.spec_intersect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
@@ -117,6 +131,7 @@ def lib():
     L.spec_diag_mfma_layout.argtypes = [vp]
     L.spec_diag_gemm_f64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.spec_diag_lanczos_info.argtypes = [vp, C.c_int, vp]
+    L.spec_diag_call_flags.argtypes = [vp, C.c_int, vp]
     L.spec_diag_mfma_raw.argtypes = [C.c_int, C.c_int, vp, vp, vp]
     L.spec_diag_gemm_f32.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp,
                                      C.c_int, vp, C.c_int, vp, C.c_int]
@@ -183,16 +198,27 @@ def _f64(t, shape=None):
 class Spectrahedron:
     """Device handle of an LMI (instances.Instance)."""
 
-    def __init__(self, inst, kmax: int | None = None, tol: float | None = None):
+    def __init__(self, inst, kmax: int | None = None, tol: float | None = None, **options):
+        """options: fields of spec_options (precision, kmax, tol, refine_ratio,
+        tol_loose) over spec_options_default."""
         _torch()
         self.inst = inst
         self.n = inst.n
         sizes, kinds, A = inst.flat()
         self._keep = (sizes, kinds, np.ascontiguousarray(A, dtype=np.float64))
         h = C.c_void_p()
-        check(lib().spec_create(self.n, len(sizes), sizes.ctypes.data_as(C.POINTER(C.c_int)),
-                                kinds.ctypes.data_as(C.POINTER(C.c_int)),
-                                self._keep[2].ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+        opt = None
+        if options:
+            opt = Options()
+            check(lib().spec_options_default(C.byref(opt)))
+            for k, val in options.items():
+                if k not in opt.as_dict():
+                    raise TypeError(f"unknown option {k}")
+                setattr(opt, k, val)
+        check(lib().spec_create_ex(self.n, len(sizes), sizes.ctypes.data_as(C.POINTER(C.c_int)),
+                                   kinds.ctypes.data_as(C.POINTER(C.c_int)),
+                                   self._keep[2].ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.byref(opt) if opt is not None else None, C.byref(h)))
         self._h = h
         n, m, md = C.c_int(), C.c_int(), C.c_int()
         check(lib().spec_dims(h, C.byref(n), C.byref(m), C.byref(md)))
@@ -202,6 +228,20 @@ class Spectrahedron:
 
     def set_lanczos(self, kmax: int, tol: float):
         check(lib().spec_set_lanczos(self._h, int(kmax), float(tol)))
+
+    def options(self):
+        o = Options()
+        check(lib().spec_get_options(self._h, C.byref(o)))
+        return o.as_dict()
+
+    def set_options(self, **changes):
+        o = Options()
+        check(lib().spec_get_options(self._h, C.byref(o)))
+        for k, val in changes.items():
+            if k not in o.as_dict():
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, val)
+        check(lib().spec_set_options(self._h, C.byref(o)))
 
     def set_precision(self, mode: int):
         """Pencil assembly precision: PREC_FP64, PREC_FP32_ASM, PREC_BF16X2_ASM."""
@@ -289,6 +329,12 @@ class Spectrahedron:
             log = log[:k]
         return x_out, samples, st.as_dict(), log
 
+    def save_walk_state(self):
+        check(lib().spec_walk_state(self._h, 0))
+
+    def restore_walk_state(self):
+        check(lib().spec_walk_state(self._h, 1))
+
     def timing(self, on: bool):
         check(lib().spec_diag_timing(self._h, int(on)))
 
@@ -341,8 +387,17 @@ class Spectrahedron:
         self._net = net
         return best.value, list(ms)
 
+    def call_flags(self, batch):
+        """Per-element bits of the last call: 1 bracket not certified, 4 far root
+        refined, 8 refining factor failed."""
+        torch = _torch()
+        torch.cuda.synchronize()
+        out = np.empty(batch, dtype=np.int32)
+        check(lib().spec_diag_call_flags(self._h, batch, out.ctypes.data_as(C.c_void_p)))
+        return out
+
     def lanczos_info(self, batch):
-        """(lambda_min, lambda_max, second Ritz value, steps) of the last call."""
+        """(lambda_min, lambda_max, learned-bracket code, steps) of the last call."""
         torch = _torch()
         torch.cuda.synchronize()
         out = np.empty((batch, 4))

@@ -145,18 +145,22 @@ def test_intersect_near_boundary():
     tp0 = o.intersect(x0, u)[1]
     x = x0 + (1 - 1e-6) * tp0[:, None] * u
     v = I.random_directions(rng, 48, inst.n)
-    tm_r, tp_r, st_r = o.intersect(x, v)
+    # reference: bisection on membership (exact at any conditioning of F(x))
+    tm_r, tp_r, st_r = o.line_bisect(x, v)
     tm, tp, st = [_np(a) for a in g.intersect(x, v)]
     ok = st_r == O.OK
     assert ok.sum() > 40
-    # t+- measured from a point at relative distance 1e-6 of the boundary: the
-    # short side has relative conditioning ~1e6, so its bar is scaled by it.
-    short = np.minimum(np.abs(tm_r), tp_r) < 1e-3 * np.maximum(np.abs(tm_r), tp_r)
+    # the far side meets 1e-9; the root next to the start is fixed by F(x)
+    # only to the rounding bound of root_bounds (two correct methods differ
+    # by that much)
+    from root_bounds import root_bars
+    bar_m, bar_p = root_bars(inst, x[ok], v[ok], tm_r[ok], tp_r[ok], T_REL)
+    assert (np.abs(tp[ok] - tp_r[ok]) <= bar_p).all()
+    assert (np.abs(tm[ok] - tm_r[ok]) <= bar_m).all()
+    near = np.minimum(np.abs(tm_r), tp_r)
     for arr, ref in ((tp, tp_r), (tm, tm_r)):
-        rel = np.abs(arr - ref) / np.abs(ref)
-        is_short = np.abs(ref) == np.minimum(np.abs(tm_r), tp_r)
-        assert (rel[ok & ~(short & is_short)] <= T_REL).all()
-        assert (rel[ok & short & is_short] <= 1e-6).all()
+        far = ok & (np.abs(ref) > near)
+        assert (np.abs(arr - ref)[far] <= T_REL * np.abs(ref[far])).all()
 
 
 def test_reflect_parity():

@@ -211,3 +211,27 @@ def test_paper_example_area_envelope():
     assert len(areas) > 100
     assert areas.min() < g["area_printed"] < areas.max()
     assert areas.min() < a0 < areas.max()
+
+
+def test_near_root_rounding_bound_covers_the_oracles_two_routes():
+    """The first-order rounding bound of a root next to its start (test
+    helper root_bounds) covers the difference between the oracle's eigen
+    route and its bisection on starts pulled back 1e-6 from the boundary,
+    and is not vacuous (well under 1e-3 of the root)."""
+    from root_bounds import root_bars
+    inst = I.gbase(20, 24, seed=19)
+    o = O.Oracle(inst)
+    rng = np.random.default_rng(16)
+    d = I.random_directions(rng, 24, inst.n)
+    x0 = 0.3 * d * o.intersect(np.zeros((24, inst.n)), d)[1][:, None]
+    u = I.random_directions(rng, 24, inst.n)
+    x = x0 + (1 - 1e-6) * o.intersect(x0, u)[1][:, None] * u
+    v = I.random_directions(rng, 24, inst.n)
+    jm, jp, js = o.intersect(x, v)
+    bm, bp, bs = o.line_bisect(x, v)
+    assert (js == O.OK).all() and (bs == O.OK).all()
+    bar_m, bar_p = root_bars(inst, x, v, bm, bp, 1e-9)
+    assert (np.abs(jm - bm) <= bar_m).all() and (np.abs(jp - bp) <= bar_p).all()
+    near = np.minimum(np.abs(bm), bp)
+    nb = np.where(np.abs(bm) < bp, bar_m, bar_p)
+    assert np.all(nb < 1e-3 * near)

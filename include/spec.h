@@ -433,6 +433,32 @@ spec_status spec_tune_mlp_delta_dev(spec_handle h, spec_mlp net, int batch, cons
                                     int ncand, const double* deltas, int reps, double* ms_out, double* best,
                                     void* stream);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * spec_intersect_noalloc_dev is spec_intersect_dev (same kernels, same
+ * results) whose scratch memory (coefficient rows, assembled pencils, Lanczos
+ * bases, per-chain first-pass results and the refinement queue) lives in one
+ * static device array of SPEC_NOALLOC_SCRATCH_BYTES per device instead of the
+ * handle's workspace: the call allocates nothing (the handle and its A-stack,
+ * and the reduced-precision copy when spec_set_precision selected one, are
+ * made beforehand).  Every call on a device shares that device's array, which
+ * keeps the last call's contents (what must start at zero is cleared by a
+ * kernel in each call), so calls that overlap on one device (other streams,
+ * other threads, other handles) race.  The array needs, in bytes, about
+ * bp (16 Kpad + 16 ldA + 8 kmax m + 64) for bp = batch rounded up to 64,
+ * Kpad = round_up(n + 1, 16), ldA = round_up(m (m + 1) / 2 + md, 128), with
+ * each piece rounded to 256 bytes (FP32/BF16 assembly adds 8 bp Kpad);
+ * a larger batch returns SPEC_ENOTSUP before any work (n = m = 200, md = 400,
+ * kmax 80: up to 128 pairs per call; n = m = 100: up to 384).  The per-call
+ * diagnostics (spec_diag_lanczos_info, spec_diag_call_flags) do not see these
+ * calls.
+ * ------------------------------------------------------------------------ */
+#define SPEC_NOALLOC_SCRATCH_BYTES (64u << 20)
+spec_status spec_intersect_noalloc_dev(spec_handle h, int batch, const double* x, const double* v,
+                                       double* t_minus, double* t_plus, int32_t* status, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,7 @@ def lib():
     L.spec_set_precision.argtypes = [vp, C.c_int]
     L.spec_membership_dev.argtypes = [vp, C.c_int, vp, vp, vp]
     L.spec_intersect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
+    L.spec_intersect_noalloc_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
     L.spec_reflect_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.spec_membership.argtypes = [vp, C.c_int, vp, vp]
     L.spec_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
@@ -277,6 +278,16 @@ class Spectrahedron:
         st = torch.empty(B, dtype=torch.int32, device="cuda")
         check(lib().spec_intersect_dev(self._h, B, _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), _ptr(st), _stream()))
         return tm, tp, st
+
+    def intersect_noalloc(self, x, v, tm, tp, st):
+        """spec_intersect_noalloc_dev into caller-provided device tensors
+        (float64 t-, t+ and int32 status of the batch size)."""
+        x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
+        B = x.shape[0]
+        assert tm.numel() >= B and tp.numel() >= B and st.numel() >= B
+        check(lib().spec_intersect_noalloc_dev(self._h, B, _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), _ptr(st),
+                                               _stream()))
+        return tm[:B], tp[:B], st[:B]
 
     def intersect_curve(self, coef, horizon=float("inf"), degree=2):
         """First positive / negative roots of det(Q0 + t Q1 + t^2 Q2) within the

@@ -66,26 +66,76 @@ def _cpu_worker(args):
     return time.time() - t0, st[0], st[5]
 
 
-def cpu_baseline(tau, x0s, budget_s=15.0):
-    cores = min(16, os.cpu_count() or 1)
-    # one oracle call at n = m = 200 takes ~0.1-0.3 s: size the sample to the budget
-    steps = 2
-    jobs = [(c, steps, tau, 9000, x0s[c % len(x0s)]) for c in range(cores)]
+def _cpu_reflect_worker(args):
+    """Oracle reflections of a chunk of logged pairs (CPU baseline)."""
+    from oracle import oracle as O
+    from paper_2010_03817_amd import instances as I
+    x, v = args
+    o = O.Oracle(I.gbase(N_DIM, M_DIM, seed=SEED_INST))
     t0 = time.time()
-    with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_cpu_worker, jobs)
+    o.reflect(x, v)
+    return time.time() - t0, len(x)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(tau, x0s, px, pv, workers=16):
+    """The FP64 CPU oracle on the host of the GPU: single-thread latency of
+    oracle reflect / intersect calls on logged walk pairs of the n = m = 200
+    workload, throughput of reflect calls over `workers` processes (one
+    process per core of the machine's CPU share), and billiard steps of whole
+    oracle walks, one chain per process."""
+    from oracle import oracle as O
+    from paper_2010_03817_amd import instances as I
+    o = O.Oracle(I.gbase(N_DIM, M_DIM, seed=SEED_INST))
+    ns = 48
+    t0 = time.time()
+    o.reflect(px[:ns], pv[:ns])
+    lat_reflect = (time.time() - t0) / ns
+    t0 = time.time()
+    o.intersect(px[ns:2 * ns], pv[ns:2 * ns])
+    lat_intersect = (time.time() - t0) / ns
+    per = 12
+    jobs = [(px[k * per:(k + 1) * per], pv[k * per:(k + 1) * per]) for k in range(workers)]
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_cpu_reflect_worker, jobs)
     wall = time.time() - t0
     calls = sum(r[1] for r in res)
-    steps_done = sum(r[2] for r in res)
     busy = max(r[0] for r in res)
+    steps = 2
+    wjobs = [(c, steps, tau, 9000, x0s[c % len(x0s)]) for c in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        wres = pool.map(_cpu_worker, wjobs)
+    wcalls = sum(r[1] for r in wres)
+    wsteps = sum(r[2] for r in wres)
+    wbusy = max(r[0] for r in wres)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
     return {
         "value": calls / busy,
         "unit": "oracle calls/s",
-        "cores": cores,
+        "cores": workers,
         "kind": "oracle",
-        "sample": f"{cores} chains x {steps} billiard steps of the FP64 CPU oracle (cyclic Jacobi), "
-                  f"one chain per process; {int(calls)} oracle calls, wall {wall:.1f} s",
-        "billiard_steps_per_s": steps_done / busy,
+        "sample": f"{calls} oracle reflect calls on logged billiard-walk pairs of the n=m=200 workload, "
+                  f"{per} per process over {workers} processes (wall {wall:.1f} s); single-thread latency on "
+                  f"{ns} pairs each; {workers} chains x {steps} billiard steps of the oracle walk",
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
+        "affinity_cpus": affinity,
+        "single_thread_s_per_call": {"reflect": lat_reflect, "intersect": lat_intersect},
+        "walk_oracle_calls_per_s": wcalls / wbusy,
+        "billiard_steps_per_s": wsteps / wbusy,
     }
 
 
@@ -469,6 +519,11 @@ def main():
     # rounds with the same seed, so the legs see the same walk states
     g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=max(args.state_rounds, 1))
     g.save_walk_state()
+    # logged segment starts of 64 chains for the CPU oracle's sample
+    _, _, _, clog = g.walk(S.BILLIARD, np.zeros((64, N_DIM)), 1 << 30, seed=31, tau=tau, max_rounds=8,
+                           log_chains=64, log_cap=512)
+    clog = clog.cpu().numpy()[-256:]
+    cpu_px, cpu_pv = clog[:, :N_DIM].copy(), clog[:, N_DIM:2 * N_DIM].copy()
 
     def leg(name, model, d):
         g.restore_walk_state()
@@ -548,7 +603,7 @@ def main():
     if not args.no_cpu:
         progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))
-        out["cpu_baseline"] = cpu_baseline(tau, xs)
+        out["cpu_baseline"] = cpu_baseline(tau, xs, cpu_px, cpu_pv)
     print(json.dumps(out), flush=True)
 
 

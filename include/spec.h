@@ -259,6 +259,13 @@ spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double*
                               uint64_t seed, const spec_walk_params* p, double* x_out, double* samples,
                               spec_walk_stats* stats, void* stream);
 
+/* spec_walk_run_dev on HOST arrays (x0, x_out: chains x n; samples nullable:
+ * chains x (steps/thin) x n), synchronous: the walk runs on the handle's
+ * stream-less default queue and the outputs are copied back before return.
+ * p->log_buf must be NULL (segment logs are device-side only). */
+spec_status spec_walk_run(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
+                          const spec_walk_params* p, double* x_out, double* samples, spec_walk_stats* stats);
+
 /* Save (restore = 0) or restore (restore = 1) the state of the chains of the
  * handle's last walk (points, step starts, directions, remaining lengths,
  * reflection and step counters, per-chain statistics) in device memory the
@@ -414,6 +421,12 @@ spec_status spec_mlp_adam_dev(spec_mlp net, const float* grad, double lr, void* 
 spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const double* v, const double* t_minus,
                                const double* t_plus, const spec_mlp_train_params* p, spec_mlp_train_stats* st,
                                void* stream);
+/* spec_mlp_train_dev on HOST arrays (x, v: rows x n; t_minus, t_plus: rows),
+ * e.g. triples saved from earlier walks; the rows are copied to the device
+ * for the call.  Synchronises. */
+spec_status spec_mlp_train(spec_mlp net, int rows, const double* x, const double* v, const double* t_minus,
+                           const double* t_plus, const spec_mlp_train_params* p, spec_mlp_train_stats* st);
+
 /* Predictions log t+_hat and log(-t-_hat) (rows each, FP64, device) of the
  * trained (standardised) network. */
 spec_status spec_mlp_predict_dev(spec_mlp net, int rows, const double* x, const double* v, double* log_tp,

@@ -194,6 +194,7 @@ spec_status reflect_tail(spec_s* h, int batch, const double* v, const double* tp
     r.wn = h->dWn;
     r.ldwn = h->Nn;
     r.lam = h->dLam;
+    r.flags = h->dFlags;
     r.status = st;
     r.s_out = s_out;
     r.w_out = w_out;
@@ -573,6 +574,36 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
                         double* x_out, spec_walk_stats* stats, hipStream_t s);
 
 }  // namespace
+
+spec_status spec_walk_run(spec_handle h, int kind, int chains, const double* x0, long long steps, uint64_t seed,
+                          const spec_walk_params* p, double* x_out, double* samples, spec_walk_stats* stats) {
+    if (!h || !p || chains < 0 || steps < 0 || (chains && (!x0 || !x_out)) || p->log_buf) return SPEC_EINVAL;
+    if (chains == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return SPEC_OK;
+    }
+    const size_t cn = (size_t)chains * h->n;
+    const long long ns = p->thin > 0 ? steps / p->thin : 0;
+    double *dx0 = nullptr, *dxo = nullptr, *dsm = nullptr;
+    spec_status rc = SPEC_OK;
+    hipError_t e = dalloc(&dx0, cn, false);
+    if (e == hipSuccess) e = dalloc(&dxo, cn, false);
+    if (e == hipSuccess && samples && ns > 0) e = dalloc(&dsm, cn * (size_t)ns, false);
+    if (e == hipSuccess) e = hipMemcpy(dx0, x0, sizeof(double) * cn, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = from_hip(e);
+    if (rc == SPEC_OK) rc = spec_walk_run_dev(h, kind, chains, dx0, steps, seed, p, dxo, dsm, stats, nullptr);
+    if (rc == SPEC_OK) {
+        e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(x_out, dxo, sizeof(double) * cn, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && dsm)
+            e = hipMemcpy(samples, dsm, sizeof(double) * cn * (size_t)ns, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = from_hip(e);
+    }
+    dfree(dx0);
+    dfree(dxo);
+    dfree(dsm);
+    return rc;
+}
 
 spec_status spec_walk_state(spec_handle h, int restore) {
     if (!h || restore < 0 || restore > 1 || h->wcap == 0) return SPEC_EINVAL;

@@ -1767,16 +1767,23 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     if (prof && t == 0) prof[i] = clock64();
     STAMP(0)
 
-    // ---- diagonal rows: ratio test from x
+    // ---- diagonal rows: ratio test from x (ties of the smallest root flagged:
+    // bit 1 of `bad`, which carries the not-interior test in bit 0)
     double dtp = INFINITY, dtm = -INFINITY;
     int dj = -1, bad = 0;
     for (int j = t; j < md; j += blockDim.x) {
         const double f = Fr[P + j], b = a.membership_only ? 0.0 : Br[P + j];
-        if (!(f > 0.0)) bad = 1;
+        if (!(f > 0.0)) bad |= 1;
         const double r = b / f;
         if (r < 0.0) {
             const double tt = -1.0 / r;
-            if (tt < dtp) { dtp = tt; dj = j; }
+            if (tt < dtp) {
+                dtp = tt;
+                dj = j;
+                bad &= 1;
+            } else if (tt == dtp) {
+                bad |= 2;
+            }
         } else if (r > 0.0) {
             dtm = fmax(dtm, -1.0 / r);
         }
@@ -1784,19 +1791,40 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     for (int o = 32; o > 0; o >>= 1) {
         const double otp = __shfl_xor(dtp, o, 64);
         const int oj = __shfl_xor(dj, o, 64);
-        if (otp < dtp || (otp == dtp && oj >= 0 && (dj < 0 || oj < dj))) { dtp = otp; dj = oj; }
+        const int ob = __shfl_xor(bad, o, 64);
+        const int nb = (bad | ob) & 1;
+        if (otp < dtp) {
+            dtp = otp;
+            dj = oj;
+            bad = nb | (ob & 2);
+        } else if (otp == dtp && oj >= 0 && dj >= 0) {
+            if (oj < dj) dj = oj;
+            bad = nb | 2;
+        } else {
+            bad = nb | (bad & 2);
+        }
         dtm = fmax(dtm, __shfl_xor(dtm, o, 64));
-        bad |= __shfl_xor(bad, o, 64);
     }
     if (lane == 0) { rtp[wv] = dtp; rtm[wv] = dtm; rj[wv] = dj; rbad[wv] = bad; }
     lds_barrier();
     dtp = INFINITY; dtm = -INFINITY; dj = -1; bad = 0;
     for (int w = 0; w < nw; ++w) {
-        if (rtp[w] < dtp || (rtp[w] == dtp && rj[w] >= 0 && (dj < 0 || rj[w] < dj))) { dtp = rtp[w]; dj = rj[w]; }
+        const int wb = rbad[w];
+        if (rtp[w] < dtp) {
+            dtp = rtp[w];
+            dj = rj[w];
+            bad = (bad & 1) | wb;
+        } else if (rtp[w] == dtp && rj[w] >= 0 && dj >= 0) {
+            if (rj[w] < dj) dj = rj[w];
+            bad = (bad | wb) | 2;
+        } else {
+            bad |= wb & 1;
+        }
         dtm = fmax(dtm, rtm[w]);
-        bad |= rbad[w];
     }
     lds_barrier();
+    const bool dtie = (bad & 2) != 0;
+    bad &= 1;
     double tp = dtp, tm = dtm;
     int hit = dj >= 0 ? dj : HIT_NONE;
     double lmin = 0.0, lmax = 0.0;
@@ -1963,7 +1991,10 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             if (!conv) st = SPEC_NOCONV;
             else if (isinf(tp) || isinf(tm)) st = SPEC_UNBOUNDED;
         }
-        if (REFINE && a.flags) flags |= a.flags[chain] & ~SPEC_FLAG_REFINE_FAILED;
+        // t+ attained by two pieces of the boundary: two diagonal rows, or a
+        // diagonal row and the dense block (exact ties, as the oracle's)
+        if (isfinite(tp) && ((hit >= 0 && dtie) || (hit == HIT_DENSE && tp == dtp))) flags |= SPEC_FLAG_TIE;
+        if (REFINE && a.flags) flags |= a.flags[chain] & ~(SPEC_FLAG_REFINE_FAILED | SPEC_FLAG_TIE);
         if (REFINE && (flags & SPEC_FLAG_CERT_FALLBACK)) cert = 1;  // from the first pass
         if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;  // informational: values are final
         if (a.flags) a.flags[chain] = flags | (cert == 1 ? SPEC_FLAG_CERT_FALLBACK : 0);

@@ -346,6 +346,29 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
     return SPEC_OK;
 }
 
+spec_status spec_mlp_train(spec_mlp net, int rows, const double* x, const double* v, const double* t_minus,
+                           const double* t_plus, const spec_mlp_train_params* p, spec_mlp_train_stats* st) {
+    if (!net || !p || rows < 2 || !x || !v || !t_minus || !t_plus) return SPEC_EINVAL;
+    const size_t rn = (size_t)rows * net->n;
+    double *dx = nullptr, *dv = nullptr, *dm = nullptr, *dp = nullptr;
+    spec_status rc = SPEC_OK;
+    hipError_t e = dalloc(&dx, rn, false);
+    if (e == hipSuccess) e = dalloc(&dv, rn, false);
+    if (e == hipSuccess) e = dalloc(&dm, (size_t)rows, false);
+    if (e == hipSuccess) e = dalloc(&dp, (size_t)rows, false);
+    if (e == hipSuccess) e = hipMemcpy(dx, x, sizeof(double) * rn, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv, v, sizeof(double) * rn, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dm, t_minus, sizeof(double) * rows, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dp, t_plus, sizeof(double) * rows, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = from_hip(e);
+    if (rc == SPEC_OK) rc = spec_mlp_train_dev(net, rows, dx, dv, dm, dp, p, st, nullptr);
+    dfree(dx);
+    dfree(dv);
+    dfree(dm);
+    dfree(dp);
+    return rc;
+}
+
 spec_status spec_mlp_predict_dev(spec_mlp net, int rows, const double* x, const double* v, double* log_tp,
                                  double* log_neg_tm, void* stream) {
     if (!net || rows < 0 || (rows && (!x || !v))) return SPEC_EINVAL;

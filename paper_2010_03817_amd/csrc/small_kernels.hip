@@ -102,6 +102,9 @@ __global__ __launch_bounds__(256) void k_reflect_finish(ReflectArgs a) {
         if (lane == 0 && st == SPEC_OK) a.status[c] = SPEC_NONSMOOTH;
         return;
     }
+    // two pieces of the boundary meet at the hit: the normal of the one that
+    // was found is used, and the status says so
+    if (a.flags && (a.flags[c] & SPEC_FLAG_TIE) && lane == 0 && st == SPEC_OK) a.status[c] = SPEC_NONSMOOTH;
     const double inv = 1.0 / sqrt(nn);
     const double sgn = vw < 0.0 ? -1.0 : 1.0;
     const double dvw = fabs(vw) * inv;  // <v, w_hat> with w_hat outward

@@ -13,8 +13,10 @@ enum : int { HIT_DENSE = -1, HIT_NONE = -3 };
 // Per-call bits of the line oracle: the learned bracket was not certified
 // (plain origin used), a far root was refined from a shifted origin, a
 // refining factor did not exist (the run from 0 was repeated at the full
-// tolerance).
-enum : int { SPEC_FLAG_CERT_FALLBACK = 1, SPEC_FLAG_REFINED = 4, SPEC_FLAG_REFINE_FAILED = 8 };
+// tolerance), t+ is attained by two pieces of the boundary at once (two
+// diagonal rows, or a diagonal row and the dense block, with equal roots: the
+// normal is not determined there).
+enum : int { SPEC_FLAG_CERT_FALLBACK = 1, SPEC_FLAG_REFINED = 4, SPEC_FLAG_REFINE_FAILED = 8, SPEC_FLAG_TIE = 16 };
 
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                     double* C, int ldc, hipStream_t s);
@@ -38,6 +40,7 @@ struct ReflectArgs {
     const double* wn;    // normal GEMM output (batch x ldwn)
     int ldwn;
     const double* lam;   // lambda_min, lambda_max, lambda_2 per chain (nullable)
+    const int32_t* flags;  // nullable: SPEC_FLAG_* bits of the line oracle call
     int32_t* status;
     double* s_out;       // reflected direction
     double* w_out;       // unit outward normal (nullable)

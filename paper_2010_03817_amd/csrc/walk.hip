@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
     }
     const int nref = S.nref[c] + 1;
     if (lane == 0) {
-        if (!(nn > 0.0) || status == SPEC_NONSMOOTH) st[4] += 1.0;
+        if (!(nn > 0.0) || status == SPEC_NONSMOOTH || (a.flags && (a.flags[c] & SPEC_FLAG_TIE))) st[4] += 1.0;
         st[1] += 1.0;
         S.ell[c] = ell - tp;
         S.nref[c] = nref;

@@ -125,6 +125,8 @@ def lib():
     L.spec_reflect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp]
     L.spec_walk_run_dev.argtypes = [vp, C.c_int, C.c_int, vp, C.c_longlong, C.c_uint64, C.POINTER(WalkParams), vp,
                                     vp, C.POINTER(WalkStats), vp]
+    L.spec_walk_run.argtypes = [vp, C.c_int, C.c_int, vp, C.c_longlong, C.c_uint64, C.POINTER(WalkParams), vp,
+                                vp, C.POINTER(WalkStats)]
     L.spec_diag_timing.argtypes = [vp, C.c_int]
     L.spec_diag_phase_profile.argtypes = [vp, C.c_int]
     L.spec_diag_phase_stamps.argtypes = [vp, C.c_int, vp]
@@ -146,6 +148,7 @@ def lib():
     L.spec_mlp_adam_dev.argtypes = [vp, vp, C.c_double, vp]
     L.spec_mlp_train_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.POINTER(MlpTrainParams),
                                      C.POINTER(MlpTrainStats), vp]
+    L.spec_mlp_train.argtypes = [vp, C.c_int, vp, vp, vp, vp, C.POINTER(MlpTrainParams), C.POINTER(MlpTrainStats)]
     L.spec_mlp_predict_dev.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     L.spec_set_mlp.argtypes = [vp, vp, C.c_double, C.c_int]
     L.spec_batch_create.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp)]
@@ -340,6 +343,20 @@ class Spectrahedron:
             log = log[:k]
         return x_out, samples, st.as_dict(), log
 
+    def walk_host(self, kind, x0, steps, seed, tau=1.0, rho=0, gauss_a=0.0, pullback=1e-6, thin=0,
+                  max_rounds=0):
+        """spec_walk_run on host arrays: (x_out, samples or None, stats)."""
+        x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1, self.n)
+        ch = x0.shape[0]
+        x_out = np.empty_like(x0)
+        ns = steps // thin if thin > 0 else 0
+        samples = np.empty((ch, ns, self.n)) if ns > 0 else None
+        p = WalkParams(tau=tau, rho=rho, gauss_a=gauss_a, pullback=pullback, thin=thin, max_rounds=max_rounds)
+        st = WalkStats()
+        check(lib().spec_walk_run(self._h, kind, ch, x0.ctypes.data, steps, seed, C.byref(p), x_out.ctypes.data,
+                                  samples.ctypes.data if samples is not None else None, C.byref(st)))
+        return x_out, samples, st.as_dict()
+
     def save_walk_state(self):
         check(lib().spec_walk_state(self._h, 0))
 
@@ -529,6 +546,18 @@ class Mlp:
         st = MlpTrainStats()
         check(lib().spec_mlp_train_dev(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), C.byref(p),
                                        C.byref(st), _stream()))
+        self.train_stats = st.as_dict()
+        return self.train_stats
+
+    def train_host(self, x, v, t_minus, t_plus, epochs=20, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=0.1,
+                   quantile=0.999, seed=7):
+        """spec_mlp_train on host (numpy) triples."""
+        a = [np.ascontiguousarray(t, dtype=np.float64) for t in (x, v, t_minus, t_plus)]
+        p = MlpTrainParams(epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, val_frac=val_frac,
+                           quantile=quantile, seed=seed)
+        st = MlpTrainStats()
+        check(lib().spec_mlp_train(self._h, a[2].shape[0], a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data,
+                                   a[3].ctypes.data, C.byref(p), C.byref(st)))
         self.train_stats = st.as_dict()
         return self.train_stats
 

@@ -33,6 +33,18 @@ def test_status_strings_and_argument_errors():
     assert L.spec_create(1, 1, one, bad, A, C.byref(h)) == S.EINVAL
     assert L.spec_destroy(None) == S.EINVAL
     assert L.spec_intersect(None, 1, None, None, None, None, None) == S.EINVAL
+    # host walk and host training: NULL handle / arrays are argument errors
+    p = S.WalkParams(tau=1.0)
+    st = S.WalkStats()
+    assert L.spec_walk_run(None, S.BILLIARD, 4, None, 10, 1, C.byref(p), None, None, C.byref(st)) == S.EINVAL
+    tp = S.MlpTrainParams()
+    ts = S.MlpTrainStats()
+    assert L.spec_mlp_train(None, 10, None, None, None, None, C.byref(tp), C.byref(ts)) == S.EINVAL
+    o = S.Options()
+    assert L.spec_options_default(C.byref(o)) == S.OK
+    assert o.kmax == 80 and o.tol == 1e-8 and o.refine_ratio == 1e3 and o.tol_loose == 1e-3
+    assert L.spec_set_options(None, C.byref(o)) == S.EINVAL
+    assert L.spec_walk_state(None, 0) == S.EINVAL
 
 
 def test_non_symmetric_block_rejected():

@@ -243,3 +243,32 @@ def test_paper_generator_intersect_and_reflect():
         assert np.allclose(tp, tp_r, rtol=T_REL, atol=0)
         assert np.allclose(w, w_r, atol=1e-7 * max(1.0, np.abs(w_r).max()))
         assert np.allclose(s, s_r, atol=2e-7)
+
+
+def test_nonsmooth_statuses_match_oracle():
+    """NONSMOOTH where two pieces of the boundary meet at the hit, as the
+    oracle: a vertex of a box (two diagonal rows tie), and a dense block whose
+    root equals a diagonal row's; generic hits stay OK.  (A multiple
+    lambda_min inside the one merged dense block is not visible to a
+    single-vector Krylov method, which sees one copy of each eigenvalue.)"""
+    S = _spec()
+    cases = []
+    box = I.box(2, 1.0)
+    cases.append((box, np.zeros((2, 2)), np.array([[1.0, 1.0], [1.0, 0.3]]) / np.array([[math.sqrt(2)], [1.0]])))
+    # dense [[1 - x1]] and the diagonal row 1 - x1, plus a second coordinate
+    A = np.zeros((3, 1, 1))
+    A[0] = 1.0
+    A[1] = -1.0
+    D = np.zeros((3, 4))
+    D[0] = [1.0, 3.0, 2.0, 2.0]
+    D[1] = [-1.0, 1.0, 0.0, 0.0]
+    D[2] = [0.0, 0.0, 1.0, -1.0]
+    mixed = I.Instance(2, [I.Block(I.DENSE, A), I.Block(I.DIAG, D)], name="dense-diag-tie")
+    cases.append((mixed, np.zeros((2, 2)), np.array([[1.0, 0.5], [-1.0, 0.3]])))
+    for inst, x, v in cases:
+        g, o = S.Spectrahedron(inst), O.Oracle(inst)
+        tp, s, w, st = [_np(a) for a in g.reflect(x, v)]
+        tp_r, s_r, w_r, st_r = o.reflect(x, v)
+        assert np.array_equal(st, st_r), (inst.name, st, st_r)
+        assert st[0] == S.NONSMOOTH and st[1] == S.OK
+        assert np.allclose(tp, tp_r, rtol=1e-15)

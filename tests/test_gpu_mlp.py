@@ -280,3 +280,18 @@ def test_learned_billiard_walk_logged_pairs(S):
     rel = np.abs(ltp - otp) / otp
     print(f"learned walk: max rel {rel.max():.2e}, fallbacks {stats['cert_fallback']:.0f} of {stats['calls']:.0f}")
     assert rel.max() <= 1e-9
+
+
+def test_host_training_matches_device_training(S):
+    """spec_mlp_train (host triples) trains the same network as
+    spec_mlp_train_dev on the same rows, seed and initial parameters."""
+    inst = I.gbase(10, 10, seed=101, scale=math.sqrt(10))
+    g = S.Spectrahedron(inst)
+    x, v, tm, tp, _, _ = _training_triples(S, g, inst, chains=32, rounds=40)
+    a = S.Mlp(inst.n, width=32, hidden=2, bf16=False, seed=4)
+    b = S.Mlp(inst.n, width=32, hidden=2, bf16=False, seed=4)
+    sa = a.train(x, v, tm, tp, epochs=3, batch=256, seed=9)
+    sb = b.train_host(x, v, tm, tp, epochs=3, batch=256, seed=9)
+    assert sa["steps"] == sb["steps"] and sa["val_rows"] == sb["val_rows"]
+    pa, pb = a.get_params(), b.get_params()
+    assert np.allclose(pa, pb, rtol=1e-5, atol=1e-6)

@@ -143,3 +143,16 @@ def test_config1_coordinate_means_match_oracle(kind):
     # a step can land outside S only when t+ is off by more than the 1e-6
     # pull-back
     assert st["not_interior"] == 0
+
+
+def test_host_walk_matches_device_walk():
+    """spec_walk_run (host arrays) runs the same chains as spec_walk_run_dev."""
+    S = _S()
+    inst = config1()
+    g = S.Spectrahedron(inst)
+    x0 = np.zeros((32, 10))
+    for kind in (S.HNR, S.BILLIARD):
+        xh, sh, sth = g.walk_host(kind, x0, 6, seed=55, tau=1.0, thin=2)
+        xd, sd, std, _ = g.walk(kind, x0, 6, seed=55, tau=1.0, thin=2)
+        assert np.array_equal(xh, _np(xd)) and np.array_equal(sh, _np(sd))
+        assert sth == std

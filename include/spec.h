@@ -106,6 +106,13 @@ spec_status spec_destroy(spec_handle h);
  *                F(x) replaced by F(x + t0 v)).  Default 1e3; 0 disables.
  *  tol_loose     tolerance of the run from x on such a side: its value only
  *                places the origin of the refining run (default 1e-3).
+ *  certify       1: after the oracle passes, every dense t+ of spec_intersect,
+ *                spec_reflect and the line walks is checked by two Cholesky
+ *                membership tests, F(x + t v) positive definite at
+ *                t = t+ (1 - 1e-9) and not at t+ (1 + 1e-9) (two more
+ *                factorisations per call); failures are flagged and counted.
+ *                0 (default): the Kato-Temple interval of spec_certificates
+ *                only.  Not applied to the uneven batch.
  * When the factor does not exist at t0 (t1 was too far out) the origin backs
  * off to t1 (1 - 2^-5) and then t1 / 2; only if those fail too is the plain
  * solve repeated at the full tolerance (counted as refine_failed in
@@ -116,6 +123,7 @@ typedef struct {
     double tol;
     double refine_ratio;
     double tol_loose;
+    int certify;
 } spec_options;
 
 spec_status spec_options_default(spec_options* opt);
@@ -165,6 +173,23 @@ spec_status spec_intersect(spec_handle h, int batch, const double* x, const doub
                            double* t_minus, double* t_plus, int32_t* status);
 spec_status spec_intersect_dev(spec_handle h, int batch, const double* x, const double* v,
                                double* t_minus, double* t_plus, int32_t* status, void* stream);
+
+/* Certified interval [t_lo, t_hi] of t+ for each element of the last
+ * spec_intersect / spec_reflect call (and the last round of a walk) on this
+ * handle, host arrays of `batch`.  A diagonal row's root is a ratio, exact up
+ * to rounding: t_lo = t_hi = t+.  For the dense block, the run that fixes t+
+ * from the origin t0 (0, the learned lower end or the refining origin) gives
+ * the Ritz value theta >= lambda_min of C and its residual bound r; with the
+ * second Ritz value bounded below by multisection on T_k, theta_2, the
+ * Kato-Temple inequality places lambda_min in [theta - r^2 / (theta_2 -
+ * theta), theta] (r enlarged by 8 eps times the spectral radius estimate for
+ * the rounding of C), so t+ = t0 - 1/lambda_min lies in [t_lo, t_hi] with
+ * t_hi the returned t+.  The interval is a posteriori: the gap uses the second
+ * Ritz value, which bounds lambda_2 from above.  Elements whose interval is
+ * wider than 2e-9 t+ are counted as uncertified (spec_walk_stats) and carry
+ * bit 32 in spec_diag_call_flags; NaN when there is none (no dense hit was
+ * computed, or a status other than OK / NONSMOOTH / CERT_FALLBACK). */
+spec_status spec_certificates(spec_handle h, int batch, double* t_lo, double* t_hi);
 
 /* REFLECTION (Alg. REFLECTION, eq. (reflection)) for lines: t_plus as above,
  * s_out = v - 2 <v, w> w the reflected direction at x + t+ v, w_out (nullable)
@@ -241,6 +266,8 @@ typedef struct {
 typedef struct {
     double calls, reflections, cap_hits, not_interior, nonsmooth, steps, noconv, rounds, cert_fallback;
     double refined, refine_failed;
+    double uncertified;  /* calls whose t+ interval (spec_certificates) is wider than 2e-9 t+ */
+    double chol_cert_failed;  /* calls whose two-sided Cholesky certificate failed (spec_options.certify) */
 } spec_walk_stats;
 
 /* Run `chains` independent chains of the walk `kind` from x0 (chains x n,

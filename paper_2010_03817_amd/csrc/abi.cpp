@@ -78,6 +78,7 @@ FusedArgs fused_args(spec_s* h, int bp, int32_t* st, double* tm, double* tp, boo
     a.rshift = h->dRShift;
     a.inst_id = 0;
     a.flags = h->dFlags;
+    a.cert = h->dCert;
     return a;
 }
 
@@ -88,9 +89,11 @@ FusedArgs fused_args(spec_s* h, int bp, int32_t* st, double* tm, double* tp, boo
 // host synchronisation (the sequence can be captured in a graph).
 spec_status run_fused(spec_s* h, FusedArgs a, int batch, hipStream_t s) {
     const bool refine = a.rlist && a.refine_ratio > 0.0 && !a.membership_only && h->m > 0;
+    const bool certify = h->certify && !a.membership_only && h->m > 0;
     if (!refine) {
         a.rlist = nullptr;
         HIPCHK(launch_line_fused(a, batch, s));
+        if (certify) HIPCHK(launch_line_certify(a, batch, s));
         return SPEC_OK;
     }
     HIPCHK(launch_zero_ints(h->dRCnt, 2, s));
@@ -103,6 +106,7 @@ spec_status run_fused(spec_s* h, FusedArgs a, int batch, hipStream_t s) {
     if (h->refine_bpc == 0) h->refine_bpc = line_refine_blocks_per_cu(h->m, h->kmax);
     const int nb = std::min(batch, h->refine_bpc * h->cus);
     HIPCHK(launch_line_refine(r, nullptr, h->dRList, h->dRCnt, h->dRCnt + 1, h->m, h->kmax, nb, s));
+    if (certify) HIPCHK(launch_line_certify(a, batch, s));
     return SPEC_OK;
 }
 
@@ -416,6 +420,7 @@ spec_status spec_options_default(spec_options* o) {
     o->tol = 1e-8;
     o->refine_ratio = 1e3;
     o->tol_loose = 1e-3;
+    o->certify = 0;
     return SPEC_OK;
 }
 
@@ -426,6 +431,7 @@ spec_status spec_get_options(spec_handle h, spec_options* o) {
     o->tol = h->tol;
     o->refine_ratio = h->refine_ratio;
     o->tol_loose = h->tol_loose;
+    o->certify = h->certify;
     return SPEC_OK;
 }
 
@@ -434,10 +440,12 @@ spec_status spec_set_options(spec_handle h, const spec_options* o) {
     if (!(o->refine_ratio >= 0.0) || !std::isfinite(o->refine_ratio)) return SPEC_EINVAL;
     if (!(o->tol_loose > 0.0 && o->tol_loose < 1.0)) return SPEC_EINVAL;
     if (o->precision < SPEC_PREC_FP64 || o->precision > SPEC_PREC_BF16X2_ASM) return SPEC_EINVAL;
+    if (o->certify < 0 || o->certify > 1) return SPEC_EINVAL;
     if (o->kmax != h->kmax || o->tol != h->tol) SPCHK(spec_set_lanczos(h, o->kmax, o->tol));
     SPCHK(spec_set_precision(h, o->precision));
     h->refine_ratio = o->refine_ratio;
     h->tol_loose = o->tol_loose;
+    h->certify = o->certify;
     return SPEC_OK;
 }
 
@@ -776,6 +784,8 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
         stats->cert_fallback = tot[7];
         stats->refined = tot[8];
         stats->refine_failed = tot[9];
+        stats->uncertified = tot[10];
+        stats->chol_cert_failed = tot[11];
     }
     return SPEC_OK;
 }
@@ -1351,6 +1361,19 @@ spec_status spec_diag_stage_times(spec_handle h, double* out, double* lanczos_st
 spec_status spec_diag_lanczos_info(spec_handle h, int batch, double* lam_out) {
     if (!h || !lam_out || batch < 0 || batch > h->cap) return SPEC_EINVAL;
     HIPCHK(hipMemcpy(lam_out, h->dLam, sizeof(double) * 4 * batch, hipMemcpyDeviceToHost));
+    return SPEC_OK;
+}
+
+spec_status spec_certificates(spec_handle h, int batch, double* t_lo, double* t_hi) {
+    if (!h || !t_lo || !t_hi || batch < 0 || batch > h->cap) return SPEC_EINVAL;
+    if (batch == 0) return SPEC_OK;
+    std::vector<double> buf((size_t)2 * batch);
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(buf.data(), h->dCert, sizeof(double) * 2 * batch, hipMemcpyDeviceToHost));
+    for (int e = 0; e < batch; ++e) {
+        t_lo[e] = buf[2 * e];
+        t_hi[e] = buf[2 * e + 1];
+    }
     return SPEC_OK;
 }
 

@@ -27,6 +27,7 @@ struct spec_s {
     double tol = 1e-8;
     // refinement of far roots from a shifted origin (spec_options)
     double refine_ratio = 1e3, tol_loose = 1e-3;
+    int certify = 0;  // 1: two-sided Cholesky certificate of every dense t+ (spec_options)
     // workspace (capacity in chains, multiple of 64); work_gen changes whenever
     // it is (re)allocated, so that cached device pointers can be revalidated
     int cap = 0;
@@ -35,6 +36,7 @@ struct spec_s {
     float* dZ32 = nullptr;
     double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
     int32_t *dHit = nullptr, *dSt = nullptr, *dFlags = nullptr;
+    double* dCert = nullptr;  // certified interval of t+ per chain (2 doubles)
     // far-root refinement queue: items, origins, counters (queued, taken)
     int2* dRList = nullptr;
     double* dRShift = nullptr;
@@ -71,7 +73,7 @@ struct spec_s {
     void free_work() {
         dfree(dZ); dfree(dZ32); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt); dfree(dFlags);
-        dfree(dRList); dfree(dRShift); dfree(dRCnt);
+        dfree(dRList); dfree(dRShift); dfree(dRCnt); dfree(dCert);
         dfree(dShift); dfree(dShiftHi); dfree(dPred); dfree(dHz);
         cap = 0;
         ++work_gen;
@@ -127,6 +129,7 @@ struct spec_s {
         HIPCHK(dalloc(&dRList, (size_t)c, false));
         HIPCHK(dalloc(&dRShift, (size_t)c));
         HIPCHK(dalloc(&dRCnt, (size_t)2));
+        HIPCHK(dalloc(&dCert, (size_t)2 * c));
         HIPCHK(dalloc(&dShift, (size_t)c));
         HIPCHK(dalloc(&dShiftHi, (size_t)c));
         HIPCHK(dalloc(&dPred, (size_t)c));

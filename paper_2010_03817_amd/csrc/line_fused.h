@@ -41,6 +41,7 @@ struct FusedArgs {
     double* rshift;
     int inst_id;
     int32_t* flags;            // nullable: per chain SPEC_FLAG_* bits
+    double* cert;              // nullable: per chain the certified interval of t+ (2 doubles)
 };
 
 // Degree-2 curve oracle: first root of det Q(t), Q(t) = Q0 + t Q1 + t^2 Q2,
@@ -85,6 +86,10 @@ hipError_t launch_line_refine(const FusedArgs& one, const FusedArgs* args, const
 int line_refine_blocks_per_cu(int max_m, int kmax);
 // p[0 .. count) = 0 by a kernel (no memset node in a captured graph); count <= 64.
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
+
+// Two-sided Cholesky certificate of the dense t+ of each chain after the
+// oracle passes (sets SPEC_FLAG_CHOL_CERT_FAILED on failure).
+hipError_t launch_line_certify(const FusedArgs& a, int nblocks, hipStream_t s);
 
 size_t fused_lds_bytes(int m, int kmax);
 int fused_threads(int m);

@@ -1292,6 +1292,34 @@ struct LzCtx {
     long long* prof;   // nullable: per-part cycles of the steering wave (slots 8..13), tests and passes (16, 17)
 };
 
+// A lower bound of the second smallest eigenvalue of T_k (al, be in LDS) for
+// the Kato-Temple interval: multisection over [th, Gershgorin top] for the
+// first point with two eigenvalues of T_k below it; returns the last point
+// with fewer (the second Ritz value lies above it).  One wave, every lane
+// with the same arguments; 4 passes of 64 points.
+__device__ inline double second_ritz_lower(const double* al, const double* be, int k, double th, int lane) {
+    double ghi = -INFINITY;
+    for (int i = lane; i < k; i += 64) {
+        const double rad = (i ? fabs(be[i]) : 0.0) + (i + 1 < k ? fabs(be[i + 1]) : 0.0);
+        ghi = fmax(ghi, al[i] + rad);
+    }
+    ghi = wave_ext_dpp<true>(ghi);
+    double lo = th, hi = ghi + 1e-14 * fabs(ghi) + 1e-300;
+    if (!(hi > lo) || sturm_lds(al, be, k, lo) >= 2) return lo;
+#pragma nounroll
+    for (int it = 0; it < 4; ++it) {
+        const double w = hi - lo;
+        const double x = lo + w * ((double)(lane + 1) * (1.0 / 65.0));
+        const unsigned long long mask = __ballot(sturm_lds(al, be, k, x) >= 2);
+        const int first = mask ? __ffsll((long long)mask) - 1 : 64;
+        const double nlo = lo + w * ((double)first * (1.0 / 65.0));
+        const double nhi = first < 64 ? lo + w * ((double)(first + 1) * (1.0 / 65.0)) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
 // Extreme eigenvalue(s) of C by Lanczos (lambda_min only when min_only),
 // restarted from the Ritz vector after kmax steps, NCYCLES cycles at most.
 // Every thread of the block calls it.  Results in sres (LDS): theta_min,
@@ -1761,6 +1789,9 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     }
     const int side = t0 < 0.0 ? 2 : 1;  // REFINE: the root refined from t0
     int flags = 0;
+    // Kato-Temple interval of the dense t+ (wave 0, lane 0 keeps it)
+    bool kt_set = false;
+    double kt_lo = NAN, kt_hi = NAN;
     int32_t st = SPEC_OK;
     long long* prof = a.prof ? a.prof + (size_t)chain * SPEC_DIAG_PHASE_SLOTS : nullptr;
 #define STAMP(i) \
@@ -1972,9 +2003,28 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
                     hit = HIT_DENSE;
                 }
             }
+            // a posteriori interval of the dense t+ from the run that fixes it
+            // (Kato-Temple): lambda_min lies in [theta - d, theta] with
+            // d = r^2 / (theta_2 - theta), r the residual bound plus the
+            // rounding level 8 eps rho, theta_2 bounded below by multisection on
+            // T_k; t+ = t0 - 1/lambda then lies in [t0 - 1/(theta - d), t0 - 1/theta]
+            const bool fixes_tp = rside != 1 && !(shifted && side == 2);
+            if (fixes_tp) {
+                kt_set = true;
+                if (wv == 0 && lmin < 0.0 && conv && k >= 3) {
+                    const double th2 = second_ritz_lower(lz.al, lz.be, k, lmin, lane);
+                    const double r = sres[1] + 8.0 * 2.220446049250313e-16 * sres[7];
+                    const double gap = th2 - lmin;
+                    if (gap > 0.0 && isfinite(r)) {
+                        const double d = r * r / gap;
+                        kt_lo = t0 - 1.0 / (lmin - d);
+                        kt_hi = t0 - 1.0 / lmin;
+                    }
+                }
+            }
             // the kernel vector of a t+ hit comes from the run that fixes t+
-            const bool need_vec = a.want_vec && rside != 1 && !(shifted && side == 2) && hit == HIT_DENSE &&
-                                  isfinite(tp) && (a.ell == nullptr || tp < a.ell[chain]);
+            const bool need_vec = a.want_vec && fixes_tp && hit == HIT_DENSE && isfinite(tp) &&
+                                  (a.ell == nullptr || tp < a.ell[chain]);
             if (need_vec)
                 ritz_u(L, scr, m, kmax, k, lmin, Qg, a.u + (size_t)chain * a.ldu, a.U2 + (size_t)chain * a.ldu2);
             if (rside) flags |= SPEC_FLAG_REFINED;
@@ -1994,7 +2044,24 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         // t+ attained by two pieces of the boundary: two diagonal rows, or a
         // diagonal row and the dense block (exact ties, as the oracle's)
         if (isfinite(tp) && ((hit >= 0 && dtie) || (hit == HIT_DENSE && tp == dtp))) flags |= SPEC_FLAG_TIE;
-        if (REFINE && a.flags) flags |= a.flags[chain] & ~(SPEC_FLAG_REFINE_FAILED | SPEC_FLAG_TIE);
+        // certified interval of t+: a diagonal row's ratio is exact; a dense
+        // hit carries the Kato-Temple interval, certified when it is within
+        // 2e-9 t+ (an uncertified value is still the Lanczos value)
+        if ((kt_set || (!REFINE && hit != HIT_DENSE)) && st != SPEC_NOT_INTERIOR && !a.membership_only) {
+            double lo = tp, hi = tp;
+            if (hit == HIT_DENSE) {
+                lo = kt_lo;
+                hi = kt_hi;
+                if (!(hi - lo <= 2e-9 * fabs(hi))) flags |= SPEC_FLAG_UNCERTIFIED;
+            }
+            if (a.cert) {
+                a.cert[2 * chain] = lo;
+                a.cert[2 * chain + 1] = hi;
+            }
+        }
+        const int keep = kt_set ? ~(SPEC_FLAG_REFINE_FAILED | SPEC_FLAG_TIE | SPEC_FLAG_UNCERTIFIED)
+                                : ~(SPEC_FLAG_REFINE_FAILED | SPEC_FLAG_TIE);
+        if (REFINE && a.flags) flags |= a.flags[chain] & keep;
         if (REFINE && (flags & SPEC_FLAG_CERT_FALLBACK)) cert = 1;  // from the first pass
         if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;  // informational: values are final
         if (a.flags) a.flags[chain] = flags | (cert == 1 ? SPEC_FLAG_CERT_FALLBACK : 0);
@@ -2062,6 +2129,41 @@ __global__ __launch_bounds__(512) void k_line_fused_multi(const FusedArgs* __res
         if (it >= nwork) break;
         const int2 w = work[it];
         line_fused_chain<false>(args[w.x], w.y, lds);
+    }
+}
+
+// Two-sided Cholesky certificate of a dense t+ (one workgroup per chain, the
+// thread and LDS shape of k_line_fused): F(x + t v) = F + t B must have a
+// factor at t = t+ (1 - 1e-9) and none at t+ (1 + 1e-9), which places the
+// boundary within 1e-9 t+ of the returned value up to the factorisations'
+// own rounding.  A failure sets SPEC_FLAG_CHOL_CERT_FAILED; values and
+// statuses are left as they are.
+__global__ __launch_bounds__(512) void k_line_certify(FusedArgs a) {
+    extern __shared__ double lds[];
+    const int chain = blockIdx.x;
+    const int m = a.m, P = a.P;
+    const int32_t st = a.status[chain];
+    const double tp = a.tp[chain];
+    if (!(st == SPEC_OK || st == SPEC_NONSMOOTH || st == SPEC_CERT_FALLBACK) || a.hit[chain] != HIT_DENSE ||
+        !isfinite(tp) || m == 0)
+        return;
+    double* L = lds;
+    double* scr = lds + P;
+    int* sflag = (int*)(scr + 256);
+    const double* Fr = a.FB + (size_t)chain * a.ldfb;
+    const double* Br = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
+    bool pass = true;
+    for (int s = 0; s < 2; ++s) {
+        const double tc = tp * (s == 0 ? 1.0 - 1e-9 : 1.0 + 1e-9);
+        fill_pencil(L, Fr, Br, tc, P, threadIdx.x, blockDim.x);
+        lds_barrier();
+        const bool ok = __builtin_amdgcn_readfirstlane((int)chol_blocked(L, m, scr, sflag)) != 0;
+        lds_barrier();
+        pass = pass && (s == 0 ? ok : !ok);
+    }
+    if (threadIdx.x == 0 && a.flags) {
+        if (pass) a.flags[chain] &= ~SPEC_FLAG_CHOL_CERT_FAILED;
+        else a.flags[chain] |= SPEC_FLAG_CHOL_CERT_FAILED;
     }
 }
 
@@ -2332,6 +2434,15 @@ hipError_t launch_line_refine(const FusedArgs& one, const FusedArgs* args, const
     else
         hipLaunchKernelGGL(k_line_refine<false>, dim3(nblocks), dim3(fused_threads(max_m)), lds, s, one, args, work,
                            nwork, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_certify(const FusedArgs& a, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    if (a.m > 2 * MAXH) return hipErrorInvalidValue;
+    const size_t lds = fused_lds_bytes(a.m, a.kmax);
+    if (lds > 163840) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_line_certify, dim3(nblocks), dim3(fused_threads(a.m)), lds, s, a);
     return hipGetLastError();
 }
 

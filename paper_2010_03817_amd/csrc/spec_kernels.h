@@ -16,7 +16,17 @@ enum : int { HIT_DENSE = -1, HIT_NONE = -3 };
 // tolerance), t+ is attained by two pieces of the boundary at once (two
 // diagonal rows, or a diagonal row and the dense block, with equal roots: the
 // normal is not determined there).
-enum : int { SPEC_FLAG_CERT_FALLBACK = 1, SPEC_FLAG_REFINED = 4, SPEC_FLAG_REFINE_FAILED = 8, SPEC_FLAG_TIE = 16 };
+// UNCERTIFIED: the a posteriori interval of a dense t+ is wider than 2e-9 t+
+// (or there is none); CHOL_CERT_FAILED: the optional Cholesky factor at the
+// interval's lower end did not exist.
+enum : int {
+    SPEC_FLAG_CERT_FALLBACK = 1,
+    SPEC_FLAG_REFINED = 4,
+    SPEC_FLAG_REFINE_FAILED = 8,
+    SPEC_FLAG_TIE = 16,
+    SPEC_FLAG_UNCERTIFIED = 32,
+    SPEC_FLAG_CHOL_CERT_FAILED = 64
+};
 
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                     double* C, int ldc, hipStream_t s);

@@ -304,6 +304,8 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
             const int f = a.flags[c];
             if (f & SPEC_FLAG_REFINED) st[8] += 1.0;
             if (f & SPEC_FLAG_REFINE_FAILED) st[9] += 1.0;
+            if (f & SPEC_FLAG_UNCERTIFIED) st[10] += 1.0;
+            if (f & SPEC_FLAG_CHOL_CERT_FAILED) st[11] += 1.0;
         }
     }
     if (status == SPEC_NOT_INTERIOR) {

@@ -6,8 +6,10 @@ namespace spec {
 
 // Per-chain statistics: oracle calls, reflections, cap hits, not-interior,
 // nonsmooth, completed steps, eigen non-convergence, learned-bracket fallbacks,
-// far roots refined from a shifted origin, refinements whose factor failed.
-constexpr int WALK_NSTAT = 10;
+// far roots refined from a shifted origin, refinements whose factor failed,
+// calls whose t+ interval was not certified to 2e-9, calls whose two-sided
+// Cholesky certificate failed.
+constexpr int WALK_NSTAT = 12;
 
 struct WalkState {
     double* x;        // chains x n: current point

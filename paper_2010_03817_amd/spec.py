@@ -37,7 +37,8 @@ class WalkParams(C.Structure):
 
 class WalkStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("calls", "reflections", "cap_hits", "not_interior", "nonsmooth", "steps",
-                                          "noconv", "rounds", "cert_fallback", "refined", "refine_failed")]
+                                          "noconv", "rounds", "cert_fallback", "refined", "refine_failed",
+                                          "uncertified", "chol_cert_failed")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -45,7 +46,7 @@ class WalkStats(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("kmax", C.c_int), ("tol", C.c_double), ("refine_ratio", C.c_double),
-                ("tol_loose", C.c_double)]
+                ("tol_loose", C.c_double), ("certify", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +110,7 @@ def lib():
     L.spec_status_str.restype = C.c_char_p
     L.spec_set_lanczos.argtypes = [vp, C.c_int, C.c_double]
     L.spec_walk_state.argtypes = [vp, C.c_int]
+    L.spec_certificates.argtypes = [vp, C.c_int, vp, vp]
     L.spec_options_default.argtypes = [C.POINTER(Options)]
     L.spec_create_ex.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.POINTER(Options), C.POINTER(vp)]
     L.spec_set_options.argtypes = [vp, C.POINTER(Options)]
@@ -414,6 +416,12 @@ class Spectrahedron:
                                             C.byref(best), _stream()))
         self._net = net
         return best.value, list(ms)
+
+    def certificates(self, batch):
+        """(t_lo, t_hi) certified interval of t+ of each element of the last call."""
+        lo, hi = np.empty(batch), np.empty(batch)
+        check(lib().spec_certificates(self._h, batch, lo.ctypes.data, hi.ctypes.data))
+        return lo, hi
 
     def call_flags(self, batch):
         """Per-element bits of the last call: 1 bracket not certified, 4 far root

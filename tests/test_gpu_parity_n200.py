@@ -133,6 +133,40 @@ def test_unrefined_plain_path_loses_accuracy_near_the_boundary(wl):
     assert r[~post].max() <= T_REL
 
 
+def check_certificates(name, g, tp, rtp, B):
+    """Every certified interval holds the oracle's t+ (up to the bisection's
+    rounding) and is at most 2e-9 t+ wide, with the returned value as its
+    upper end; most calls are certified."""
+    lo, hi = g.certificates(B)
+    fl = g.call_flags(B)
+    cert = (fl & 32) == 0
+    slack = 1e-13 * rtp
+    print(f"{name}: {int(cert.sum())} of {B} certified; widths up to {np.max((hi - lo)[cert] / hi[cert]):.1e}")
+    assert cert.mean() >= 0.9
+    assert np.all(lo[cert] <= rtp[cert] + slack[cert]) and np.all(rtp[cert] <= hi[cert] + slack[cert])
+    assert np.all(hi[cert] - lo[cert] <= 2e-9 * hi[cert])
+    assert np.array_equal(hi, tp)
+
+
+def test_plain_certificates(wl):
+    """Kato-Temple intervals of the plain path (refined from the shifted
+    origin near the boundary), and the optional two-sided Cholesky
+    certificate: F(x + t v) definite at t+ (1 - 1e-9), not at t+ (1 + 1e-9)."""
+    g = wl["g"]
+    B = len(wl["x"])
+    tp = g.reflect(wl["x"], wl["v"])[0].cpu().numpy()
+    check_certificates("plain reflect", g, tp, wl["rtp"], B)
+    g.set_options(certify=1)
+    try:
+        tp2 = g.reflect(wl["x"], wl["v"])[0].cpu().numpy()
+        fl = g.call_flags(B)
+    finally:
+        g.set_options(certify=0)
+    assert np.array_equal(tp, tp2)
+    print(f"two-sided Cholesky certificate failures: {int(np.sum(fl & 64 > 0))} of {B}")
+    assert np.sum(fl & 64 > 0) == 0
+
+
 def _train(S, g, tau, seed):
     """A network of the benchmark's shape trained on the walk's own segment
     starts (labels from the device oracle)."""
@@ -153,6 +187,7 @@ def test_learned_reflect_and_walk(wl):
         tp, s, w, st = g.reflect(wl["x"], wl["v"])
         cert = g.lanczos_info(len(wl["x"]))[:, 2]
         tp = tp.cpu().numpy()
+        check_certificates("learned reflect", g, tp, wl["rtp"], len(tp))
         r = rel(tp, wl["rtp"])
         report("learned reflect", r, wl["kappa"])
         print(f"  certificate fallbacks {int((cert == 1).sum())} of {len(tp)}")

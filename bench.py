@@ -199,18 +199,16 @@ def roofline(run, chains, extra_chol=0.0):
 
 
 def summary(run, chains, calls_per_step=None):
-    """Rates of a timed run.  Billiard steps per second is the long-run rate
-    calls/s / (oracle calls per completed step), with calls per step taken
-    from a long walk of the same chains when given (a short window holds about
-    one heavy-tailed step per chain); the window's own count is kept beside it."""
+    """Rates of a timed run.  Billiard steps per second are the steps the
+    chains completed inside the timed rounds per second (the chains are
+    state_rounds rounds old, several steps each, so step ends are no longer
+    in phase); calls per completed step of the same window beside them."""
     st, wall = run["stats"], run["wall"]
     calls = st["calls"]
-    cps = calls_per_step if calls_per_step else st["calls"] / max(st["steps"], 1)
     return {
         "oracle_calls_per_s": calls / wall,
-        "billiard_steps_per_s": calls / wall / cps,
-        "calls_per_step": cps,
-        "billiard_steps_in_window_per_s": st["steps"] / wall,
+        "billiard_steps_per_s": st["steps"] / wall,
+        "calls_per_step": calls / max(st["steps"], 1),
         "ms_per_round": 1e3 * wall / max(st["rounds"], 1),
         "reflections_per_step": st["reflections"] / max(st["steps"], 1),
         "lanczos_steps_per_call": run["lz_steps"] / max(calls, 1),
@@ -223,20 +221,27 @@ def summary(run, chains, calls_per_step=None):
     }
 
 
-def train_learned(g, S, x0, tau, chains, rows_target, epochs, seed=77):
+def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_rounds, seed=77):
     """Walk-generated (x, v, t-, t+) triples -> trained network, and the
     constant-prediction control (the same network with zero weights predicts
-    the training mean of log t+ for every pair).  Rows of one chain in ten are
-    held out whole: half of them tune each bracket half-width through the real
-    learned kernel, the other half measure errors and Lanczos steps.  Returns
-    the network with its half-width, the control with its half-width, and a
+    the training mean of log t+ for every pair).  The triples are the segment
+    starts of data_chains billiard chains (their own seed) after burn_rounds
+    rounds from the centre, the same age as the timed chains: many chains over
+    few rounds, since the network generalises to unseen chains far better
+    than from fewer, longer chains.  Rows of one chain in ten are held out
+    whole: half of them tune each bracket half-width through the real learned
+    kernel, the other half measure errors and Lanczos steps.  Returns the
+    network with its half-width, the control with its half-width, and a
     report."""
     import torch
     n = N_DIM
     t0 = time.perf_counter()
-    rounds = max(1, -(-rows_target // chains))
-    _, _, wst, log = g.walk(S.BILLIARD, x0, 1 << 40, seed=2024, tau=tau, max_rounds=rounds,
-                            log_chains=chains, log_cap=rounds * chains)
+    rounds = max(1, -(-rows_target // data_chains))
+    xd = torch.zeros((data_chains, n), dtype=torch.float64, device="cuda")
+    g.walk(S.BILLIARD, xd, 1 << 40, seed=seed, tau=tau, max_rounds=max(burn_rounds, 1))
+    _, _, wst, log = g.walk(S.BILLIARD, xd, 1 << 40, seed=seed, tau=tau, max_rounds=rounds, resume=True,
+                            log_chains=data_chains, log_cap=rounds * data_chains)
+    del xd
     calls_per_step = wst["calls"] / max(wst["steps"], 1)
     held = (log[:, 2 * n + 2].to(torch.int64) % 10) == 9  # whole chains held out
     order = torch.cat([torch.nonzero(~held).flatten(), torch.nonzero(held).flatten()])
@@ -300,6 +305,7 @@ def train_learned(g, S, x0, tau, chains, rows_target, epochs, seed=77):
     report = {
         "calls_per_step": calls_per_step, "walk_calls": wst["calls"], "walk_steps": wst["steps"],
         "rows": rows, "held_out_rows": nval, "holdout": "whole chains (chain index % 10 == 9)",
+        "data_chains": data_chains, "data_rounds": rounds, "data_burn_in_rounds": burn_rounds,
         "data_seconds": t_data, "train_seconds": t_train,
         "epochs": epochs, "adam_steps": tr["steps"], "train_loss": tr["train_loss"], "val_loss": tr["val_loss"],
         "val_loss_constant_predictor": tr.get("val_loss_const"),
@@ -466,13 +472,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--state-rounds", type=int, default=30,
+    ap.add_argument("--state-rounds", type=int, default=150,
                     help="rounds walked from the centre before the chain state shared by the legs is saved")
     ap.add_argument("--chains", type=int, default=CHAINS)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-rows", type=int, default=2_000_000)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--data-chains", type=int, default=65536,
+                    help="billiard chains whose segment starts make the training triples")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
@@ -513,7 +521,8 @@ def main():
     net = ctl = report = None
     if not args.no_learned:
         progress("learned path: training data, training, half-width tuning")
-        net, delta, ctl, cdelta, report = train_learned(g, S, x0, tau, chains, args.train_rows, args.epochs)
+        net, delta, ctl, cdelta, report = train_learned(g, S, tau, chains, args.train_rows, args.epochs,
+                                                        args.data_chains, args.state_rounds)
     # one chain state for every leg: fresh chains walked state_rounds rounds and
     # saved; each leg restores it, runs the warm-up rounds and then the timed
     # rounds with the same seed, so the legs see the same walk states

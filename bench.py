@@ -390,25 +390,40 @@ def uneven_leg(S, I, samples_per_phase):
 def hmc_precision_leg(g, S, tau, chains, rounds):
     """HMC with reflections for the Gaussian exp(-|x|^2 / 2) (sigma = 1) on the
     n = m = 200 instance, travel time tau eta with tau = the diameter
-    estimate: segment (curve-oracle call) and step rates in FP64, and the
-    first-root error of the FP32 and BF16-pair pencil assemblies against FP64
-    on logged segments."""
+    estimate, in each precision of the pencil assembly (FP64; FP32 and BF16
+    hi+lo with escalation to FP64 pencils when the reduced-precision F(p) has
+    min pivot / max pivot < 1e-3): segment (curve-oracle call) and step rates
+    of the same chain state, escalation rates, and on logged segments of the
+    FP64 walk the first-root error of each mode against FP64, bucketed by
+    kappa(F(p)) (numpy eigenvalues on a sample), with hit / no-hit
+    disagreements inside and outside the escalated segments."""
     import torch
     n = N_DIM
     sigma, a = 1.0, 0.5
     x0 = torch.zeros((chains, n), dtype=torch.float64, device="cuda")
-    g.walk(S.HMC, x0, 1 << 40, seed=77, gauss_a=a, tau=tau, max_rounds=2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, st, log = g.walk(S.HMC, x0, 1 << 40, seed=77, gauss_a=a, tau=tau, max_rounds=rounds, resume=True,
-                           log_chains=chains, log_cap=chains * rounds)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    out = {"chains": chains, "sigma": sigma, "tau": tau, "rounds": rounds, "seconds": wall,
-           "curve_calls_per_s": st["calls"] / wall, "steps_in_window_per_s": st["steps"] / wall,
-           "reflections_per_call": st["reflections"] / max(st["calls"], 1), "not_interior": st["not_interior"],
-           "noconv": st["noconv"]}
-    # first roots of logged segments' pencils in each assembly precision
+    g.walk(S.HMC, x0, 1 << 40, seed=77, gauss_a=a, tau=tau, max_rounds=8)
+    g.save_walk_state()
+    out = {"chains": chains, "sigma": sigma, "tau": tau, "rounds": rounds, "escalate_ratio": 1e-3}
+    log = None
+    modes = (("fp64", S.PREC_FP64), ("fp32", S.PREC_FP32_ASM), ("bf16x2", S.PREC_BF16X2_ASM))
+    for name, mode in modes:
+        g.restore_walk_state()
+        g.set_precision(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kw = dict(log_chains=chains, log_cap=chains * rounds) if mode == S.PREC_FP64 else {}
+        _, _, st, lg = g.walk(S.HMC, x0, 1 << 40, seed=77, gauss_a=a, tau=tau, max_rounds=rounds, resume=True,
+                              **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if lg is not None:
+            log = lg
+        out[name] = {"seconds": wall, "curve_calls_per_s": st["calls"] / wall, "steps_per_s": st["steps"] / wall,
+                     "reflections_per_call": st["reflections"] / max(st["calls"], 1),
+                     "escalated_rate": st["escalated"] / max(st["calls"], 1),
+                     "not_interior": st["not_interior"], "noconv": st["noconv"]}
+    g.set_precision(S.PREC_FP64)
+    # first roots of logged segments' pencils in each mode
     L = log[: min(log.shape[0], 4096)]
     p, v = L[:, :n], L[:, n:2 * n]
     coef = torch.zeros((L.shape[0], 3, n + 1), dtype=torch.float64, device="cuda")
@@ -416,19 +431,49 @@ def hmc_precision_leg(g, S, tau, chains, rounds):
     coef[:, 1, 1:] = 2 * sigma * v
     coef[:, 2, 0], coef[:, 2, 1:] = 1.0, -p
     roots = {}
-    for name, mode in (("fp64", S.PREC_FP64), ("fp32", S.PREC_FP32_ASM), ("bf16x2", S.PREC_BF16X2_ASM)):
+    for name, mode in modes:
         g.set_precision(mode)
         _, tp, stc = g.intersect_curve(coef, 1.0)
-        roots[name] = (tp.cpu().numpy(), stc.cpu().numpy())
+        roots[name] = (tp.cpu().numpy(), stc.cpu().numpy(), (g.call_flags(coef.shape[0]) & 128) > 0)
     g.set_precision(S.PREC_FP64)
-    ref, rst = roots["fp64"]
+    # kappa(F(p)) on a sample of the segments (dense block and box rows)
+    pn = p.cpu().numpy()
+    A = g.inst.blocks[0].A
+    D = g.inst.blocks[1].A if len(g.inst.blocks) > 1 else None
+    samp = np.linspace(0, len(pn) - 1, min(384, len(pn))).astype(int)
+    kap = np.empty(len(samp))
+    for j, k in enumerate(samp):
+        ev = np.linalg.eigvalsh(A[0] + np.tensordot(pn[k], A[1:], 1))
+        lo, hi = ev.min(), ev.max()
+        if D is not None:
+            dv = D[0] + pn[k] @ D[1:]
+            lo, hi = min(lo, dv.min()), max(hi, dv.max())
+        kap[j] = hi / lo
+    edges = [1.0, 1e2, 1e4, 1e6, np.inf]
+    ref, rst, _ = roots["fp64"]
     for name in ("fp32", "bf16x2"):
-        tp, stc = roots[name]
-        ok = np.isfinite(ref) & np.isfinite(tp) & (rst == 0) & (stc == 0)
-        rel = np.abs(tp[ok] - ref[ok]) / ref[ok]
-        out[f"{name}_vs_fp64_root_rel"] = {"segments": int(ok.sum()), "median": float(np.median(rel)),
-                                           "p99": float(np.quantile(rel, 0.99)), "max": float(rel.max()),
-                                           "hit_disagreements": int(np.sum(np.isfinite(ref) != np.isfinite(tp)))}
+        tp, stc, esc = roots[name]
+        ok = (rst == 0) & (stc == 0)
+        both = ok & np.isfinite(ref) & np.isfinite(tp)
+        rel = np.where(both, np.abs(tp - ref) / np.where(both, ref, 1.0), np.nan)
+        dis = ok & (np.isfinite(ref) != np.isfinite(tp))
+        buckets = []
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            sel = samp[(kap >= lo) & (kap < hi)]
+            r = rel[sel]
+            r = r[np.isfinite(r)]
+            buckets.append({"kappa": [lo, hi], "segments": int(len(sel)), "escalated": int(esc[sel].sum()),
+                            "median": float(np.median(r)) if len(r) else None,
+                            "max": float(r.max()) if len(r) else None,
+                            "hit_disagreements": int(dis[sel].sum())})
+        r_all = rel[np.isfinite(rel)]
+        out[f"{name}_vs_fp64_root_rel"] = {
+            "segments": int(ok.sum()), "escalated": int(esc.sum()),
+            "median": float(np.median(r_all)), "p99": float(np.quantile(r_all, 0.99)), "max": float(r_all.max()),
+            "max_not_escalated": float(np.nanmax(np.where(esc, np.nan, rel))) if np.any(both & ~esc) else None,
+            "hit_disagreements": int(dis.sum()),
+            "hit_disagreements_not_escalated": int((dis & ~esc).sum()),
+            "by_kappa_sample": buckets}
     return out
 
 
@@ -485,7 +530,8 @@ def main():
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--hmc-chains", type=int, default=8192)
-    ap.add_argument("--hmc-rounds", type=int, default=4)
+    ap.add_argument("--hmc-rounds", type=int, default=20,
+                    help="timed rounds of the HMC leg per precision mode (2000 for the full walk length)")
     ap.add_argument("--uneven-samples", type=int, default=256,
                     help="samples per cooling phase of the 256-spectrahedra volume (2000 for the full run)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -113,6 +113,17 @@ spec_status spec_destroy(spec_handle h);
  *                factorisations per call); failures are flagged and counted.
  *                0 (default): the Kato-Temple interval of spec_certificates
  *                only.  Not applied to the uneven batch.
+ *  escalate_ratio  precision split (spec_set_precision FP32 / BF16 hi+lo
+ *                assembly): a call is redone with FP64 pencils when its
+ *                reduced-precision F (F(p) of a curve) has min pivot / max
+ *                pivot of its Cholesky factor below this (the pivots lie in
+ *                [lambda_min, lambda_max], so lambda_min < ratio lambda_max
+ *                then), when that F is not definite, and when the call ends at
+ *                the boundary with a reflection to form (a reflection point
+ *                pulled back by a relative 1e-6 needs the FP64 root); the
+ *                factorisation and eigen solve are FP64 in every mode.
+ *                Intersections without a reflection keep the reduced-precision
+ *                roots.  Default 1e-3; 0 disables.  Counted as escalated.
  * When the factor does not exist at t0 (t1 was too far out) the origin backs
  * off to t1 (1 - 2^-5) and then t1 / 2; only if those fail too is the plain
  * solve repeated at the full tolerance (counted as refine_failed in
@@ -124,6 +135,7 @@ typedef struct {
     double refine_ratio;
     double tol_loose;
     int certify;
+    double escalate_ratio;
 } spec_options;
 
 spec_status spec_options_default(spec_options* opt);
@@ -268,6 +280,7 @@ typedef struct {
     double refined, refine_failed;
     double uncertified;  /* calls whose t+ interval (spec_certificates) is wider than 2e-9 t+ */
     double chol_cert_failed;  /* calls whose two-sided Cholesky certificate failed (spec_options.certify) */
+    double escalated;    /* calls whose reduced-precision pencils were redone in FP64 (escalate_ratio) */
 } spec_walk_stats;
 
 /* Run `chains` independent chains of the walk `kind` from x0 (chains x n,

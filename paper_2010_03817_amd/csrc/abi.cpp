@@ -133,7 +133,30 @@ spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, 
         a.shift = h->dShift;
         if (h->lmode == 2) a.shift_hi = h->dShiftHi;
     }
+    const bool esc = h->prec > 0 && h->esc_ratio > 0.0 && h->m > 0;
+    if (esc) {
+        HIPCHK(launch_zero_ints(h->dECnt, 1, s));
+        a.elist = h->dEList;
+        a.ecount = h->dECnt;
+        a.esc_ratio = h->esc_ratio;
+    }
     SPCHK(run_fused(h, a, batch, s));
+    if (esc) {
+        // the chains whose reduced-precision F was ill-conditioned: every pencil
+        // again in FP64 (their rows, the others unused), then their oracle pass
+        int cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, h->dECnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (cnt > 0) {
+            HIPCHK(gemm_f64(false, v ? 2 * bp : bp, h->ldA, h->Kpad, h->dZ, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA,
+                            s));
+            FusedArgs e = a;
+            e.idx = h->dEList;
+            e.elist = nullptr;
+            e.escalated = 1;
+            SPCHK(run_fused(h, e, cnt, s));
+        }
+    }
     mark(h, 3, s);
     return SPEC_OK;
 }
@@ -171,7 +194,33 @@ spec_status curve_oracle(spec_s* h, int batch, const double* horizon, double hsc
     a.ldu = h->m;
     a.U2 = h->dU2;
     a.ldu2 = h->ldA;
+    a.flags = h->dFlags;
+    const bool esc = h->prec > 0 && h->esc_ratio > 0.0 && h->m > 0;
+    if (esc) {
+        HIPCHK(launch_zero_ints(h->dECnt, 1, s));
+        a.elist = h->dEList;
+        a.ecount = h->dECnt;
+        a.esc_ratio = h->esc_ratio;
+    }
     HIPCHK(launch_curve2(a, batch, s));
+    if (esc) {
+        // curves whose reduced-precision F(p) was ill-conditioned: their three
+        // coefficient rows gathered and assembled in FP64 (rows j of the
+        // compact pencils belong to chain list[j]), then their Weyl stepping
+        int cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, h->dECnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (cnt > 0) {
+            const int bc = round_up(cnt, 64);
+            HIPCHK(launch_gather_rows(cnt, bc, 3, h->Kpad, h->dEList, h->dZ, bp, h->dZc, s));
+            HIPCHK(gemm_f64(false, 3 * bc, h->ldA, h->Kpad, h->dZc, h->Kpad, h->dA, h->ldA, h->dFB, h->ldA, s));
+            CurveArgs e = a;
+            e.brow0 = bc;
+            e.idx = h->dEList;
+            e.elist = nullptr;
+            HIPCHK(launch_curve2(e, cnt, s));
+        }
+    }
     mark(h, 3, s);
     return SPEC_OK;
 }
@@ -421,6 +470,7 @@ spec_status spec_options_default(spec_options* o) {
     o->refine_ratio = 1e3;
     o->tol_loose = 1e-3;
     o->certify = 0;
+    o->escalate_ratio = 1e-3;
     return SPEC_OK;
 }
 
@@ -432,6 +482,7 @@ spec_status spec_get_options(spec_handle h, spec_options* o) {
     o->refine_ratio = h->refine_ratio;
     o->tol_loose = h->tol_loose;
     o->certify = h->certify;
+    o->escalate_ratio = h->esc_ratio;
     return SPEC_OK;
 }
 
@@ -441,11 +492,13 @@ spec_status spec_set_options(spec_handle h, const spec_options* o) {
     if (!(o->tol_loose > 0.0 && o->tol_loose < 1.0)) return SPEC_EINVAL;
     if (o->precision < SPEC_PREC_FP64 || o->precision > SPEC_PREC_BF16X2_ASM) return SPEC_EINVAL;
     if (o->certify < 0 || o->certify > 1) return SPEC_EINVAL;
+    if (!(o->escalate_ratio >= 0.0 && o->escalate_ratio < 1.0)) return SPEC_EINVAL;
     if (o->kmax != h->kmax || o->tol != h->tol) SPCHK(spec_set_lanczos(h, o->kmax, o->tol));
     SPCHK(spec_set_precision(h, o->precision));
     h->refine_ratio = o->refine_ratio;
     h->tol_loose = o->tol_loose;
     h->certify = o->certify;
+    h->esc_ratio = o->escalate_ratio;
     return SPEC_OK;
 }
 
@@ -722,7 +775,6 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
         HIPCHK(hipStreamSynchronize(s));
     }
     const bool billiard = kind == SPEC_WALK_BILLIARD;
-    if (kind == SPEC_WALK_HMC) a.flags = nullptr;  // the curve oracle writes no call flags
     long long rounds = 0;
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
     const bool hmc = kind == SPEC_WALK_HMC;
@@ -786,6 +838,7 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
         stats->refine_failed = tot[9];
         stats->uncertified = tot[10];
         stats->chol_cert_failed = tot[11];
+        stats->escalated = tot[12];
     }
     return SPEC_OK;
 }

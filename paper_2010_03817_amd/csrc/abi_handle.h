@@ -28,6 +28,7 @@ struct spec_s {
     // refinement of far roots from a shifted origin (spec_options)
     double refine_ratio = 1e3, tol_loose = 1e-3;
     int certify = 0;  // 1: two-sided Cholesky certificate of every dense t+ (spec_options)
+    double esc_ratio = 1e-3;  // reduced-precision pencils: FP64 again below this pivot ratio
     // workspace (capacity in chains, multiple of 64); work_gen changes whenever
     // it is (re)allocated, so that cached device pointers can be revalidated
     int cap = 0;
@@ -37,6 +38,10 @@ struct spec_s {
     double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
     int32_t *dHit = nullptr, *dSt = nullptr, *dFlags = nullptr;
     double* dCert = nullptr;  // certified interval of t+ per chain (2 doubles)
+    // precision escalation: queued chains, count, compact coefficient rows
+    int32_t* dEList = nullptr;
+    int* dECnt = nullptr;
+    double* dZc = nullptr;
     // far-root refinement queue: items, origins, counters (queued, taken)
     int2* dRList = nullptr;
     double* dRShift = nullptr;
@@ -74,6 +79,7 @@ struct spec_s {
         dfree(dZ); dfree(dZ32); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt); dfree(dFlags);
         dfree(dRList); dfree(dRShift); dfree(dRCnt); dfree(dCert);
+        dfree(dEList); dfree(dECnt); dfree(dZc);
         dfree(dShift); dfree(dShiftHi); dfree(dPred); dfree(dHz);
         cap = 0;
         ++work_gen;
@@ -130,6 +136,9 @@ struct spec_s {
         HIPCHK(dalloc(&dRShift, (size_t)c));
         HIPCHK(dalloc(&dRCnt, (size_t)2));
         HIPCHK(dalloc(&dCert, (size_t)2 * c));
+        HIPCHK(dalloc(&dEList, (size_t)c));
+        HIPCHK(dalloc(&dECnt, (size_t)1));
+        HIPCHK(dalloc(&dZc, (size_t)3 * c * Kpad));
         HIPCHK(dalloc(&dShift, (size_t)c));
         HIPCHK(dalloc(&dShiftHi, (size_t)c));
         HIPCHK(dalloc(&dPred, (size_t)c));

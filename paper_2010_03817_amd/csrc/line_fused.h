@@ -42,6 +42,13 @@ struct FusedArgs {
     int inst_id;
     int32_t* flags;            // nullable: per chain SPEC_FLAG_* bits
     double* cert;              // nullable: per chain the certified interval of t+ (2 doubles)
+    // precision escalation (reduced-precision pencils): a chain whose factor at
+    // the plain origin has min pivot / max pivot < esc_ratio is queued in elist
+    // (count *ecount) without results; `escalated` marks the FP64 pass over them
+    int32_t* elist;            // nullable: no escalation
+    int* ecount;
+    double esc_ratio;
+    int escalated;
 };
 
 // Degree-2 curve oracle: first root of det Q(t), Q(t) = Q0 + t Q1 + t^2 Q2,
@@ -66,6 +73,13 @@ struct CurveArgs {
     int ldu;
     double* U2;
     int ldu2;
+    // precision escalation as FusedArgs; idx (nullable): workgroup j handles
+    // chain idx[j] with pencil rows j (a compacted FP64 assembly)
+    int32_t* elist;
+    int* ecount;
+    double esc_ratio;
+    const int32_t* idx;
+    int32_t* flags;            // nullable: SPEC_FLAG_ESCALATED set on the FP64 pass
 };
 hipError_t launch_curve2(const CurveArgs& a, int nblocks, hipStream_t s);
 

@@ -1292,6 +1292,30 @@ struct LzCtx {
     long long* prof;   // nullable: per-part cycles of the steering wave (slots 8..13), tests and passes (16, 17)
 };
 
+// Conditioning indicator of the factored pencil: the Cholesky pivots
+// d_i = L_ii^2 lie in [lambda_min, lambda_max], so min d / max d (from the
+// inverse's diagonal, W_ii = 1 / L_ii, in place after tri_inverse) is at
+// least lambda_min / lambda_max; a value below the escalation threshold
+// certainly means an ill-conditioned F.  Wave 0 reduces, `out` (LDS) passes
+// the value to every thread (barrier included).
+__device__ inline double pivot_ratio(const double* W, int m, double* out) {
+    const int t = threadIdx.x, lane = t & 63;
+    if (t < 64) {
+        double lo = INFINITY, hi = 0.0;
+        for (int i = lane; i < m; i += 64) {
+            const double w = W[pk(i, i)];
+            const double d = w * w;  // 1 / pivot
+            lo = fmin(lo, d);
+            hi = fmax(hi, d);
+        }
+        lo = wave_ext_dpp<false>(lo);
+        hi = wave_ext_dpp<true>(hi);
+        if (lane == 0) out[0] = lo / hi;  // min pivot / max pivot
+    }
+    lds_barrier();
+    return out[0];
+}
+
 // A lower bound of the second smallest eigenvalue of T_k (al, be in LDS) for
 // the Kato-Temple interval: multisection over [th, Gershgorin top] for the
 // first point with two eigenvalues of T_k below it; returns the last point
@@ -1856,6 +1880,13 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     lds_barrier();
     const bool dtie = (bad & 2) != 0;
     bad &= 1;
+    // reduced-precision pencils that are not definite at the plain origin are
+    // decided by the FP64 pass (their rounding can move a start next to the
+    // boundary outside)
+    if (!REFINE && bad && a.elist) {
+        if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+        return;
+    }
     double tp = dtp, tm = dtm;
     int hit = dj >= 0 ? dj : HIT_NONE;
     double lmin = 0.0, lmax = 0.0;
@@ -1912,7 +1943,20 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         }
         if (prof && t == 64) prof[20] = cst[3];
         long long ist[3] = {0, 0, 0};  // triangular-inverse part cycles (profiling)
+        if (!REFINE && !ok && a.elist) {
+            if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+            return;
+        }
         if (ok && !a.membership_only) tri_inverse(L, m, scr, prof ? ist : nullptr);
+        // reduced-precision pencils of an ill-conditioned F are passed on to an
+        // FP64 assembly (the chain is queued; that pass writes its results)
+        if (!REFINE && ok && !a.membership_only && a.elist && t0 == 0.0) {
+            const double pr = pivot_ratio(L, m, rtp);
+            if (pr < a.esc_ratio) {
+                if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+                return;
+            }
+        }
         if (prof && t == 0) {
             prof[21] = ist[1];
             prof[22] = ist[2];
@@ -2025,6 +2069,12 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
             // the kernel vector of a t+ hit comes from the run that fixes t+
             const bool need_vec = a.want_vec && fixes_tp && hit == HIT_DENSE && isfinite(tp) &&
                                   (a.ell == nullptr || tp < a.ell[chain]);
+            // a reflection from reduced-precision pencils: the hit point (pulled
+            // back by a relative 1e-6) and the normal need the FP64 root
+            if (!REFINE && need_vec && a.elist) {
+                if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+                return;
+            }
             if (need_vec)
                 ritz_u(L, scr, m, kmax, k, lmin, Qg, a.u + (size_t)chain * a.ldu, a.U2 + (size_t)chain * a.ldu2);
             if (rside) flags |= SPEC_FLAG_REFINED;
@@ -2064,6 +2114,7 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         if (REFINE && a.flags) flags |= a.flags[chain] & keep;
         if (REFINE && (flags & SPEC_FLAG_CERT_FALLBACK)) cert = 1;  // from the first pass
         if (st == SPEC_OK && cert) st = SPEC_CERT_FALLBACK;  // informational: values are final
+        if (a.escalated) flags |= SPEC_FLAG_ESCALATED;
         if (a.flags) a.flags[chain] = flags | (cert == 1 ? SPEC_FLAG_CERT_FALLBACK : 0);
         a.tm[chain] = tm;
         a.tp[chain] = tp;
@@ -2218,7 +2269,8 @@ __device__ __forceinline__ double first_root_q(double a, double b) {
 __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
     extern __shared__ double lds[];
     const int m = a.m, P = a.P, md = a.md;
-    const int chain = blockIdx.x;
+    const int row = blockIdx.x;                      // pencil rows of this workgroup
+    const int chain = a.idx ? a.idx[row] : row;     // its chain (outputs, basis, horizon)
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
     double* L = lds;
     double* scr = lds + P;
@@ -2227,9 +2279,9 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
     double* rtm = rtp + 8;
     int* rj = (int*)(rtm + 8);
     int* rbad = rj + 8;
-    const double* Q0 = a.FB + (size_t)chain * a.ldfb;
-    const double* Q1 = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
-    const double* Q2 = a.FB + (size_t)(2 * a.brow0 + chain) * a.ldfb;
+    const double* Q0 = a.FB + (size_t)row * a.ldfb;
+    const double* Q1 = a.FB + (size_t)(a.brow0 + row) * a.ldfb;
+    const double* Q2 = a.FB + (size_t)(2 * a.brow0 + row) * a.ldfb;
     const double hz = a.horizon ? a.horizon[chain] : a.hscalar;
     int32_t st = SPEC_OK;
 
@@ -2267,6 +2319,11 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
     int iters = 0;
     bool conv = true;
 
+    // reduced-precision pencils not definite at p: decided by the FP64 pass
+    if (bad && a.elist) {
+        if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+        return;
+    }
     if (bad) st = SPEC_NOT_INTERIOR;
     if (!bad && m > 0) {
         const int kmax = a.kmax;
@@ -2285,6 +2342,10 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                 const bool ok = chol_blocked(L, m, scr, sflag);
                 lds_barrier();
                 if (!ok) {
+                    if (it == 0 && dir == 0 && a.elist) {
+                        if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+                        return;
+                    }
                     if (it == 0) {
                         st = SPEC_NOT_INTERIOR;
                         break;
@@ -2303,6 +2364,15 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                     continue;
                 }
                 tri_inverse(L, m, scr);
+                // reduced-precision pencils of an ill-conditioned F(p): queued for
+                // an FP64 assembly, which writes this chain's results
+                if (it == 0 && dir == 0 && a.elist) {
+                    const double pr = pivot_ratio(L, m, rtp);
+                    if (pr < a.esc_ratio) {
+                        if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+                        return;
+                    }
+                }
                 // lambda_min of D2, then of D1 (its basis stays for the kernel vector)
                 double d[2] = {0.0, 0.0};
                 for (int pass = backoff ? 1 : 0; pass < 2; ++pass) {
@@ -2366,6 +2436,12 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
             lds_barrier();
         }
     }
+    // a hit from reduced-precision pencils: the reflection point and normal
+    // need the FP64 root (the FP64 pass writes this chain's results)
+    if (a.elist && st == SPEC_OK && isfinite(tp) && tp <= hz) {
+        if (t == 0) a.elist[atomicAdd(a.ecount, 1)] = chain;
+        return;
+    }
     if (t == 0) {
         double tm = -tmd;
         if (st == SPEC_NOT_INTERIOR) {
@@ -2381,6 +2457,7 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
         a.hit[chain] = isfinite(tp) ? hit : HIT_NONE;
         a.status[chain] = st;
         if (a.iters) a.iters[chain] = iters;
+        if (a.flags) a.flags[chain] = a.idx ? SPEC_FLAG_ESCALATED : 0;
     }
 }
 

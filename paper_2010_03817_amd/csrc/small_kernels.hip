@@ -28,6 +28,28 @@ __global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__
     }
 }
 
+// Compact rows: for j < count, rows k * zc0 + j of Zc = rows k * z0 + list[j]
+// of Z (k < nrows); rows count <= j < zc0 of Zc are zero.
+__global__ void k_gather_rows(int count, int zc0, int nrows, int Kpad, const int32_t* __restrict__ list,
+                              const double* __restrict__ Z, int z0, double* __restrict__ Zc) {
+    const int j = blockIdx.x;
+    if (j >= zc0) return;
+    const int c = j < count ? list[j] : -1;
+    for (int k = 0; k < nrows; ++k) {
+        double* dst = Zc + ((size_t)k * zc0 + j) * Kpad;
+        const double* src = c >= 0 ? Z + ((size_t)k * z0 + c) * Kpad : nullptr;
+        for (int i = threadIdx.x; i < Kpad; i += blockDim.x) dst[i] = src ? src[i] : 0.0;
+    }
+}
+
+hipError_t launch_gather_rows(int count, int zc0, int nrows, int Kpad, const int32_t* list, const double* Z, int z0,
+                              double* Zc, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (zc0 < count) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_rows, dim3(zc0), dim3(64), 0, s, count, zc0, nrows, Kpad, list, Z, z0, Zc);
+    return hipGetLastError();
+}
+
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s) {
     if (batch <= 0) return hipSuccess;

@@ -25,7 +25,8 @@ enum : int {
     SPEC_FLAG_REFINE_FAILED = 8,
     SPEC_FLAG_TIE = 16,
     SPEC_FLAG_UNCERTIFIED = 32,
-    SPEC_FLAG_CHOL_CERT_FAILED = 64
+    SPEC_FLAG_CHOL_CERT_FAILED = 64,
+    SPEC_FLAG_ESCALATED = 128  // reduced-precision pencils redone in FP64 (ill-conditioned F)
 };
 
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
@@ -36,6 +37,12 @@ hipError_t mfma_probe(double* out, hipStream_t s);
 // rows batch <= c < zrow0 of both halves are zero (zrow0 >= batch).
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s);
+
+// Compact copy of the coefficient rows of the chains in list[0 .. count):
+// rows k * zc0 + j of Zc = rows k * z0 + list[j] of Z, k < nrows; the rows
+// count .. zc0 - 1 of each group are zero.
+hipError_t launch_gather_rows(int count, int zc0, int nrows, int Kpad, const int32_t* list, const double* Z, int z0,
+                              double* Zc, hipStream_t s);
 
 // Rows k * zrow0 + c, k = 0, 1, 2, of Z: coefficient rows of curve c
 // (nrows of them given, the rest zero), zero-padded to Kpad.

@@ -306,6 +306,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
             if (f & SPEC_FLAG_REFINE_FAILED) st[9] += 1.0;
             if (f & SPEC_FLAG_UNCERTIFIED) st[10] += 1.0;
             if (f & SPEC_FLAG_CHOL_CERT_FAILED) st[11] += 1.0;
+            if (f & SPEC_FLAG_ESCALATED) st[12] += 1.0;
         }
     }
     if (status == SPEC_NOT_INTERIOR) {

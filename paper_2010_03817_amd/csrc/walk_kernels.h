@@ -8,8 +8,8 @@ namespace spec {
 // nonsmooth, completed steps, eigen non-convergence, learned-bracket fallbacks,
 // far roots refined from a shifted origin, refinements whose factor failed,
 // calls whose t+ interval was not certified to 2e-9, calls whose two-sided
-// Cholesky certificate failed.
-constexpr int WALK_NSTAT = 12;
+// Cholesky certificate failed, calls redone in FP64 (precision escalation).
+constexpr int WALK_NSTAT = 13;
 
 struct WalkState {
     double* x;        // chains x n: current point

@@ -38,7 +38,7 @@ class WalkParams(C.Structure):
 class WalkStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("calls", "reflections", "cap_hits", "not_interior", "nonsmooth", "steps",
                                           "noconv", "rounds", "cert_fallback", "refined", "refine_failed",
-                                          "uncertified", "chol_cert_failed")]
+                                          "uncertified", "chol_cert_failed", "escalated")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -46,7 +46,7 @@ class WalkStats(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("kmax", C.c_int), ("tol", C.c_double), ("refine_ratio", C.c_double),
-                ("tol_loose", C.c_double), ("certify", C.c_int)]
+                ("tol_loose", C.c_double), ("certify", C.c_int), ("escalate_ratio", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 N_DIM, M_DIM, SEED_INST, CHAINS = 200, 200, 103, 16384
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FUSED_STAGE = "k_line_fused+k_line_refine<false>"
 
 
 def _fused_traffic(chains, leg):
@@ -190,10 +191,10 @@ def roofline(run, chains, extra_chol=0.0):
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["traffic_unit"] = "bytes per launch"
-    roof["kernel"] = {"fused": "k_line_fused", "assemble": "k_gemm_f64_128<false>", "normal": "k_gemm_f64_128<true>",
+    roof["kernel"] = {"fused": FUSED_STAGE, "assemble": "k_gemm_f64_128<false>", "normal": "k_gemm_f64_128<true>",
                       "predict": "k_gemm_f32", "update": "k_walk_update"}[dom]
     if dom == "fused":
-        roof["launches"] = "k_line_fused and its refining pass k_line_refine<false> per round (one stage)"
+        roof["launches"] = "per round: k_line_fused over every chain, then k_line_refine<false> over the queued ones"
     roof["ms_per_launch"] = ms_dom
     return roof
 
@@ -592,7 +593,7 @@ def main():
     cps = report["calls_per_step"] if report else None
     plain = leg("plain path", None, 0.0)
     roof = roofline(plain, chains, extra_chol=plain["stats"]["refined"])
-    if roof["kernel"] == "k_line_fused":
+    if roof["kernel"] == FUSED_STAGE:
         roof["traffic"] = _fused_traffic(chains, "plain")
     # assembly GEMM (F(x) and B(v) rows of every chain): FP64 MFMA utilisation
     P = M_DIM * (M_DIM + 1) // 2
@@ -611,7 +612,7 @@ def main():
         learned_sum = summary(learned, chains, cps)
         learned_sum["roofline"] = roofline(learned, chains,
                                            extra_chol=learned["stats"]["cert_fallback"] + learned["stats"]["refined"])
-        if learned_sum["roofline"]["kernel"] == "k_line_fused":
+        if learned_sum["roofline"]["kernel"] == FUSED_STAGE:
             learned_sum["roofline"]["traffic"] = _fused_traffic(chains, "learned")
         learned_sum["training"] = report
         control = leg(f"constant-shift control (delta {cdelta:.3f})", ctl, cdelta)

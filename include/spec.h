@@ -369,7 +369,8 @@ spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uin
  * larger), so that small instances run many workgroups per compute unit;
  * 3 = one launch per instance.  0 = chosen by spec_batch_tune on first use.
  * With use_graph, a round is captured once per walk phase into a HIP graph
- * and replayed.
+ * and replayed.  Batch calls need every handle in FP64 assembly
+ * (SPEC_PREC_FP64; SPEC_ENOTSUP otherwise).
  * ------------------------------------------------------------------------ */
 typedef struct spec_batch_s* spec_batch;
 
@@ -382,6 +383,15 @@ spec_status spec_batch_set_strategy(spec_batch b, int strategy, int use_graph);
  * with each strategy (ms per round into ms_out[3], nullable) and keep the
  * fastest (*chosen, nullable).  The handles' walk state is overwritten. */
 spec_status spec_batch_tune(spec_batch b, int chains, int rounds, double* ms_out, int* chosen);
+/* One oracle round of the batch on given pairs (t- and t+ of every line, as
+ * spec_intersect, Lemma "PEP and S cap C"): x and v are host arrays holding,
+ * instance after instance, `chains` rows of that instance's n doubles
+ * (row-major); t_minus, t_plus and status are host arrays of count * chains,
+ * instance after instance.  The launch follows the batch's strategy (0 runs
+ * strategy 1 without tuning).  The handles' walk state and call buffers are
+ * overwritten.  Synchronises. */
+spec_status spec_batch_intersect(spec_batch b, int chains, const double* x, const double* v, double* t_minus,
+                                 double* t_plus, int32_t* status);
 /* spec_volume_estimate for every instance, all walks advancing together:
  * log_vol, ci_lo, ci_hi: host arrays of `count`; oracle_calls (nullable):
  * total over instances.  Synchronises. */

@@ -932,6 +932,9 @@ int persistent_blocks(int max_m, int kmax) {
 // longest items start first); classes split at m <= 64 and m <= 128.
 spec_status batch_plan(spec_batch_s* b, int chains) {
     const int K = (int)b->hs.size();
+    // the batch launches carry no precision escalation: FP64 pencils only
+    for (int i = 0; i < K; ++i)
+        if (b->hs[i]->prec != 0) return SPEC_ENOTSUP;
     for (int i = 0; i < K; ++i) {
         SPCHK(b->hs[i]->ensure(chains));
         SPCHK(b->hs[i]->ensure_walk(chains));
@@ -1477,6 +1480,54 @@ spec_status spec_batch_set_strategy(spec_batch b, int strategy, int use_graph) {
 spec_status spec_batch_tune(spec_batch b, int chains, int rounds, double* ms_out, int* chosen) {
     if (!b || chains < 1 || rounds < 1) return SPEC_EINVAL;
     return batch_tune(b, chains, rounds, ms_out, chosen);
+}
+
+spec_status spec_batch_intersect(spec_batch b, int chains, const double* x, const double* v, double* t_minus,
+                                 double* t_plus, int32_t* status) {
+    if (!b || chains < 0) return SPEC_EINVAL;
+    if (chains == 0) return SPEC_OK;
+    if (!x || !v || !t_minus || !t_plus || !status) return SPEC_EINVAL;
+    const int K = (int)b->hs.size();
+    hipStream_t s = b->stream;
+    SPCHK(batch_plan(b, chains));
+    const int strategy = b->strategy == 0 ? 1 : b->strategy;
+    // every instance's pairs into its walk buffers, then its pencils
+    size_t off = 0;
+    for (int i = 0; i < K; ++i) {
+        spec_handle h = b->hs[i];
+        const size_t cnt = (size_t)chains * h->n;
+        HIPCHK(hipMemcpyAsync(h->wX, x + off, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->wV, v + off, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+        off += cnt;
+        int bp = 0;
+        SPCHK(assemble(h, chains, h->wX, h->wV, &bp, s));
+    }
+    if (strategy == 3 || K == 1) {
+        for (int i = 0; i < K; ++i) {
+            spec_handle h = b->hs[i];
+            FusedArgs a = fused_args(h, round_up(chains, 64), h->dSt, h->dTm, h->dTp, false, nullptr);
+            SPCHK(run_fused(h, a, chains, s));
+        }
+    } else {
+        HIPCHK(launch_zero_ints(b->dRCnt, 2, s));
+        const auto& list = strategy == 1 ? b->all : b->classes;
+        for (const auto& k : list)
+            HIPCHK(launch_line_fused_multi(b->dArgs, b->dWork + k.off, k.count, b->dCounter, k.max_m, k.kmax,
+                                           k.nblocks, s));
+        const auto& a = b->all[0];
+        FusedArgs none{};
+        HIPCHK(launch_line_refine(none, b->dArgsRef, b->dRList, b->dRCnt, b->dRCnt + 1, a.max_m, a.kmax,
+                                  persistent_blocks(a.max_m, a.kmax), s));
+    }
+    for (int i = 0; i < K; ++i) {
+        spec_handle h = b->hs[i];
+        const size_t o = (size_t)i * chains;
+        HIPCHK(hipMemcpyAsync(t_minus + o, h->dTm, chains * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(t_plus + o, h->dTp, chains * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(status + o, h->dSt, chains * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return SPEC_OK;
 }
 
 spec_status spec_batch_volume(spec_batch b, const spec_volume_params* p, uint64_t seed, double* log_vol,

@@ -158,6 +158,7 @@ def lib():
     L.spec_batch_set_strategy.argtypes = [vp, C.c_int, C.c_int]
     L.spec_batch_tune.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_int)]
     L.spec_batch_volume.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, vp, vp, vp, C.POINTER(C.c_double)]
+    L.spec_batch_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     L.spec_volume_estimate.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(VolumeStats), vp]
     L.spec_tune_mlp_delta_dev.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, C.POINTER(C.c_double),
@@ -471,6 +472,24 @@ class Batch:
         k = C.c_int()
         check(lib().spec_batch_tune(self._h, int(chains), int(rounds), ms.ctypes.data_as(C.c_void_p), C.byref(k)))
         return k.value, list(ms)
+
+    def intersect(self, xs, vs):
+        """One batched oracle round on host pairs: xs[i], vs[i] of shape
+        (chains, n_i) for instance i; returns (t_minus, t_plus, status), each of
+        shape (count, chains)."""
+        K = len(self.specs)
+        chains = int(np.shape(xs[0])[0])
+        for i, g in enumerate(self.specs):
+            if np.shape(xs[i]) != (chains, g.n) or np.shape(vs[i]) != (chains, g.n):
+                raise ValueError(f"instance {i}: pairs must have shape ({chains}, {g.n})")
+        x = np.ascontiguousarray(np.concatenate([np.asarray(a, np.float64).ravel() for a in xs]))
+        v = np.ascontiguousarray(np.concatenate([np.asarray(a, np.float64).ravel() for a in vs]))
+        tm, tp = np.empty((K, chains)), np.empty((K, chains))
+        st = np.empty((K, chains), np.int32)
+        check(lib().spec_batch_intersect(self._h, chains, x.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                         tm.ctypes.data_as(C.c_void_p), tp.ctypes.data_as(C.c_void_p),
+                                         st.ctypes.data_as(C.c_void_p)))
+        return tm, tp, st
 
     def volume(self, phases=20, samples_per_phase=2000, chains=64, walk_len=10, groups=8, a0=0.0, a_end=0.0,
                seed=1, burn_in=-1):

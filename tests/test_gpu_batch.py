@@ -77,3 +77,67 @@ def test_tune_then_volume_revalidates_the_plan(S):
     b2.set_strategy(chosen, True)
     lv2, lo2, hi2, _ = b2.volume(**PARAMS)
     assert np.array_equal(lv, lv2) and np.array_equal(lo, lo2)
+
+
+def _wide_mix():
+    """Dense blocks from m = 200 down to m = 7 (ragged against every tile
+    size), an arrow ball and a box: one launch holds items whose m differ by
+    almost 30x."""
+    return [I.gbase(200, 200, seed=61), I.gbase(37, 137, seed=62), I.arrow_ball(64), I.gbase(90, 65, seed=63),
+            I.gbase(20, 33, seed=64), I.box(7, 1.0), I.gbase(12, 7, seed=65)]
+
+
+def _wide_pairs(insts, chains, seed):
+    """Per instance: interior starts at 10-90 % of the way to the boundary and
+    starts 1e-6 short of it (as after a reflection), random directions."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(seed)
+    xs, vs = [], []
+    for inst in insts:
+        o = O.Oracle(inst)
+        d = I.random_directions(rng, chains, inst.n)
+        _, tp0, st0 = o.intersect(np.zeros((chains, inst.n)), d)
+        assert (st0 == O.OK).all()
+        f = np.where(np.arange(chains) % 3 == 2, 1 - 1e-6, rng.uniform(0.1, 0.9, chains))
+        xs.append((f * tp0)[:, None] * d)
+        vs.append(I.random_directions(rng, chains, inst.n))
+    return xs, vs
+
+
+def test_batch_intersect_wide_mix_matches_oracle(S):
+    """One k_line_fused_multi launch over instances with m from 7 to 200 (and
+    the per-class and per-instance launches): t- and t+ of every pair within
+    1e-9 of the oracle's bisection on membership (plus the rounding bound of
+    a root next to its start), statuses identical; the three strategies
+    meet the same bar.  (The launches differ in workgroup size, which sets
+    the summation order of the cross-wave reductions, so they agree to
+    rounding, not bit for bit.)"""
+    from oracle import oracle as O
+    from root_bounds import root_bars
+    insts = _wide_mix()
+    chains = 6
+    xs, vs = _wide_pairs(insts, chains, seed=71)
+    b = S.Batch([S.Spectrahedron(i) for i in insts])
+    out = {}
+    for strategy in (1, 2, 3):
+        b.set_strategy(strategy, False)
+        out[strategy] = b.intersect(xs, vs)
+    for k, inst in enumerate(insts):
+        o = O.Oracle(inst)
+        tm_e, tp_e, st_e = o.intersect(xs[k], vs[k])
+        tm_r, tp_r, st_r = o.line_bisect(xs[k], vs[k], guess=np.stack([tm_e, tp_e], 1))
+        bar_m, bar_p = root_bars(inst, xs[k], vs[k], tm_r, tp_r, 1e-9)
+        for strategy, (tm, tp, st) in out.items():
+            assert np.array_equal(st[k], st_r), (strategy, k, st[k], st_r)
+            assert (np.abs(tm[k] - tm_r) <= bar_m).all(), (strategy, k, np.abs(tm[k] - tm_r) / bar_m)
+            assert (np.abs(tp[k] - tp_r) <= bar_p).all(), (strategy, k, np.abs(tp[k] - tp_r) / bar_p)
+
+
+def test_batch_intersect_rejects_reduced_precision(S):
+    insts = [I.gbase(6, 14, seed=41), I.arrow_ball(5)]
+    specs = [S.Spectrahedron(i) for i in insts]
+    specs[0].set_precision(1)
+    b = S.Batch(specs)
+    x = [np.zeros((4, 6)), np.zeros((4, 5))]
+    with pytest.raises(S.SpecError):
+        b.intersect(x, [np.ones((4, 6)), np.ones((4, 5))])

@@ -513,6 +513,117 @@ def paper_workload_leg(S, I, chains, rounds, warmup):
     return out
 
 
+def _tau_of(g, S, n):
+    """2 x the longest chord of a 64-chain, 20-step Hit-and-Run pre-run."""
+    _, _, _, log = g.walk(S.HNR, np.zeros((64, n)), 20, seed=11, log_chains=64, log_cap=64 * 20)
+    lg = log.cpu().numpy()
+    return 2.0 * float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+
+
+TABLE3_W = (1, 5, 10, 20, 30, 40, 50)
+TABLE3_PAPER_S = {100: (1.4, 3.2, 7.7, 9.5, 16.1, 21.4, 28.2), 200: (16.2, 75.7, 148.0, 303.0, 443.0, 584.0, 722.0)}
+
+
+def walk_length_leg(S, I, instances, points, sizes=(100, 200)):
+    """The walk-length table of the paper's expectation experiments (Section 4,
+    sampling for expectations): seconds to draw `points` points with the
+    billiard walk at walk lengths 1..50 on S-n-n spectrahedra of the paper's
+    generator, averaged over `instances` seeds.  One point per chain: `points`
+    chains walk W steps from the centre, all in one batch (the paper's run is
+    one sequential chain that keeps every W-th point).  Wall time of each walk
+    call, device synchronised on both sides; the paper's seconds (one CPU core)
+    beside them as context."""
+    import torch
+    out = {}
+    for n in sizes:
+        secs = {W: [] for W in TABLE3_W}
+        calls = {W: [] for W in TABLE3_W}
+        rounds = {W: [] for W in TABLE3_W}
+        for k in range(instances):
+            seed = 10000 + 100 * n + k
+            g = S.Spectrahedron(I.paper_random(n, n, seed=seed))
+            tau = _tau_of(g, S, n)
+            x0 = torch.zeros((points, n), dtype=torch.float64, device="cuda")
+            g.walk(S.BILLIARD, x0, 1, seed=1, tau=tau)  # workspaces
+            for W in TABLE3_W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, st, _ = g.walk(S.BILLIARD, x0, W, seed=5000 + 7 * k + W, tau=tau)
+                torch.cuda.synchronize()
+                secs[W].append(time.perf_counter() - t0)
+                calls[W].append(st["calls"])
+                rounds[W].append(st["rounds"])
+                assert st["steps"] == points * W and st["not_interior"] == 0
+            del g, x0
+            progress(f"walk-length table: S-{n}-{n} instance {k + 1}/{instances}")
+        out[f"S-{n}-{n}"] = {
+            "instances": instances, "points": points, "walk_lengths": list(TABLE3_W),
+            "seconds_mean": [float(np.mean(secs[W])) for W in TABLE3_W],
+            "seconds_sd": [float(np.std(secs[W])) for W in TABLE3_W],
+            "oracle_calls_mean": [float(np.mean(calls[W])) for W in TABLE3_W],
+            "rounds_mean": [float(np.mean(rounds[W])) for W in TABLE3_W],
+            "oracle_calls_per_s": [float(np.sum(calls[W]) / np.sum(secs[W])) for W in TABLE3_W],
+            "paper_seconds": list(TABLE3_PAPER_S[n]),
+            "paper_hardware": "Intel Core i7-6700 @3.4 GHz, one sequential walk, average of 10 instances "
+                              "(context, not the target)",
+        }
+    return out
+
+
+def estimator_leg(S, I, n, trials, points, lengths=TABLE3_W):
+    """Expectation estimators of the paper's uniform-sampling experiment
+    (Section 4, eq. estimator_error): I = E_pi[f] for f = 1(S cap H), H = {c x <=
+    b1 or c x >= b2}, estimated by the mean of f over N = `points` points, M =
+    `trials` times, for Hit-and-Run, coordinate Hit-and-Run and the billiard
+    walk at each walk length W.  Each trial is one chain from the centre that
+    keeps every W-th point (the paper's form); all trials of a walk run as one
+    batch.  S is S-n-n of the paper's generator (seed 20050), c a seeded unit
+    vector; b1 < b2 are chosen on a long reference run so that the two
+    functions have means near the paper's 0.0993 and 0.588, and a second,
+    independent reference run gives the values reported as the truth."""
+    import torch
+    g = S.Spectrahedron(I.paper_random(n, n, seed=20050))
+    tau = _tau_of(g, S, n)
+    c = np.random.default_rng(20051).standard_normal(n)
+    c /= np.linalg.norm(c)
+
+    def proj(samples):
+        return samples.cpu().numpy() @ c
+
+    ref_chains = 8192
+    x0 = torch.zeros((ref_chains, n), dtype=torch.float64, device="cuda")
+    xa, _, _, _ = g.walk(S.BILLIARD, x0, 100, seed=31, tau=tau)
+    xb, _, _, _ = g.walk(S.BILLIARD, x0, 100, seed=32, tau=tau)
+    ya, yb = proj(xa), proj(xb)
+    funcs = {}
+    for name, tail in (("f1", 0.0993), ("f2", 0.588)):
+        b1, b2 = np.quantile(ya, [tail / 2, 1 - tail / 2])
+        fb = ((yb <= b1) | (yb >= b2)).astype(float)
+        funcs[name] = {"b1": float(b1), "b2": float(b2), "truth": float(fb.mean()),
+                       "truth_se": float(fb.std() / np.sqrt(len(fb)))}
+    out = {"n": n, "m": n, "instance_seed": 20050, "trials": trials, "points": points, "walk_lengths": list(lengths),
+           "functions": funcs, "reference": f"{ref_chains} billiard chains x 100 steps from the centre, twice"}
+    xs = torch.zeros((trials, n), dtype=torch.float64, device="cuda")
+    for kind, name in ((S.HNR, "hit_and_run"), (S.CHNR, "coordinate_hit_and_run"), (S.BILLIARD, "billiard")):
+        res = {f: {"mean": [], "sd": []} for f in funcs}
+        secs = []
+        for W in lengths:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, smp, st, _ = g.walk(kind, xs, points * W, seed=900 + W, tau=tau, thin=W)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            y = proj(smp)  # trials x points
+            for f, d in funcs.items():
+                est = ((y <= d["b1"]) | (y >= d["b2"])).mean(axis=1)
+                res[f]["mean"].append(float(est.mean()))
+                res[f]["sd"].append(float(est.std(ddof=1)))
+        res["seconds"] = secs
+        out[name] = res
+        progress(f"estimators: {name} done")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -535,6 +646,9 @@ def main():
                     help="timed rounds of the HMC leg per precision mode (2000 for the full walk length)")
     ap.add_argument("--uneven-samples", type=int, default=256,
                     help="samples per cooling phase of the 256-spectrahedra volume (2000 for the full run)")
+    ap.add_argument("--walk-lengths", action="store_true",
+                    help="also run the walk-length table (S-100-100, S-200-200) and the estimator study")
+    ap.add_argument("--walk-length-instances", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -656,6 +770,10 @@ def main():
     if not args.no_paper:
         progress("paper workload: billiard on S-100-100 and S-200-200")
         out["paper_workload"] = paper_workload_leg(S, I, chains, args.steps, args.warmup)
+    if args.walk_lengths:
+        progress("walk-length table and expectation estimators")
+        out["walk_length_table"] = walk_length_leg(S, I, args.walk_length_instances, 200)
+        out["expectation_estimators"] = estimator_leg(S, I, 50, 20, 200)
     if not args.no_cpu:
         progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))

@@ -231,3 +231,41 @@ def test_refine_backoff_after_a_loose_first_pass(wl):
     assert np.sum(fl & 4 > 0) >= 32
     assert r[~failed].max() <= T_REL
     assert np.array_equal(tp[failed], tp_off[failed])
+
+
+def test_paper_generator_s200_walk_pairs():
+    """S-200-200 of the paper's own generator (Section 4: A0 = Z Z^T + I,
+    A_i = blkdiag(Qt, -Qt), no box block; the first instance of the
+    walk-length table): the billiard walk's logged segment starts, post-
+    reflection starts included, and Hit-and-Run chords against the oracle's
+    bisection, t+ at 1e-9 and t- at 1e-9 plus the near-root rounding bound."""
+    S = _S()
+    inst = I.paper_random(N, M, seed=10000 + 100 * N)
+    g, o = S.Spectrahedron(inst), O.Oracle(inst)
+    _, _, _, log = g.walk(S.HNR, np.zeros((64, N)), 6, seed=12, log_chains=64, log_cap=64 * 6)
+    hl = log.cpu().numpy()
+    tau = 2.0 * float(np.max(hl[:, 2 * N + 1] - hl[:, 2 * N]))
+    st, bl = billiard_log(S, g, 64, 12, tau, seed=13)
+    print(f"paper S-200-200 billiard: {st}")
+    assert st["not_interior"] == 0 and st["noconv"] == 0
+    pick = np.linspace(0, len(bl) - 1, 40).astype(int)
+    hpick = np.linspace(0, len(hl) - 1, 16).astype(int)
+    x = np.concatenate([bl[pick, :N], hl[hpick, :N]])
+    v = np.concatenate([bl[pick, N:2 * N], hl[hpick, N:2 * N]])
+    rtm, rtp, rst = bisect_threads(o, x, v)
+    assert (rst == O.OK).all()
+    kappa = (rtp - rtm) / np.minimum(np.abs(rtm), rtp)
+    print(f"kappa up to {kappa.max():.2e}; {int((kappa > 1e4).sum())} starts next to the boundary")
+    assert (kappa > 1e4).sum() >= 16
+    # the walks' own t+ (billiard) and t-, t+ (Hit-and-Run)
+    r = rel(bl[pick, 2 * N + 1], rtp[:40])
+    report("paper S-200-200 billiard log", r, kappa[:40])
+    assert r.max() <= T_REL
+    bar_m, bar_p = root_bars(inst, x, v, rtm, rtp, T_REL)
+    assert np.all(np.abs(hl[hpick, 2 * N + 1] - rtp[40:]) <= bar_p[40:])
+    assert np.all(np.abs(hl[hpick, 2 * N] - rtm[40:]) <= bar_m[40:])
+    # the call-level oracle on the same pairs
+    tm, tp, st2 = [t.cpu().numpy() for t in g.intersect(x, v)]
+    assert (st2 == S.OK).all()
+    assert np.all(np.abs(tp - rtp) <= bar_p), np.max(np.abs(tp - rtp) / bar_p)
+    assert np.all(np.abs(tm - rtm) <= bar_m), np.max(np.abs(tm - rtm) / bar_m)

@@ -712,6 +712,31 @@ static double chord_sample(int n, const double* x, const double* v, double vv, d
     return t;
 }
 
+/* Position on the chord [t-, t+] of x + t v under the Boltzmann density
+ * exp(-<c, y> / T) (the optimisation section, eq. (sdp)): along the line the
+ * density is proportional to exp(-lam t), lam = <c, v> / T, a truncated
+ * exponential, sampled by inverting its CDF.  For lam >= 0 the CDF from t-
+ * is (1 - e^{-lam (t - t-)}) / (1 - e^{-lam L}), L = t+ - t-; for lam < 0 the
+ * same form is taken from t+ backwards with 1 - u, so that t grows with u. */
+static double chord_sample_boltz(int n, const double* x, const double* v, const double* c, double T,
+                                 double tm, double tp, double u) {
+    double cv = 0.0;
+    for (int i = 0; i < n; i++) cv += c[i] * v[i];
+    (void)x;
+    double lam = cv / T, L = tp - tm;
+    if (fabs(lam * L) < 1e-12) return tm + u * L;
+    double t;
+    if (lam > 0.0) {
+        t = tm - log1p(u * expm1(-lam * L)) / lam;
+    } else {
+        double mu = -lam;
+        t = tp + log1p((1.0 - u) * expm1(-mu * L)) / mu;
+    }
+    if (t < tm) t = tm;
+    if (t > tp) t = tp;
+    return t;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Walks                                                                     */
 /* ------------------------------------------------------------------------ */
@@ -754,9 +779,9 @@ typedef struct {
 
 /* One step of each walk for one chain; x is updated in place. */
 static void walk_step(const orc_lmi* h, int kind, uint64_t seed, uint32_t chain, uint32_t step,
-                      double tau, int rho, double gauss_a, double pullback, double* x, double* v,
-                      double* p, double* s_dir, double* u, double* coef, scratch* s, double* Q0,
-                      double* Q1, double* Q2, wstats* ws) {
+                      double tau, int rho, double gauss_a, const double* bc, double bT, double pullback,
+                      double* x, double* v, double* p, double* s_dir, double* u, double* coef, scratch* s,
+                      double* Q0, double* Q1, double* Q2, wstats* ws) {
     int n = h->n;
     ws->steps += 1;
     if (kind == ORC_HNR || kind == ORC_CHNR) {
@@ -776,7 +801,8 @@ static void walk_step(const orc_lmi* h, int kind, uint64_t seed, uint32_t chain,
         if (r.status == ORC_NOCONV) ws->noconv += 1;
         if (isinf(r.tp) || isinf(r.tm)) return; /* unbounded chord: stay */
         draw_u2(seed, chain, step, 0, TAG_POS, uu);
-        double t = chord_sample(n, x, v, 1.0, r.tm, r.tp, gauss_a, uu[0]);
+        double t = bc ? chord_sample_boltz(n, x, v, bc, bT, r.tm, r.tp, uu[0])
+                      : chord_sample(n, x, v, 1.0, r.tm, r.tp, gauss_a, uu[0]);
         for (int i = 0; i < n; i++) x[i] += t * v[i];
         return;
     }
@@ -804,6 +830,62 @@ static void walk_step(const orc_lmi* h, int kind, uint64_t seed, uint32_t chain,
             for (int i = 0; i < n; i++) p[i] += (1.0 - pullback) * r.tp * v[i];
             ell -= r.tp;
             memcpy(v, s_dir, sizeof(double) * n);
+            nref++;
+            ws->refl += 1;
+            if (nref > rho) { ws->caps += 1; return; }
+        }
+        memcpy(x, p, sizeof(double) * n);
+        return;
+    }
+    if (bc) {
+        /* Alg. HMC with reflections for the Boltzmann density exp(-<c, x> / T):
+         * the ODE of eq. (boltz_ode) has the solution
+         * p(t) = p + t v - t^2 c / (2T), velocity v - t c / T, so
+         * F(p(t)) = F(p) + t B(v) + t^2 B(-c / (2T)): a degree-2 curve whose
+         * first root inside the remaining travel time ends the segment. */
+        double ell = tau * uu[0];
+        draw_normals(seed, chain, step, TAG_MOM, n, v);
+        memcpy(p, x, sizeof(double) * n);
+        int nref = 0;
+        while (ell > 0.0) {
+            coef[0] = 1.0;
+            for (int i = 0; i < n; i++) coef[1 + i] = p[i];
+            coef[n + 1] = 0.0;
+            for (int i = 0; i < n; i++) coef[n + 2 + i] = v[i];
+            coef[2 * (n + 1)] = 0.0;
+            for (int i = 0; i < n; i++) coef[2 * (n + 1) + 1 + i] = -bc[i] / (2.0 * bT);
+            int status = ORC_OK, it = 0, bh, jh;
+            double ts = curve2_first(h, coef, 1.0, ell, s, Q0, Q1, Q2, &status, &it, &bh, &jh);
+            ws->calls += 1;
+            if (status == ORC_NOT_INTERIOR) { ws->notint += 1; return; }
+            if (status == ORC_NOCONV) ws->noconv += 1;
+            if (isinf(ts)) {
+                /* no boundary within the travel time left: fly to its end */
+                for (int i = 0; i < n; i++) {
+                    p[i] += ell * v[i] - ell * ell * bc[i] / (2.0 * bT);
+                    v[i] -= ell * bc[i] / bT;
+                }
+                ell = 0.0;
+                break;
+            }
+            /* hit point, velocity there, normal, reflected velocity */
+            double* ph = s_dir;
+            double* vh = s->w;
+            for (int i = 0; i < n; i++) {
+                ph[i] = p[i] + ts * v[i] - ts * ts * bc[i] / (2.0 * bT);
+                vh[i] = v[i] - ts * bc[i] / bT;
+            }
+            double* wn = (double*)malloc(sizeof(double) * n);
+            if (h->kind[bh] == ORC_DENSE) kernel_vector(h, bh, ph, s, u);
+            normal_at(h, bh, jh, u, wn);
+            double* snew = (double*)malloc(sizeof(double) * n);
+            int zero = reflect_dir(n, vh, wn, snew);
+            if (zero) ws->nonsmooth += 1;
+            double t1 = (1.0 - pullback) * ts;
+            for (int i = 0; i < n; i++) p[i] += t1 * v[i] - t1 * t1 * bc[i] / (2.0 * bT);
+            memcpy(v, snew, sizeof(double) * n);
+            free(wn); free(snew);
+            ell -= ts;
             nref++;
             ws->refl += 1;
             if (nref > rho) { ws->caps += 1; return; }
@@ -887,8 +969,8 @@ int orc_walk(const orc_lmi* h, int kind, int chains, const double* x0, int64_t s
         double* x = x_out + (size_t)c * n;
         memcpy(x, x0 + (size_t)c * n, sizeof(double) * n);
         for (int64_t k = 0; k < steps; k++) {
-            walk_step(h, kind, seed, (uint32_t)c, (uint32_t)k, tau, rho, gauss_a, pullback, x, v, p,
-                      sd, u, coef, &s, Q0, Q1, Q2, &ws);
+            walk_step(h, kind, seed, (uint32_t)c, (uint32_t)k, tau, rho, gauss_a, NULL, 0.0, pullback, x, v,
+                      p, sd, u, coef, &s, Q0, Q1, Q2, &ws);
             if (samples && thin > 0 && (k + 1) % thin == 0) {
                 int64_t j = (k + 1) / thin - 1;
                 memcpy(samples + ((size_t)c * nsamp + j) * n, x, sizeof(double) * n);
@@ -902,6 +984,109 @@ int orc_walk(const orc_lmi* h, int kind, int chains, const double* x0, int64_t s
     free(v); free(p); free(sd); free(u); free(coef); free(Q0); free(Q1); free(Q2);
     scratch_free(&s);
     return ORC_OK;
+}
+
+/* Walks on the Boltzmann density exp(-<c, x> / T) truncated to S (the
+ * optimisation section): Hit-and-Run and coordinate Hit-and-Run with the
+ * truncated exponential on each chord, HMC with reflections on the curve of
+ * eq. (boltz_ode).  `steps` steps of chain `chain` from x_in, step k drawing
+ * with counter (chain, step0 + k); every thin-th point into samples
+ * (nullable); counts added to stats (8 entries, nullable). */
+static int walk_chain_boltz(const orc_lmi* h, int kind, int chain, const double* x_in, int64_t step0,
+                            int64_t steps, uint64_t seed, double tau, int rho, const double* c, double T,
+                            double pullback, int thin, double* samples, double* x_out, double* stats) {
+    int n = h->n;
+    scratch s;
+    if (scratch_alloc(h, &s)) { scratch_free(&s); return ORC_ENOMEM; }
+    size_t mm = (size_t)max_block(h);
+    double* v = (double*)malloc(sizeof(double) * n);
+    double* p = (double*)malloc(sizeof(double) * n);
+    double* sd = (double*)malloc(sizeof(double) * n);
+    double* u = (double*)malloc(sizeof(double) * mm);
+    double* coef = (double*)malloc(sizeof(double) * 3 * (n + 1));
+    double* Q0 = (double*)malloc(sizeof(double) * mm * mm);
+    double* Q1 = (double*)malloc(sizeof(double) * mm * mm);
+    double* Q2 = (double*)malloc(sizeof(double) * mm * mm);
+    wstats ws = {0, 0, 0, 0, 0, 0, 0};
+    memcpy(x_out, x_in, sizeof(double) * n);
+    for (int64_t k = 0; k < steps; k++) {
+        walk_step(h, kind, seed, (uint32_t)chain, (uint32_t)(step0 + k), tau, rho, 0.0, c, T, pullback, x_out,
+                  v, p, sd, u, coef, &s, Q0, Q1, Q2, &ws);
+        if (samples && thin > 0 && (k + 1) % thin == 0)
+            memcpy(samples + (size_t)((k + 1) / thin - 1) * n, x_out, sizeof(double) * n);
+    }
+    if (stats) {
+        stats[0] += ws.calls; stats[1] += ws.refl; stats[2] += ws.caps; stats[3] += ws.notint;
+        stats[4] += ws.nonsmooth; stats[5] += ws.steps; stats[6] += ws.noconv;
+    }
+    free(v); free(p); free(sd); free(u); free(coef); free(Q0); free(Q1); free(Q2);
+    scratch_free(&s);
+    return ORC_OK;
+}
+
+int orc_walk_boltz(const orc_lmi* h, int kind, int chains, const double* x0, int64_t step0, int64_t steps,
+                   uint64_t seed, double tau, int rho, const double* c, double T, double pullback,
+                   int thin, double* x_out, double* samples, double* stats) {
+    if (!h || chains < 0 || steps < 0 || step0 < 0 || !c || !(T > 0.0) || (chains && (!x0 || !x_out)))
+        return ORC_EINVAL;
+    if (kind != ORC_HNR && kind != ORC_CHNR && kind != ORC_HMC) return ORC_EINVAL;
+    if (kind == ORC_HMC && !(tau > 0.0)) return ORC_EINVAL;
+    int n = h->n;
+    int64_t nsamp = thin > 0 ? steps / thin : 0;
+    if (stats) for (int k = 0; k < 8; k++) stats[k] = 0.0;
+    for (int j = 0; j < chains; j++) {
+        int rc = walk_chain_boltz(h, kind, j, x0 + (size_t)j * n, step0, steps, seed, tau, rho, c, T, pullback,
+                                  thin, samples ? samples + (size_t)j * nsamp * n : NULL, x_out + (size_t)j * n,
+                                  stats);
+        if (rc != ORC_OK) return rc;
+    }
+    return ORC_OK;
+}
+
+/* Simulated annealing for min <c, x> over S (eq. (sdp); the schedule of the
+ * optimisation section): at iteration i the chain walks walk_len steps of the
+ * Boltzmann walk at T_i = T0 (1 - cool)^i with travel-time scale
+ * tau_i = tau0 sqrt(T_i / T0) (HMC; with time measured in units of sqrt(T)
+ * this is HMC at temperature T with momenta N(0, T I) and a fixed travel
+ * time), then the best <c, x> seen so far is updated.
+ * Per chain: x_best, f_best; best[j * iters + i] is chain j's best after
+ * iteration i.  The step counter runs on across iterations. */
+int orc_sdp_anneal(const orc_lmi* h, int kind, int chains, const double* x0, const double* c, double T0,
+                   double cool, int iters, int walk_len, uint64_t seed, double tau0, int rho, double pullback,
+                   double* x_best, double* f_best, double* best) {
+    if (!h || chains < 0 || iters < 0 || walk_len < 1 || !c || !(T0 > 0.0) || !(cool >= 0.0 && cool < 1.0) ||
+        (chains && (!x0 || !x_best || !f_best)))
+        return ORC_EINVAL;
+    int n = h->n;
+    double* x = (double*)malloc(sizeof(double) * n);
+    double* y = (double*)malloc(sizeof(double) * n);
+    int rc = ORC_OK;
+    for (int j = 0; j < chains && rc == ORC_OK; j++) {
+        memcpy(x, x0 + (size_t)j * n, sizeof(double) * n);
+        double fb = 0.0;
+        for (int i = 0; i < n; i++) fb += c[i] * x[i];
+        memcpy(x_best + (size_t)j * n, x, sizeof(double) * n);
+        double T = T0;
+        for (int it = 0; it < iters; it++) {
+            /* one chain of the walk, with its own chain index for the draws */
+            rc = walk_chain_boltz(h, kind, j, x, (int64_t)it * walk_len, walk_len, seed, tau0 * sqrt(T / T0), rho, c,
+                                  T, pullback, 0, NULL, y, NULL);
+            if (rc != ORC_OK) break;
+            memcpy(x, y, sizeof(double) * n);
+            double f = 0.0;
+            for (int i = 0; i < n; i++) f += c[i] * x[i];
+            if (f < fb) {
+                fb = f;
+                memcpy(x_best + (size_t)j * n, x, sizeof(double) * n);
+            }
+            if (best) best[(size_t)j * iters + it] = fb;
+            T *= 1.0 - cool;
+        }
+        f_best[j] = fb;
+    }
+    free(x);
+    free(y);
+    return rc;
 }
 
 int orc_billiard_segment(const orc_lmi* h, int batch, const double* x, const double* v,

@@ -71,6 +71,21 @@ int orc_walk(const orc_lmi* h, int kind, int chains, const double* x0, int64_t s
              uint64_t seed, double tau, int rho, double gauss_a, double pullback,
              int thin, double* x_out, double* samples, double* stats);
 
+/* Walks on the Boltzmann density exp(-<c, x> / T) truncated to S (kind
+ * ORC_HNR, ORC_CHNR: truncated exponential on each chord; ORC_HMC: HMC with
+ * reflections on p(t) = p + t v - t^2 c / (2T)); step k of chain j draws
+ * with counter (j, step0 + k).  stats as orc_walk. */
+int orc_walk_boltz(const orc_lmi* h, int kind, int chains, const double* x0, int64_t step0, int64_t steps,
+                   uint64_t seed, double tau, int rho, const double* c, double T, double pullback,
+                   int thin, double* x_out, double* samples, double* stats);
+
+/* Annealing for min <c, x> over S: iteration i walks walk_len Boltzmann steps
+ * at T_i = T0 (1 - cool)^i (HMC travel-time scale tau0 sqrt(T_i / T0)), then keeps
+ * the best <c, x>; best (nullable) is chains x iters. */
+int orc_sdp_anneal(const orc_lmi* h, int kind, int chains, const double* x0, const double* c, double T0,
+                   double cool, int iters, int walk_len, uint64_t seed, double tau0, int rho, double pullback,
+                   double* x_best, double* f_best, double* best);
+
 /* One segment of the billiard walk for a given (x, v, ell): used to check the
  * device step machine on identical inputs. Writes x_new, v_new, ell_left and
  * flags[0] = 1 if reflected, flags[1] = status. */

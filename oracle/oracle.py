@@ -49,6 +49,10 @@ def lib():
         L.orc_walk.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int64, C.c_uint64, C.c_double, C.c_int,
                                C.c_double, C.c_double, C.c_int, dp, dp, dp]
         L.orc_billiard_segment.argtypes = [vp, C.c_int, dp, dp, dp, C.c_double, dp, dp, dp, i32p]
+        L.orc_walk_boltz.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint64, C.c_double,
+                                     C.c_int, dp, C.c_double, C.c_double, C.c_int, dp, dp, dp]
+        L.orc_sdp_anneal.argtypes = [vp, C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                     C.c_uint64, C.c_double, C.c_int, C.c_double, dp, dp, dp]
         L.orc_volume.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_double,
                                  C.c_double, C.c_int, dp, dp, dp, dp]
         L.orc_mlp_nparams.argtypes = [C.c_int, ip]
@@ -165,6 +169,36 @@ class Oracle:
         if rc != OK:
             raise ValueError(f"orc_walk failed: {rc}")
         return xo, samples[:, :ns], stats
+
+    def walk_boltz(self, kind, x0, steps, seed, c, T, tau=1.0, rho=None, pullback=1e-6, thin=0, step0=0):
+        """Walk on exp(-<c, x> / T) truncated to S (HNR, CHNR or HMC)."""
+        x0 = _d(x0).reshape(-1, self.n)
+        ch = x0.shape[0]
+        rho = 10 * self.n if rho is None else rho
+        c = _d(c).reshape(self.n)
+        xo = np.empty_like(x0)
+        ns = steps // thin if thin > 0 else 0
+        samples = np.empty((ch, max(ns, 1), self.n))
+        stats = np.zeros(8)
+        rc = lib().orc_walk_boltz(self._h, kind, ch, _p(x0), step0, steps, seed, tau, rho, _p(c), T, pullback,
+                                  thin, _p(xo), _p(samples), _p(stats))
+        if rc != OK:
+            raise ValueError(f"orc_walk_boltz failed: {rc}")
+        return xo, samples[:, :ns], stats
+
+    def sdp_anneal(self, kind, x0, c, T0, cool, iters, walk_len, seed, tau0, rho=None, pullback=1e-6):
+        """Annealing for min <c, x> over S: (x_best, f_best, best per iteration)."""
+        x0 = _d(x0).reshape(-1, self.n)
+        ch = x0.shape[0]
+        rho = 10 * self.n if rho is None else rho
+        c = _d(c).reshape(self.n)
+        xb, fb = np.empty_like(x0), np.empty(ch)
+        best = np.empty((ch, max(iters, 1)))
+        rc = lib().orc_sdp_anneal(self._h, kind, ch, _p(x0), _p(c), T0, cool, iters, walk_len, seed, tau0, rho,
+                                  pullback, _p(xb), _p(fb), _p(best))
+        if rc != OK:
+            raise ValueError(f"orc_sdp_anneal failed: {rc}")
+        return xb, fb, best[:, :iters]
 
     def billiard_segment(self, x, v, ell, pullback=1e-6):
         x = _d(x).reshape(-1, self.n)

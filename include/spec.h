@@ -252,7 +252,16 @@ spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const
  *            segments of chains c < log_chains: records of 2n+4 doubles
  *            (x, v, t-, t+, chain, status) (HMC: (p, velocity, remaining travel time,
  *            first root u+ of the segment's pencil, chain, status)), log_count (device int32, zeroed
- *            by the caller) counts the records attempted. */
+ *            by the caller) counts the records attempted.
+ *  boltz_c, boltz_T   Boltzmann target exp(-<boltz_c, x> / boltz_T) restricted
+ *            to S (the optimisation section, eq. (sdp)); boltz_c null = none,
+ *            else n doubles (device memory for spec_walk_run_dev, host memory
+ *            for spec_walk_run) and boltz_T > 0.  Hit-and-Run and coordinate
+ *            Hit-and-Run draw the chord point from the truncated exponential
+ *            exp(-t <c, v> / T); HMC follows p(t) = p + t v - t^2 c / (2T)
+ *            (eq. (boltz_ode)), each segment one degree-2 curve whose horizon
+ *            is the travel time left, and reflects the velocity v - t c / T at
+ *            the hit.  Not with the billiard walk or with gauss_a > 0. */
 typedef struct {
     double tau;
     int rho;
@@ -265,6 +274,8 @@ typedef struct {
     int log_cap;
     double* log_buf;
     int32_t* log_count;
+    const double* boltz_c;
+    double boltz_T;
 } spec_walk_params;
 
 /* Totals over chains, counted over the rounds of this call (a resumed call
@@ -293,11 +304,47 @@ typedef struct {
  * Kinds HNR, CHNR, BILLIARD, HMC (Alg. HMC with reflections for the Gaussian
  * target exp(-gauss_a |x|^2): travel time ell = tau eta, momentum N(0, I),
  * exact elliptic flow, each segment a degree-2 curve solved as in
- * spec_intersect_curve; gauss_a > 0 and tau > 0 required); SPEC_EINVAL for
- * bad arguments. */
+ * spec_intersect_curve; or for the Boltzmann target of boltz_c, boltz_T;
+ * exactly one of the two and tau > 0 required); SPEC_EINVAL for bad
+ * arguments. */
 spec_status spec_walk_run_dev(spec_handle h, int kind, int chains, const double* x0, long long steps,
                               uint64_t seed, const spec_walk_params* p, double* x_out, double* samples,
                               spec_walk_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Semidefinite optimisation by annealing (the optimisation section:
+ * min <c, x> over S, eq. (sdp)).  Every chain walks the Boltzmann density
+ * exp(-<c, x> / T_i) for walk_len steps at each temperature
+ * T_i = T0 (1 - cool)^i, i = 0 .. iterations - 1, and keeps the best <c, x>
+ * it has visited.  HMC (walk length one in the paper's runs) uses the travel
+ * time scale tau_i = tau0 sqrt(T_i / T0): with time measured in units of
+ * sqrt(T) this is HMC at temperature T with momenta N(0, T I) and a fixed
+ * travel time, so the pull of c moves a chain by O(tau0^2 |c| / T0) per step
+ * at every temperature.  Draws continue the chain's step counter across
+ * temperatures (Philox counter (chain, step)).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int kind;        /* SPEC_WALK_HMC, SPEC_WALK_HNR or SPEC_WALK_CHNR */
+    int iterations;  /* temperatures */
+    int walk_len;    /* steps per temperature (>= 1) */
+    double T0;       /* first temperature (> 0; the paper: about diam(S) for |c| = 1) */
+    double cool;     /* T_{i+1} = T_i (1 - cool); <= 0: 1 / sqrt(n) */
+    double tau0;     /* HMC travel-time scale at T0 (> 0 for HMC; the paper: the diameter) */
+    int rho;         /* reflection cap per step (<= 0: 10 n) */
+    double pullback; /* as spec_walk_params (<= 0: 1e-6) */
+    double f_star;   /* known optimum for hit_iter (NaN: none) */
+    double eps;      /* relative error that counts as reached (<= 0: 0.05) */
+} spec_anneal_params;
+
+/* Host arrays: x0 (chains x n) interior starts, c (n); outputs x_best
+ * (chains x n, nullable), f_best (chains), best (chains x iterations,
+ * nullable: each chain's best <c, x> after each temperature), hit_iter
+ * (chains, nullable: first iteration whose best is within eps |f_star| of
+ * f_star, -1 if none or f_star is NaN), stats (nullable: walk totals over all
+ * temperatures).  Synchronises.  SPEC_EINVAL for bad arguments. */
+spec_status spec_sdp_anneal(spec_handle h, const spec_anneal_params* p, int chains, const double* x0,
+                            const double* c, uint64_t seed, double* x_best, double* f_best, double* best,
+                            int32_t* hit_iter, spec_walk_stats* stats);
 
 /* spec_walk_run_dev on HOST arrays (x0, x_out: chains x n; samples nullable:
  * chains x (steps/thin) x n), synchronous: the walk runs on the handle's

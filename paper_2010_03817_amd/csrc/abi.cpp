@@ -645,14 +645,20 @@ spec_status spec_walk_run(spec_handle h, int kind, int chains, const double* x0,
     }
     const size_t cn = (size_t)chains * h->n;
     const long long ns = p->thin > 0 ? steps / p->thin : 0;
-    double *dx0 = nullptr, *dxo = nullptr, *dsm = nullptr;
+    double *dx0 = nullptr, *dxo = nullptr, *dsm = nullptr, *dbc = nullptr;
     spec_status rc = SPEC_OK;
     hipError_t e = dalloc(&dx0, cn, false);
     if (e == hipSuccess) e = dalloc(&dxo, cn, false);
     if (e == hipSuccess && samples && ns > 0) e = dalloc(&dsm, cn * (size_t)ns, false);
     if (e == hipSuccess) e = hipMemcpy(dx0, x0, sizeof(double) * cn, hipMemcpyHostToDevice);
+    spec_walk_params pd = *p;
+    if (e == hipSuccess && p->boltz_c) {
+        e = dalloc(&dbc, (size_t)h->n, false);
+        if (e == hipSuccess) e = hipMemcpy(dbc, p->boltz_c, sizeof(double) * h->n, hipMemcpyHostToDevice);
+        pd.boltz_c = dbc;
+    }
     if (e != hipSuccess) rc = from_hip(e);
-    if (rc == SPEC_OK) rc = spec_walk_run_dev(h, kind, chains, dx0, steps, seed, p, dxo, dsm, stats, nullptr);
+    if (rc == SPEC_OK) rc = spec_walk_run_dev(h, kind, chains, dx0, steps, seed, &pd, dxo, dsm, stats, nullptr);
     if (rc == SPEC_OK) {
         e = hipDeviceSynchronize();
         if (e == hipSuccess) e = hipMemcpy(x_out, dxo, sizeof(double) * cn, hipMemcpyDeviceToHost);
@@ -663,6 +669,82 @@ spec_status spec_walk_run(spec_handle h, int kind, int chains, const double* x0,
     dfree(dx0);
     dfree(dxo);
     dfree(dsm);
+    dfree(dbc);
+    return rc;
+}
+
+spec_status spec_sdp_anneal(spec_handle h, const spec_anneal_params* p, int chains, const double* x0,
+                            const double* c, uint64_t seed, double* x_best, double* f_best, double* best,
+                            int32_t* hit_iter, spec_walk_stats* stats) {
+    if (!h || !p || chains < 0 || !x0 || !c || !f_best) return SPEC_EINVAL;
+    if (p->kind != SPEC_WALK_HMC && p->kind != SPEC_WALK_HNR && p->kind != SPEC_WALK_CHNR) return SPEC_EINVAL;
+    if (p->iterations < 0 || p->walk_len < 1 || !(p->T0 > 0.0) || !(p->cool < 1.0)) return SPEC_EINVAL;
+    if (p->kind == SPEC_WALK_HMC && !(p->tau0 > 0.0)) return SPEC_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (chains == 0) return SPEC_OK;
+    const int n = h->n, iters = p->iterations;
+    const double cool = p->cool > 0.0 ? p->cool : 1.0 / std::sqrt((double)n);
+    const double eps = p->eps > 0.0 ? p->eps : 0.05;
+    const size_t cn = (size_t)chains * n;
+    hipStream_t s = nullptr;
+    double *dx0 = nullptr, *dx = nullptr, *dc = nullptr, *dxb = nullptr, *dfb = nullptr, *dbest = nullptr;
+    int32_t* dhit = nullptr;
+    spec_status rc = SPEC_OK;
+    auto fail = [&](hipError_t e) {
+        if (rc == SPEC_OK && e != hipSuccess) rc = from_hip(e);
+        return rc != SPEC_OK;
+    };
+    if (!fail(dalloc(&dx0, cn, false)) && !fail(dalloc(&dx, cn, false)) && !fail(dalloc(&dc, (size_t)n, false)) &&
+        !fail(dalloc(&dxb, cn, false)) && !fail(dalloc(&dfb, (size_t)chains, false)) &&
+        !fail(dalloc(&dhit, (size_t)chains, false)) &&
+        !fail(dalloc(&dbest, (size_t)chains * std::max(iters, 1), false)) &&
+        !fail(hipMemcpy(dx0, x0, sizeof(double) * cn, hipMemcpyHostToDevice)) &&
+        !fail(hipMemcpy(dc, c, sizeof(double) * n, hipMemcpyHostToDevice)) &&
+        !fail(anneal_track(chains, n, dx0, dc, 0, iters, dxb, dfb, dbest, dhit, p->f_star, eps, true, s))) {
+        spec_walk_params wp{};
+        wp.rho = p->rho;
+        wp.pullback = p->pullback > 0.0 ? p->pullback : 1e-6;
+        wp.boltz_c = dc;
+        double T = p->T0;
+        for (int it = 0; it < iters && rc == SPEC_OK; ++it) {
+            wp.tau = p->kind == SPEC_WALK_HMC ? p->tau0 * std::sqrt(T / p->T0) : 1.0;
+            wp.boltz_T = T;
+            wp.resume = it > 0;
+            spec_walk_stats st{};
+            rc = walk_run_impl(h, p->kind, chains, dx0, (long long)(it + 1) * p->walk_len, seed, &wp, dx, nullptr,
+                               0, 0, stats ? &st : nullptr, s);
+            if (rc != SPEC_OK) break;
+            if (fail(anneal_track(chains, n, dx, dc, it, iters, dxb, dfb, dbest, dhit, p->f_star, eps, false, s)))
+                break;
+            if (stats) {
+                stats->calls += st.calls;
+                stats->reflections += st.reflections;
+                stats->cap_hits += st.cap_hits;
+                stats->not_interior += st.not_interior;
+                stats->nonsmooth += st.nonsmooth;
+                stats->steps += st.steps;
+                stats->noconv += st.noconv;
+                stats->rounds += st.rounds;
+                stats->refined += st.refined;
+                stats->refine_failed += st.refine_failed;
+                stats->uncertified += st.uncertified;
+            }
+            T *= 1.0 - cool;
+        }
+    }
+    if (rc == SPEC_OK && !fail(hipDeviceSynchronize())) {
+        if (x_best) fail(hipMemcpy(x_best, dxb, sizeof(double) * cn, hipMemcpyDeviceToHost));
+        fail(hipMemcpy(f_best, dfb, sizeof(double) * chains, hipMemcpyDeviceToHost));
+        if (best && iters > 0) fail(hipMemcpy(best, dbest, sizeof(double) * chains * iters, hipMemcpyDeviceToHost));
+        if (hit_iter) fail(hipMemcpy(hit_iter, dhit, sizeof(int32_t) * chains, hipMemcpyDeviceToHost));
+    }
+    dfree(dx0);
+    dfree(dx);
+    dfree(dc);
+    dfree(dxb);
+    dfree(dfb);
+    dfree(dbest);
+    dfree(dhit);
     return rc;
 }
 
@@ -717,7 +799,8 @@ spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0,
     if (kind != SPEC_WALK_HNR && kind != SPEC_WALK_CHNR && kind != SPEC_WALK_BILLIARD && kind != SPEC_WALK_HMC)
         return SPEC_EINVAL;
     if ((kind == SPEC_WALK_BILLIARD || kind == SPEC_WALK_HMC) && !(p->tau > 0.0)) return SPEC_EINVAL;
-    if (kind == SPEC_WALK_HMC && !(p->gauss_a > 0.0)) return SPEC_EINVAL;
+    if (p->boltz_c && (!(p->boltz_T > 0.0) || p->gauss_a > 0.0 || kind == SPEC_WALK_BILLIARD)) return SPEC_EINVAL;
+    if (kind == SPEC_WALK_HMC && !(p->gauss_a > 0.0) && !p->boltz_c) return SPEC_EINVAL;
     if (p->gauss_a < 0.0 || !(p->pullback >= 0.0 && p->pullback < 1.0) || p->thin < 0) return SPEC_EINVAL;
     if (p->log_buf && (!p->log_count || p->log_cap < 0)) return SPEC_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -743,6 +826,8 @@ WalkArgs make_walk_args(spec_handle h, int kind, int chains, long long steps, ui
     a.gauss_a = p->gauss_a;
     a.pullback = p->pullback;
     a.rho = p->rho > 0 ? p->rho : 10 * h->n;
+    a.bc = p->boltz_c;
+    a.bT = p->boltz_T;
     a.st = WalkState{h->wX, h->wXs, h->wV, h->wEll, h->wNref, h->wStep, h->wActive, h->wStats};
     a.status = h->dSt;
     a.flags = h->dFlags;
@@ -810,7 +895,9 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
             HIPCHK(hipStreamSynchronize(s));
             h->lanczos_steps += ls;
         }
-        if (rounds % 16 == 0 || rounds == max_rounds) {
+        // the first checks early (short calls, e.g. one step per annealing
+        // temperature, end after a few rounds), then every 16 rounds
+        if (rounds % 16 == 0 || rounds == max_rounds || (rounds & (rounds - 1)) == 0) {
             int32_t live = 0;
             HIPCHK(walk_count_active(chains, h->wActive, h->wCount, s));
             HIPCHK(hipMemcpyAsync(&live, h->wCount, sizeof(int32_t), hipMemcpyDeviceToHost, s));

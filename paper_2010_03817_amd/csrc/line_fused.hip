@@ -2333,8 +2333,8 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
             const double sg = dir == 0 ? 1.0 : -1.0;
             const bool vec_dir = a.want_vec && dir == 0;
             double tau = 0.0, tau_prev = 0.0, root = INFINITY;
-            bool vec_ok = false, backoff = false;
-            int rung = 0;
+            bool vec_ok = false, backoff = false, done = false;
+            int rung = 0, halvings = 0;
             for (int it = 0; it < 210; ++it) {
                 ++iters;
                 fill_quadratic(L, Q0, Q1, Q2, tau, sg, P, t, blockDim.x);
@@ -2348,7 +2348,18 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                     }
                     if (it == 0) {
                         st = SPEC_NOT_INTERIOR;
+                        done = true;
                         break;
+                    }
+                    // a step above the rounding level that left the feasible set:
+                    // its bound was not a lower bound of lambda_min (single-vector
+                    // Lanczos can converge to the second of two nearly equal smallest
+                    // eigenvalues, as where two faces of S meet).  Halve it back
+                    // towards the last definite iterate and step again from there.
+                    if (!backoff && tau - tau_prev > 1e-12 * tau && halvings < 60) {
+                        ++halvings;
+                        tau = tau_prev + 0.5 * (tau - tau_prev);
+                        continue;
                     }
                     // definiteness lost at the rounding level: the root is tau.  For the
                     // kernel vector, factor just inside it: root (1 - delta) for delta =
@@ -2356,7 +2367,10 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                     // until a factor exists; there the pencil's most negative
                     // eigenvalue is isolated and its eigenvector is the kernel direction.
                     if (!backoff) root = tau;
-                    if (!vec_dir || rung == 4) break;  // no factor next to the root: no kernel vector
+                    if (!vec_dir || rung == 4) {  // no factor next to the root: no kernel vector
+                        done = true;
+                        break;
+                    }
                     backoff = true;
                     const double delta = rung == 0 ? 1e-12 : (rung == 1 ? 1e-10 : (rung == 2 ? 1e-8 : 1e-6));
                     ++rung;
@@ -2401,19 +2415,33 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
                 }
                 if (backoff) {
                     vec_ok = true;
+                    done = true;
                     break;
                 }
                 const double step = first_root_q(d[1], d[0]);
-                if (!(step < INFINITY)) break;
+                if (!(step < INFINITY)) {
+                    done = true;
+                    break;
+                }
                 const double next = tau + step;
-                if (next > hz) break;
+                if (next > hz) {
+                    done = true;
+                    break;
+                }
                 if (step <= 1e-15 * next) {
                     root = next;
                     vec_ok = true;
+                    done = true;
                     break;
                 }
                 tau_prev = tau;
                 tau = next;
+            }
+            if (!done) {
+                // out of iterations: the last definite iterate bounds the root
+                // from below (no kernel vector there)
+                conv = false;
+                if (!backoff) root = tau_prev;
             }
             if (st != SPEC_OK) break;
             if (dir == 0) {

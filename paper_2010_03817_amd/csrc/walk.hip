@@ -92,6 +92,8 @@ __global__ __launch_bounds__(256) void k_walk_init(WalkArgs a, const double* __r
 // a degree-2 pencil in u with the same roots.  A segment covers at most a
 // quarter turn (u <= 1).  This kernel writes the pencil's coefficient rows
 // [1, p], [0, 2 sigma v], [1, -p] and the horizon u_h = tan(theta_h / 2).
+// For the Boltzmann target exp(-<c, x> / T) the trajectory is itself the
+// degree-2 curve p + t v - t^2 c / (2T) (eq. (boltz_ode)) in t.
 __global__ __launch_bounds__(256) void k_hmc_prep(WalkArgs a, double* __restrict__ Z, int zrow0, int Kpad,
                                                   double* __restrict__ horizon) {
     const int lane = threadIdx.x & 63;
@@ -99,12 +101,25 @@ __global__ __launch_bounds__(256) void k_hmc_prep(WalkArgs a, double* __restrict
     if (c >= a.chains) return;
     const WalkState& S = a.st;
     const int n = a.n;
-    const double sigma = 1.0 / sqrt(2.0 * a.gauss_a);
+    const double sigma = a.bc ? 0.0 : 1.0 / sqrt(2.0 * a.gauss_a);
     const double* x = S.x + (size_t)c * n;
     const double* v = S.v + (size_t)c * n;
     double* z0 = Z + (size_t)c * Kpad;
     double* z1 = Z + (size_t)(zrow0 + c) * Kpad;
     double* z2 = Z + (size_t)(2 * zrow0 + c) * Kpad;
+    if (a.bc) {
+        // Boltzmann trajectory p + t v - t^2 c / (2T): rows [1, p], [0, v],
+        // [0, -c / (2T)] in t itself; the horizon is the travel time left
+        const double h2 = -0.5 / a.bT;
+        for (int k = lane; k < Kpad; k += 64) {
+            const bool in = k >= 1 && k <= n;
+            z0[k] = k == 0 ? 1.0 : (in ? x[k - 1] : 0.0);
+            z1[k] = in ? v[k - 1] : 0.0;
+            z2[k] = in ? h2 * a.bc[k - 1] : 0.0;
+        }
+        if (lane == 0) horizon[c] = fmax(S.ell[c], 0.0);
+        return;
+    }
     for (int k = lane; k < Kpad; k += 64) {
         double r0 = 0.0, r1 = 0.0, r2 = 0.0;
         if (k == 0) {
@@ -240,6 +255,23 @@ __device__ inline double trunc_normal_at(double mu, double sig, double lo, doubl
     return fmin(fmax(t, lo), hi);
 }
 
+// Chord point of Hit-and-Run for exp(-<c, y> / T): along x + t v the density
+// is exp(-lam t), lam = <c, v> / T, on [tm, tp]; inverse CDF from the end
+// where the density is largest (lam >= 0: from tm with u; lam < 0: from tp
+// with 1 - u, so t grows with u either way).
+__device__ inline double trunc_exp_at(double lam, double tm, double tp, double u) {
+    const double L = tp - tm;
+    if (fabs(lam * L) < 1e-12) return tm + u * L;
+    double t;
+    if (lam > 0.0) {
+        t = tm - log1p(u * expm1(-lam * L)) / lam;
+    } else {
+        const double mu = -lam;
+        t = tp + log1p((1.0 - u) * expm1(-mu * L)) / mu;
+    }
+    return fmin(fmax(t, tm), tp);
+}
+
 // Finish a step: record the sample, advance the counter, start the next.
 // Every lane of the chain's wave calls it; each lane touches its own
 // coordinates only.
@@ -317,6 +349,58 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         end_step(a, c, lane);
         return;
     }
+    if (a.kind == SPEC_WALK_HMC && a.bc) {
+        // Boltzmann trajectory p + t v - t^2 c / (2T), velocity v - t c / T:
+        // fly to the end of the travel time, or reflect at the first root
+        const double iT = 1.0 / a.bT;
+        const double ell = S.ell[c];
+        const double ts = tp;
+        if (!(ts <= ell) || !isfinite(ts)) {
+            for (int i = lane; i < n; i += 64) {
+                const double ci = a.bc[i];
+                x[i] += ell * v[i] - 0.5 * ell * ell * ci * iT;
+                v[i] -= ell * ci * iT;
+            }
+            if (lane == 0) S.ell[c] = 0.0;
+            end_step(a, c, lane);
+            return;
+        }
+        const int hit = a.hit[c];
+        double nn = 0.0, vw = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double vh = v[i] - ts * a.bc[i] * iT;
+            const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                               : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+            nn += wi * wi;
+            vw += wi * vh;
+        }
+        nn = wave_sum(nn);
+        vw = wave_sum(vw);
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        const double coef = 2.0 * vw * inv * inv;
+        const double t1 = (1.0 - a.pullback) * ts;
+        for (int i = lane; i < n; i += 64) {
+            const double ci = a.bc[i];
+            const double wi = hit == HIT_DENSE ? a.wn[(size_t)c * a.ldwn + i]
+                                               : a.Astk[(size_t)(i + 1) * a.ldA + a.P + hit];
+            const double vh = v[i] - ts * ci * iT;
+            x[i] += t1 * v[i] - 0.5 * t1 * t1 * ci * iT;
+            v[i] = vh - coef * wi;
+        }
+        const int nref = S.nref[c] + 1;
+        if (lane == 0) {
+            if (!(nn > 0.0) || status == SPEC_NONSMOOTH) st[4] += 1.0;
+            st[1] += 1.0;
+            S.ell[c] = ell - ts;
+            S.nref[c] = nref;
+        }
+        if (nref > a.rho) {
+            if (lane == 0) st[2] += 1.0;
+            for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+            end_step(a, c, lane);
+        }
+        return;
+    }
     if (a.kind == SPEC_WALK_HMC) {
         // one segment of the trajectory: up to the boundary (reflect) or the
         // horizon (rotate), then continue while travel time is left
@@ -384,7 +468,12 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
             double u0, u1;
             draw_u2(a.seed, (uint32_t)c, (uint32_t)S.step[c], 0, TAG_POS, u0, u1);
             double t;
-            if (a.gauss_a > 0.0) {
+            if (a.bc) {
+                double cv = 0.0;
+                for (int i = lane; i < n; i += 64) cv += a.bc[i] * v[i];
+                cv = wave_sum(cv);
+                t = trunc_exp_at(cv / a.bT, tm, tp, u0);
+            } else if (a.gauss_a > 0.0) {
                 double xv = 0.0;
                 for (int i = lane; i < n; i += 64) xv += x[i] * v[i];
                 xv = wave_sum(xv);
@@ -464,6 +553,45 @@ __global__ void k_sum_stats(int chains, const double* __restrict__ stats, double
     double s = 0.0;
     for (int c = 0; c < chains; ++c) s += stats[(size_t)c * WALK_NSTAT + k];
     out[k] = s;
+}
+
+// Annealing bookkeeping, one wave per chain: f = <c, x>; a smaller f
+// replaces the chain's best (value and point); best history and the first
+// iteration within eps |f_star| of f_star.  init: the start point is the
+// first best.
+__global__ __launch_bounds__(256) void k_anneal_track(int chains, int n, const double* __restrict__ x,
+                                                      const double* __restrict__ cv, int it, int iters,
+                                                      double* __restrict__ xb, double* __restrict__ fb,
+                                                      double* __restrict__ best, int32_t* __restrict__ hit,
+                                                      double f_star, double eps, int init) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= chains) return;
+    const double* xc = x + (size_t)c * n;
+    double f = 0.0;
+    for (int i = lane; i < n; i += 64) f += cv[i] * xc[i];
+    f = wave_sum(f);
+    const bool better = init || f < fb[c];
+    if (better)
+        for (int i = lane; i < n; i += 64) xb[(size_t)c * n + i] = xc[i];
+    if (lane == 0) {
+        const double b = better ? f : fb[c];
+        fb[c] = b;
+        if (init) {
+            hit[c] = -1;
+        } else {
+            if (best) best[(size_t)c * iters + it] = b;
+            if (hit[c] < 0 && isfinite(f_star) && b - f_star <= eps * fabs(f_star)) hit[c] = it;
+        }
+    }
+}
+
+hipError_t anneal_track(int chains, int n, const double* x, const double* c, int it, int iters, double* xb,
+                        double* fb, double* best, int32_t* hit, double f_star, double eps, bool init,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_anneal_track, dim3((chains + 3) / 4), dim3(256), 0, s, chains, n, x, c, it, iters, xb, fb,
+                       best, hit, f_star, eps, init ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t walk_init(const WalkArgs& a, const double* x0, hipStream_t s) {

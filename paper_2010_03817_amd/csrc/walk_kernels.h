@@ -28,6 +28,8 @@ struct WalkArgs {
     uint64_t seed;
     double tau, gauss_a, pullback;
     int rho;
+    const double* bc;  // Boltzmann target exp(-<bc, x> / bT) (nullable: none)
+    double bT;
     WalkState st;
     // oracle results of the current round
     const int32_t* status;
@@ -56,6 +58,10 @@ hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStrea
 hipError_t walk_resume(const WalkArgs& a, hipStream_t s);
 // HMC: coefficient rows of the segment's degree-2 pencil into Z and horizons.
 hipError_t walk_hmc_prep(const WalkArgs& a, double* Z, int zrow0, int Kpad, double* horizon, hipStream_t s);
+// Annealing: per-chain best <c, x> (init: from x0) and the history.
+hipError_t anneal_track(int chains, int n, const double* x, const double* c, int it, int iters, double* xb,
+                        double* fb, double* best, int32_t* hit, double f_star, double eps, bool init,
+                        hipStream_t s);
 // Volume helpers: exact Gaussian draws, per-group log-mean-exp of a phase,
 // per-group membership counts.
 hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double sd, double* X, hipStream_t s);

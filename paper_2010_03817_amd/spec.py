@@ -32,7 +32,14 @@ class WalkParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("rho", C.c_int), ("gauss_a", C.c_double), ("pullback", C.c_double),
                 ("thin", C.c_int), ("max_rounds", C.c_longlong), ("resume", C.c_int), ("log_chains", C.c_int),
                 ("log_cap", C.c_int),
-                ("log_buf", C.c_void_p), ("log_count", C.c_void_p)]
+                ("log_buf", C.c_void_p), ("log_count", C.c_void_p), ("boltz_c", C.c_void_p),
+                ("boltz_T", C.c_double)]
+
+
+class AnnealParams(C.Structure):
+    _fields_ = [("kind", C.c_int), ("iterations", C.c_int), ("walk_len", C.c_int), ("T0", C.c_double),
+                ("cool", C.c_double), ("tau0", C.c_double), ("rho", C.c_int), ("pullback", C.c_double),
+                ("f_star", C.c_double), ("eps", C.c_double)]
 
 
 class WalkStats(C.Structure):
@@ -159,6 +166,8 @@ def lib():
     L.spec_batch_tune.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_int)]
     L.spec_batch_volume.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, vp, vp, vp, C.POINTER(C.c_double)]
     L.spec_batch_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+    L.spec_sdp_anneal.argtypes = [vp, C.POINTER(AnnealParams), C.c_int, vp, vp, C.c_uint64, vp, vp, vp, vp,
+                                  C.POINTER(WalkStats)]
     L.spec_volume_estimate.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(VolumeStats), vp]
     L.spec_tune_mlp_delta_dev.argtypes = [vp, vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, C.POINTER(C.c_double),
@@ -321,7 +330,7 @@ class Spectrahedron:
         return tp, s, w, st
 
     def walk(self, kind, x0, steps, seed, tau=1.0, rho=0, gauss_a=0.0, pullback=1e-6, thin=0, max_rounds=0,
-             log_chains=0, log_cap=0, resume=False):
+             log_chains=0, log_cap=0, resume=False, boltz_c=None, boltz_T=0.0):
         """Run chains of a walk (HNR, CHNR, BILLIARD) from x0; returns
         (x_out, samples or None, stats dict, log or None).  The log holds rows
         (x, v, t-, t+, chain, status) of segments of the first log_chains chains."""
@@ -335,9 +344,10 @@ class Spectrahedron:
         if log_cap > 0:
             log = torch.empty((log_cap, 2 * self.n + 4), dtype=torch.float64, device="cuda")
             cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        bc = None if boltz_c is None else _f64(boltz_c).reshape(self.n)
         p = WalkParams(tau=tau, rho=rho, gauss_a=gauss_a, pullback=pullback, thin=thin, max_rounds=max_rounds,
                        resume=int(resume), log_chains=log_chains, log_cap=log_cap, log_buf=_ptr(log),
-                       log_count=_ptr(cnt))
+                       log_count=_ptr(cnt), boltz_c=_ptr(bc), boltz_T=boltz_T)
         st = WalkStats()
         check(lib().spec_walk_run_dev(self._h, kind, ch, _ptr(x0), steps, seed, C.byref(p), _ptr(x_out),
                                       _ptr(samples), C.byref(st), _stream()))
@@ -359,6 +369,26 @@ class Spectrahedron:
         check(lib().spec_walk_run(self._h, kind, ch, x0.ctypes.data, steps, seed, C.byref(p), x_out.ctypes.data,
                                   samples.ctypes.data if samples is not None else None, C.byref(st)))
         return x_out, samples, st.as_dict()
+
+    def sdp_anneal(self, x0, c, T0, tau0, iterations=70, walk_len=1, kind=None, cool=0.0, seed=1, rho=0,
+                   pullback=1e-6, f_star=float("nan"), eps=0.05):
+        """spec_sdp_anneal on host arrays: (x_best, f_best, best history
+        (chains x iterations), hit_iter, stats)."""
+        kind = HMC if kind is None else kind
+        x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1, self.n)
+        c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.n)
+        ch = x0.shape[0]
+        p = AnnealParams(kind=kind, iterations=iterations, walk_len=walk_len, T0=T0, cool=cool, tau0=tau0, rho=rho,
+                         pullback=pullback, f_star=f_star, eps=eps)
+        xb, fb = np.empty_like(x0), np.empty(ch)
+        best = np.empty((ch, max(iterations, 1)))
+        hit = np.empty(ch, np.int32)
+        st = WalkStats()
+        check(lib().spec_sdp_anneal(self._h, C.byref(p), ch, x0.ctypes.data_as(C.c_void_p),
+                                    c.ctypes.data_as(C.c_void_p), int(seed), xb.ctypes.data_as(C.c_void_p),
+                                    fb.ctypes.data_as(C.c_void_p), best.ctypes.data_as(C.c_void_p),
+                                    hit.ctypes.data_as(C.c_void_p), C.byref(st)))
+        return xb, fb, best[:, :iterations], hit, st.as_dict()
 
     def save_walk_state(self):
         check(lib().spec_walk_state(self._h, 0))

@@ -624,6 +624,73 @@ def estimator_leg(S, I, n, trials, points, lengths=TABLE3_W):
     return out
 
 
+TABLE4_PAPER = {  # iterations / seconds / failures out of 10, one CPU core (context, not the target)
+    30: {"hmc_r": (20.1, 2.9, 0), "hnr_w1": (184.3, 3.4, 1), "hnr_w2": (52.1, 5.2, 0)},
+    40: {"hmc_r": (24.6, 7.9, 0), "hnr_w1": (223.3, 9.9, 2), "hnr_w2": (61.9, 17.1, 0)},
+    50: {"hmc_r": (29.2, 12.7, 0), "hnr_w1": (251.2, 22.3, 3), "hnr_w2": (72.3, 44.6, 0)},
+    60: {"hmc_r": (32.8, 24.32, 0), "hnr_w1": (272.7, 41.1, 3), "hnr_w2": (81.5, 98.9, 0)},
+}
+
+
+def anneal_leg(S, I, per_size, chains, max_iters):
+    """The annealing table of the paper's optimisation section: iterations
+    (temperatures) until the best <c, x> is within 5 % of the optimum, run
+    time and failures, for HMC with reflections (walk length one) and
+    Hit-and-Run with walk lengths 4 sqrt(n) and 4 n, on S-n-n of the paper's
+    generator (n = 30 .. 60) with seeded unit objectives.  The optima are the
+    stored ones of the oracle's barrier method (tests/golden/sdp_optima.json).
+    Every chain is one run of the method: T0 = d |c| and tau0 = d with d the
+    longest chord of a Hit-and-Run pre-run, cooling 1 - 1/sqrt(n), starts drawn
+    by 20 billiard steps from the centre; a chain that is not within 5 % after
+    `max_iters` temperatures is a failure.  Wall time of each call (all chains
+    of one instance together) with the device synchronised."""
+    import torch
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "tests", "golden", "sdp_optima.json")) as fh:
+        optima = json.load(fh)["optima"]
+    methods = (("hmc_r", S.HMC, lambda n: 1), ("hnr_w1", S.HNR, lambda n: int(round(4 * math.sqrt(n)))),
+               ("hnr_w2", S.HNR, lambda n: 4 * n))
+    out = {"chains_per_instance": chains, "max_iterations": max_iters, "eps": 0.05}
+    for n in sorted({e["n"] for e in optima}):
+        rows = [e for e in optima if e["n"] == n][:per_size]
+        res = {k: {"iters": [], "seconds": [], "failures": 0, "runs": 0, "calls": 0.0} for k, _, _ in methods}
+        for e in rows:
+            g = S.Spectrahedron(I.paper_random(n, n, seed=e["instance_seed"]))
+            c = I.objective(n, e["objective_seed"])
+            _, _, _, log = g.walk(S.HNR, np.zeros((64, n)), 20, seed=11, log_chains=64, log_cap=64 * 20)
+            lg = log.cpu().numpy()
+            d = float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+            x0, _, _, _ = g.walk(S.BILLIARD, torch.zeros((chains, n), dtype=torch.float64, device="cuda"), 20,
+                                 seed=12, tau=2.0 * d)
+            x0 = x0.cpu().numpy()
+            for name, kind, wl in methods:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, fb, _, hit, st = g.sdp_anneal(x0, c, d * np.linalg.norm(c), d, iterations=max_iters,
+                                                 walk_len=wl(n), kind=kind, seed=13, f_star=e["f_star"],
+                                                 stop_when_reached=True)
+                torch.cuda.synchronize()
+                r = res[name]
+                r["seconds"].append(time.perf_counter() - t0)
+                ok = hit >= 0
+                r["iters"].extend((hit[ok] + 1).tolist())
+                r["failures"] += int((~ok).sum())
+                r["runs"] += len(hit)
+                r["calls"] += st["calls"]
+                assert np.all(fb >= e["f_star"] - 1e-9 * abs(e["f_star"]))
+            del g
+        progress(f"annealing table: S-{n}-{n} done")
+        out[f"S-{n}-{n}"] = {
+            name: {"walk_len": wl(n), "mean_iterations": float(np.mean(r["iters"])) if r["iters"] else None,
+                   "seconds_per_instance": float(np.mean(r["seconds"])),
+                   "failure_rate": r["failures"] / max(r["runs"], 1), "instances": len(rows),
+                   "oracle_calls_per_s": r["calls"] / max(sum(r["seconds"]), 1e-9),
+                   "paper": {"iterations": TABLE4_PAPER[n][name][0], "seconds": TABLE4_PAPER[n][name][1],
+                             "failures_of_10": TABLE4_PAPER[n][name][2]} if n in TABLE4_PAPER else None}
+            for (name, _, wl), r in ((m, res[m[0]]) for m in methods)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -649,6 +716,11 @@ def main():
     ap.add_argument("--walk-lengths", action="store_true",
                     help="also run the walk-length table (S-100-100, S-200-200) and the estimator study")
     ap.add_argument("--walk-length-instances", type=int, default=10)
+    ap.add_argument("--anneal", action="store_true",
+                    help="also run the annealing table (min <c, x> on S-30-30 .. S-60-60)")
+    ap.add_argument("--anneal-instances", type=int, default=10)
+    ap.add_argument("--anneal-chains", type=int, default=64)
+    ap.add_argument("--anneal-max-iters", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -774,6 +846,9 @@ def main():
         progress("walk-length table and expectation estimators")
         out["walk_length_table"] = walk_length_leg(S, I, args.walk_length_instances, 200)
         out["expectation_estimators"] = estimator_leg(S, I, 50, 20, 200)
+    if args.anneal:
+        progress("annealing table")
+        out["anneal_table"] = anneal_leg(S, I, args.anneal_instances, args.anneal_chains, args.anneal_max_iters)
     if not args.no_cpu:
         progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))

@@ -334,6 +334,8 @@ typedef struct {
     double pullback; /* as spec_walk_params (<= 0: 1e-6) */
     double f_star;   /* known optimum for hit_iter (NaN: none) */
     double eps;      /* relative error that counts as reached (<= 0: 0.05) */
+    int stop_when_reached;  /* nonzero (with f_star): stop after the first temperature at which
+                               every chain is within eps; later entries of `best` repeat the last */
 } spec_anneal_params;
 
 /* Host arrays: x0 (chains x n) interior starts, c (n); outputs x_best

@@ -3,6 +3,7 @@
 // entry point.  All arithmetic of the oracle runs in the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -689,6 +690,7 @@ spec_status spec_sdp_anneal(spec_handle h, const spec_anneal_params* p, int chai
     hipStream_t s = nullptr;
     double *dx0 = nullptr, *dx = nullptr, *dc = nullptr, *dxb = nullptr, *dfb = nullptr, *dbest = nullptr;
     int32_t* dhit = nullptr;
+    int ran = 0;
     spec_status rc = SPEC_OK;
     auto fail = [&](hipError_t e) {
         if (rc == SPEC_OK && e != hipSuccess) rc = from_hip(e);
@@ -706,6 +708,8 @@ spec_status spec_sdp_anneal(spec_handle h, const spec_anneal_params* p, int chai
         wp.pullback = p->pullback > 0.0 ? p->pullback : 1e-6;
         wp.boltz_c = dc;
         double T = p->T0;
+        const bool stop = p->stop_when_reached && std::isfinite(p->f_star);
+        std::vector<int32_t> hh(stop ? chains : 0);
         for (int it = 0; it < iters && rc == SPEC_OK; ++it) {
             wp.tau = p->kind == SPEC_WALK_HMC ? p->tau0 * std::sqrt(T / p->T0) : 1.0;
             wp.boltz_T = T;
@@ -730,12 +734,21 @@ spec_status spec_sdp_anneal(spec_handle h, const spec_anneal_params* p, int chai
                 stats->uncertified += st.uncertified;
             }
             T *= 1.0 - cool;
+            ran = it + 1;
+            if (stop) {
+                if (fail(hipMemcpy(hh.data(), dhit, sizeof(int32_t) * chains, hipMemcpyDeviceToHost))) break;
+                if (std::all_of(hh.begin(), hh.end(), [](int32_t v) { return v >= 0; })) break;
+            }
         }
     }
     if (rc == SPEC_OK && !fail(hipDeviceSynchronize())) {
         if (x_best) fail(hipMemcpy(x_best, dxb, sizeof(double) * cn, hipMemcpyDeviceToHost));
         fail(hipMemcpy(f_best, dfb, sizeof(double) * chains, hipMemcpyDeviceToHost));
-        if (best && iters > 0) fail(hipMemcpy(best, dbest, sizeof(double) * chains * iters, hipMemcpyDeviceToHost));
+        if (best && iters > 0) {
+            fail(hipMemcpy(best, dbest, sizeof(double) * chains * iters, hipMemcpyDeviceToHost));
+            for (int j = 0; j < chains && ran > 0; ++j)
+                for (int it = ran; it < iters; ++it) best[(size_t)j * iters + it] = best[(size_t)j * iters + ran - 1];
+        }
         if (hit_iter) fail(hipMemcpy(hit_iter, dhit, sizeof(int32_t) * chains, hipMemcpyDeviceToHost));
     }
     dfree(dx0);

@@ -216,6 +216,19 @@ def interior_points(inst: Instance, rng: np.random.Generator, batch: int, frac: 
     return x0 + (f * tp)[:, None] * v
 
 
+def objective(n: int, seed: int) -> np.ndarray:
+    """A seeded unit objective vector c for min <c, x> over S."""
+    c = np.random.default_rng(seed).standard_normal(n)
+    return c / np.linalg.norm(c)
+
+
+def sdp_family(sizes=(30, 40, 50, 60), per_size: int = 10):
+    """The optimisation workload of the paper's annealing table: per size n,
+    `per_size` spectrahedra S-n-n of its generator with seeded objectives;
+    entries (n, instance seed, objective seed)."""
+    return [(n, 30000 + 100 * n + k, 31000 + 100 * n + k) for n in sizes for k in range(per_size)]
+
+
 def uneven_family(count: int, seed: int, lo: int = 20, hi: int = 200, balls: int = 16):
     """`count` instances with n and m log-uniform in [lo, hi]; the first
     `balls` are arrow-LMI unit balls of random n (known volume)."""

@@ -39,7 +39,7 @@ class WalkParams(C.Structure):
 class AnnealParams(C.Structure):
     _fields_ = [("kind", C.c_int), ("iterations", C.c_int), ("walk_len", C.c_int), ("T0", C.c_double),
                 ("cool", C.c_double), ("tau0", C.c_double), ("rho", C.c_int), ("pullback", C.c_double),
-                ("f_star", C.c_double), ("eps", C.c_double)]
+                ("f_star", C.c_double), ("eps", C.c_double), ("stop_when_reached", C.c_int)]
 
 
 class WalkStats(C.Structure):
@@ -371,7 +371,7 @@ class Spectrahedron:
         return x_out, samples, st.as_dict()
 
     def sdp_anneal(self, x0, c, T0, tau0, iterations=70, walk_len=1, kind=None, cool=0.0, seed=1, rho=0,
-                   pullback=1e-6, f_star=float("nan"), eps=0.05):
+                   pullback=1e-6, f_star=float("nan"), eps=0.05, stop_when_reached=False):
         """spec_sdp_anneal on host arrays: (x_best, f_best, best history
         (chains x iterations), hit_iter, stats)."""
         kind = HMC if kind is None else kind
@@ -379,7 +379,7 @@ class Spectrahedron:
         c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.n)
         ch = x0.shape[0]
         p = AnnealParams(kind=kind, iterations=iterations, walk_len=walk_len, T0=T0, cool=cool, tau0=tau0, rho=rho,
-                         pullback=pullback, f_star=f_star, eps=eps)
+                         pullback=pullback, f_star=f_star, eps=eps, stop_when_reached=int(bool(stop_when_reached)))
         xb, fb = np.empty_like(x0), np.empty(ch)
         best = np.empty((ch, max(iterations, 1)))
         hit = np.empty(ch, np.int32)

@@ -204,6 +204,13 @@ def test_hit_and_run_annealing_and_api_errors(S):
     _, fb, _, hit, _ = g.sdp_anneal(x0, c, diam * np.linalg.norm(c), diam, iterations=40,
                                     walk_len=int(4 * math.sqrt(n)), kind=S.HNR, seed=3, f_star=fstar)
     assert np.median((fb - fstar) / abs(fstar)) <= 0.05
+    # stop_when_reached: the run ends at the first temperature where every
+    # chain is within eps; the history repeats the last best after that
+    _, fb2, best2, hit2, _ = g.sdp_anneal(x0[:8], c, diam * np.linalg.norm(c), diam, iterations=40, seed=3,
+                                          f_star=fstar, stop_when_reached=True)
+    assert np.all(hit2 >= 0)
+    last = int(hit2.max())
+    assert np.all(best2[:, last:] == best2[:, last:last + 1]) and np.array_equal(fb2, best2[:, -1])
     with pytest.raises(S.SpecError):
         g.sdp_anneal(x0, c, -1.0, diam)
     with pytest.raises(S.SpecError):

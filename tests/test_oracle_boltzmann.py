@@ -133,3 +133,58 @@ def test_hit_and_run_annealing_on_the_ball():
     fstar = -np.linalg.norm(c)
     assert np.all(fb >= fstar - 1e-9 * abs(fstar))
     assert np.median((fb - fstar) / abs(fstar)) <= 0.05
+
+
+@pytest.mark.parametrize("body", ["box", "dense_box", "simplex", "ball"])
+def test_barrier_optimum_matches_closed_forms(body):
+    """The log-barrier reference optimum (oracle/sdp_barrier.py) equals the
+    known optima of linear programs over a box, the centred simplex and the
+    ball (as LMIs: diagonal rows, a dense diagonal block, an arrow block)."""
+    from oracle.sdp_barrier import sdp_min
+    n = 7
+    c = np.random.default_rng(23).standard_normal(n)
+    if body == "box":
+        inst, fstar = I.box(n, 1.0), -np.abs(c).sum()
+    elif body == "dense_box":
+        inst, fstar = I.box_as_dense(n, 1.0), -np.abs(c).sum()
+    elif body == "simplex":
+        inst, fstar = I.simplex(n), min(0.0, c.min()) - c.sum() / (n + 1)
+    else:
+        inst, fstar = I.arrow_ball(n), -np.linalg.norm(c)
+    x, f, _ = sdp_min(inst, c)
+    assert abs(f - fstar) <= 1e-9 * abs(fstar), (f, fstar)
+    assert abs(c @ x - f) == 0.0
+
+
+def test_annealing_against_the_barrier_optimum_on_a_paper_instance():
+    """On S-8-8 of the paper's generator the oracle's annealing never goes
+    below the barrier optimum and its median chain ends within 5 % of it."""
+    from oracle.sdp_barrier import sdp_min
+    n = 8
+    inst = I.paper_random(n, n, seed=808)
+    c = I.objective(n, 809)
+    _, fstar, _ = sdp_min(inst, c)
+    o = O.Oracle(inst)
+    # diameter estimate: the longest chord through the centre along the axes
+    E = np.eye(n)
+    tm, tp, _ = o.intersect(np.zeros((n, n)), E)
+    diam = float(np.max(tp - tm))
+    iters = math.ceil(math.log(1e-7) / math.log(1 - 1 / math.sqrt(n)))
+    xb, fb, best = o.sdp_anneal(O.HMC, np.zeros((8, n)), c, diam, 1 / math.sqrt(n), iters, 1, 5, diam)
+    assert np.all(fb >= fstar - 1e-9 * abs(fstar))
+    assert np.median((fb - fstar) / abs(fstar)) <= 0.05
+
+
+def test_stored_optima_come_from_the_barrier_method():
+    """The first stored optimum of the annealing workload is what the oracle's
+    barrier method gives for it."""
+    import json
+    import os
+    from oracle.sdp_barrier import sdp_min
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sdp_optima.json")) as fh:
+        doc = json.load(fh)
+    e = doc["optima"][0]
+    inst = I.paper_random(e["n"], e["m"], seed=e["instance_seed"])
+    _, f, _ = sdp_min(inst, I.objective(e["n"], e["objective_seed"]))
+    assert abs(f - e["f_star"]) <= 1e-9 * abs(e["f_star"])
+    assert len(doc["optima"]) == len(I.sdp_family())

@@ -801,7 +801,11 @@ static void walk_step(const orc_lmi* h, int kind, uint64_t seed, uint32_t chain,
         if (r.status == ORC_NOCONV) ws->noconv += 1;
         if (isinf(r.tp) || isinf(r.tm)) return; /* unbounded chord: stay */
         draw_u2(seed, chain, step, 0, TAG_POS, uu);
-        double t = bc ? chord_sample_boltz(n, x, v, bc, bT, r.tm, r.tp, uu[0])
+        /* the Boltzmann chord is sampled on [(1-pullback) t-, (1-pullback) t+]:
+         * at low temperature its mass sits within T / <c, v> of an end, and a
+         * point closer to the boundary than the rounding of F would stop the
+         * chain (the reflections' pull-back, applied to the chord ends) */
+        double t = bc ? chord_sample_boltz(n, x, v, bc, bT, (1.0 - pullback) * r.tm, (1.0 - pullback) * r.tp, uu[0])
                       : chord_sample(n, x, v, 1.0, r.tm, r.tp, gauss_a, uu[0]);
         for (int i = 0; i < n; i++) x[i] += t * v[i];
         return;

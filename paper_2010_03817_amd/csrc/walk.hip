@@ -472,7 +472,8 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
                 double cv = 0.0;
                 for (int i = lane; i < n; i += 64) cv += a.bc[i] * v[i];
                 cv = wave_sum(cv);
-                t = trunc_exp_at(cv / a.bT, tm, tp, u0);
+                // on the chord pulled back from both ends, as the oracle
+                t = trunc_exp_at(cv / a.bT, (1.0 - a.pullback) * tm, (1.0 - a.pullback) * tp, u0);
             } else if (a.gauss_a > 0.0) {
                 double xv = 0.0;
                 for (int i = lane; i < n; i += 64) xv += x[i] * v[i];

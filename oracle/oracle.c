@@ -1259,6 +1259,188 @@ int orc_volume(const orc_lmi* h, int phases, int spp, int chains, int walk_len, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Volume: the ball sequence of eq. (mmc_vol)                                */
+/* ------------------------------------------------------------------------ */
+
+enum { TAG_BALL = 7, TAG_BALL_R = 8 };
+
+/* One billiard step (Alg. Billiard) inside S cap rho B (rho = INFINITY: S):
+ * the segment ends at the first of t+ of S, the ball's exit
+ * -<p, v> + sqrt(<p, v>^2 + rho^2 - |p|^2) and the length left; a hit
+ * reflects on S's normal or on the ball's radial normal p + t v.  More than
+ * 10 n reflections: the chain stays. */
+static void billiard_ball_step(const orc_lmi* h, uint64_t seed, uint32_t chain, uint32_t step, uint32_t tagbase,
+                               double tau, double rho, double pullback, double* x, double* v, double* p,
+                               double* sdir, double* u, double* w, scratch* s) {
+    int n = h->n;
+    double uu[2];
+    draw_u2(seed, chain, step, 0, tagbase | TAG_LEN, uu);
+    double ell = -tau * log(uu[0]);
+    random_unit(seed, chain, step, tagbase | TAG_DIR, n, v);
+    memcpy(p, x, sizeof(double) * n);
+    int nref = 0;
+    for (;;) {
+        line_res r = line_oracle(h, p, v, s, u);
+        if (r.status == ORC_NOT_INTERIOR) return;
+        double tb = INFINITY;
+        if (isfinite(rho)) {
+            double pv = 0.0, pp = 0.0;
+            for (int i = 0; i < n; i++) { pv += p[i] * v[i]; pp += p[i] * p[i]; }
+            double disc = pv * pv + rho * rho - pp;
+            tb = -pv + sqrt(disc > 0.0 ? disc : 0.0);
+        }
+        double th = tb < r.tp ? tb : r.tp;
+        if (th >= ell) {
+            for (int i = 0; i < n; i++) p[i] += ell * v[i];
+            break;
+        }
+        if (tb < r.tp) {
+            for (int i = 0; i < n; i++) w[i] = p[i] + tb * v[i];
+        } else {
+            normal_at(h, r.bplus, r.jplus, u, w);
+        }
+        reflect_dir(n, v, w, sdir);
+        for (int i = 0; i < n; i++) p[i] += (1.0 - pullback) * th * v[i];
+        ell -= th;
+        memcpy(v, sdir, sizeof(double) * n);
+        if (++nref > 10 * n) return;
+    }
+    memcpy(x, p, sizeof(double) * n);
+}
+
+static int cmp_double(const void* a, const void* b) {
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* vol(S) by the ball sequence S_i = S cap rho_i B (eq. (mmc_vol)): rho_0 =
+ * infinity (S itself); in phase i every chain walks burn_in billiard steps in
+ * S_i, then keeps spc samples walk_len steps apart.  The next radius
+ * rho_{i+1} is the q-quantile of |x| over the first half of the samples (all
+ * chains), and vol(S_{i+1}) / vol(S_i) is the fraction of the second half
+ * inside rho_{i+1} B, per group of chains.  The sequence ends at the first
+ * rho_k whose ball has at least a fraction q inside S by ball_draws exact
+ * uniform draws per group; vol(S_k) = vol(rho_k B) times that group's
+ * fraction.  Chains outside the next ball are moved radially onto
+ * (1 - 1e-6) rho_{i+1} (inside S: S is convex and holds 0).  Interval: mean
+ * +- t_{0.975, g-1} sd / sqrt(g) of the per-group log-volumes.  Returns
+ * ORC_NOCONV if max_phases phases do not reach a ball mostly inside S. */
+int orc_volume_balls(const orc_lmi* h, int chains, int spc, int walk_len, int burn_in, double q, int max_phases,
+                     int ball_draws, uint64_t seed, double tau, int ng, double* log_vol, double* ci_lo,
+                     double* ci_hi, double* radii, int* phases_out) {
+    if (!h || chains < 1 || spc < 2 || walk_len < 1 || burn_in < 0 || !(q > 0.0 && q < 1.0) || max_phases < 1 ||
+        ball_draws < 1 || !(tau > 0.0) || ng < 2 || chains % ng || !log_vol || !ci_lo || !ci_hi)
+        return ORC_EINVAL;
+    int n = h->n;
+    scratch s;
+    if (scratch_alloc(h, &s)) { scratch_free(&s); return ORC_ENOMEM; }
+    size_t mm = (size_t)max_block(h);
+    double* X = (double*)calloc((size_t)chains * n, sizeof(double));
+    double* v = (double*)malloc(sizeof(double) * n);
+    double* p = (double*)malloc(sizeof(double) * n);
+    double* sd = (double*)malloc(sizeof(double) * n);
+    double* w = (double*)malloc(sizeof(double) * n);
+    double* u = (double*)malloc(sizeof(double) * mm);
+    double* nrm = (double*)malloc(sizeof(double) * (size_t)chains * spc);
+    double* first = (double*)malloc(sizeof(double) * (size_t)chains * spc);
+    double* lv = (double*)calloc(ng, sizeof(double));
+    int per_group = chains / ng, h1 = spc / 2;
+    double rho = INFINITY;
+    int rc = ORC_NOCONV, ph;
+    for (ph = 0; ph < max_phases; ph++) {
+        uint32_t tagbase = (uint32_t)(ph + 1) << 8;
+        if (radii) radii[ph] = rho;
+        for (int c = 0; c < chains; c++) {
+            double* x = X + (size_t)c * n;
+            int step = 0;
+            for (int b = 0; b < burn_in; b++, step++)
+                billiard_ball_step(h, seed, (uint32_t)c, (uint32_t)step, tagbase, tau, rho, 1e-6, x, v, p, sd, u, w,
+                                   &s);
+            for (int k = 0; k < spc; k++) {
+                for (int t = 0; t < walk_len; t++, step++)
+                    billiard_ball_step(h, seed, (uint32_t)c, (uint32_t)step, tagbase, tau, rho, 1e-6, x, v, p, sd,
+                                       u, w, &s);
+                double r2 = 0.0;
+                for (int i = 0; i < n; i++) r2 += x[i] * x[i];
+                nrm[(size_t)c * spc + k] = sqrt(r2);
+            }
+        }
+        /* next radius from the first halves */
+        int cnt1 = 0;
+        for (int c = 0; c < chains; c++)
+            for (int k = 0; k < h1; k++) first[cnt1++] = nrm[(size_t)c * spc + k];
+        qsort(first, cnt1, sizeof(double), cmp_double);
+        int qi = (int)floor(q * cnt1);
+        if (qi >= cnt1) qi = cnt1 - 1;
+        double rnext = first[qi];
+        /* the ratio per group from the second halves */
+        for (int g = 0; g < ng; g++) {
+            int in = 0, tot = 0;
+            for (int c = g * per_group; c < (g + 1) * per_group; c++)
+                for (int k = h1; k < spc; k++, tot++) in += nrm[(size_t)c * spc + k] <= rnext;
+            lv[g] -= log((double)in / tot);
+        }
+        /* does the ball hold a fraction q inside S? exact uniform draws */
+        int hits_all = 0;
+        double* pg = (double*)malloc(sizeof(double) * ng);
+        for (int g = 0; g < ng; g++) {
+            int hits = 0;
+            for (int k = 0; k < ball_draws; k++) {
+                draw_normals(seed, (uint32_t)g, (uint32_t)k, tagbase | TAG_BALL, n, v);
+                double nn = 0.0;
+                for (int i = 0; i < n; i++) nn += v[i] * v[i];
+                double uu[2];
+                draw_u2(seed, (uint32_t)g, (uint32_t)k, 0, tagbase | TAG_BALL_R, uu);
+                double rad = rnext * pow(uu[0], 1.0 / n) / sqrt(nn);
+                for (int i = 0; i < n; i++) v[i] *= rad;
+                int8_t inside;
+                orc_membership(h, 1, v, &inside);
+                hits += inside;
+            }
+            pg[g] = (double)hits / ball_draws;
+            hits_all += hits;
+        }
+        rho = rnext;
+        if ((double)hits_all / ((double)ng * ball_draws) >= q) {
+            double lball = 0.5 * n * log(3.14159265358979323846) + n * log(rho) - lgamma(0.5 * n + 1.0);
+            for (int g = 0; g < ng; g++) lv[g] += lball + log(pg[g]);
+            free(pg);
+            if (radii) radii[ph + 1] = rho;
+            rc = ORC_OK;
+            ph++;
+            break;
+        }
+        free(pg);
+        /* chains into the next ball */
+        for (int c = 0; c < chains; c++) {
+            double* x = X + (size_t)c * n;
+            double r2 = 0.0;
+            for (int i = 0; i < n; i++) r2 += x[i] * x[i];
+            double lim = (1.0 - 1e-6) * rho;
+            if (r2 > lim * lim) {
+                double sc = lim / sqrt(r2);
+                for (int i = 0; i < n; i++) x[i] *= sc;
+            }
+        }
+    }
+    if (phases_out) *phases_out = ph;
+    if (rc == ORC_OK) {
+        double mean = 0.0, var = 0.0;
+        for (int g = 0; g < ng; g++) mean += lv[g];
+        mean /= ng;
+        for (int g = 0; g < ng; g++) var += (lv[g] - mean) * (lv[g] - mean);
+        var /= (ng - 1);
+        double half = student_q975(ng - 1) * sqrt(var / ng);
+        *log_vol = mean;
+        *ci_lo = mean - half;
+        *ci_hi = mean + half;
+    }
+    free(X); free(v); free(p); free(sd); free(w); free(u); free(nrm); free(first); free(lv);
+    scratch_free(&s);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* MLP (the learned bracket's network), FP64                                 */
 /* ------------------------------------------------------------------------ */
 

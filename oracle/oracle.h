@@ -98,6 +98,16 @@ int orc_volume(const orc_lmi* h, int phases, int samples_per_phase, int chains,
                int walk_len, uint64_t seed, double a0, double a_end, int n_groups,
                double* log_vol, double* ci_lo, double* ci_hi, double* log_ratios);
 
+/* Volume by the ball sequence S_i = S cap rho_i B of eq. (mmc_vol): billiard
+ * samples of each S_i, next radius the q-quantile of |x| (first half of the
+ * samples), ratios from the second half per group, last ball when at least a
+ * fraction q of it lies in S (ball_draws exact draws per group).  radii
+ * (nullable, max_phases + 1) receives rho_0 = inf, rho_1, ...; ORC_NOCONV if
+ * max_phases do not suffice.  0 must be interior to S. */
+int orc_volume_balls(const orc_lmi* h, int chains, int spc, int walk_len, int burn_in, double q, int max_phases,
+                     int ball_draws, uint64_t seed, double tau, int ng, double* log_vol, double* ci_lo,
+                     double* ci_hi, double* radii, int* phases_out);
+
 /* Small MLP: dims[0] -> ... -> dims[nl], GELU between layers, linear output.
  * params: for each layer l, W_l (dims[l] x dims[l+1], row-major) then b_l. */
 int64_t orc_mlp_nparams(int nl, const int* dims);

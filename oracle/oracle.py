@@ -49,6 +49,8 @@ def lib():
         L.orc_walk.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int64, C.c_uint64, C.c_double, C.c_int,
                                C.c_double, C.c_double, C.c_int, dp, dp, dp]
         L.orc_billiard_segment.argtypes = [vp, C.c_int, dp, dp, dp, C.c_double, dp, dp, dp, i32p]
+        L.orc_volume_balls.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                       C.c_uint64, C.c_double, C.c_int, dp, dp, dp, dp, ip]
         L.orc_walk_boltz.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int64, C.c_int64, C.c_uint64, C.c_double,
                                      C.c_int, dp, C.c_double, C.c_double, C.c_int, dp, dp, dp]
         L.orc_sdp_anneal.argtypes = [vp, C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, C.c_int, C.c_int,
@@ -199,6 +201,17 @@ class Oracle:
         if rc != OK:
             raise ValueError(f"orc_sdp_anneal failed: {rc}")
         return xb, fb, best[:, :iters]
+
+    def volume_balls(self, chains, spc, walk_len, burn_in, q, max_phases, ball_draws, seed, tau, groups=8):
+        """Ball-sequence volume: (log_vol, ci_lo, ci_hi, radii, phases, status)."""
+        lv, lo, hi = C.c_double(), C.c_double(), C.c_double()
+        radii = np.full(max_phases + 1, np.nan)
+        ph = C.c_int()
+        rc = lib().orc_volume_balls(self._h, chains, spc, walk_len, burn_in, q, max_phases, ball_draws, seed, tau,
+                                    groups, C.byref(lv), C.byref(lo), C.byref(hi), _p(radii), C.byref(ph))
+        if rc not in (OK, NOCONV):
+            raise ValueError(f"orc_volume_balls failed: {rc}")
+        return lv.value, lo.value, hi.value, radii[:ph.value + 1], ph.value, rc
 
     def billiard_segment(self, x, v, ell, pullback=1e-6):
         x = _d(x).reshape(-1, self.n)

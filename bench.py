@@ -624,6 +624,39 @@ def estimator_leg(S, I, n, trials, points, lengths=TABLE3_W):
     return out
 
 
+TABLE2_PAPER = {  # volume (mean +- t s / sqrt(10)), points, seconds; one CPU core (context, not the target)
+    40: ("(1.34 +- 0.12)e-06", 9975.2, 6.7), 60: ("(1.23 +- 0.11)e-20", 20370.9, 28.5),
+    80: ("(4.24 +- 0.26)e-33", 31539.1, 124.4), 100: ("(1.21 +- 0.10)e-51", 52962.7, 362.3),
+}
+
+
+def volume_balls_leg(S, I, sizes=(40, 60, 80, 100), chains=2048, samples_per_chain=20):
+    """The volume table of the paper (ball sequence, eq. (mmc_vol)): log10 of
+    vol(S-n-n) of its generator (one seeded instance per size; the paper's
+    instances are not published, so the volumes differ), the 95 % interval
+    over 8 groups of chains, the balls, billiard points and wall time."""
+    import torch
+    out = {}
+    for n in sizes:
+        g = S.Spectrahedron(I.paper_random(n, n, seed=40000 + n))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lv, lo, hi, st = g.volume_balls(chains=chains, samples_per_chain=samples_per_chain, seed=41000 + n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ln10 = math.log(10.0)
+        out[f"S-{n}-{n}"] = {
+            "instance_seed": 40000 + n, "log10_volume": lv / ln10, "log10_ci": [lo / ln10, hi / ln10],
+            "relative_half_width": math.expm1(0.5 * (hi - lo)), "balls": st["phases"], "points": st["points"],
+            "oracle_calls": st["oracle_calls"], "seconds": dt,
+            "paper": {"volume": TABLE2_PAPER[n][0], "points": TABLE2_PAPER[n][1], "seconds": TABLE2_PAPER[n][2],
+                      "note": "its own random instances, one CPU core (context, not the target)"},
+        }
+        progress(f"ball-sequence volume: S-{n}-{n} done")
+        del g
+    return out
+
+
 TABLE4_PAPER = {  # iterations / seconds / failures out of 10, one CPU core (context, not the target)
     30: {"hmc_r": (20.1, 2.9, 0), "hnr_w1": (184.3, 3.4, 1), "hnr_w2": (52.1, 5.2, 0)},
     40: {"hmc_r": (24.6, 7.9, 0), "hnr_w1": (223.3, 9.9, 2), "hnr_w2": (61.9, 17.1, 0)},
@@ -719,6 +752,8 @@ def main():
     ap.add_argument("--anneal", action="store_true",
                     help="also run the annealing table (min <c, x> on S-30-30 .. S-60-60)")
     ap.add_argument("--anneal-instances", type=int, default=10)
+    ap.add_argument("--volume-balls", action="store_true",
+                    help="also run the ball-sequence volume table (S-40-40 .. S-100-100)")
     ap.add_argument("--anneal-chains", type=int, default=64)
     ap.add_argument("--anneal-max-iters", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -846,6 +881,9 @@ def main():
         progress("walk-length table and expectation estimators")
         out["walk_length_table"] = walk_length_leg(S, I, args.walk_length_instances, 200)
         out["expectation_estimators"] = estimator_leg(S, I, 50, 20, 200)
+    if args.volume_balls:
+        progress("ball-sequence volume table")
+        out["volume_balls_table"] = volume_balls_leg(S, I)
     if args.anneal:
         progress("annealing table")
         out["anneal_table"] = anneal_leg(S, I, args.anneal_instances, args.anneal_chains, args.anneal_max_iters)

@@ -261,7 +261,12 @@ spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const
  *            exp(-t <c, v> / T); HMC follows p(t) = p + t v - t^2 c / (2T)
  *            (eq. (boltz_ode)), each segment one degree-2 curve whose horizon
  *            is the travel time left, and reflects the velocity v - t c / T at
- *            the hit.  Not with the billiard walk or with gauss_a > 0. */
+ *            the hit.  Not with the billiard walk or with gauss_a > 0.
+ *  ball_radius  billiard walk only: walk in S cap {|x| <= ball_radius} (the
+ *            bodies S_i of eq. (mmc_vol)); a segment ends at the first of S's
+ *            boundary, the sphere and the length left, and reflects on the
+ *            sphere's radial normal when that comes first (0 = no ball; x0
+ *            inside the ball). */
 typedef struct {
     double tau;
     int rho;
@@ -276,6 +281,7 @@ typedef struct {
     int32_t* log_count;
     const double* boltz_c;
     double boltz_T;
+    double ball_radius;
 } spec_walk_params;
 
 /* Totals over chains, counted over the rounds of this call (a resumed call
@@ -407,6 +413,47 @@ typedef struct {
  * EINVAL for bad parameters (phases <= 256, groups >= 2, chains % groups == 0). */
 spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uint64_t seed, double* log_vol,
                                  double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Volume by the ball sequence of eq. (mmc_vol): S_i = S cap rho_i B with
+ * rho_0 = infinity.  In phase i the chains walk burn_in billiard steps in S_i
+ * from where the last phase left them, then keep samples_per_chain points
+ * walk_len steps apart.  The next radius rho_{i+1} is the q-quantile of |x|
+ * over the first half of the samples (all chains); vol(S_{i+1}) / vol(S_i)
+ * is the fraction of the second half inside rho_{i+1} B, per group of chains.
+ * The sequence ends at the first ball with at least a fraction q inside S by
+ * ball_draws exact uniform draws per group: vol(S_k) = vol(rho_k B) times the
+ * group's fraction.  Chains outside the next ball move radially onto
+ * (1 - 1e-6) rho_{i+1} (inside S, which is convex and holds 0).  0 must be an
+ * interior point of S.  Phase i walks with the seed  seed + 7919 (i + 1).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int chains;             /* a multiple of groups (default 1024) */
+    int groups;             /* independent groups for the interval (default 8) */
+    int samples_per_chain;  /* per phase, even (default 16) */
+    int walk_len;           /* billiard steps between kept points (default 1) */
+    int burn_in;            /* steps at the start of each phase (< 0: n / 4; rounded up to walk_len) */
+    double q;               /* target ratio of consecutive volumes (default 0.2) */
+    int max_phases;         /* at most 256 (default 256) */
+    int ball_draws;         /* exact draws per group for the stop test and the last ball (default 4096) */
+    double tau;             /* billiard length scale (<= 0: 2 x the longest chord of a 64-chain Hit-and-Run
+                               pre-run from 0) */
+} spec_volume_balls_params;
+
+typedef struct {
+    int phases;             /* balls after S itself */
+    double radii[257];      /* rho_1 .. rho_phases */
+    double log_ratios[257]; /* [i] = mean over groups of log(vol(S_{i+1}) / vol(S_i)); [phases] = log vol(S_k) */
+    double points;          /* billiard points generated (steps of all chains) */
+    double oracle_calls;
+    double tau;
+} spec_volume_balls_stats;
+
+/* log vol(S) and its 95 % interval over the groups (mean +- t_{0.975,g-1}
+ * sd / sqrt(g)); host outputs, synchronises.  SPEC_EINVAL for bad parameters,
+ * SPEC_NOCONV if max_phases balls do not reach one mostly inside S. */
+spec_status spec_volume_balls(spec_handle h, const spec_volume_balls_params* p, uint64_t seed, double* log_vol,
+                              double* ci_lo, double* ci_hi, spec_volume_balls_stats* st);
 
 /* ------------------------------------------------------------------------
  * Uneven batching: many spectrahedra (different n and m) whose chains run

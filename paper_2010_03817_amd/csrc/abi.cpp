@@ -813,6 +813,7 @@ spec_status walk_run_impl(spec_handle h, int kind, int chains, const double* x0,
         return SPEC_EINVAL;
     if ((kind == SPEC_WALK_BILLIARD || kind == SPEC_WALK_HMC) && !(p->tau > 0.0)) return SPEC_EINVAL;
     if (p->boltz_c && (!(p->boltz_T > 0.0) || p->gauss_a > 0.0 || kind == SPEC_WALK_BILLIARD)) return SPEC_EINVAL;
+    if (p->ball_radius < 0.0 || (p->ball_radius > 0.0 && kind != SPEC_WALK_BILLIARD)) return SPEC_EINVAL;
     if (kind == SPEC_WALK_HMC && !(p->gauss_a > 0.0) && !p->boltz_c) return SPEC_EINVAL;
     if (p->gauss_a < 0.0 || !(p->pullback >= 0.0 && p->pullback < 1.0) || p->thin < 0) return SPEC_EINVAL;
     if (p->log_buf && (!p->log_count || p->log_cap < 0)) return SPEC_EINVAL;
@@ -841,6 +842,7 @@ WalkArgs make_walk_args(spec_handle h, int kind, int chains, long long steps, ui
     a.rho = p->rho > 0 ? p->rho : 10 * h->n;
     a.bc = p->boltz_c;
     a.bT = p->boltz_T;
+    a.ball_r = p->ball_radius > 0.0 ? p->ball_radius : INFINITY;
     a.st = WalkState{h->wX, h->wXs, h->wV, h->wEll, h->wNref, h->wStep, h->wActive, h->wStats};
     a.status = h->dSt;
     a.flags = h->dFlags;
@@ -1544,6 +1546,161 @@ spec_status spec_volume_estimate(spec_handle h, const spec_volume_params* p, uin
                                  double* ci_lo, double* ci_hi, spec_volume_stats* st, void* stream) {
     if (!h || !p || !log_vol) return SPEC_EINVAL;
     return volume_many(nullptr, &h, 1, p, seed, log_vol, ci_lo, ci_hi, st, (hipStream_t)stream);
+}
+
+spec_status spec_volume_balls(spec_handle h, const spec_volume_balls_params* p, uint64_t seed, double* log_vol,
+                              double* ci_lo, double* ci_hi, spec_volume_balls_stats* st) {
+    if (!h || !p || !log_vol || !ci_lo || !ci_hi) return SPEC_EINVAL;
+    const int n = h->n;
+    const int G = p->groups > 0 ? p->groups : 8;
+    const int C = p->chains > 0 ? p->chains : 1024;
+    const int K = p->samples_per_chain > 0 ? p->samples_per_chain : 16;
+    const int W = p->walk_len > 0 ? p->walk_len : 1;
+    const double q = p->q > 0.0 ? p->q : 0.2;
+    const int maxph = p->max_phases > 0 ? p->max_phases : 256;
+    const int M = p->ball_draws > 0 ? p->ball_draws : 4096;
+    if (G < 2 || C % G || K < 2 || K % 2 || !(q < 1.0) || maxph > 256) return SPEC_EINVAL;
+    int burn = p->burn_in >= 0 ? p->burn_in : (n + 3) / 4;
+    burn = (burn + W - 1) / W * W;
+    const int per_group = C / G, half = K / 2;
+    hipStream_t s = nullptr;
+    if (st) std::memset(st, 0, sizeof(*st));
+    double *dX = nullptr, *dXo = nullptr, *dSamp = nullptr, *dNorm = nullptr, *dBall = nullptr, *dOut = nullptr;
+    double* dLog = nullptr;
+    int8_t* dFlag = nullptr;
+    int32_t* dCnt = nullptr;
+    auto cleanup = [&]() {
+        dfree(dX); dfree(dXo); dfree(dSamp); dfree(dNorm); dfree(dBall); dfree(dOut); dfree(dLog);
+        dfree(dFlag); dfree(dCnt);
+    };
+#define BCHK(expr)                                                  \
+    do {                                                            \
+        spec_status _r = (expr);                                    \
+        if (_r != SPEC_OK) { cleanup(); return _r; }                \
+    } while (0)
+#define BHIP(expr) BCHK(from_hip(expr))
+    const int pre = 64, pre_steps = 20;
+    BHIP(dalloc(&dX, (size_t)std::max(C, pre) * n));  // zero: every chain starts at 0
+    BHIP(dalloc(&dXo, (size_t)std::max(C, pre) * n, false));
+    BHIP(dalloc(&dSamp, (size_t)C * K * n, false));
+    BHIP(dalloc(&dNorm, (size_t)C * K, false));
+    BHIP(dalloc(&dBall, (size_t)G * M * n, false));
+    BHIP(dalloc(&dFlag, (size_t)G * M, false));
+    BHIP(dalloc(&dOut, (size_t)G, false));
+    BHIP(dalloc(&dLog, (size_t)pre * pre_steps * (2 * n + 4), false));
+    BHIP(dalloc(&dCnt, 1));
+    double calls = 0.0, points = 0.0;
+    double tau = p->tau;
+    if (!(tau > 0.0)) {
+        spec_walk_params wp{};
+        wp.tau = 1.0;
+        wp.pullback = 1e-6;
+        wp.log_chains = pre;
+        wp.log_cap = pre * pre_steps;
+        wp.log_buf = dLog;
+        wp.log_count = dCnt;
+        spec_walk_stats ws{};
+        BCHK(walk_run_impl(h, SPEC_WALK_HNR, pre, dX, pre_steps, seed ^ 0x5851F42D4C957F2Dull, &wp, dXo, nullptr, 0,
+                           0, &ws, s));
+        calls += ws.calls;
+        std::vector<double> lg((size_t)wp.log_cap * (2 * n + 4));
+        BHIP(hipMemcpy(lg.data(), dLog, sizeof(double) * lg.size(), hipMemcpyDeviceToHost));
+        double d = 0.0;
+        for (int r = 0; r < wp.log_cap; ++r) {
+            const double tm = lg[(size_t)r * (2 * n + 4) + 2 * n], tp = lg[(size_t)r * (2 * n + 4) + 2 * n + 1];
+            if (std::isfinite(tm) && std::isfinite(tp)) d = std::max(d, tp - tm);
+        }
+        if (!(d > 0.0)) { cleanup(); return SPEC_UNBOUNDED; }
+        tau = 2.0 * d;
+    }
+    const double pi = 3.14159265358979323846;
+    std::vector<double> lv(G, 0.0), nrm((size_t)C * K), first((size_t)C * half);
+    std::vector<double> hits(G);
+    double rho = INFINITY;
+    int phases = 0;
+    bool done = false;
+    for (int ph = 0; ph < maxph && !done; ++ph) {
+        // billiard in S cap rho B: burn-in, then K points walk_len steps apart
+        spec_walk_params wp{};
+        wp.tau = tau;
+        wp.pullback = 1e-6;
+        wp.thin = W;
+        wp.ball_radius = std::isfinite(rho) ? rho : 0.0;
+        spec_walk_stats ws{};
+        BCHK(walk_run_impl(h, SPEC_WALK_BILLIARD, C, dX, burn + (long long)K * W, seed + 7919ull * (ph + 1), &wp,
+                           dXo, dSamp, burn / W, K, &ws, s));
+        calls += ws.calls;
+        points += ws.steps;
+        BHIP(row_norms((long long)C * K, n, dSamp, dNorm, s));
+        BHIP(hipMemcpy(nrm.data(), dNorm, sizeof(double) * nrm.size(), hipMemcpyDeviceToHost));
+        // next radius: the q-quantile of |x| over the first halves
+        for (int c = 0; c < C; ++c)
+            for (int k = 0; k < half; ++k) first[(size_t)c * half + k] = nrm[(size_t)c * K + k];
+        size_t qi = (size_t)std::floor(q * (double)first.size());
+        if (qi >= first.size()) qi = first.size() - 1;
+        std::nth_element(first.begin(), first.begin() + qi, first.end());
+        const double rnext = first[qi];
+        // ratio per group from the second halves
+        double lr = 0.0;
+        for (int g = 0; g < G; ++g) {
+            long long in = 0, tot = 0;
+            for (int c = g * per_group; c < (g + 1) * per_group; ++c)
+                for (int k = half; k < K; ++k, ++tot) in += nrm[(size_t)c * K + k] <= rnext;
+            const double r = std::log((double)in / (double)tot);
+            lv[g] -= r;
+            lr += r / G;
+        }
+        if (st && ph < 256) {
+            st->radii[ph] = rnext;
+            st->log_ratios[ph] = lr;
+        }
+        // stop test: exact uniform draws in rnext B, membership in S
+        const uint32_t tagbase = (uint32_t)(ph + 1) << 8;
+        BHIP(ball_points(G * M, M, n, seed, tagbase, rnext, dBall, s));
+        for (int q0 = 0; q0 < G * M; q0 += 4096)
+            BCHK(spec_membership_dev(h, std::min(4096, G * M - q0), dBall + (size_t)q0 * n, dFlag + q0, s));
+        BHIP(count_groups(G, M, dFlag, dOut, s));
+        BHIP(hipMemcpy(hits.data(), dOut, sizeof(double) * G, hipMemcpyDeviceToHost));
+        double all = 0.0;
+        for (double x : hits) all += x;
+        rho = rnext;
+        phases = ph + 1;
+        if (all / ((double)G * M) >= q) {
+            const double lball = 0.5 * n * std::log(pi) + n * std::log(rho) - std::lgamma(0.5 * n + 1.0);
+            double lk = 0.0;
+            for (int g = 0; g < G; ++g) {
+                const double t = lball + std::log(hits[g] / M);
+                lv[g] += t;
+                lk += t / G;
+            }
+            if (st && phases < 257) st->log_ratios[phases] = lk;
+            done = true;
+            break;
+        }
+        // the chains continue inside the next ball
+        BHIP(hipMemcpy(dX, dXo, sizeof(double) * C * n, hipMemcpyDeviceToDevice));
+        BHIP(shrink_into_ball(C, n, dX, (1.0 - 1e-6) * rho, s));
+    }
+    cleanup();
+#undef BCHK
+#undef BHIP
+    if (st) {
+        st->phases = phases;
+        st->points = points;
+        st->oracle_calls = calls;
+        st->tau = tau;
+    }
+    if (!done) return SPEC_NOCONV;
+    double mean = 0.0, var = 0.0;
+    for (double x : lv) mean += x;
+    mean /= G;
+    for (double x : lv) var += (x - mean) * (x - mean);
+    var /= (G - 1);
+    const double hw = student_t975(G - 1) * std::sqrt(var / G);
+    *log_vol = mean;
+    *ci_lo = mean - hw;
+    *ci_hi = mean + hw;
+    return SPEC_OK;
 }
 
 spec_status spec_batch_create(int count, const spec_handle* hs, spec_batch* out) {

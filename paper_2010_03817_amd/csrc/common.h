@@ -35,7 +35,7 @@ __device__ __forceinline__ u4 philox10(u4 c, uint32_t k0, uint32_t k1) {
 
 // Stream tags (low byte of the fourth counter word).
 enum : uint32_t {
-    TAG_DIR = 1, TAG_LEN = 2, TAG_POS = 3, TAG_COORD = 4, TAG_MOM = 5, TAG_GAUSS0 = 6,
+    TAG_DIR = 1, TAG_LEN = 2, TAG_POS = 3, TAG_COORD = 4, TAG_MOM = 5, TAG_GAUSS0 = 6, TAG_BALL = 7, TAG_BALL_R = 8,
     TAG_MLP_BATCH = 0x40, TAG_MLP_INIT = 0x41
 };
 

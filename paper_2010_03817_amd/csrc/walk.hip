@@ -489,6 +489,48 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
     }
     // billiard (Alg. Billiard): move to the end of the segment or reflect
     const double ell = S.ell[c];
+    if (a.ball_r < INFINITY) {
+        // in S cap r B: the sphere's exit -<x, v> + sqrt(<x, v>^2 + r^2 - |x|^2)
+        double xv = 0.0, xx = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            xv += x[i] * v[i];
+            xx += x[i] * x[i];
+        }
+        xv = wave_sum(xv);
+        xx = wave_sum(xx);
+        const double disc = xv * xv + a.ball_r * a.ball_r - xx;
+        const double tb = -xv + sqrt(fmax(disc, 0.0));
+        if (tb < tp && tb < ell) {
+            // reflect on the radial normal w = x + tb v
+            double ww = 0.0, wv = 0.0;
+            for (int i = lane; i < n; i += 64) {
+                const double wi = x[i] + tb * v[i];
+                ww += wi * wi;
+                wv += wi * v[i];
+            }
+            ww = wave_sum(ww);
+            wv = wave_sum(wv);
+            const double coef = ww > 0.0 ? 2.0 * wv / ww : 0.0;
+            const double step_len = (1.0 - a.pullback) * tb;
+            for (int i = lane; i < n; i += 64) {
+                const double wi = x[i] + tb * v[i];
+                x[i] += step_len * v[i];
+                v[i] -= coef * wi;
+            }
+            const int nref = S.nref[c] + 1;
+            if (lane == 0) {
+                st[1] += 1.0;
+                S.ell[c] = ell - tb;
+                S.nref[c] = nref;
+            }
+            if (nref > a.rho) {
+                if (lane == 0) st[2] += 1.0;
+                for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+                end_step(a, c, lane);
+            }
+            return;
+        }
+    }
     if (!(tp < ell)) {
         for (int i = lane; i < n; i += 64) x[i] += ell * v[i];
         end_step(a, c, lane);
@@ -585,6 +627,75 @@ __global__ __launch_bounds__(256) void k_anneal_track(int chains, int n, const d
             if (hit[c] < 0 && isfinite(f_star) && b - f_star <= eps * fabs(f_star)) hit[c] = it;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_row_norms(long long rows, int n, const double* __restrict__ X,
+                                                   double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const long long r = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double xi = X[(size_t)r * n + i];
+        s += xi * xi;
+    }
+    s = wave_sum(s);
+    if (lane == 0) out[r] = sqrt(s);
+}
+
+// Uniform in rho B: direction g / |g| from normals of stream (grp, k,
+// tagbase | TAG_BALL), radius rho u^(1/n) from (grp, k, tagbase | TAG_BALL_R).
+// One wave per point.
+__global__ __launch_bounds__(256) void k_ball_points(int count, int per_group, int n, uint64_t seed,
+                                                     uint32_t tagbase, double rho, double* __restrict__ X) {
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= count) return;
+    const uint32_t grp = (uint32_t)(q / per_group), k = (uint32_t)(q % per_group);
+    double ss = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double g = dir_component(seed, grp, k, tagbase | TAG_BALL, i);
+        ss += g * g;
+    }
+    ss = wave_sum(ss);
+    double u0, u1;
+    draw_u2(seed, grp, k, 0, tagbase | TAG_BALL_R, u0, u1);
+    const double rad = rho * pow(u0, 1.0 / n) / sqrt(ss);
+    for (int i = lane; i < n; i += 64) X[(size_t)q * n + i] = rad * dir_component(seed, grp, k, tagbase | TAG_BALL, i);
+}
+
+__global__ __launch_bounds__(256) void k_shrink_into_ball(int chains, int n, double* __restrict__ X, double lim) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= chains) return;
+    double* x = X + (size_t)c * n;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) s += x[i] * x[i];
+    s = wave_sum(s);
+    if (s > lim * lim) {
+        const double sc = lim / sqrt(s);
+        for (int i = lane; i < n; i += 64) x[i] *= sc;
+    }
+}
+
+hipError_t row_norms(long long rows, int n, const double* X, double* out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, n, X, out);
+    return hipGetLastError();
+}
+
+hipError_t ball_points(int count, int per_group, int n, uint64_t seed, uint32_t tagbase, double rho, double* X,
+                       hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ball_points, dim3((count + 3) / 4), dim3(256), 0, s, count, per_group, n, seed, tagbase, rho,
+                       X);
+    return hipGetLastError();
+}
+
+hipError_t shrink_into_ball(int chains, int n, double* X, double lim, hipStream_t s) {
+    if (chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shrink_into_ball, dim3((chains + 3) / 4), dim3(256), 0, s, chains, n, X, lim);
+    return hipGetLastError();
 }
 
 hipError_t anneal_track(int chains, int n, const double* x, const double* c, int it, int iters, double* xb,

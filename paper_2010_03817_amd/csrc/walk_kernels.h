@@ -30,6 +30,7 @@ struct WalkArgs {
     int rho;
     const double* bc;  // Boltzmann target exp(-<bc, x> / bT) (nullable: none)
     double bT;
+    double ball_r;     // billiard in S cap {|x| <= ball_r} (INFINITY: no ball)
     WalkState st;
     // oracle results of the current round
     const int32_t* status;
@@ -62,6 +63,13 @@ hipError_t walk_hmc_prep(const WalkArgs& a, double* Z, int zrow0, int Kpad, doub
 hipError_t anneal_track(int chains, int n, const double* x, const double* c, int it, int iters, double* xb,
                         double* fb, double* best, int32_t* hit, double f_star, double eps, bool init,
                         hipStream_t s);
+// Ball-sequence volume: |x| of rows, exact uniform draws in rho B (point
+// q = g * per_group + k from stream (g, k, tagbase | TAG_BALL*)), and chains
+// moved radially into a ball of radius lim.
+hipError_t row_norms(long long rows, int n, const double* X, double* out, hipStream_t s);
+hipError_t ball_points(int count, int per_group, int n, uint64_t seed, uint32_t tagbase, double rho, double* X,
+                       hipStream_t s);
+hipError_t shrink_into_ball(int chains, int n, double* X, double lim, hipStream_t s);
 // Volume helpers: exact Gaussian draws, per-group log-mean-exp of a phase,
 // per-group membership counts.
 hipError_t gauss_points(int count, int per_group, int n, uint64_t seed, double sd, double* X, hipStream_t s);

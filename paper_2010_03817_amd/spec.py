@@ -33,7 +33,18 @@ class WalkParams(C.Structure):
                 ("thin", C.c_int), ("max_rounds", C.c_longlong), ("resume", C.c_int), ("log_chains", C.c_int),
                 ("log_cap", C.c_int),
                 ("log_buf", C.c_void_p), ("log_count", C.c_void_p), ("boltz_c", C.c_void_p),
-                ("boltz_T", C.c_double)]
+                ("boltz_T", C.c_double), ("ball_radius", C.c_double)]
+
+
+class VolumeBallsParams(C.Structure):
+    _fields_ = [("chains", C.c_int), ("groups", C.c_int), ("samples_per_chain", C.c_int), ("walk_len", C.c_int),
+                ("burn_in", C.c_int), ("q", C.c_double), ("max_phases", C.c_int), ("ball_draws", C.c_int),
+                ("tau", C.c_double)]
+
+
+class VolumeBallsStats(C.Structure):
+    _fields_ = [("phases", C.c_int), ("radii", C.c_double * 257), ("log_ratios", C.c_double * 257),
+                ("points", C.c_double), ("oracle_calls", C.c_double), ("tau", C.c_double)]
 
 
 class AnnealParams(C.Structure):
@@ -166,6 +177,8 @@ def lib():
     L.spec_batch_tune.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_int)]
     L.spec_batch_volume.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, vp, vp, vp, C.POINTER(C.c_double)]
     L.spec_batch_intersect.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+    L.spec_volume_balls.argtypes = [vp, C.POINTER(VolumeBallsParams), C.c_uint64, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(VolumeBallsStats)]
     L.spec_sdp_anneal.argtypes = [vp, C.POINTER(AnnealParams), C.c_int, vp, vp, C.c_uint64, vp, vp, vp, vp,
                                   C.POINTER(WalkStats)]
     L.spec_volume_estimate.argtypes = [vp, C.POINTER(VolumeParams), C.c_uint64, C.POINTER(C.c_double),
@@ -330,7 +343,7 @@ class Spectrahedron:
         return tp, s, w, st
 
     def walk(self, kind, x0, steps, seed, tau=1.0, rho=0, gauss_a=0.0, pullback=1e-6, thin=0, max_rounds=0,
-             log_chains=0, log_cap=0, resume=False, boltz_c=None, boltz_T=0.0):
+             log_chains=0, log_cap=0, resume=False, boltz_c=None, boltz_T=0.0, ball_radius=0.0):
         """Run chains of a walk (HNR, CHNR, BILLIARD) from x0; returns
         (x_out, samples or None, stats dict, log or None).  The log holds rows
         (x, v, t-, t+, chain, status) of segments of the first log_chains chains."""
@@ -347,7 +360,7 @@ class Spectrahedron:
         bc = None if boltz_c is None else _f64(boltz_c).reshape(self.n)
         p = WalkParams(tau=tau, rho=rho, gauss_a=gauss_a, pullback=pullback, thin=thin, max_rounds=max_rounds,
                        resume=int(resume), log_chains=log_chains, log_cap=log_cap, log_buf=_ptr(log),
-                       log_count=_ptr(cnt), boltz_c=_ptr(bc), boltz_T=boltz_T)
+                       log_count=_ptr(cnt), boltz_c=_ptr(bc), boltz_T=boltz_T, ball_radius=ball_radius)
         st = WalkStats()
         check(lib().spec_walk_run_dev(self._h, kind, ch, _ptr(x0), steps, seed, C.byref(p), _ptr(x_out),
                                       _ptr(samples), C.byref(st), _stream()))
@@ -369,6 +382,21 @@ class Spectrahedron:
         check(lib().spec_walk_run(self._h, kind, ch, x0.ctypes.data, steps, seed, C.byref(p), x_out.ctypes.data,
                                   samples.ctypes.data if samples is not None else None, C.byref(st)))
         return x_out, samples, st.as_dict()
+
+    def volume_balls(self, chains=1024, groups=8, samples_per_chain=16, walk_len=1, burn_in=-1, q=0.2,
+                     max_phases=256, ball_draws=4096, tau=0.0, seed=1):
+        """spec_volume_balls: (log_vol, ci_lo, ci_hi, stats dict with radii and
+        log_ratios trimmed to the phases run)."""
+        p = VolumeBallsParams(chains=chains, groups=groups, samples_per_chain=samples_per_chain, walk_len=walk_len,
+                              burn_in=burn_in, q=q, max_phases=max_phases, ball_draws=ball_draws, tau=tau)
+        lv, lo, hi = C.c_double(), C.c_double(), C.c_double()
+        st = VolumeBallsStats()
+        check(lib().spec_volume_balls(self._h, C.byref(p), int(seed), C.byref(lv), C.byref(lo), C.byref(hi),
+                                      C.byref(st)))
+        k = st.phases
+        return lv.value, lo.value, hi.value, {"phases": k, "radii": list(st.radii[:k]),
+                                              "log_ratios": list(st.log_ratios[:k + 1]), "points": st.points,
+                                              "oracle_calls": st.oracle_calls, "tau": st.tau}
 
     def sdp_anneal(self, x0, c, T0, tau0, iterations=70, walk_len=1, kind=None, cool=0.0, seed=1, rho=0,
                    pullback=1e-6, f_star=float("nan"), eps=0.05, stop_when_reached=False):

@@ -326,13 +326,46 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
     return net, best, ctl, cbest, report
 
 
-def uneven_leg(S, I, samples_per_phase):
-    """256 spectrahedra, n and m log-uniform in [20, 200] (every 16th an arrow
-    ball of known volume), 64 chains each: launch strategy autotuned, oracle
-    round rate of the whole mixed batch, and a batched Gaussian-cooling
-    volume of the 16 balls (phase count from the cooling rule: a fixed 20
-    phases leaves the ratio estimators' variance exponential in n / 20 at
-    n ~ 200) with their errors against pi^(n/2) / Gamma(n/2 + 1)."""
+def uneven_volume_all(S, I, samples_per_phase, chunk=32):
+    """The batched Gaussian-cooling volume of all 256 spectrahedra of the
+    uneven workload (the 16 balls of known volume among them), in batches of
+    `chunk` instances that advance together (the cooling rule's phase count is
+    the largest of a batch), `samples_per_phase` samples per phase."""
+    insts, balls = _uneven_family(I)
+    res, t0 = [], time.perf_counter()
+    calls = 0.0
+    for c0 in range(0, len(insts), chunk):
+        specs = [S.Spectrahedron(i) for i in insts[c0:c0 + chunk]]
+        b = S.Batch(specs)
+        lv, lo, hi, cl = b.volume(phases=0, samples_per_phase=samples_per_phase, chains=64, walk_len=4, groups=8,
+                                  seed=404 + c0, burn_in=200)
+        calls += cl
+        for j in range(len(specs)):
+            res.append((float(lv[j]), float(lo[j]), float(hi[j])))
+        b.close()
+        del specs
+        progress(f"uneven volume: {min(c0 + chunk, len(insts))}/{len(insts)} instances, "
+                 f"{time.perf_counter() - t0:.0f} s")
+    wall = time.perf_counter() - t0
+    inside = inside2 = 0
+    per_ball = []
+    for k in balls:
+        nb = insts[k].n
+        truth = 0.5 * nb * math.log(math.pi) - math.lgamma(0.5 * nb + 1)
+        lv, lo, hi = res[k]
+        w = hi - lo
+        inside += int(lo <= truth <= hi)
+        inside2 += int(lo - 0.5 * w <= truth <= hi + 0.5 * w)
+        per_ball.append({"n": nb, "err": lv - truth, "ci_half": 0.5 * w})
+    widths = np.array([r[2] - r[1] for r in res])
+    return {"instances": len(insts), "samples_per_phase": samples_per_phase, "chains_per_instance": 64,
+            "batch": chunk, "seconds": wall, "oracle_calls": calls, "oracle_calls_per_s": calls / wall,
+            "balls_within_ci": f"{inside}/{len(balls)}", "balls_within_doubled_ci": f"{inside2}/{len(balls)}",
+            "balls": per_ball, "ci_width_median": float(np.median(widths)), "ci_width_max": float(widths.max()),
+            "finite": int(np.isfinite([r[0] for r in res]).sum())}
+
+
+def _uneven_family(I):
     rng = np.random.default_rng(104)
     insts, balls = [], []
     for k in range(256):
@@ -344,6 +377,17 @@ def uneven_leg(S, I, samples_per_phase):
             balls.append(k)
         else:
             insts.append(I.gbase(n, m, seed=1000 + k))
+    return insts, balls
+
+
+def uneven_leg(S, I, samples_per_phase):
+    """256 spectrahedra, n and m log-uniform in [20, 200] (every 16th an arrow
+    ball of known volume), 64 chains each: launch strategy autotuned, oracle
+    round rate of the whole mixed batch, and a batched Gaussian-cooling
+    volume of the 16 balls (phase count from the cooling rule: a fixed 20
+    phases leaves the ratio estimators' variance exponential in n / 20 at
+    n ~ 200) with their errors against pi^(n/2) / Gamma(n/2 + 1)."""
+    insts, balls = _uneven_family(I)
     specs = [S.Spectrahedron(i) for i in insts]
     b = S.Batch(specs)
     chains = 64
@@ -624,6 +668,74 @@ def estimator_leg(S, I, n, trials, points, lengths=TABLE3_W):
     return out
 
 
+def config2_leg(S, I, chains=4096, steps=10000, chunk=500, log_per_chunk=128):
+    """Plain batched billiard at the paper's scale: G-BASE n = m = 100 (plus
+    the 200-row box block), FP64, `chains` chains of `steps` steps each with
+    tau = 2 x the diameter estimate, walked in chunks of `chunk` steps (the
+    chains resume where they stopped).  In every chunk the first segments of
+    64 chains are logged; afterwards the oracle recomputes >= 1000 of the
+    logged (x, v) by bisection on membership in parallel host threads, and
+    every far root must agree to 1e-9 (the near root of a start next to the
+    boundary to 1e-9 plus the rounding bound of its assembly and factor)."""
+    import torch
+    n = 100
+    inst = I.gbase(n, n, seed=102)
+    g = S.Spectrahedron(inst)
+    _, _, _, log = g.walk(S.HNR, np.zeros((64, n)), 20, seed=11, log_chains=64, log_cap=64 * 20)
+    lg = log.cpu().numpy()
+    tau = 2.0 * float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+    x0 = torch.zeros((chains, n), dtype=torch.float64, device="cuda")
+    logs, tot = [], {"calls": 0.0, "steps": 0.0, "reflections": 0.0, "not_interior": 0.0, "noconv": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        done = min(steps, done + chunk)
+        _, _, st, lgc = g.walk(S.BILLIARD, x0, done, seed=2020, tau=tau, resume=done > chunk,
+                               log_chains=64, log_cap=log_per_chunk)
+        logs.append(lgc.cpu().numpy())
+        for k in tot:
+            tot[k] += st[k]
+        wall = time.perf_counter() - t0
+        progress(f"config 2: {done}/{steps} steps per chain, {tot['steps'] / wall:.0f} billiard steps/s")
+    wall = time.perf_counter() - t0
+    pairs = np.concatenate(logs)
+    x, v, tpw = pairs[:, :n], pairs[:, n:2 * n], pairs[:, 2 * n + 1]
+    out = {"n": n, "m": n, "box_rows": 2 * n, "chains": chains, "steps_per_chain": steps, "tau": tau,
+           "instance_seed": 102, "seconds": wall, "billiard_steps_per_s": tot["steps"] / wall,
+           "oracle_calls_per_s": tot["calls"] / wall, "calls_per_step": tot["calls"] / max(tot["steps"], 1),
+           "not_interior": tot["not_interior"], "noconv": tot["noconv"], "logged_pairs": len(pairs)}
+    return out, (x, v, tpw)
+
+
+def cpu_baseline_config2(x, v, tpw, workers=16):
+    """The CPU oracle on the logged pairs of the paper-scale walk: its
+    bisection on membership over `workers` host threads (oracle calls/s on
+    the host cores), and the walk's own t+ against it (every far root to
+    1e-9)."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    from paper_2010_03817_amd import instances as I
+    o = O.Oracle(I.gbase(100, 100, seed=102))
+    workers = min(workers, os.cpu_count() or 1)
+    tm_r, tp_r = np.empty(len(x)), np.empty(len(x))
+    parts = [q for q in np.array_split(np.arange(len(x)), workers) if len(q)]
+
+    def job(ix):
+        a, b, _ = o.line_bisect(x[ix], v[ix])
+        tm_r[ix], tp_r[ix] = a, b
+
+    t1 = time.perf_counter()
+    with cf.ThreadPoolExecutor(len(parts)) as ex:
+        list(ex.map(job, parts))
+    wall = time.perf_counter() - t1
+    rel = np.abs(tpw - tp_r) / tp_r
+    return {"kind": "oracle", "pairs": len(x), "threads": len(parts), "seconds": wall,
+            "oracle_calls_per_s": len(x) / wall, "method": "bisection on Cholesky membership",
+            "tplus_rel_max": float(rel.max()), "tplus_rel_median": float(np.median(rel)),
+            "within_1e-9": int((rel <= 1e-9).sum())}
+
+
 TABLE2_PAPER = {  # volume (mean +- t s / sqrt(10)), points, seconds; one CPU core (context, not the target)
     40: ("(1.34 +- 0.12)e-06", 9975.2, 6.7), 60: ("(1.23 +- 0.11)e-20", 20370.9, 28.5),
     80: ("(4.24 +- 0.26)e-33", 31539.1, 124.4), 100: ("(1.21 +- 0.10)e-51", 52962.7, 362.3),
@@ -752,6 +864,12 @@ def main():
     ap.add_argument("--anneal", action="store_true",
                     help="also run the annealing table (min <c, x> on S-30-30 .. S-60-60)")
     ap.add_argument("--anneal-instances", type=int, default=10)
+    ap.add_argument("--config2", action="store_true",
+                    help="also run the paper-scale plain walk (n = m = 100, 4096 chains x 1e4 billiard steps) and "
+                         "check logged pairs with the oracle")
+    ap.add_argument("--config2-steps", type=int, default=10000)
+    ap.add_argument("--uneven-volume-all", action="store_true",
+                    help="also estimate the volume of all 256 uneven spectrahedra (--uneven-samples per phase)")
     ap.add_argument("--volume-balls", action="store_true",
                     help="also run the ball-sequence volume table (S-40-40 .. S-100-100)")
     ap.add_argument("--anneal-chains", type=int, default=64)
@@ -881,6 +999,15 @@ def main():
         progress("walk-length table and expectation estimators")
         out["walk_length_table"] = walk_length_leg(S, I, args.walk_length_instances, 200)
         out["expectation_estimators"] = estimator_leg(S, I, 50, 20, 200)
+    if args.config2:
+        progress("config 2: paper-scale billiard walk")
+        out["config2"], c2pairs = config2_leg(S, I, steps=args.config2_steps)
+        if not args.no_cpu:
+            progress("config 2: CPU oracle on the logged pairs")
+            out["config2"]["cpu_baseline"] = cpu_baseline_config2(*c2pairs)
+    if args.uneven_volume_all:
+        progress("uneven volume of all 256 instances")
+        out["uneven_volume_all"] = uneven_volume_all(S, I, args.uneven_samples)
     if args.volume_balls:
         progress("ball-sequence volume table")
         out["volume_balls_table"] = volume_balls_leg(S, I)

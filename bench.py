@@ -668,7 +668,7 @@ def estimator_leg(S, I, n, trials, points, lengths=TABLE3_W):
     return out
 
 
-def config2_leg(S, I, chains=4096, steps=10000, chunk=500, log_per_chunk=128):
+def config2_leg(S, I, chains=4096, steps=10000, chunk=500, log_per_chunk=128, start=None, save=None, seed=2020):
     """Plain batched billiard at the paper's scale: G-BASE n = m = 100 (plus
     the 200-row box block), FP64, `chains` chains of `steps` steps each with
     tau = 2 x the diameter estimate, walked in chunks of `chunk` steps (the
@@ -684,21 +684,28 @@ def config2_leg(S, I, chains=4096, steps=10000, chunk=500, log_per_chunk=128):
     _, _, _, log = g.walk(S.HNR, np.zeros((64, n)), 20, seed=11, log_chains=64, log_cap=64 * 20)
     lg = log.cpu().numpy()
     tau = 2.0 * float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+    # start: chain positions saved by an earlier run (a step boundary, where the
+    # walk is Markov: the continuation draws new directions and lengths)
     x0 = torch.zeros((chains, n), dtype=torch.float64, device="cuda")
+    if start:
+        x0 = torch.from_numpy(np.load(start)).to(device="cuda", dtype=torch.float64)
+        assert tuple(x0.shape) == (chains, n)
     logs, tot = [], {"calls": 0.0, "steps": 0.0, "reflections": 0.0, "not_interior": 0.0, "noconv": 0.0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
     while done < steps:
         done = min(steps, done + chunk)
-        _, _, st, lgc = g.walk(S.BILLIARD, x0, done, seed=2020, tau=tau, resume=done > chunk,
-                               log_chains=64, log_cap=log_per_chunk)
+        xo, _, st, lgc = g.walk(S.BILLIARD, x0, done, seed=seed, tau=tau, resume=done > chunk,
+                                log_chains=64, log_cap=log_per_chunk)
         logs.append(lgc.cpu().numpy())
         for k in tot:
             tot[k] += st[k]
         wall = time.perf_counter() - t0
         progress(f"config 2: {done}/{steps} steps per chain, {tot['steps'] / wall:.0f} billiard steps/s")
     wall = time.perf_counter() - t0
+    if save:
+        np.save(save, xo.cpu().numpy())
     pairs = np.concatenate(logs)
     x, v, tpw = pairs[:, :n], pairs[:, n:2 * n], pairs[:, 2 * n + 1]
     out = {"n": n, "m": n, "box_rows": 2 * n, "chains": chains, "steps_per_chain": steps, "tau": tau,
@@ -868,6 +875,9 @@ def main():
                     help="also run the paper-scale plain walk (n = m = 100, 4096 chains x 1e4 billiard steps) and "
                          "check logged pairs with the oracle")
     ap.add_argument("--config2-steps", type=int, default=10000)
+    ap.add_argument("--config2-start", default=None, help="continue from chain positions saved by --config2-save")
+    ap.add_argument("--config2-save", default=None, help="save the final chain positions (.npy)")
+    ap.add_argument("--config2-seed", type=int, default=2020)
     ap.add_argument("--uneven-volume-all", action="store_true",
                     help="also estimate the volume of all 256 uneven spectrahedra (--uneven-samples per phase)")
     ap.add_argument("--volume-balls", action="store_true",
@@ -1001,7 +1011,8 @@ def main():
         out["expectation_estimators"] = estimator_leg(S, I, 50, 20, 200)
     if args.config2:
         progress("config 2: paper-scale billiard walk")
-        out["config2"], c2pairs = config2_leg(S, I, steps=args.config2_steps)
+        out["config2"], c2pairs = config2_leg(S, I, steps=args.config2_steps, start=args.config2_start,
+                                              save=args.config2_save, seed=args.config2_seed)
         if not args.no_cpu:
             progress("config 2: CPU oracle on the logged pairs")
             out["config2"]["cpu_baseline"] = cpu_baseline_config2(*c2pairs)

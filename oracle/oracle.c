@@ -807,6 +807,10 @@ static void walk_step(const orc_lmi* h, int kind, uint64_t seed, uint32_t chain,
          * chain (the reflections' pull-back, applied to the chord ends) */
         double t = bc ? chord_sample_boltz(n, x, v, bc, bT, (1.0 - pullback) * r.tm, (1.0 - pullback) * r.tp, uu[0])
                       : chord_sample(n, x, v, 1.0, r.tm, r.tp, gauss_a, uu[0]);
+        /* every chord point at least the pull-back from the ends: a point
+         * within the roots' own error of the boundary may lie outside */
+        if (t < (1.0 - pullback) * r.tm) t = (1.0 - pullback) * r.tm;
+        if (t > (1.0 - pullback) * r.tp) t = (1.0 - pullback) * r.tp;
         for (int i = 0; i < n; i++) x[i] += t * v[i];
         return;
     }
@@ -825,7 +829,10 @@ static void walk_step(const orc_lmi* h, int kind, uint64_t seed, uint32_t chain,
             if (r.status == ORC_NOT_INTERIOR) { ws->notint += 1; return; }
             if (r.status == ORC_NOCONV) ws->noconv += 1;
             if (r.tp >= ell) {
-                for (int i = 0; i < n; i++) p[i] += ell * v[i];
+                /* the step ends inside: at ell, but never nearer the boundary
+                 * than the pull-back of a reflection */
+                double te = ell < (1.0 - pullback) * r.tp ? ell : (1.0 - pullback) * r.tp;
+                for (int i = 0; i < n; i++) p[i] += te * v[i];
                 break;
             }
             normal_at(h, r.bplus, r.jplus, u, s->w);
@@ -1115,7 +1122,8 @@ int orc_billiard_segment(const orc_lmi* h, int batch, const double* x, const dou
             continue;
         }
         if (r.tp >= ell[e]) {
-            for (int i = 0; i < n; i++) { xo[i] = xe[i] + ell[e] * ve[i]; vo[i] = ve[i]; }
+            double te = ell[e] < (1.0 - pullback) * r.tp ? ell[e] : (1.0 - pullback) * r.tp;
+            for (int i = 0; i < n; i++) { xo[i] = xe[i] + te * ve[i]; vo[i] = ve[i]; }
             ell_left[e] = 0.0;
             continue;
         }
@@ -1220,6 +1228,9 @@ int orc_volume(const orc_lmi* h, int phases, int spp, int chains, int walk_len, 
                     double uu[2];
                     draw_u2(seed, (uint32_t)c, step, 0, tagbase | TAG_POS, uu);
                     double t = chord_sample(n, x, v, 1.0, r.tm, r.tp, a[ph], uu[0]);
+                    /* at least the walks' pull-back 1e-6 from the chord's ends */
+                    if (t < (1.0 - 1e-6) * r.tm) t = (1.0 - 1e-6) * r.tm;
+                    if (t > (1.0 - 1e-6) * r.tp) t = (1.0 - 1e-6) * r.tp;
                     for (int i = 0; i < n; i++) x[i] += t * v[i];
                 }
                 double r2 = 0.0;
@@ -1291,7 +1302,8 @@ static void billiard_ball_step(const orc_lmi* h, uint64_t seed, uint32_t chain, 
         }
         double th = tb < r.tp ? tb : r.tp;
         if (th >= ell) {
-            for (int i = 0; i < n; i++) p[i] += ell * v[i];
+            double te = ell < (1.0 - pullback) * th ? ell : (1.0 - pullback) * th;
+            for (int i = 0; i < n; i++) p[i] += te * v[i];
             break;
         }
         if (tb < r.tp) {

@@ -482,6 +482,9 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
             } else {
                 t = tm + u0 * (tp - tm);
             }
+            // every chord point at least the pull-back from the ends: a point
+            // within the roots' own error of the boundary may lie outside
+            t = fmin(fmax(t, (1.0 - a.pullback) * tm), (1.0 - a.pullback) * tp);
             for (int i = lane; i < n; i += 64) x[i] += t * v[i];
         }
         end_step(a, c, lane);
@@ -489,6 +492,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
     }
     // billiard (Alg. Billiard): move to the end of the segment or reflect
     const double ell = S.ell[c];
+    double tlim = tp;  // nearest boundary along the segment (S, or S cap r B)
     if (a.ball_r < INFINITY) {
         // in S cap r B: the sphere's exit -<x, v> + sqrt(<x, v>^2 + r^2 - |x|^2)
         double xv = 0.0, xx = 0.0;
@@ -500,6 +504,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         xx = wave_sum(xx);
         const double disc = xv * xv + a.ball_r * a.ball_r - xx;
         const double tb = -xv + sqrt(fmax(disc, 0.0));
+        tlim = fmin(tp, tb);
         if (tb < tp && tb < ell) {
             // reflect on the radial normal w = x + tb v
             double ww = 0.0, wv = 0.0;
@@ -532,7 +537,10 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         }
     }
     if (!(tp < ell)) {
-        for (int i = lane; i < n; i += 64) x[i] += ell * v[i];
+        // the step ends inside: at ell, but never nearer the boundary than the
+        // pull-back of a reflection
+        const double te = fmin(ell, (1.0 - a.pullback) * tlim);
+        for (int i = lane; i < n; i += 64) x[i] += te * v[i];
         end_step(a, c, lane);
         return;
     }

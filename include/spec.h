@@ -215,10 +215,11 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
                              double* t_plus, double* s_out, double* w_out, int32_t* status,
                              void* stream);
 
-/* INTERSECTION for polynomial curves of degree 1 or 2 (Alg. INTERSECTION,
- * Lemma "PEP and S cap C"): with Q_k = coef[e][k][0] A0 + sum_i
- * coef[e][k][i] A_i (coef: batch x (degree+1) x (n+1), row-major), the first
- * positive / negative roots of det(Q0 + t Q1 + t^2 Q2) within |t| <= horizon
+/* INTERSECTION for polynomial curves of degree 1 to SPEC_CURVE_MAX_DEGREE
+ * (Alg. INTERSECTION, Lemma "PEP and S cap C", eq. (PEP)): with Q_k =
+ * coef[e][k][0] A0 + sum_i coef[e][k][i] A_i (coef: batch x (degree+1) x
+ * (n+1), row-major), the first positive / negative roots of
+ * det(Q0 + t Q1 + .. + t^d Q_d) within |t| <= horizon
  * (+-INFINITY when there is none), i.e. the ends of the interval around 0 on
  * which Q(t) stays positive definite.  Q0 must be positive definite
  * (else NOT_INTERIOR, NaN outputs).  Dense blocks by certified Weyl steps:
@@ -226,7 +227,13 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
  * L^-1 Q2 L^-T from below (Lanczos Ritz value minus residual bound), so Q
  * stays definite over the step; diagonal rows by their scalar quadratics.
  * status[e]: OK, NOT_INTERIOR, NOCONV (the eigen solve of L^-1 Q'(tau) L^-T did
- * not converge; the bounds stay certified, the step only shorter). */
+ * not converge; the bounds stay certified, the step only shorter).  Degree
+ * >= 3: the same stepping with the Taylor coefficients of Q at tau,
+ * L^-1 Q^(k)(tau) / k! L^-T, k = 1 .. d, each bounded from below by Lanczos,
+ * and the step to the root of 1 + sum_k min(d_k, 0) s^k; diagonal rows by the
+ * same stepping on their scalar polynomials; always FP64 pencils, and the
+ * handle's workspace grows by (2 d + 3) rows per curve. */
+#define SPEC_CURVE_MAX_DEGREE 6
 spec_status spec_intersect_curve(spec_handle h, int batch, int degree, const double* coef, double horizon,
                                  double* t_minus, double* t_plus, int32_t* status);
 spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const double* coef, double horizon,

@@ -549,13 +549,41 @@ spec_status spec_reflect_dev(spec_handle h, int batch, const double* x, const do
 
 spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const double* coef, double horizon,
                                      double* t_minus, double* t_plus, int32_t* status, void* stream) {
-    if (!h || batch < 0 || (degree != 1 && degree != 2) || !(horizon > 0.0) ||
+    if (!h || batch < 0 || degree < 1 || degree > SPEC_CURVE_MAX_DEGREE || !(horizon > 0.0) ||
         (batch && (!coef || !t_minus || !t_plus || !status)))
         return SPEC_EINVAL;
     if (batch == 0) return SPEC_OK;
     hipStream_t s = (hipStream_t)stream;
     SPCHK(h->ensure(batch));
     const int bp = round_up(batch, 64);
+    if (degree >= 3) {
+        // FP64 pencils Q_0 .. Q_d of every curve, then the Taylor-Weyl stepping
+        SPCHK(h->ensure_poly((size_t)(degree + 1) * bp, (size_t)(degree + 2) * bp));
+        HIPCHK(launch_build_z_rows(batch, h->n, h->Kpad, degree + 1, coef, h->dZp, bp, s));
+        HIPCHK(gemm_f64(false, (degree + 1) * bp, h->ldA, h->Kpad, h->dZp, h->Kpad, h->dA, h->ldA, h->dFBp, h->ldA,
+                        s));
+        CurveArgs a{};
+        a.m = h->m;
+        a.md = h->md;
+        a.P = h->P;
+        a.kmax = h->kmax;
+        a.tol = h->tol;
+        a.FB = h->dFBp;
+        a.ldfb = h->ldA;
+        a.brow0 = bp;
+        a.hscalar = horizon;
+        a.both = 1;
+        a.Q = h->dQ;
+        a.ldq = h->ldq();
+        a.status = status;
+        a.tm = t_minus;
+        a.tp = t_plus;
+        a.hit = h->dHit;
+        a.degree = degree;
+        a.comb = h->dFBp + (size_t)(degree + 1) * bp * h->ldA;
+        HIPCHK(launch_curve_poly(a, batch, s));
+        return SPEC_OK;
+    }
     HIPCHK(launch_build_z_coef(batch, h->n, h->Kpad, degree + 1, coef, h->dZ, bp, s));
     return curve_oracle(h, batch, nullptr, horizon, t_minus, t_plus, status, true, false, nullptr, s);
 }
@@ -564,7 +592,8 @@ spec_status spec_intersect_curve_dev(spec_handle h, int batch, int degree, const
 
 spec_status spec_intersect_curve(spec_handle h, int batch, int degree, const double* coef, double horizon,
                                  double* t_minus, double* t_plus, int32_t* status) {
-    if (!h || batch < 0 || (degree != 1 && degree != 2) || (batch && (!coef || !t_minus || !t_plus || !status)))
+    if (!h || batch < 0 || degree < 1 || degree > SPEC_CURVE_MAX_DEGREE ||
+        (batch && (!coef || !t_minus || !t_plus || !status)))
         return SPEC_EINVAL;
     if (batch == 0) return SPEC_OK;
     SPCHK(h->ensure_stage(batch));

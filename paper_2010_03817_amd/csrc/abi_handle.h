@@ -75,7 +75,28 @@ struct spec_s {
     int32_t *vNref = nullptr, *vActive = nullptr;
     long long* vStep = nullptr;
 
+    // degree >= 3 curves: coefficient rows ((d + 1) per curve) and pencils
+    // ((d + 1) per curve plus a scratch row), sized on first use
+    double *dZp = nullptr, *dFBp = nullptr;
+    size_t pz_rows = 0, pf_rows = 0;
+    spec_status ensure_poly(size_t zrows, size_t frows) {
+        if (zrows > pz_rows) {
+            dfree(dZp);
+            pz_rows = 0;
+            HIPCHK(dalloc(&dZp, zrows * Kpad));
+            pz_rows = zrows;
+        }
+        if (frows > pf_rows) {
+            dfree(dFBp);
+            pf_rows = 0;
+            HIPCHK(dalloc(&dFBp, frows * ldA, false));
+            pf_rows = frows;
+        }
+        return SPEC_OK;
+    }
     void free_work() {
+        dfree(dZp); dfree(dFBp);
+        pz_rows = pf_rows = 0;
         dfree(dZ); dfree(dZ32); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt); dfree(dFlags);
         dfree(dRList); dfree(dRShift); dfree(dRCnt); dfree(dCert);

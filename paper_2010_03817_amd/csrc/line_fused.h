@@ -80,8 +80,16 @@ struct CurveArgs {
     double esc_ratio;
     const int32_t* idx;
     int32_t* flags;            // nullable: SPEC_FLAG_ESCALATED set on the FP64 pass
+    // degree >= 3 (launch_curve_poly): rows k brow0 + c, k = 0 .. degree, hold
+    // Q_k; comb rows c (ld ldfb) are per-curve scratch for the Taylor
+    // coefficients of the pencil
+    int degree;
+    double* comb;
 };
 hipError_t launch_curve2(const CurveArgs& a, int nblocks, hipStream_t s);
+// First roots of det Q(t), Q(t) = sum_k t^k Q_k, for 3 <= degree <= 6
+// (certified Taylor-Weyl stepping; no kernel vector).
+hipError_t launch_curve_poly(const CurveArgs& a, int nblocks, hipStream_t s);
 
 // Persistent launch over (instance, chain) items of several spectrahedra:
 // args[instance] as for launch_line_fused, work[i] = (instance, chain) in the

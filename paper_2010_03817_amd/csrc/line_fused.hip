@@ -2489,6 +2489,261 @@ __global__ __launch_bounds__(512) void k_curve2(CurveArgs a) {
     }
 }
 
+// ---- degree-d curves (the polynomial eigenvalue problem of eq. (PEP))
+
+constexpr int CURVE_DMAX = 6;
+
+__device__ __forceinline__ double binom_small(int j, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (j - k + i) / i;
+    return r;
+}
+
+// Smallest s > 0 with 1 + sum_{k=1..d} min(c_k, 0) s^k = 0 (+inf if every
+// c_k >= 0): a decreasing function of s, so the root is bracketed by doubling
+// and bisected to the last representable step.
+__device__ inline double first_root_lower(const double* c, int d) {
+    bool neg = false;
+    for (int k = 1; k <= d; ++k) neg |= c[k] < 0.0;
+    if (!neg) return INFINITY;
+    auto g = [&](double s) {
+        double v = 0.0;
+        for (int k = d; k >= 1; --k) v = (v + fmin(c[k], 0.0)) * s;
+        return 1.0 + v;
+    };
+    double hi = 1.0;
+    while (g(hi) > 0.0 && hi < 1e300) hi *= 2.0;
+    double lo = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (g(mid) > 0.0) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// First positive root of q(t) = sum_k q_k t^k with q_0 > 0, not beyond hz:
+// at tau, q(tau + s) / q(tau) = 1 + sum_k c_k s^k (Taylor coefficients over
+// q(tau)) stays positive up to the root of the lower bound above; step there
+// until the step is at the rounding level.
+__device__ inline double poly_first_root(const double* q, int d, double hz) {
+    double tau = 0.0;
+    for (int it = 0; it < 400; ++it) {
+        double c[CURVE_DMAX + 1];
+        for (int k = 0; k <= d; ++k) {
+            double v = 0.0;
+            for (int j = d; j >= k; --j) v = v * tau + binom_small(j, k) * q[j];
+            c[k] = v;
+        }
+        if (!(c[0] > 0.0)) return tau;
+        for (int k = 1; k <= d; ++k) c[k] /= c[0];
+        const double step = first_root_lower(c, d);
+        if (!(step < INFINITY)) return INFINITY;
+        const double next = tau + step;
+        if (next > hz) return INFINITY;
+        if (step <= 1e-15 * next) return next;
+        tau = next;
+    }
+    return tau;
+}
+
+// F of the curve at tau: L = sum_k (sg tau)^k Q_k (Horner), packed.
+__device__ inline void fill_poly(double* L, const double* const* Qk, int d, double tau, double sg, int P, int t,
+                                 int bd) {
+    const double x = sg * tau;
+    for (int e = t; e < P; e += bd) {
+        double v = Qk[d][e];
+        for (int k = d - 1; k >= 0; --k) v = v * x + Qk[k][e];
+        L[e] = v;
+    }
+}
+
+// One workgroup per curve, the shape of k_curve2.  Dense block: at tau with
+// Q(tau) = L L^T, L^-1 Q(tau + s) L^-T = I + sum_k s^k D_k with
+// D_k = L^-1 (sum_{j >= k} C(j, k) tau^(j-k) Q_j) L^-T; by Weyl's inequality the
+// pencil stays definite while 1 + sum_k s^k lambda_min(D_k) > 0, and
+// 1 + sum_k min(d_k, 0) s^k with d_k = Ritz value minus residual bound is a
+// lower bound of it, decreasing in s.  Each combination is written to the
+// curve's scratch row and its lambda_min taken by Lanczos.  Steps that leave
+// S are halved back as in k_curve2.  Diagonal rows: scalar polynomials.
+__global__ __launch_bounds__(512) void k_curve_poly(CurveArgs a) {
+    extern __shared__ double lds[];
+    const int m = a.m, P = a.P, md = a.md, d = a.degree;
+    const int row = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+    double* L = lds;
+    double* scr = lds + P;
+    int* sflag = (int*)(scr + 256);
+    double* rtp = scr + 264;
+    double* rtm = rtp + 8;
+    int* rj = (int*)(rtm + 8);
+    int* rbad = rj + 8;
+    const double* Qk[CURVE_DMAX + 1];
+    for (int k = 0; k <= d; ++k) Qk[k] = a.FB + ((size_t)k * a.brow0 + row) * a.ldfb;
+    double* comb = a.comb + (size_t)row * a.ldfb;
+    const double hz = a.horizon ? a.horizon[row] : a.hscalar;
+    int32_t st = SPEC_OK;
+
+    // ---- diagonal rows
+    double dtp = INFINITY, dtm = INFINITY;
+    int dj = -1, bad = 0;
+    for (int j = t; j < md; j += blockDim.x) {
+        double q[CURVE_DMAX + 1], qm[CURVE_DMAX + 1];
+        for (int k = 0; k <= d; ++k) {
+            q[k] = Qk[k][P + j];
+            qm[k] = (k & 1) ? -q[k] : q[k];
+        }
+        if (!(q[0] > 0.0)) {
+            bad = 1;
+            continue;
+        }
+        const double sp = poly_first_root(q, d, hz);
+        if (sp <= hz && sp < dtp) { dtp = sp; dj = j; }
+        if (a.both) dtm = fmin(dtm, poly_first_root(qm, d, hz));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double otp = __shfl_xor(dtp, o, 64);
+        const int oj = __shfl_xor(dj, o, 64);
+        if (otp < dtp || (otp == dtp && oj >= 0 && (dj < 0 || oj < dj))) { dtp = otp; dj = oj; }
+        dtm = fmin(dtm, __shfl_xor(dtm, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if (lane == 0) { rtp[wv] = dtp; rtm[wv] = dtm; rj[wv] = dj; rbad[wv] = bad; }
+    lds_barrier();
+    dtp = INFINITY; dtm = INFINITY; dj = -1; bad = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (rtp[w] < dtp || (rtp[w] == dtp && rj[w] >= 0 && (dj < 0 || rj[w] < dj))) { dtp = rtp[w]; dj = rj[w]; }
+        dtm = fmin(dtm, rtm[w]);
+        bad |= rbad[w];
+    }
+    lds_barrier();
+    double tp = dtp, tmd = dtm;
+    int hit = dj >= 0 ? dj : HIT_NONE;
+    int iters = 0;
+    bool conv = true;
+    if (bad) st = SPEC_NOT_INTERIOR;
+    if (!bad && m > 0) {
+        const int kmax = a.kmax;
+        double* Qg = a.Q + (size_t)row * a.ldq;
+        const LzLayout lz = lz_layout(scr, kmax);
+        for (int dir = 0; dir < (a.both ? 2 : 1) && st == SPEC_OK; ++dir) {
+            const double sg = dir == 0 ? 1.0 : -1.0;
+            double tau = 0.0, tau_prev = 0.0, root = INFINITY;
+            bool done = false;
+            int halvings = 0;
+            for (int it = 0; it < 400; ++it) {
+                ++iters;
+                fill_poly(L, Qk, d, tau, sg, P, t, blockDim.x);
+                lds_barrier();
+                const bool ok = chol_blocked(L, m, scr, sflag);
+                lds_barrier();
+                if (!ok) {
+                    if (it == 0) {
+                        st = SPEC_NOT_INTERIOR;
+                        done = true;
+                        break;
+                    }
+                    if (tau - tau_prev > 1e-12 * tau && halvings < 60) {
+                        ++halvings;
+                        tau = tau_prev + 0.5 * (tau - tau_prev);
+                        continue;
+                    }
+                    root = tau;  // definiteness lost at the rounding level
+                    done = true;
+                    break;
+                }
+                tri_inverse(L, m, scr);
+                double dk[CURVE_DMAX + 1];
+                dk[0] = 1.0;
+                for (int k = 1; k <= d; ++k) {
+                    // Taylor coefficient sum_{j >= k} C(j, k) tau^(j-k) sg^j Q_j into the scratch row
+                    for (int e = t; e < P; e += blockDim.x) {
+                        double v = 0.0;
+                        for (int j = d; j >= k; --j) v = v * tau + binom_small(j, k) * ((j & 1) ? sg : 1.0) * Qk[j][e];
+                        comb[e] = v;
+                    }
+                    __syncthreads();  // the row is read back by the whole workgroup
+                    LzCtx lc;
+                    lc.m = m;
+                    lc.kmax = kmax;
+                    lc.min_only = 1;
+                    lc.first_check = 0;
+                    lc.tol = k == 1 ? fmax(a.tol, 1e-6) : fmax(a.tol, 1e-3);
+                    lc.loose_ratio = 0.0;
+                    lc.tol_loose = 0.0;
+                    lc.B0 = comb;
+                    lc.b0 = 1.0;
+                    lc.B1 = nullptr;
+                    lc.b1 = 0.0;
+                    lc.Qg = Qg;
+                    lc.prof = nullptr;
+                    lanczos_extreme(L, scr, lc);
+                    __syncthreads();
+                    if (k == 1 && lz.sres[4] != 1.0) conv = false;
+                    dk[k] = lz.sres[0] - lz.sres[1];
+                    lds_barrier();
+                }
+                const double step = first_root_lower(dk, d);
+                if (!(step < INFINITY)) {
+                    done = true;
+                    break;
+                }
+                const double next = tau + step;
+                if (next > hz) {
+                    done = true;
+                    break;
+                }
+                if (step <= 1e-15 * next) {
+                    root = next;
+                    done = true;
+                    break;
+                }
+                tau_prev = tau;
+                tau = next;
+            }
+            if (!done) {
+                conv = false;
+                root = tau_prev;
+            }
+            if (dir == 0) {
+                if (root <= tp) {
+                    tp = root;
+                    hit = HIT_DENSE;
+                }
+            } else {
+                tmd = fmin(tmd, root);
+            }
+            lds_barrier();
+        }
+    }
+    if (t == 0) {
+        double tm = -tmd;
+        if (st == SPEC_NOT_INTERIOR) {
+            tm = NAN;
+            tp = NAN;
+            hit = HIT_NONE;
+        } else if (!conv) {
+            st = SPEC_NOCONV;
+        }
+        if (!a.both && st != SPEC_NOT_INTERIOR) tm = NAN;
+        a.tm[row] = tm;
+        a.tp[row] = tp;
+        a.hit[row] = isfinite(tp) ? hit : HIT_NONE;
+        a.status[row] = st;
+        if (a.iters) a.iters[row] = iters;
+        if (a.flags) a.flags[row] = 0;
+    }
+}
+
+hipError_t launch_curve_poly(const CurveArgs& a, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    if (a.degree < 3 || a.degree > CURVE_DMAX || !a.comb) return hipErrorInvalidValue;
+    const size_t lds = fused_lds_bytes(a.m, a.kmax);
+    if (lds > 163840 || a.m > 2 * MAXH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_curve_poly, dim3(nblocks), dim3(fused_threads(a.m)), lds, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_curve2(const CurveArgs& a, int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     const size_t lds = fused_lds_bytes(a.m, a.kmax);

@@ -71,6 +71,25 @@ __global__ void k_build_z_coef(int batch, int n, int Kpad, int nrows, const doub
     }
 }
 
+// All `nrows` coefficient rows of a curve: row k of curve c at k zrow0 + c.
+__global__ void k_build_z_rows(int batch, int n, int Kpad, int nrows, const double* __restrict__ coef,
+                               double* __restrict__ Z, int zrow0) {
+    const int c = blockIdx.x;
+    if (c >= batch) return;
+    for (int k = 0; k < nrows; ++k) {
+        double* z = Z + ((size_t)k * zrow0 + c) * Kpad;
+        for (int i = threadIdx.x; i < Kpad; i += blockDim.x)
+            z[i] = i <= n ? coef[((size_t)c * nrows + k) * (n + 1) + i] : 0.0;
+    }
+}
+
+hipError_t launch_build_z_rows(int batch, int n, int Kpad, int nrows, const double* coef, double* Z, int zrow0,
+                               hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_z_rows, dim3(batch), dim3(64), 0, s, batch, n, Kpad, nrows, coef, Z, zrow0);
+    return hipGetLastError();
+}
+
 hipError_t launch_build_z_coef(int batch, int n, int Kpad, int nrows, const double* coef, double* Z, int zrow0,
                                hipStream_t s) {
     if (batch <= 0) return hipSuccess;

@@ -48,6 +48,9 @@ hipError_t launch_gather_rows(int count, int zc0, int nrows, int Kpad, const int
 // (nrows of them given, the rest zero), zero-padded to Kpad.
 hipError_t launch_build_z_coef(int batch, int n, int Kpad, int nrows, const double* coef, double* Z, int zrow0,
                                hipStream_t s);
+// All nrows coefficient rows of each curve: row k of curve c at k * zrow0 + c.
+hipError_t launch_build_z_rows(int batch, int n, int Kpad, int nrows, const double* coef, double* Z, int zrow0,
+                               hipStream_t s);
 struct ReflectArgs {
     int batch, n, m, P, md, ldA;
     const double* Astk;  // (rows) x ldA; row i+1 = A_i packed, diagonal part at column P

@@ -318,8 +318,8 @@ class Spectrahedron:
         return tm[:B], tp[:B], st[:B]
 
     def intersect_curve(self, coef, horizon=float("inf"), degree=2):
-        """First positive / negative roots of det(Q0 + t Q1 + t^2 Q2) within the
-        horizon; coef: batch x (degree+1) x (n+1)."""
+        """First positive / negative roots of det(sum_k t^k Q_k) within the
+        horizon; coef: batch x (degree+1) x (n+1), degree 1 .. 6."""
         torch = _torch()
         coef = _f64(coef).reshape(-1, degree + 1, self.n + 1)
         B = coef.shape[0]

@@ -884,6 +884,8 @@ def main():
                     help="also run the ball-sequence volume table (S-40-40 .. S-100-100)")
     ap.add_argument("--anneal-chains", type=int, default=64)
     ap.add_argument("--anneal-max-iters", type=int, default=400)
+    ap.add_argument("--lanczos-tol", type=float, default=1e-8,
+                    help="relative residual at which the Lanczos runs of the oracle stop")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -897,6 +899,7 @@ def main():
 
     inst = I.gbase(N_DIM, M_DIM, seed=SEED_INST)
     g = S.Spectrahedron(inst)
+    g.set_lanczos(80, args.lanczos_tol)
     # diameter estimate: longest chord seen by a short Hit-and-Run pre-run
     pre = 64
     _, _, _, log = g.walk(S.HNR, np.zeros((pre, N_DIM)), 20, seed=11, log_chains=pre, log_cap=pre * 20)
@@ -983,6 +986,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "billiard walk, n=m=200 G-BASE spectrahedron (+400 box rows), FP64 oracle",
                    "chains": chains, "n": N_DIM, "m": M_DIM, "tau": tau, "instance_seed": SEED_INST,
+                   "lanczos_tol": args.lanczos_tol,
                    "path": "learned" if learned_sum is not None else "plain"},
         "billiard_steps_per_s": head["billiard_steps_per_s"],
         "roofline": head["roofline"],

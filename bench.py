@@ -244,11 +244,17 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
                             log_chains=data_chains, log_cap=rounds * data_chains)
     del xd
     calls_per_step = wst["calls"] / max(wst["steps"], 1)
-    held = (log[:, 2 * n + 2].to(torch.int64) % 10) == 9  # whole chains held out
-    order = torch.cat([torch.nonzero(~held).flatten(), torch.nonzero(held).flatten()])
+    # whole chains held out: chain % 10 == 8 is the trainer's validation set
+    # (early stopping), chain % 10 == 9 the half-width tuning and evaluation
+    # rows, which training never sees
+    cid = log[:, 2 * n + 2].to(torch.int64) % 10
+    val8, held = cid == 8, cid == 9
+    train = ~(val8 | held)
+    order = torch.cat([torch.nonzero(train).flatten(), torch.nonzero(val8).flatten(), torch.nonzero(held).flatten()])
     x = log[order, :n].contiguous()
     v = log[order, n:2 * n].contiguous()
     nheld = int(held.sum())
+    nval8 = int(val8.sum())
     del log
     tm = torch.empty(x.shape[0], dtype=torch.float64, device="cuda")
     tp = torch.empty_like(tm)
@@ -258,15 +264,19 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
         tm[r0:r0 + chains], tp[r0:r0 + chains] = a, b
         ok[r0:r0 + chains] = (st == S.OK) & torch.isfinite(a) & torch.isfinite(b) & (a < 0) & (b > 0)
     nval = int(ok[x.shape[0] - nheld:].sum())
+    nv8 = int(ok[x.shape[0] - nheld - nval8:x.shape[0] - nheld].sum())
     x, v, tm, tp = x[ok], v[ok], tm[ok], tp[ok]
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     rows = x.shape[0]
-    vf = (nval + 0.25) / rows  # the trainer holds out the last round(vf rows) rows: exactly the held chains
+    ntv = rows - nval  # training and validation rows (the trainer holds out the last nv8 of them)
+    vf = (nv8 + 0.25) / ntv
     net = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed)
     t1 = time.perf_counter()
-    progress(f"training on {rows - nval} triples, {nval} held out ({t_data:.1f} s to generate)")
-    tr = net.train(x, v, tm, tp, epochs=epochs, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf, seed=seed)
+    progress(f"training on {ntv - nv8} triples, {nv8} for early stopping, {nval} held out "
+             f"({t_data:.1f} s to generate)")
+    tr = net.train(x[:ntv], v[:ntv], tm[:ntv], tp[:ntv], epochs=epochs, batch=4096, lr=1e-3, lr_final=1e-5,
+                   val_frac=vf, seed=seed, keep_best=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     xv, vv, tpv = x[rows - nval:], v[rows - nval:], tp[rows - nval:]
@@ -281,7 +291,8 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
     best, ms = g.tune_mlp_delta(net, xa, va, cands, reps=2)
     # the control: constant log t+ prediction (training mean), tuned the same way
     ctl = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed + 1)
-    ctl.train(x, v, tm, tp, epochs=1, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf, seed=seed)
+    ctl.train(x[:ntv], v[:ntv], tm[:ntv], tp[:ntv], epochs=1, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf,
+              seed=seed)
     ctl.set_params(np.zeros(ctl.nparams, dtype=np.float32))
     lca = ctl.predict(xa, va)[0].cpu().numpy()
     ccands = [float(np.quantile(np.abs(lca - ltpa), q)) for q in levels]
@@ -305,7 +316,10 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
 
     report = {
         "calls_per_step": calls_per_step, "walk_calls": wst["calls"], "walk_steps": wst["steps"],
-        "rows": rows, "held_out_rows": nval, "holdout": "whole chains (chain index % 10 == 9)",
+        "rows": rows, "held_out_rows": nval, "early_stopping_rows": nv8,
+        "holdout": "whole chains: index % 10 == 8 early stopping (the trainer's validation rows), "
+                   "index % 10 == 9 half-width tuning and evaluation (never seen by training)",
+        "best_epoch": tr.get("best_epoch"),
         "data_chains": data_chains, "data_rounds": rounds, "data_burn_in_rounds": burn_rounds,
         "data_seconds": t_data, "train_seconds": t_train,
         "epochs": epochs, "adam_steps": tr["steps"], "train_loss": tr["train_loss"], "val_loss": tr["val_loss"],
@@ -317,6 +331,8 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
                     "delta": cbest},
         "eval_rows": int(xb.shape[0]),
         "eval_logtp_err_median": {"network": float(np.median(err_net)), "control": float(np.median(err_ctl))},
+        "eval_logtp_err_rms": {"network": float(np.sqrt(np.mean(err_net**2))),
+                               "control": float(np.sqrt(np.mean(err_ctl**2)))},
         "eval_lanczos_steps_per_call": {"learned": steps_l, "control": steps_c, "plain": steps_p},
         "eval_fallback_rate": {"learned": fb_l, "control": fb_c},
         "learned_vs_plain_tp_rel": relstats(tpl, tpp),

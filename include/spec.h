@@ -535,6 +535,8 @@ typedef struct {
     double quantile;     /* bracket half-width delta = this quantile of |log t+_hat - log t+|
                             on the validation rows (default 0.999) */
     uint64_t seed;       /* minibatch sampling */
+    int keep_best;       /* nonzero: the loss on the validation rows is taken after every epoch and
+                            the parameters of the best epoch are kept (early stopping) */
 } spec_mlp_train_params;
 
 typedef struct {
@@ -547,6 +549,7 @@ typedef struct {
     double err_q[8];     /* |log t+_hat - log t+| on validation at the levels
                             0.5, 0.7, 0.8, 0.9, 0.95, 0.99, 0.995, 0.999 */
     double val_loss_const; /* the same loss of the constant prediction (the training means) */
+    double best_epoch;   /* keep_best: the epoch kept (1-based), else the last */
 } spec_mlp_train_stats;
 
 /* New network for n coordinates; parameters from Philox (key seed):

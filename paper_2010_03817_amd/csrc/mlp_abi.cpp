@@ -285,6 +285,29 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
     const long long per_epoch = std::max(1LL, (long long)ntrain / batch);
     const double pi = 3.14159265358979323846;
     double train_loss = 0.0;
+    // early stopping: the validation loss after every epoch, the best parameters kept
+    const bool keep_best = p->keep_best != 0;
+    float* dBest = nullptr;
+    double* dVl = nullptr;
+    double best_vl = INFINITY;
+    int best_epoch = epochs;
+    if (keep_best) {
+        HIPCHK(dalloc(&dBest, (size_t)net->np, false));
+        HIPCHK(dalloc(&dVl, (size_t)1));
+    }
+    auto val_loss_now = [&](double* out) -> spec_status {
+        HIPCHK(hipMemsetAsync(dVl, 0, sizeof(double), s));
+        for (int r0 = 0; r0 < nval; r0 += cap_rows) {
+            const int cnt = std::min(cap_rows, nval - r0);
+            SPCHK(mlp_forward_x(net, cnt, dXall + (size_t)(ntrain + r0) * ldx, ldx, s));
+            HIPCHK(mlp_mse(cnt, 2, net->dY, 2, dTall + (size_t)(ntrain + r0) * 2, net->dDY, dVl, s));
+        }
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, dVl, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *out = v / (2.0 * nval);
+        return SPEC_OK;
+    };
     for (long long it = 0; it < steps; ++it) {
         const double lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(pi * (double)it / (double)steps));
         if (it == steps - per_epoch || (it == 0 && steps <= per_epoch))
@@ -297,6 +320,21 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
         SPCHK(mlp_backward(net, batch, net->dX, ldx, net->dG, s));
         net->step += 1;
         HIPCHK(mlp_adam(net->np, net->dP, net->dG, net->dM, net->dV, net->step, (float)lr, 0.9f, 0.999f, 1e-8f, s));
+        if (keep_best && ((it + 1) % per_epoch == 0 || it + 1 == steps)) {
+            double vl = 0.0;
+            SPCHK(val_loss_now(&vl));
+            if (vl < best_vl) {
+                best_vl = vl;
+                best_epoch = (int)std::min<long long>(epochs, (it + 1 + per_epoch - 1) / per_epoch);
+                HIPCHK(hipMemcpyAsync(dBest, net->dP, sizeof(float) * net->np, hipMemcpyDeviceToDevice, s));
+            }
+        }
+    }
+    if (keep_best) {
+        HIPCHK(hipMemcpyAsync(net->dP, dBest, sizeof(float) * net->np, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        dfree(dBest);
+        dfree(dVl);
     }
     {
         double l = 0.0;
@@ -334,6 +372,7 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
         st->train_loss = train_loss;
         st->val_loss = vl / (2.0 * nval);
         st->val_loss_const = vc / (2.0 * nval);
+        st->best_epoch = best_epoch;
         st->delta = quantile(err, qq);
         st->err_median = quantile(err, 0.5);
         st->err_p99 = quantile(err, 0.99);

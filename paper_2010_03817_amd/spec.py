@@ -82,13 +82,14 @@ class VolumeStats(C.Structure):
 
 class MlpTrainParams(C.Structure):
     _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("lr_final", C.c_double),
-                ("val_frac", C.c_double), ("quantile", C.c_double), ("seed", C.c_uint64)]
+                ("val_frac", C.c_double), ("quantile", C.c_double), ("seed", C.c_uint64), ("keep_best", C.c_int)]
 
 
 class MlpTrainStats(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("train_loss", "val_loss", "delta", "err_median", "err_p99", "err_max",
                                           "steps", "val_rows")] + [("err_q", C.c_double * 8),
-                                                                   ("val_loss_const", C.c_double)]
+                                                                   ("val_loss_const", C.c_double),
+                                                                   ("best_epoch", C.c_double)]
     QUANTILE_LEVELS = (0.5, 0.7, 0.8, 0.9, 0.95, 0.99, 0.995, 0.999)
 
     def as_dict(self):
@@ -623,11 +624,11 @@ class Mlp:
         check(lib().spec_mlp_adam_dev(self._h, _ptr(grad), float(lr), _stream()))
 
     def train(self, x, v, t_minus, t_plus, epochs=20, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=0.1,
-              quantile=0.999, seed=7):
+              quantile=0.999, seed=7, keep_best=False):
         x, v = _f64(x).reshape(-1, self.n), _f64(v).reshape(-1, self.n)
         tm, tp = _f64(t_minus).reshape(-1), _f64(t_plus).reshape(-1)
         p = MlpTrainParams(epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, val_frac=val_frac,
-                           quantile=quantile, seed=seed)
+                           quantile=quantile, seed=seed, keep_best=int(bool(keep_best)))
         st = MlpTrainStats()
         check(lib().spec_mlp_train_dev(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(tm), _ptr(tp), C.byref(p),
                                        C.byref(st), _stream()))

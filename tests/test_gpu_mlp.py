@@ -297,6 +297,24 @@ def test_host_training_matches_device_training(S):
     assert np.allclose(pa, pb, rtol=1e-5, atol=1e-6)
 
 
+def test_early_stopping_keeps_the_best_epoch(S):
+    """keep_best: the same training run (seed, rows, initial parameters) with
+    the validation loss taken after every epoch keeps the best epoch's
+    parameters, so its validation loss is at most the last epoch's."""
+    inst = I.gbase(10, 10, seed=101, scale=math.sqrt(10))
+    g = S.Spectrahedron(inst)
+    x, v, tm, tp, _, _ = _training_triples(S, g, inst, chains=32, rounds=40)
+    a = S.Mlp(inst.n, width=64, hidden=2, bf16=True, seed=4)
+    b = S.Mlp(inst.n, width=64, hidden=2, bf16=True, seed=4)
+    sa = a.train(x, v, tm, tp, epochs=12, batch=128, lr=3e-3, seed=9)
+    sb = b.train(x, v, tm, tp, epochs=12, batch=128, lr=3e-3, seed=9, keep_best=True)
+    print(f"last epoch val {sa['val_loss']:.4f}; best epoch {sb['best_epoch']:.0f} val {sb['val_loss']:.4f}")
+    assert 1 <= sb["best_epoch"] <= 12
+    assert sb["val_loss"] <= sa["val_loss"] * (1 + 1e-6)
+    if sb["best_epoch"] == 12:
+        assert np.array_equal(a.get_params(), b.get_params())
+
+
 def test_network_beats_constant_control_at_full_size(S):
     """n = m = 200 (the benchmark's instance): a network of the benchmark's
     shape trained on segment starts of many short billiard chains predicts

@@ -859,6 +859,41 @@ def anneal_leg(S, I, per_size, chains, max_iters):
     return out
 
 
+def anneal_trace_leg(S, I, chains=16, iterations=70):
+    """The objective trace of the paper's annealing figure: on S-50-50 (the
+    first instance of the annealing workload) the best <c, x> after each of 70
+    temperatures, HMC with reflections at walk length one against Hit-and-Run
+    at walk length 500 + 4 n^2 = 10500, as the relative error to the stored
+    optimum (median and range over the chains), with wall times."""
+    import torch
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "tests", "golden", "sdp_optima.json")) as fh:
+        e = [r for r in json.load(fh)["optima"] if r["n"] == 50][0]
+    n = 50
+    g = S.Spectrahedron(I.paper_random(n, n, seed=e["instance_seed"]))
+    c = I.objective(n, e["objective_seed"])
+    _, _, _, log = g.walk(S.HNR, np.zeros((64, n)), 20, seed=11, log_chains=64, log_cap=64 * 20)
+    lg = log.cpu().numpy()
+    d = float(np.max(lg[:, 2 * n + 1] - lg[:, 2 * n]))
+    x0, _, _, _ = g.walk(S.BILLIARD, torch.zeros((chains, n), dtype=torch.float64, device="cuda"), 20, seed=12,
+                         tau=2.0 * d)
+    x0 = x0.cpu().numpy()
+    out = {"instance_seed": e["instance_seed"], "f_star": e["f_star"], "chains": chains, "iterations": iterations}
+    for name, kind, wl in (("hmc_r", S.HMC, 1), ("hit_and_run", S.HNR, 500 + 4 * n * n)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, best, hit, st = g.sdp_anneal(x0, c, d * np.linalg.norm(c), d, iterations=iterations, walk_len=wl,
+                                           kind=kind, seed=14, f_star=e["f_star"])
+        torch.cuda.synchronize()
+        rel = (best - e["f_star"]) / abs(e["f_star"])
+        out[name] = {"walk_len": wl, "seconds": time.perf_counter() - t0, "oracle_calls": st["calls"],
+                     "rel_err_median": [float(v) for v in np.median(rel, 0)],
+                     "rel_err_min": [float(v) for v in rel.min(0)], "rel_err_max": [float(v) for v in rel.max(0)],
+                     "first_within_5pc": [int(h) + 1 if h >= 0 else None for h in hit]}
+        progress(f"annealing trace: {name} done")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -887,6 +922,8 @@ def main():
     ap.add_argument("--anneal", action="store_true",
                     help="also run the annealing table (min <c, x> on S-30-30 .. S-60-60)")
     ap.add_argument("--anneal-instances", type=int, default=10)
+    ap.add_argument("--anneal-trace", action="store_true",
+                    help="also trace the best objective over 70 temperatures on S-50-50 (HMC-r, Hit-and-Run)")
     ap.add_argument("--config2", action="store_true",
                     help="also run the paper-scale plain walk (n = m = 100, 4096 chains x 1e4 billiard steps) and "
                          "check logged pairs with the oracle")
@@ -1045,6 +1082,9 @@ def main():
     if args.anneal:
         progress("annealing table")
         out["anneal_table"] = anneal_leg(S, I, args.anneal_instances, args.anneal_chains, args.anneal_max_iters)
+    if args.anneal_trace:
+        progress("annealing trace (HMC-r against Hit-and-Run of walk length 500 + 4 n^2)")
+        out["anneal_trace"] = anneal_trace_leg(S, I)
     if not args.no_cpu:
         progress("CPU oracle baseline")
         xs = np.zeros((4, N_DIM))

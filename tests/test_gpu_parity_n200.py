@@ -269,3 +269,46 @@ def test_paper_generator_s200_walk_pairs():
     assert (st2 == S.OK).all()
     assert np.all(np.abs(tp - rtp) <= bar_p), np.max(np.abs(tp - rtp) / bar_p)
     assert np.all(np.abs(tm - rtm) <= bar_m), np.max(np.abs(tm - rtm) / bar_m)
+
+
+def _sampled_round(S, g, tau, chains, seed, warm_rounds, count):
+    """Segment starts of one round of `chains` billiard chains (the benchmark's
+    launch: one workgroup per chain over the whole grid), taken after
+    `warm_rounds` rounds from the centre: the round's record of `count`
+    chains spread evenly over the grid."""
+    import torch
+    x0 = torch.zeros((chains, N), dtype=torch.float64, device="cuda")
+    g.walk(S.BILLIARD, x0, 1 << 30, seed=seed, tau=tau, max_rounds=warm_rounds)
+    _, _, st, log = g.walk(S.BILLIARD, x0, 1 << 30, seed=seed, tau=tau, max_rounds=1, resume=True,
+                           log_chains=chains, log_cap=chains)
+    log = log.cpu().numpy()
+    order = np.argsort(log[:, 2 * N + 2])
+    log = log[order]
+    pick = np.linspace(0, len(log) - 1, count).astype(int)
+    return st, log[pick]
+
+
+@pytest.mark.parametrize("path", ["plain", "learned"])
+def test_bench_launch_of_16384_chains_sampled(wl, path):
+    """The benchmark's launch configuration (16384 chains at n = m = 200): t+ of
+    96 sampled segment starts of one round, 20 rounds from the centre
+    (post-reflection starts included), against the oracle's bisection."""
+    S, g, o = wl["S"], wl["g"], wl["o"]
+    if path == "learned":
+        net, tr = _train(S, g, wl["tau"], seed=78)
+        g.set_mlp(net, tr["err_q"][0.9], 1)
+    try:
+        st, log = _sampled_round(S, g, wl["tau"], 16384, seed=4242, warm_rounds=20, count=96)
+    finally:
+        g.set_mlp(None)
+    assert len(log) == 96 and st["not_interior"] == 0 and st["noconv"] == 0
+    chains = log[:, 2 * N + 2].astype(int)
+    assert len(np.unique(chains)) == 96 and chains.max() > 16000  # spread over the grid
+    x, v, tpw = log[:, :N], log[:, N:2 * N], log[:, 2 * N + 1]
+    rtm, rtp, rst = bisect_threads(o, x, v)
+    assert (rst == O.OK).all()
+    kappa = (rtp - rtm) / np.abs(rtm)
+    r = rel(tpw, rtp)
+    report(f"16384-chain {path} round", r, kappa)
+    print(f"  {int((kappa > 1e4).sum())} of 96 start next to the boundary")
+    assert r.max() <= T_REL

@@ -271,43 +271,61 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
     rows = x.shape[0]
     ntv = rows - nval  # training and validation rows (the trainer holds out the last nv8 of them)
     vf = (nv8 + 0.25) / ntv
-    net = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed)
-    t1 = time.perf_counter()
-    progress(f"training on {ntv - nv8} triples, {nv8} for early stopping, {nval} held out "
-             f"({t_data:.1f} s to generate)")
-    tr = net.train(x[:ntv], v[:ntv], tm[:ntv], tp[:ntv], epochs=epochs, batch=4096, lr=1e-3, lr_final=1e-5,
-                   val_frac=vf, seed=seed, keep_best=True)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
     xv, vv, tpv = x[rows - nval:], v[rows - nval:], tp[rows - nval:]
     half = min(nval // 2, chains)
     xa, va = xv[:half], vv[:half]                      # half-width tuning
     xb, vb, tpb = xv[half:half + chains], vv[half:half + chains], tpv[half:half + chains]  # evaluation
     ltpa = torch.log(tpv[:half]).cpu().numpy()
+    ltpb = torch.log(tpb).cpu().numpy()
     levels = (0.5, 0.7, 0.8, 0.9, 0.95, 0.99)
-    # the network: candidates from its errors on the tuning rows
-    lpa = net.predict(xa, va)[0].cpu().numpy()
-    cands = [float(np.quantile(np.abs(lpa - ltpa), q)) for q in levels]
-    best, ms = g.tune_mlp_delta(net, xa, va, cands, reps=2)
-    # the control: constant log t+ prediction (training mean), tuned the same way
-    ctl = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed + 1)
-    ctl.train(x[:ntv], v[:ntv], tm[:ntv], tp[:ntv], epochs=1, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf,
-              seed=seed)
-    ctl.set_params(np.zeros(ctl.nparams, dtype=np.float32))
-    lca = ctl.predict(xa, va)[0].cpu().numpy()
-    ccands = [float(np.quantile(np.abs(lca - ltpa), q)) for q in levels]
-    cbest, cms = g.tune_mlp_delta(ctl, xa, va, ccands, reps=2)
-    # evaluation rows: t+ of learned, control and plain against each other, Lanczos steps
+
     def reflect_eval(model, delta):
         g.set_mlp(model, delta, 1) if model is not None else g.set_mlp(None)
         tpx = g.reflect(xb, vb)[0]
         info = g.lanczos_info(xb.shape[0])
         return tpx, float(info[:, 3].mean()), float(np.mean(info[:, 2] == 1))
-    tpl, steps_l, fb_l = reflect_eval(net, best)
+
+    def tune(model):
+        """Half-width candidates from the model's errors on the tuning rows,
+        chosen by timing the real learned kernel."""
+        lpa = model.predict(xa, va)[0].cpu().numpy()
+        cands = [float(np.quantile(np.abs(lpa - ltpa), q)) for q in levels]
+        best, ms = g.tune_mlp_delta(model, xa, va, cands, reps=2)
+        return best, ms, cands
+
+    def fit(products):
+        """Train a network (early stopping on the index % 10 == 8 chains), tune
+        its half-width and evaluate it on the unseen chains."""
+        net = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed, products=products)
+        t1 = time.perf_counter()
+        tr = net.train(x[:ntv], v[:ntv], tm[:ntv], tp[:ntv], epochs=epochs, batch=4096, lr=1e-3,
+                       lr_final=1e-5, val_frac=vf, seed=seed, keep_best=True)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        best, ms, cands = tune(net)
+        tpl, steps, fb = reflect_eval(net, best)
+        err = np.abs(net.predict(xb, vb)[0].cpu().numpy() - ltpb)
+        rep = {"inputs": net.nin, "train_seconds": t_train, "best_epoch": tr.get("best_epoch"),
+               "adam_steps": tr["steps"], "train_loss": tr["train_loss"], "val_loss": tr["val_loss"],
+               "val_loss_constant_predictor": tr.get("val_loss_const"),
+               "val_logtp_err": {str(k): val for k, val in tr["err_q"].items()},
+               "delta_candidates": dict(zip([str(q) for q in levels], cands)), "tune_ms": ms, "delta": best,
+               "eval_logtp_err_median": float(np.median(err)), "eval_logtp_err_rms": float(np.sqrt(np.mean(err**2))),
+               "eval_lanczos_steps_per_call": steps, "eval_fallback_rate": fb}
+        return net, best, tpl, rep
+
+    progress(f"training on {ntv - nv8} triples, {nv8} for early stopping, {nval} held out "
+             f"({t_data:.1f} s to generate)")
+    net, best, tpl, rep = fit(True)
+    net400, best400, _, rep400 = fit(False)
+    # the control: constant log t+ prediction (training mean), tuned the same way
+    ctl = S.Mlp(n, width=256, hidden=3, bf16=True, seed=seed + 1)
+    ctl.train(x[:ntv], v[:ntv], tm[:ntv], tp[:ntv], epochs=1, batch=4096, lr=1e-3, lr_final=1e-5, val_frac=vf,
+              seed=seed)
+    ctl.set_params(np.zeros(ctl.nparams, dtype=np.float32))
+    cbest, cms, ccands = tune(ctl)
     tpc, steps_c, fb_c = reflect_eval(ctl, cbest)
     tpp, steps_p, _ = reflect_eval(None, 0.0)
-    ltpb = torch.log(tpb).cpu().numpy()
-    err_net = np.abs(net.predict(xb, vb)[0].cpu().numpy() - ltpb)
     err_ctl = np.abs(ctl.predict(xb, vb)[0].cpu().numpy() - ltpb)
 
     def relstats(a, b):
@@ -319,27 +337,22 @@ def train_learned(g, S, tau, chains, rows_target, epochs, data_chains, burn_roun
         "rows": rows, "held_out_rows": nval, "early_stopping_rows": nv8,
         "holdout": "whole chains: index % 10 == 8 early stopping (the trainer's validation rows), "
                    "index % 10 == 9 half-width tuning and evaluation (never seen by training)",
-        "best_epoch": tr.get("best_epoch"),
         "data_chains": data_chains, "data_rounds": rounds, "data_burn_in_rounds": burn_rounds,
-        "data_seconds": t_data, "train_seconds": t_train,
-        "epochs": epochs, "adam_steps": tr["steps"], "train_loss": tr["train_loss"], "val_loss": tr["val_loss"],
-        "val_loss_constant_predictor": tr.get("val_loss_const"),
-        "val_logtp_err": {str(k): v for k, v in tr["err_q"].items()},
-        "delta_candidates": dict(zip([str(q) for q in levels], cands)), "tune_ms": ms, "delta": best,
+        "data_seconds": t_data, "epochs": epochs,
+        "network": dict(rep, inputs_are="[x, v, <x, v>, |x|^2] (the two products computed from x and v)"),
+        "network_400_inputs": dict(rep400, inputs_are="[x, v]"),
         "control": {"kind": "constant log t+ (training mean), zero-weight network",
                     "delta_candidates": dict(zip([str(q) for q in levels], ccands)), "tune_ms": cms,
-                    "delta": cbest},
+                    "delta": cbest, "eval_logtp_err_median": float(np.median(err_ctl)),
+                    "eval_logtp_err_rms": float(np.sqrt(np.mean(err_ctl**2))),
+                    "eval_lanczos_steps_per_call": steps_c, "eval_fallback_rate": fb_c},
         "eval_rows": int(xb.shape[0]),
-        "eval_logtp_err_median": {"network": float(np.median(err_net)), "control": float(np.median(err_ctl))},
-        "eval_logtp_err_rms": {"network": float(np.sqrt(np.mean(err_net**2))),
-                               "control": float(np.sqrt(np.mean(err_ctl**2)))},
-        "eval_lanczos_steps_per_call": {"learned": steps_l, "control": steps_c, "plain": steps_p},
-        "eval_fallback_rate": {"learned": fb_l, "control": fb_c},
+        "eval_lanczos_steps_per_call_plain": steps_p,
         "learned_vs_plain_tp_rel": relstats(tpl, tpp),
         "control_vs_plain_tp_rel": relstats(tpc, tpp),
     }
     g.set_mlp(None)
-    return net, best, ctl, cbest, report
+    return net, best, ctl, cbest, report, net400, best400
 
 
 def uneven_volume_all(S, I, samples_per_phase, chunk=32):
@@ -973,8 +986,9 @@ def main():
     net = ctl = report = None
     if not args.no_learned:
         progress("learned path: training data, training, half-width tuning")
-        net, delta, ctl, cdelta, report = train_learned(g, S, tau, chains, args.train_rows, args.epochs,
-                                                        args.data_chains, args.state_rounds)
+        net, delta, ctl, cdelta, report, net400, delta400 = train_learned(g, S, tau, chains, args.train_rows,
+                                                                          args.epochs, args.data_chains,
+                                                                          args.state_rounds)
     # one chain state for every leg: fresh chains walked state_rounds rounds and
     # saved; each leg restores it, runs the warm-up rounds and then the timed
     # rounds with the same seed, so the legs see the same walk states
@@ -1022,6 +1036,8 @@ def main():
         learned_sum["training"] = report
         control = leg(f"constant-shift control (delta {cdelta:.3f})", ctl, cdelta)
         control_sum = summary(control, chains, cps)
+        learned400 = leg(f"learned path, network on [x, v] only (delta {delta400:.3f})", net400, delta400)
+        learned400_sum = summary(learned400, chains, cps)
 
     head = learned_sum if learned_sum is not None else plain_sum
     out = {
@@ -1051,6 +1067,9 @@ def main():
         out["control"] = control_sum
         out["learned_over_plain"] = learned_sum["oracle_calls_per_s"] / plain_sum["oracle_calls_per_s"]
         out["learned_over_control"] = learned_sum["oracle_calls_per_s"] / control_sum["oracle_calls_per_s"]
+        out["learned_400_inputs"] = learned400_sum
+        out["learned_over_learned_400_inputs"] = (learned_sum["oracle_calls_per_s"]
+                                                  / learned400_sum["oracle_calls_per_s"])
         out["comparison"] = ("plain, learned and control legs continue the same saved chain state with the same "
                              "seed (warm-up rounds, then the timed rounds)")
     if not args.no_hmc:

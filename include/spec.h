@@ -555,12 +555,22 @@ typedef struct {
 /* New network for n coordinates; parameters from Philox (key seed):
  * W ~ U(-1/sqrt(in), 1/sqrt(in)), b = 0.  width <= 1024, 1 <= hidden <= 8. */
 spec_status spec_mlp_create(int n, int width, int hidden, int use_bf16, uint64_t seed, spec_mlp* out);
+/* As spec_mlp_create; products = 1 appends two features computed from (x, v),
+ * <x, v> and |x|^2, to the 2n inputs (2n + 2 inputs): the boundary distance
+ * along v depends on them through a product of the inputs, which the network
+ * does not learn from the raw coordinates on walk data. */
+spec_status spec_mlp_create_ex(int n, int width, int hidden, int use_bf16, uint64_t seed, int products,
+                               spec_mlp* out);
+/* The feature standardisation of a trained network: mu and isd (inputs each:
+ * features are (f - mu) * isd) and target = (mean, sd) of log t+ then of
+ * log(-t-). */
+spec_status spec_mlp_standardization(spec_mlp net, float* mu, float* isd, float* target);
 spec_status spec_mlp_destroy(spec_mlp net);
 spec_status spec_mlp_nparams(spec_mlp net, long long* np);
 /* Copy the FP32 master parameters to / from host memory (np floats). */
 spec_status spec_mlp_get_params(spec_mlp net, float* host);
 spec_status spec_mlp_set_params(spec_mlp net, const float* host);
-/* Raw network (no standardisation): Y (rows x 2) from X (rows x 2n), device
+/* Raw network (no standardisation): Y (rows x 2) from X (rows x inputs: 2n, or 2n + 2 with products), device
  * pointers, float32. */
 spec_status spec_mlp_forward_dev(spec_mlp net, int rows, const float* X, float* Y, void* stream);
 /* Mean over rows x 2 entries of (Y - T)^2 and its gradient (np floats, device)

@@ -33,8 +33,15 @@ hipError_t gemm_asm(int prec, int M, int N, int K, const float* A, int lda, cons
                     hipStream_t s);
 hipError_t to_f32(size_t count, const double* x, float* y, hipStream_t s);
 
-// Features [(x - mu_x) * isd_x, (v - mu_v) * isd_v, 1] of rows (FP64 in, FP32 out, ldf >= 2n + 1).
-hipError_t mlp_features(int rows, int n, const double* x, int ldx, const double* v, int ldv, const float* mu,
+// Features [(x - mu_x) * isd_x, (v - mu_v) * isd_v, (products), 1] of rows (FP64 in, FP32 out,
+// ldf >= 2n + nextra + 1).
+// The two products of (x, v) that may follow them in the features: <x, v> and
+// |x|^2 (rows x 2, FP64).
+hipError_t mlp_products(int rows, int n, const double* x, int ldx, const double* v, int ldv, double* out,
+                        hipStream_t s);
+// nextra = 2 appends the standardised products <x, v>, |x|^2 before the ones column.
+hipError_t mlp_features(int rows, int n, int nextra, const double* x, int ldx, const double* v, int ldv,
+                        const float* mu,
                         const float* isd, float* F, int ldf, hipStream_t s);
 // Standardised targets ((log t+ - mu0) * isd0, (log(-t-) - mu1) * isd1).
 hipError_t mlp_targets(int rows, const double* tm, const double* tp, const float* tmu, const float* tisd,

@@ -191,9 +191,32 @@ hipError_t gemm_mode(int mode, dim3 g, int M, int N, int K, const float* A, int 
     return hipGetLastError();
 }
 
-__global__ void k_features(int rows, int n, const double* __restrict__ x, int ldx, const double* __restrict__ v,
-                           int ldv, const float* __restrict__ mu, const float* __restrict__ isd, float* __restrict__ F,
-                           int ldf) {
+// <x, v> and |x|^2 of row r in FP64 (128 threads: two waves).
+__device__ inline void row_products(int n, const double* __restrict__ x, const double* __restrict__ v, double& xv,
+                                    double& xx) {
+    __shared__ double red[2][2];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a += x[i] * v[i];
+        b += x[i] * x[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = a;
+        red[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    xv = red[0][0] + red[1][0];
+    xx = red[0][1] + red[1][1];
+}
+
+__global__ __launch_bounds__(128) void k_features(int rows, int n, int nextra, const double* __restrict__ x, int ldx,
+                                                  const double* __restrict__ v, int ldv,
+                                                  const float* __restrict__ mu, const float* __restrict__ isd,
+                                                  float* __restrict__ F, int ldf) {
     const int r = blockIdx.x;
     if (r >= rows) return;
     float* f = F + (size_t)r * ldf;
@@ -201,7 +224,27 @@ __global__ void k_features(int rows, int n, const double* __restrict__ x, int ld
         f[i] = ((float)x[(size_t)r * ldx + i] - mu[i]) * isd[i];
         f[n + i] = ((float)v[(size_t)r * ldv + i] - mu[n + i]) * isd[n + i];
     }
-    if (threadIdx.x == 0) f[2 * n] = 1.0f;
+    if (nextra) {
+        double xv, xx;
+        row_products(n, x + (size_t)r * ldx, v + (size_t)r * ldv, xv, xx);
+        if (threadIdx.x == 0) {
+            f[2 * n] = ((float)xv - mu[2 * n]) * isd[2 * n];
+            f[2 * n + 1] = ((float)xx - mu[2 * n + 1]) * isd[2 * n + 1];
+        }
+    }
+    if (threadIdx.x == 0) f[2 * n + nextra] = 1.0f;
+}
+
+__global__ __launch_bounds__(128) void k_products(int rows, int n, const double* __restrict__ x, int ldx,
+                                                  const double* __restrict__ v, int ldv, double* __restrict__ out) {
+    const int r = blockIdx.x;
+    if (r >= rows) return;
+    double xv, xx;
+    row_products(n, x + (size_t)r * ldx, v + (size_t)r * ldv, xv, xx);
+    if (threadIdx.x == 0) {
+        out[2 * r] = xv;
+        out[2 * r + 1] = xx;
+    }
 }
 
 __global__ void k_targets(int rows, const double* __restrict__ tm, const double* __restrict__ tp,
@@ -370,10 +413,18 @@ hipError_t to_f32(size_t count, const double* x, float* y, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t mlp_features(int rows, int n, const double* x, int ldx, const double* v, int ldv, const float* mu,
-                        const float* isd, float* F, int ldf, hipStream_t s) {
+hipError_t mlp_features(int rows, int n, int nextra, const double* x, int ldx, const double* v, int ldv,
+                        const float* mu, const float* isd, float* F, int ldf, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
-    k_features<<<rows, 128, 0, s>>>(rows, n, x, ldx, v, ldv, mu, isd, F, ldf);
+    if (nextra != 0 && nextra != 2) return hipErrorInvalidValue;
+    k_features<<<rows, 128, 0, s>>>(rows, n, nextra, x, ldx, v, ldv, mu, isd, F, ldf);
+    return hipGetLastError();
+}
+
+hipError_t mlp_products(int rows, int n, const double* x, int ldx, const double* v, int ldv, double* out,
+                        hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    k_products<<<rows, 128, 0, s>>>(rows, n, x, ldx, v, ldv, out);
     return hipGetLastError();
 }
 

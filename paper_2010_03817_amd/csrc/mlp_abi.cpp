@@ -91,7 +91,7 @@ spec_status mlp_backward(spec_mlp_s* net, int rows, const float* X, int ldx, flo
 spec_status mlp_predict_rows(spec_mlp_s* net, int rows, const double* x, int ldx, const double* v, int ldv,
                              hipStream_t s) {
     SPCHK(net->ensure(rows, s));
-    HIPCHK(mlp_features(rows, net->n, x, ldx, v, ldv, net->dMu, net->dIsd, net->dX, net->ld_in(), s));
+    HIPCHK(mlp_features(rows, net->n, net->nextra, x, ldx, v, ldv, net->dMu, net->dIsd, net->dX, net->ld_in(), s));
     return mlp_forward_x(net, rows, net->dX, net->ld_in(), s);
 }
 
@@ -111,7 +111,14 @@ double quantile(std::vector<double> v, double q) {
 extern "C" {
 
 spec_status spec_mlp_create(int n, int width, int hidden, int use_bf16, uint64_t seed, spec_mlp* out) {
-    if (!out || n < 1 || width < 1 || width > 1024 || hidden < 1 || hidden > MLP_MAX_LAYERS - 1) return SPEC_EINVAL;
+    return spec_mlp_create_ex(n, width, hidden, use_bf16, seed, 0, out);
+}
+
+spec_status spec_mlp_create_ex(int n, int width, int hidden, int use_bf16, uint64_t seed, int products,
+                               spec_mlp* out) {
+    if (!out || n < 1 || width < 1 || width > 1024 || hidden < 1 || hidden > MLP_MAX_LAYERS - 1 || products < 0 ||
+        products > 1)
+        return SPEC_EINVAL;
     *out = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SPEC_EDEVICE;
@@ -122,7 +129,8 @@ spec_status spec_mlp_create(int n, int width, int hidden, int use_bf16, uint64_t
     net->hidden = hidden;
     net->nl = hidden + 1;
     net->bf16 = use_bf16 ? 1 : 0;
-    net->dims[0] = 2 * n;
+    net->nextra = products ? 2 : 0;
+    net->dims[0] = 2 * n + net->nextra;
     for (int l = 1; l <= hidden; ++l) net->dims[l] = width;
     net->dims[hidden + 1] = 2;
     int64_t o = 0;
@@ -135,9 +143,10 @@ spec_status spec_mlp_create(int n, int width, int hidden, int use_bf16, uint64_t
     if (e == hipSuccess) e = dalloc(&net->dG, (size_t)o);
     if (e == hipSuccess) e = dalloc(&net->dM, (size_t)o);
     if (e == hipSuccess) e = dalloc(&net->dV, (size_t)o);
-    if (e == hipSuccess) e = dalloc(&net->dMu, (size_t)2 * n);
-    std::vector<float> ones((size_t)2 * n, 1.0f);
-    if (e == hipSuccess) e = dalloc(&net->dIsd, (size_t)2 * n, false);
+    const int nin = net->dims[0];
+    if (e == hipSuccess) e = dalloc(&net->dMu, (size_t)nin);
+    std::vector<float> ones((size_t)nin, 1.0f);
+    if (e == hipSuccess) e = dalloc(&net->dIsd, (size_t)nin, false);
     if (e == hipSuccess) e = hipMemcpy(net->dIsd, ones.data(), sizeof(float) * ones.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = mlp_init(net->nl, net->dims, net->dP, seed, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -155,6 +164,17 @@ spec_status spec_mlp_destroy(spec_mlp net) {
     net->free_work();
     dfree(net->dP); dfree(net->dG); dfree(net->dM); dfree(net->dV); dfree(net->dMu); dfree(net->dIsd);
     delete net;
+    return SPEC_OK;
+}
+
+spec_status spec_mlp_standardization(spec_mlp net, float* mu, float* isd, float* target) {
+    if (!net || !mu || !isd || !target) return SPEC_EINVAL;
+    HIPCHK(hipMemcpy(mu, net->dMu, sizeof(float) * net->dims[0], hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(isd, net->dIsd, sizeof(float) * net->dims[0], hipMemcpyDeviceToHost));
+    target[0] = net->tmu[0];
+    target[1] = net->tmu[1];
+    target[2] = net->tsd[0];
+    target[3] = net->tsd[1];
     return SPEC_OK;
 }
 
@@ -225,7 +245,7 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
     const int nval = std::max(1, (int)std::lround(vf * rows));
     const int ntrain = rows - nval;
     if (ntrain < 1) return SPEC_EINVAL;
-    const int n = net->n, nin = 2 * n;
+    const int n = net->n, nin = net->dims[0];
     hipStream_t s = (hipStream_t)stream;
 
     // targets on the host (rows x 2 doubles): standardisation of the training rows
@@ -252,6 +272,14 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
     HIPCHK(dalloc(&dSq, (size_t)nin));
     HIPCHK(mlp_col_moments(ntrain, n, x, n, dSum, dSq, s));
     HIPCHK(mlp_col_moments(ntrain, n, v, n, dSum + n, dSq + n, s));
+    if (net->nextra) {
+        double* dPr = nullptr;
+        HIPCHK(dalloc(&dPr, (size_t)2 * ntrain, false));
+        HIPCHK(mlp_products(ntrain, n, x, n, v, n, dPr, s));
+        HIPCHK(mlp_col_moments(ntrain, 2, dPr, 2, dSum + 2 * n, dSq + 2 * n, s));
+        HIPCHK(hipStreamSynchronize(s));
+        dfree(dPr);
+    }
     std::vector<double> hs(nin), hq(nin);
     HIPCHK(hipMemcpyAsync(hs.data(), dSum, sizeof(double) * nin, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hq.data(), dSq, sizeof(double) * nin, hipMemcpyDeviceToHost, s));
@@ -276,7 +304,7 @@ spec_status spec_mlp_train_dev(spec_mlp net, int rows, const double* x, const do
     HIPCHK(dalloc(&dTm, (size_t)4, false));
     const float tmi[4] = {net->tmu[0], net->tmu[1], 1.0f / net->tsd[0], 1.0f / net->tsd[1]};
     HIPCHK(hipMemcpy(dTm, tmi, sizeof(tmi), hipMemcpyHostToDevice));
-    HIPCHK(mlp_features(rows, n, x, n, v, n, net->dMu, net->dIsd, dXall, ldx, s));
+    HIPCHK(mlp_features(rows, n, net->nextra, x, n, v, n, net->dMu, net->dIsd, dXall, ldx, s));
     HIPCHK(mlp_targets(rows, t_minus, t_plus, dTm, dTm + 2, dTall, s));
 
     const int cap_rows = std::max(batch, std::min(nval, 65536));

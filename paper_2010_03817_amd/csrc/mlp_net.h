@@ -10,6 +10,7 @@ constexpr int MLP_MAX_LAYERS = 9;
 struct spec_mlp_s {
     int device = 0;
     int n = 0, width = 0, hidden = 0, nl = 0, bf16 = 1;
+    int nextra = 0;  // 2: the features end with <x, v> and |x|^2 (dims[0] = 2 n + nextra)
     int dims[MLP_MAX_LAYERS + 1] = {};
     int64_t off[MLP_MAX_LAYERS] = {};  // parameter offset of layer l
     int64_t np = 0;

@@ -160,6 +160,8 @@ def lib():
     L.spec_diag_gemm_f32.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp,
                                      C.c_int, vp, C.c_int, vp, C.c_int]
     L.spec_mlp_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
+    L.spec_mlp_create_ex.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_int, C.POINTER(vp)]
+    L.spec_mlp_standardization.argtypes = [vp, vp, vp, vp]
     L.spec_mlp_destroy.argtypes = [vp]
     L.spec_mlp_nparams.argtypes = [vp, C.POINTER(C.c_longlong)]
     L.spec_mlp_get_params.argtypes = [vp, vp]
@@ -565,12 +567,14 @@ class Batch:
 class Mlp:
     """Learned-bracket network (include/spec.h, spec_mlp_*)."""
 
-    def __init__(self, n, width=256, hidden=3, bf16=True, seed=1):
+    def __init__(self, n, width=256, hidden=3, bf16=True, seed=1, products=False):
         _torch()
         h = C.c_void_p()
-        check(lib().spec_mlp_create(int(n), int(width), int(hidden), int(bool(bf16)), int(seed), C.byref(h)))
+        check(lib().spec_mlp_create_ex(int(n), int(width), int(hidden), int(bool(bf16)), int(seed),
+                                       int(bool(products)), C.byref(h)))
         self._h = h
         self.n = n
+        self.nin = 2 * n + (2 if products else 0)
         k = C.c_longlong()
         check(lib().spec_mlp_nparams(h, C.byref(k)))
         self.nparams = k.value
@@ -586,6 +590,13 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+    def standardization(self):
+        """(mu, isd, target (mean, sd of log t+, of log(-t-))) of the features."""
+        mu, isd, tg = np.empty(self.nin, np.float32), np.empty(self.nin, np.float32), np.empty(4, np.float32)
+        check(lib().spec_mlp_standardization(self._h, mu.ctypes.data_as(C.c_void_p), isd.ctypes.data_as(C.c_void_p),
+                                             tg.ctypes.data_as(C.c_void_p)))
+        return mu, isd, tg
 
     def get_params(self):
         out = np.empty(self.nparams, dtype=np.float32)
@@ -604,16 +615,16 @@ class Mlp:
         return a.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, cols)
 
     def forward(self, X):
-        """Raw network outputs (rows x 2) for raw features X (rows x 2n)."""
+        """Raw network outputs (rows x 2) for raw features X (rows x inputs)."""
         torch = _torch()
-        X = self._f32(X, 2 * self.n)
+        X = self._f32(X, self.nin)
         Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda")
         check(lib().spec_mlp_forward_dev(self._h, X.shape[0], _ptr(X), _ptr(Y), _stream()))
         return Y
 
     def loss_grad(self, X, T):
         torch = _torch()
-        X = self._f32(X, 2 * self.n)
+        X = self._f32(X, self.nin)
         T = self._f32(T, 2)
         G = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
         loss = C.c_double()

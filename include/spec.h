@@ -124,6 +124,17 @@ spec_status spec_destroy(spec_handle h);
  *                factorisation and eigen solve are FP64 in every mode.
  *                Intersections without a reflection keep the reduced-precision
  *                roots.  Default 1e-3; 0 disables.  Counted as escalated.
+ *  refresh_period  line walks (Hit-and-Run, coordinate Hit-and-Run, billiard)
+ *                with FP64 pencils: F(x) is assembled from x in the first
+ *                round of a spec_walk_run* call and every refresh_period rounds
+ *                after it; in between a chain that moved by x <- x + s v is
+ *                given F(x + s v) = F(x) + s B(v) (the identity of Lemma "PEP
+ *                and S cap C"), so that those rounds assemble only B(v).  The
+ *                sum adds one rounding of F per round, below the assembly's own
+ *                (n + 1)-term rounding over a period.  A chain sent back to its
+ *                step start (reflection cap, not-interior restart) skips its
+ *                oracle calls until the next assembly round (not counted as
+ *                calls).  Default 16; 1 assembles every round.
  * When the factor does not exist at t0 (t1 was too far out) the origin backs
  * off to t1 (1 - 2^-5) and then t1 / 2; only if those fail too is the plain
  * solve repeated at the full tolerance (counted as refine_failed in
@@ -136,6 +147,7 @@ typedef struct {
     double tol_loose;
     int certify;
     double escalate_ratio;
+    int refresh_period;
 } spec_options;
 
 spec_status spec_options_default(spec_options* opt);

@@ -41,6 +41,10 @@ spec_status spec_diag_call_flags(spec_handle h, int batch, int32_t* flags_out);
  * Lanczos step count summed over chains of the timed rounds (1 double). */
 spec_status spec_diag_timing(spec_handle h, int on);
 spec_status spec_diag_stage_times(spec_handle h, double* ms_and_counts, double* lanczos_steps);
+/* Pencil rows (F(x) and B(v) rows, one per chain each) that the line-oracle
+ * rounds assembled while timing was on: a round that carries F(x) over
+ * assembles only the B(v) rows (spec_options.refresh_period). */
+spec_status spec_diag_assembly_rows(spec_handle h, double* rows);
 
 /* Phase stamps of the per-chain kernel: spec_diag_phase_profile(h, c)
  * records, for the next calls on chains < c, SPEC_DIAG_PHASE_SLOTS values

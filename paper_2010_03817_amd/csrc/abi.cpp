@@ -44,6 +44,25 @@ spec_status assemble(spec_s* h, int batch, const double* x, const double* v, int
     return pencil_gemm(h, M, s);
 }
 
+// B(v) rows alone (F carried over from the previous walk round): rows
+// bp + c of FB = B(v_c), FP64.
+spec_status assemble_b(spec_s* h, int batch, const double* v, int* bp_out, hipStream_t s) {
+    const int bp = round_up(batch, 64);
+    *bp_out = bp;
+    HIPCHK(launch_build_z(batch, h->n, h->Kpad, nullptr, v, h->dZ, bp, s));
+    HIPCHK(gemm_f64(false, bp, h->ldA, h->Kpad, h->dZ + (size_t)bp * h->Kpad, h->Kpad, h->dA, h->ldA,
+                    h->dFB + (size_t)bp * h->ldA, h->ldA, s));
+    return SPEC_OK;
+}
+
+// F(x) of a walk round carried over from the previous one: F rows and B rows
+// of the previous [F; B] block and the chains' moves (see FusedArgs::upd_F).
+struct FCarry {
+    const double* F;
+    const double* B;
+    const double* s;
+};
+
 inline void mark(spec_s* h, int i, hipStream_t s) {
     if (h->timing) (void)hipEventRecord(h->ev[i], s);
 }
@@ -100,6 +119,7 @@ spec_status run_fused(spec_s* h, FusedArgs a, int batch, hipStream_t s) {
     HIPCHK(launch_zero_ints(h->dRCnt, 2, s));
     HIPCHK(launch_line_fused(a, batch, s));
     FusedArgs r = a;
+    r.upd_F = r.upd_B = r.upd_s = nullptr;  // the first pass has written F(x) to FB
     r.shift = h->dRShift;
     r.shift_hi = nullptr;
     r.idx = nullptr;
@@ -116,10 +136,16 @@ spec_status run_fused(spec_s* h, FusedArgs a, int batch, hipStream_t s) {
 // bracket when there is one (t+ only).
 spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, double* tm, double* tp,
                         int32_t* st, bool want_vec, const double* ell, hipStream_t s, bool min_only = false,
-                        bool learned = false) {
+                        bool learned = false, const FCarry* carry = nullptr) {
     int bp = 0;
     mark(h, 0, s);
-    SPCHK(assemble(h, batch, x, v, &bp, s));
+    if (carry) {
+        if (h->prec != 0) return SPEC_EINVAL;  // FP64 pencils only
+        SPCHK(assemble_b(h, batch, v, &bp, s));
+    } else {
+        SPCHK(assemble(h, batch, x, v, &bp, s));
+    }
+    if (h->timing) h->asm_rows += carry ? bp : 2.0 * bp;
     mark(h, 1, s);
     const bool use_net = learned && min_only && h->net && h->lmode > 0 && h->m > 0;
     if (use_net) {
@@ -130,6 +156,11 @@ spec_status line_oracle(spec_s* h, int batch, const double* x, const double* v, 
     mark(h, 2, s);
     FusedArgs a = fused_args(h, bp, st, tm, tp, want_vec, ell);
     a.min_only = min_only ? 1 : 0;
+    if (carry) {
+        a.upd_F = carry->F;
+        a.upd_B = carry->B;
+        a.upd_s = carry->s;
+    }
     if (use_net) {
         a.shift = h->dShift;
         if (h->lmode == 2) a.shift_hi = h->dShiftHi;
@@ -472,6 +503,7 @@ spec_status spec_options_default(spec_options* o) {
     o->tol_loose = 1e-3;
     o->certify = 0;
     o->escalate_ratio = 1e-3;
+    o->refresh_period = 16;
     return SPEC_OK;
 }
 
@@ -484,6 +516,7 @@ spec_status spec_get_options(spec_handle h, spec_options* o) {
     o->tol_loose = h->tol_loose;
     o->certify = h->certify;
     o->escalate_ratio = h->esc_ratio;
+    o->refresh_period = h->refresh;
     return SPEC_OK;
 }
 
@@ -494,12 +527,14 @@ spec_status spec_set_options(spec_handle h, const spec_options* o) {
     if (o->precision < SPEC_PREC_FP64 || o->precision > SPEC_PREC_BF16X2_ASM) return SPEC_EINVAL;
     if (o->certify < 0 || o->certify > 1) return SPEC_EINVAL;
     if (!(o->escalate_ratio >= 0.0 && o->escalate_ratio < 1.0)) return SPEC_EINVAL;
+    if (o->refresh_period < 1) return SPEC_EINVAL;
     if (o->kmax != h->kmax || o->tol != h->tol) SPCHK(spec_set_lanczos(h, o->kmax, o->tol));
     SPCHK(spec_set_precision(h, o->precision));
     h->refine_ratio = o->refine_ratio;
     h->tol_loose = o->tol_loose;
     h->certify = o->certify;
     h->esc_ratio = o->escalate_ratio;
+    h->refresh = o->refresh_period;
     return SPEC_OK;
 }
 
@@ -907,16 +942,36 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
     long long rounds = 0;
     const long long max_rounds = p->max_rounds > 0 ? p->max_rounds : (long long)1 << 62;
     const bool hmc = kind == SPEC_WALK_HMC;
+    // line walks in FP64 carry F(x) over between full assemblies: round r
+    // assembles B(v) only and forms F(x) = F(x_prev) + s B(v_prev) from the
+    // previous round's [F; B] block (the two blocks alternate); every
+    // `refresh` rounds (and in the first) F(x) is assembled from x again
+    const bool carry = !hmc && h->prec == 0 && h->m > 0 && h->refresh > 1;
+    struct BlockOrder {  // the handle's F block is the original one again on exit
+        spec_s* h;
+        bool swapped = false;
+        ~BlockOrder() {
+            if (swapped) std::swap(h->dFB, h->dFB2);
+        }
+    } order{h};
+    if (carry) SPCHK(h->ensure_fb2());
+    a.upd_s = carry ? h->dUpdS : nullptr;
+    const int bp = round_up(chains, 64);
     while (rounds < max_rounds) {
         if (hmc) {
-            HIPCHK(walk_hmc_prep(a, h->dZ, round_up(chains, 64), h->Kpad, h->dHz, s));
+            HIPCHK(walk_hmc_prep(a, h->dZ, bp, h->Kpad, h->dHz, s));
             SPCHK(curve_oracle(h, chains, h->dHz, INFINITY, h->dTm, h->dTp, h->dSt, false, true, nullptr, s));
+        } else if (carry && rounds % h->refresh != 0) {
+            std::swap(h->dFB, h->dFB2);
+            order.swapped = !order.swapped;
+            const FCarry fc{h->dFB2, h->dFB2 + (size_t)bp * h->ldA, h->dUpdS};
+            SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard,
+                              billiard ? h->wEll : nullptr, s, billiard, billiard, &fc));
         } else {
             SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard,
                               billiard ? h->wEll : nullptr, s, billiard, billiard));
         }
         if (billiard || hmc) {
-            const int bp = round_up(chains, 64);
             const int Kn = round_up(h->P, 16);
             if (h->m > 0)
                 HIPCHK(gemm_f64(true, bp, h->Nn, Kn, h->dU2, h->ldA, h->dA + h->ldA, h->ldA, h->dWn, h->Nn, s));
@@ -1512,6 +1567,7 @@ spec_status spec_diag_timing(spec_handle h, int on) {
         if (!h->dLamSum) HIPCHK(dalloc(&h->dLamSum, 1));
         for (int i = 0; i < 5; ++i) h->stage_ms[i] = h->stage_n[i] = 0.0;
         h->lanczos_steps = 0.0;
+        h->asm_rows = 0.0;
     }
     h->timing = on != 0;
     return SPEC_OK;
@@ -1542,6 +1598,12 @@ spec_status spec_diag_stage_times(spec_handle h, double* out, double* lanczos_st
         out[5 + i] = h->stage_n[i];
     }
     if (lanczos_steps) *lanczos_steps = h->lanczos_steps;
+    return SPEC_OK;
+}
+
+spec_status spec_diag_assembly_rows(spec_handle h, double* rows) {
+    if (!h || !rows) return SPEC_EINVAL;
+    *rows = h->asm_rows;
     return SPEC_OK;
 }
 

@@ -29,6 +29,9 @@ struct spec_s {
     double refine_ratio = 1e3, tol_loose = 1e-3;
     int certify = 0;  // 1: two-sided Cholesky certificate of every dense t+ (spec_options)
     double esc_ratio = 1e-3;  // reduced-precision pencils: FP64 again below this pivot ratio
+    // line walks: F(x) assembled from x every `refresh` rounds and carried
+    // over as F + s B(v) in between (1: assembled every round)
+    int refresh = 16;
     // workspace (capacity in chains, multiple of 64); work_gen changes whenever
     // it is (re)allocated, so that cached device pointers can be revalidated
     int cap = 0;
@@ -36,6 +39,10 @@ struct spec_s {
     double *dZ = nullptr, *dFB = nullptr, *dQ = nullptr, *dU = nullptr, *dU2 = nullptr, *dWn = nullptr;
     float* dZ32 = nullptr;
     double *dLam = nullptr, *dTm = nullptr, *dTp = nullptr;
+    // carried-over F(x): the other [F; B] block of the walk rounds (2 cap rows,
+    // on first use) and the chains' moves
+    double *dFB2 = nullptr, *dUpdS = nullptr;
+    int fb2_cap = 0;
     int32_t *dHit = nullptr, *dSt = nullptr, *dFlags = nullptr;
     double* dCert = nullptr;  // certified interval of t+ per chain (2 doubles)
     // precision escalation: queued chains, count, compact coefficient rows
@@ -56,6 +63,7 @@ struct spec_s {
     bool timing = false;
     hipEvent_t ev[6] = {};
     double stage_ms[5] = {0, 0, 0, 0, 0}, stage_n[5] = {0, 0, 0, 0, 0}, lanczos_steps = 0;
+    double asm_rows = 0;  // pencil rows assembled by the timed walk rounds
     double* dLamSum = nullptr;
     long long* dProf = nullptr;
     int prof_cap = 0;
@@ -98,6 +106,8 @@ struct spec_s {
         dfree(dZp); dfree(dFBp);
         pz_rows = pf_rows = 0;
         dfree(dZ); dfree(dZ32); dfree(dFB); dfree(dQ); dfree(dU); dfree(dU2); dfree(dWn);
+        dfree(dFB2); dfree(dUpdS);
+        fb2_cap = 0;
         dfree(dLam); dfree(dTm); dfree(dTp); dfree(dHit); dfree(dSt); dfree(dFlags);
         dfree(dRList); dfree(dRShift); dfree(dRCnt); dfree(dCert);
         dfree(dEList); dfree(dECnt); dfree(dZc);
@@ -164,7 +174,16 @@ struct spec_s {
         HIPCHK(dalloc(&dShiftHi, (size_t)c));
         HIPCHK(dalloc(&dPred, (size_t)c));
         HIPCHK(dalloc(&dHz, (size_t)c));
+        HIPCHK(dalloc(&dUpdS, (size_t)c));
         cap = c;
+        return SPEC_OK;
+    }
+    spec_status ensure_fb2() {
+        if (dFB2 && fb2_cap == cap) return SPEC_OK;
+        dfree(dFB2);
+        fb2_cap = 0;
+        HIPCHK(dalloc(&dFB2, (size_t)2 * cap * ldA, false));
+        fb2_cap = cap;
         return SPEC_OK;
     }
     size_t ldq() const { return (size_t)kmax * std::max(m, 1); }

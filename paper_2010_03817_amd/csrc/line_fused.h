@@ -49,6 +49,15 @@ struct FusedArgs {
     int* ecount;
     double esc_ratio;
     int escalated;
+    // F(x) carried over from the previous round of a line walk (first pass
+    // only): F(x_c) = upd_F[c] + s upd_B[c] with s = upd_s[c], the chain's move
+    // along its previous direction (x_c = x_prev + s v_prev), written to FB's
+    // row c for the later passes; s NaN: the chain was moved off that line
+    // (back to its step start) and waits for the next full assembly (status
+    // WALK_STALE, nothing else written).  Null: FB's F rows are current.
+    const double* upd_F;
+    const double* upd_B;
+    const double* upd_s;
 };
 
 // Degree-2 curve oracle: first root of det Q(t), Q(t) = Q0 + t Q1 + t^2 Q2,

@@ -470,6 +470,34 @@ __device__ __forceinline__ void fill_pencil(double* L, const double* F, const do
     }
 }
 
+// The same with F carried over from the previous round of a walk:
+// F[e] = Fp[e] + s Bp[e] is written to Fo and L[e] = F[e] + sh B[e] (B null:
+// F alone).  Each thread reads back nothing it wrote, so the fill can be
+// repeated (another origin) without a fence.
+__device__ __forceinline__ void fill_pencil_upd(double* L, const double* Fp, const double* Bp, double s, double* Fo,
+                                                const double* B, double sh, int P, int t, int bd) {
+    constexpr int U = 8;
+    for (int e0 = t; e0 < P; e0 += U * bd) {
+        double f[U], bp[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bd;
+            f[u] = e < P ? Fp[e] : 0.0;
+            bp[u] = e < P ? Bp[e] : 0.0;
+            b[u] = B && e < P ? B[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * bd;
+            if (e < P) {
+                const double fx = fma(s, bp[u], f[u]);
+                Fo[e] = fx;
+                L[e] = B ? fma(sh, b[u], fx) : fx;
+            }
+        }
+    }
+}
+
 // L[e] = Q0[e] + tau (sg Q1[e] + tau Q2[e]) for e < P, loads batched as in
 // fill_pencil.
 __device__ __forceinline__ void fill_quadratic(double* L, const double* Q0, const double* Q1, const double* Q2,
@@ -1805,6 +1833,31 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
 
     const double* Fr = a.FB + (size_t)chain * a.ldfb;
     const double* Br = a.FB + (size_t)(a.brow0 + chain) * a.ldfb;
+    // F(x) carried over from the walk's previous round: formed from (Fp, Bp,
+    // us) wherever F is read, and written to this chain's F row
+    const bool upd = !REFINE && a.upd_F != nullptr;
+    double us = 0.0;
+    const double *Fp = nullptr, *Bp = nullptr;
+    double* Fo = nullptr;
+    if (upd) {
+        us = a.upd_s[chain];
+        if (!(us == us)) {  // moved off its line: no F(x) until the next full assembly
+            if (t == 0) {
+                a.status[chain] = WALK_STALE;
+                a.tm[chain] = NAN;
+                a.tp[chain] = NAN;
+                a.hit[chain] = HIT_NONE;
+                if (a.flags) a.flags[chain] = 0;
+                if (a.lam) {
+                    for (int i = 0; i < 4; ++i) a.lam[4 * chain + i] = 0.0;
+                }
+            }
+            return;
+        }
+        Fp = a.upd_F + (size_t)chain * a.ldfb;
+        Bp = a.upd_B + (size_t)chain * a.ldfb;
+        Fo = const_cast<double*>(Fr);
+    }
     double t0 = a.shift ? a.shift[chain] : 0.0;
     if (REFINE) {
         if (!isfinite(t0)) t0 = 0.0;
@@ -1827,7 +1880,14 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     double dtp = INFINITY, dtm = -INFINITY;
     int dj = -1, bad = 0;
     for (int j = t; j < md; j += blockDim.x) {
-        const double f = Fr[P + j], b = a.membership_only ? 0.0 : Br[P + j];
+        double f;
+        if (upd) {
+            f = fma(us, Bp[P + j], Fp[P + j]);
+            Fo[P + j] = f;
+        } else {
+            f = Fr[P + j];
+        }
+        const double b = a.membership_only ? 0.0 : Br[P + j];
         if (!(f > 0.0)) bad |= 1;
         const double r = b / f;
         if (r < 0.0) {
@@ -1912,7 +1972,9 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         STAMP(1)
         for (;;) {
             const double sh = phase == 0 ? a.shift_hi[chain] : t0;
-            fill_pencil(L, Fr, a.membership_only || sh == 0.0 ? nullptr : Br, sh, P, t, blockDim.x);
+            const double* Bs = a.membership_only || sh == 0.0 ? nullptr : Br;
+            if (upd) fill_pencil_upd(L, Fp, Bp, us, Fo, Bs, sh, P, t, blockDim.x);
+            else fill_pencil(L, Fr, Bs, sh, P, t, blockDim.x);
             lds_barrier();
             ok = chol_blocked(L, m, scr, sflag, prof ? cst : nullptr);
             lds_barrier();

@@ -10,6 +10,11 @@ namespace spec {
 // Which block attains t+ : a diagonal row index (>= 0), the dense block, or none.
 enum : int { HIT_DENSE = -1, HIT_NONE = -3 };
 
+// Status of a walk chain's oracle call skipped for want of F(x): the chain was
+// moved off its line in the previous round and waits for the next full
+// assembly of F (walk rounds that carry F over; never returned by the ABI).
+constexpr int32_t WALK_STALE = 100;
+
 // Per-call bits of the line oracle: the learned bracket was not certified
 // (plain origin used), a far root was refined from a shifted origin, a
 // refining factor did not exist (the run from 0 was repeated at the full

@@ -301,12 +301,22 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= a.chains) return;
     const WalkState& S = a.st;
-    if (!S.active[c]) return;
+    // the move of this round for a carried-over F(x) (see WalkArgs::upd_s)
+    auto moved = [&](double sv) {
+        if (a.upd_s && lane == 0) a.upd_s[c] = sv;
+    };
+    if (!S.active[c]) {
+        moved(0.0);
+        return;
+    }
+    const int32_t status = a.status[c];
+    // no oracle call this round: the chain waits for a full assembly of F
+    // (its move stays NaN); nothing is logged or counted
+    if (status == WALK_STALE) return;
     const int n = a.n;
     double* x = S.x + (size_t)c * n;
     double* v = S.v + (size_t)c * n;
     double* st = S.stats + (size_t)c * WALK_NSTAT;
-    const int32_t status = a.status[c];
     const double tp = a.tp[c], tm = a.tm[c];
     // log the segment start (x, v) with its t-, t+
     if (a.log_buf && c < a.log_chains) {
@@ -346,6 +356,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         // step from its start point
         if (lane == 0) st[3] += 1.0;
         for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+        moved(NAN);
         end_step(a, c, lane);
         return;
     }
@@ -486,6 +497,9 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
             // within the roots' own error of the boundary may lie outside
             t = fmin(fmax(t, (1.0 - a.pullback) * tm), (1.0 - a.pullback) * tp);
             for (int i = lane; i < n; i += 64) x[i] += t * v[i];
+            moved(t);
+        } else {
+            moved(0.0);
         }
         end_step(a, c, lane);
         return;
@@ -522,6 +536,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
                 x[i] += step_len * v[i];
                 v[i] -= coef * wi;
             }
+            moved(step_len);
             const int nref = S.nref[c] + 1;
             if (lane == 0) {
                 st[1] += 1.0;
@@ -531,6 +546,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
             if (nref > a.rho) {
                 if (lane == 0) st[2] += 1.0;
                 for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+                moved(NAN);
                 end_step(a, c, lane);
             }
             return;
@@ -541,6 +557,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         // pull-back of a reflection
         const double te = fmin(ell, (1.0 - a.pullback) * tlim);
         for (int i = lane; i < n; i += 64) x[i] += te * v[i];
+        moved(te);
         end_step(a, c, lane);
         return;
     }
@@ -564,6 +581,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         x[i] += step_len * v[i];
         v[i] -= coef * wi;
     }
+    moved(step_len);
     const int nref = S.nref[c] + 1;
     if (lane == 0) {
         if (!(nn > 0.0) || status == SPEC_NONSMOOTH || (a.flags && (a.flags[c] & SPEC_FLAG_TIE))) st[4] += 1.0;
@@ -575,6 +593,7 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
         // too many reflections: the chain stays at the step's start point
         if (lane == 0) st[2] += 1.0;
         for (int i = lane; i < n; i += 64) x[i] = S.xs[(size_t)c * n + i];
+        moved(NAN);
         end_step(a, c, lane);
     }
 }

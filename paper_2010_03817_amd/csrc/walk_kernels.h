@@ -49,6 +49,10 @@ struct WalkArgs {
     double* log_buf;   // log_cap records of (x, v, t-, t+, chain, status)
     int32_t* log_count;
     int log_cap, log_chains;
+    // nullable (line walks that carry F(x) over between rounds): per chain the
+    // move s of this round, x <- x + s v along the round's direction; NaN when
+    // x is set otherwise (back to the step start), 0 when it stays
+    double* upd_s;
 };
 
 hipError_t walk_init(const WalkArgs& a, const double* x0, hipStream_t s);

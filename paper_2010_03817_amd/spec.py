@@ -64,7 +64,8 @@ class WalkStats(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("kmax", C.c_int), ("tol", C.c_double), ("refine_ratio", C.c_double),
-                ("tol_loose", C.c_double), ("certify", C.c_int), ("escalate_ratio", C.c_double)]
+                ("tol_loose", C.c_double), ("certify", C.c_int), ("escalate_ratio", C.c_double),
+                ("refresh_period", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -152,6 +153,7 @@ def lib():
     L.spec_diag_phase_profile.argtypes = [vp, C.c_int]
     L.spec_diag_phase_stamps.argtypes = [vp, C.c_int, vp]
     L.spec_diag_stage_times.argtypes = [vp, vp, vp]
+    L.spec_diag_assembly_rows.argtypes = [vp, vp]
     L.spec_diag_mfma_layout.argtypes = [vp]
     L.spec_diag_gemm_f64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     L.spec_diag_lanczos_info.argtypes = [vp, C.c_int, vp]
@@ -232,7 +234,8 @@ class Spectrahedron:
 
     def __init__(self, inst, kmax: int | None = None, tol: float | None = None, **options):
         """options: fields of spec_options (precision, kmax, tol, refine_ratio,
-        tol_loose) over spec_options_default."""
+        tol_loose, certify, escalate_ratio, refresh_period) over
+        spec_options_default."""
         _torch()
         self.inst = inst
         self.n = inst.n
@@ -437,6 +440,12 @@ class Spectrahedron:
         check(lib().spec_diag_stage_times(self._h, out.ctypes.data_as(C.c_void_p), C.byref(ls)))
         names = ["assemble", "predict", "fused", "normal", "update"]
         return {k: (out[i], out[5 + i]) for i, k in enumerate(names)}, ls.value
+
+    def assembly_rows(self):
+        """Pencil rows assembled by line-oracle rounds while timing was on."""
+        r = C.c_double()
+        check(lib().spec_diag_assembly_rows(self._h, C.byref(r)))
+        return r.value
 
     def phase_profile(self, max_chains: int):
         check(lib().spec_diag_phase_profile(self._h, int(max_chains)))

@@ -281,14 +281,15 @@ def test_paper_generator_s200_walk_pairs():
 def _sampled_round(S, g, tau, chains, seed, warm_rounds, count):
     """Segment starts of one round of `chains` billiard chains (the benchmark's
     launch: one workgroup per chain over the whole grid), taken after
-    `warm_rounds` rounds from the centre: the round's record of `count`
-    chains spread evenly over the grid."""
+    `warm_rounds` rounds from the centre: the second round of a walk call, the
+    first whose F(x) is carried over (F(x) + s B(v) from the round before),
+    its record of `count` chains spread evenly over the grid."""
     import torch
     x0 = torch.zeros((chains, N), dtype=torch.float64, device="cuda")
     g.walk(S.BILLIARD, x0, 1 << 30, seed=seed, tau=tau, max_rounds=warm_rounds)
-    _, _, st, log = g.walk(S.BILLIARD, x0, 1 << 30, seed=seed, tau=tau, max_rounds=1, resume=True,
-                           log_chains=chains, log_cap=chains)
-    log = log.cpu().numpy()
+    _, _, st, log = g.walk(S.BILLIARD, x0, 1 << 30, seed=seed, tau=tau, max_rounds=2, resume=True,
+                           log_chains=chains, log_cap=2 * chains)
+    log = log.cpu().numpy()[chains:]  # every chain logs once in the first round
     order = np.argsort(log[:, 2 * N + 2])
     log = log[order]
     pick = np.linspace(0, len(log) - 1, count).astype(int)
@@ -298,8 +299,9 @@ def _sampled_round(S, g, tau, chains, seed, warm_rounds, count):
 @pytest.mark.parametrize("path", ["plain", "learned"])
 def test_bench_launch_of_16384_chains_sampled(wl, path):
     """The benchmark's launch configuration (16384 chains at n = m = 200): t+ of
-    96 sampled segment starts of one round, 20 rounds from the centre
-    (post-reflection starts included), against the oracle's bisection."""
+    96 sampled segment starts of one round with F(x) carried over, 21 rounds
+    from the centre (post-reflection starts included), against the oracle's
+    bisection."""
     S, g, o = wl["S"], wl["g"], wl["o"]
     if path == "learned":
         net, tr = _train(S, g, wl["tau"], seed=78)

@@ -55,6 +55,36 @@ def test_billiard_first_step_matches_oracle():
     assert st["reflections"] == sr[1] and st["calls"] == sr[0]
 
 
+def test_carried_f_takes_the_same_steps():
+    """Line walks assemble F(x) every refresh_period rounds and carry it over
+    as F(x + s v) = F(x) + s B(v) in between: a billiard walk with the default
+    period (16) and one that assembles every round take the same steps (the
+    same calls and reflections, end points to the rounding that reflections
+    amplify); with a reflection cap of one, chains sent back to their step
+    start wait for the next assembly round, with the same cap hits and calls."""
+    S = _S()
+    inst = config1()
+    x0 = np.zeros((64, 10))
+    res = {}
+    for per in (1, 16):
+        g = S.Spectrahedron(inst, refresh_period=per)
+        assert g.options()["refresh_period"] == per
+        for rho in (0, 1):
+            xg, _, st, _ = g.walk(S.BILLIARD, x0, 3, seed=505, tau=1.0, rho=rho)
+            res[per, rho] = (_np(xg), st)
+    for rho in (0, 1):
+        (x1, s1), (x16, s16) = res[1, rho], res[16, rho]
+        print(f"rho {rho}: rounds {s1['rounds']} / {s16['rounds']}, max |dx| {np.abs(x16 - x1).max():.2e}")
+        for k in ("calls", "reflections", "cap_hits", "steps", "not_interior"):
+            assert s1[k] == s16[k], (rho, k, s1[k], s16[k])
+        assert np.allclose(x16, x1, atol=1e-6)
+    assert res[1, 0][1]["rounds"] > 16  # rounds past the first refresh period
+    assert res[1, 1][1]["cap_hits"] > 0
+    assert res[16, 1][1]["rounds"] > res[1, 1][1]["rounds"]  # the chains sent back waited
+    with pytest.raises(S.SpecError):
+        S.Spectrahedron(inst, refresh_period=0)
+
+
 @pytest.mark.parametrize("kind", ["hnr", "billiard"])
 def test_logged_pairs_parity(kind):
     """Per-segment t+- of a running walk against the oracle recomputing the

@@ -17,7 +17,8 @@ extern "C" {
 spec_status spec_diag_mfma_layout(double* host_out);
 
 /* C = A * B (transB = 0: B is K x N) or A * B^T (transB = 1: B is N x K),
- * all row-major float64 host arrays; M, N multiples of 64, K of 16. */
+ * all row-major float64 host arrays; M, N multiples of 64, K of 16 (also
+ * N = 208 with transB = 1: the narrow kernel of the boundary normal). */
 spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A, const double* B, double* C);
 
 /* After an intersect/reflect call of `batch` elements: per element

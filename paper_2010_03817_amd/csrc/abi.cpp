@@ -257,14 +257,20 @@ spec_status curve_oracle(spec_s* h, int batch, const double* horizon, double hsc
     return SPEC_OK;
 }
 
+// The normal GEMM w = vec(u u^T) * Astack^T over bp rows: w_i = u^T A_i u in
+// columns i < n of Wn (208 columns by the narrow kernel when n rounds up to
+// 13 blocks of 16, else the Nn = round_up(n, 64) columns).
+hipError_t normal_gemm(spec_s* h, int bp, hipStream_t s) {
+    const int Kn = round_up(h->P, 16);
+    const int ncols = round_up(h->n, 16) == 208 ? 208 : h->Nn;
+    return gemm_f64(true, bp, ncols, Kn, h->dU2, h->ldA, h->dA + h->ldA, h->ldA, h->dWn, h->Nn, s);
+}
+
 // w = vec(u u^T) * Astack^T for the dense hits, then s and the unit normal.
 spec_status reflect_tail(spec_s* h, int batch, const double* v, const double* tp, int32_t* st, double* s_out,
                          double* w_out, hipStream_t s) {
     const int bp = round_up(batch, 64);
-    if (h->m > 0) {
-        const int Kn = round_up(h->P, 16);
-        HIPCHK(gemm_f64(true, bp, h->Nn, Kn, h->dU2, h->ldA, h->dA + h->ldA, h->ldA, h->dWn, h->Nn, s));
-    }
+    if (h->m > 0) HIPCHK(normal_gemm(h, bp, s));
     ReflectArgs r{};
     r.batch = batch;
     r.n = h->n;
@@ -971,11 +977,7 @@ spec_status walk_rounds(spec_handle h, WalkArgs& a, int kind, int chains, const 
             SPCHK(line_oracle(h, chains, h->wX, h->wV, h->dTm, h->dTp, h->dSt, billiard,
                               billiard ? h->wEll : nullptr, s, billiard, billiard));
         }
-        if (billiard || hmc) {
-            const int Kn = round_up(h->P, 16);
-            if (h->m > 0)
-                HIPCHK(gemm_f64(true, bp, h->Nn, Kn, h->dU2, h->ldA, h->dA + h->ldA, h->ldA, h->dWn, h->Nn, s));
-        }
+        if ((billiard || hmc) && h->m > 0) HIPCHK(normal_gemm(h, bp, s));
         mark(h, 4, s);
         HIPCHK(walk_update(a, s));
         mark(h, 5, s);
@@ -1544,7 +1546,8 @@ spec_status spec_diag_mfma_layout(double* host_out) {
 
 spec_status spec_diag_gemm_f64(int transB, int M, int N, int K, const double* A, const double* B, double* C) {
     if (!A || !B || !C || M < 0 || N < 0 || K < 0) return SPEC_EINVAL;
-    if (M % 64 || N % 64 || K % 16) return SPEC_EINVAL;
+    const bool narrow = transB && N == 208;  // the normal GEMM's 13 column blocks
+    if (M % 64 || (N % 64 && !narrow) || K % 16) return SPEC_EINVAL;
     double *dA = nullptr, *dB = nullptr, *dC = nullptr;
     hipError_t e = dalloc(&dA, (size_t)M * K, false);
     if (e == hipSuccess) e = dalloc(&dB, (size_t)K * N, false);

@@ -267,8 +267,158 @@ __global__ void k_zero_f64(double* __restrict__ C, size_t n) {
     if (i < n) C[i] = 0.0;
 }
 
+// Narrow transposed product C (M x 16 NB, ld ldc) = A (M x K) B^T, B given as
+// 16 NB rows of length K (the normal w = vec(u u^T) Astack^T with n just
+// above a multiple of 64: n = 200 takes 13 column blocks, 208 columns, where
+// the 128-wide tiles would compute 256).  A workgroup of NW waves computes a
+// 16 NW x 16 NB tile; wave w the rows 16 w .. 16 w + 15 against all NB column
+// blocks, so each A operand feeds NB MFMAs.  K slices of 16 go through a double-buffered
+// LDS stage as in k_gemm_f64_128 (the next slice read into registers while
+// the current one is multiplied, one barrier per slice); items are the tiles,
+// or their two K halves added into a zeroed C (ksplit = 2), walked by a
+// persistent grid of about two workgroups per CU, workgroup g in the eighth
+// of the items of its XCD (g mod 8).  M % (16 NW) == 0, K % 16 == 0.
+constexpr int NLA = BK + 1;
+template <int NB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_f64_nt_narrow(int M, int K, const double* __restrict__ A, int lda,
+                                                                const double* __restrict__ B, int ldb,
+                                                                double* __restrict__ C, int ldc, int ksplit) {
+    constexpr int NC = 16 * NB, NLB = NC + 2, NM = 16 * NW;
+    static_assert(NC <= 64 * NW, "one B row per thread");
+    __shared__ double As[2][NM * NLA];
+    __shared__ double Bs[2][BK * NLB];
+    const int total = M / NM;
+    const int items = total * ksplit;
+    const int G = gridDim.x, g = blockIdx.x;
+    const bool ranges = items % 8 == 0 && G % 8 == 0;
+    const int per = items / 8, GX = G / 8;
+    const int nks = K / BK, kmid = (nks / 2) * BK;
+    auto item_at = [&](int i) -> int {
+        if (ranges) {
+            const int j = g / 8 + GX * i;
+            return j < per ? (g % 8) * per + j : -1;
+        }
+        const int it = g + G * i;
+        return it < items ? it : -1;
+    };
+    struct Job {
+        int row0, kbeg, kend;
+    };
+    auto job_of = [&](int it) -> Job {
+        const int part = it / total;
+        Job jb;
+        jb.row0 = (it - part * total) * NM;
+        jb.kbeg = ksplit == 2 && part == 1 ? kmid : 0;
+        jb.kend = ksplit == 2 && part == 0 ? kmid : K;
+        return jb;
+    };
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // one K slice: A rows t / 4, four columns each; B row t (t < NC), 16 columns
+    const int ar = t >> 2, ac = (t & 3) * 4;
+    const bool bown = t < NC;
+    double ra[4], rb[BK];
+    auto fetch = [&](int row0, int k0) {
+        const double* pa = A + (size_t)(row0 + ar) * lda + k0 + ac;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = pa[q];
+        if (bown) {
+            const double* pb = B + (size_t)t * ldb + k0;
+#pragma unroll
+            for (int q = 0; q < BK; ++q) rb[q] = pb[q];
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[buf][ar * NLA + ac + q] = ra[q];
+        if (bown) {
+#pragma unroll
+            for (int q = 0; q < BK; ++q) Bs[buf][q * NLB + t] = rb[q];
+        }
+    };
+    int it = item_at(0);
+    if (it < 0) return;  // uniform over the workgroup
+    Job jb = job_of(it);
+    fetch(jb.row0, jb.kbeg);
+    stash(0);
+    __syncthreads();
+    for (int i = 1;; ++i) {
+        d4 acc[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = jb.kbeg, s = 0; k0 < jb.kend; k0 += BK, ++s) {
+            const int cur = s & 1;
+            const bool more = k0 + BK < jb.kend;
+            if (more) fetch(jb.row0, k0 + BK);
+            const double* as = As[cur];
+            const double* bs = Bs[cur];
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                const double a = as[(16 * wv + (lane & 15)) * NLA + ks + (lane >> 4)];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const double b = bs[(ks + (lane >> 4)) * NLB + 16 * q + (lane & 15)];
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+                }
+            }
+            if (more) stash(cur ^ 1);
+            __syncthreads();
+        }
+        const int nit = item_at(i);
+        Job nj{0, 0, 0};
+        if (nit >= 0) {
+            nj = job_of(nit);
+            fetch(nj.row0, nj.kbeg);
+        }
+        // accumulator r of lane l holds D[l/16 + 4 r][l % 16] of its 16x16 block
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = jb.row0 + 16 * wv + (lane >> 4) + 4 * r;
+                double* pc = &C[(size_t)rr * ldc + 16 * q + (lane & 15)];
+                if (ksplit == 2) unsafeAtomicAdd(pc, acc[q][r]);
+                else __builtin_nontemporal_store(acc[q][r], pc);
+            }
+        if (nit < 0) break;
+        stash(0);
+        __syncthreads();
+        jb = nj;
+    }
+}
+
+static int cu_count() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                     double* C, int ldc, hipStream_t s) {
+    if (transB && N == 208 && M % 64 == 0 && K % BK == 0 && ldc >= N) {
+        if (M == 0) return hipSuccess;
+        // the narrow transposed product (13 column blocks) in 64-row tiles, two
+        // 4-wave workgroups per CU (128-row tiles of one 8-wave workgroup per
+        // CU measured slower); two K halves per tile when the tiles are fewer
+        // than the workgroups that fit
+        const int cus = cu_count(), tiles = M / 64;
+        const int ksplit = tiles < 2 * cus && K >= 4096 ? 2 : 1;
+        if (ksplit == 2) {
+            const size_t n = (size_t)M * ldc;
+            hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, n);
+        }
+        const int items = tiles * ksplit;
+        const int grid = items < 2 * cus ? items : 2 * cus;
+        hipLaunchKernelGGL((k_gemm_f64_nt_narrow<13, 4>), dim3(grid), dim3(256), 0, s, M, K, A, lda, B, ldb, C, ldc,
+                           ksplit);
+        return hipGetLastError();
+    }
     if (M % GT_M || N % GT_N || K % GT_K) return hipErrorInvalidValue;
     if (M == 0 || N == 0) return hipSuccess;
     if (M % BT == 0 && N % BT == 0) {
@@ -282,15 +432,7 @@ hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, 
             hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, n);
         }
         // persistent grid: two workgroups per CU (LDS 68 KB each), at most one per item
-        static int cus = 0;
-        if (cus == 0) {
-            int dev = 0, v = 0;
-            if (hipGetDevice(&dev) == hipSuccess &&
-                hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-                cus = v;
-            else
-                cus = 256;
-        }
+        const int cus = cu_count();
         const int items = tiles * ksplit;
         const int grid = items < 2 * cus ? items : 2 * cus;
         if (transB)

@@ -59,6 +59,23 @@ def test_gemm_f64(transB, shape):
     assert np.allclose(Cg, Cr, rtol=1e-13, atol=1e-13 * np.abs(Cr).max())
 
 
+@pytest.mark.parametrize("shape", [(64, 208, 16), (192, 208, 4112), (640, 208, 80), (1024, 208, 4112),
+                                   (16384, 208, 20112)])
+def test_gemm_f64_narrow_transposed(shape):
+    """The 208-column transposed product of the boundary normal (n = 200):
+    one K slice, several tiles, the split into two K halves (odd slice count)
+    and the full shape of 16384 chains at m = 200, against numpy (the last on
+    a sample of rows)."""
+    rng = np.random.default_rng(2)
+    M, N, K = shape
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((N, K))
+    Cg = _spec().gemm_f64(A, B, True)
+    rows = np.arange(M) if M <= 1024 else np.linspace(0, M - 1, 97).astype(int)
+    Cr = A[rows] @ B.T
+    assert np.allclose(Cg[rows], Cr, rtol=1e-13, atol=1e-13 * np.abs(Cr).max())
+
+
 def _check_intersect(inst, batch, seed, frac_hi=0.95, rel=T_REL):
     S = _spec()
     o = O.Oracle(inst)

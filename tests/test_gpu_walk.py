@@ -85,6 +85,22 @@ def test_carried_f_takes_the_same_steps():
         S.Spectrahedron(inst, refresh_period=0)
 
 
+def test_carried_f_rows_feed_the_later_passes():
+    """In a round that carries F(x) over, the fused kernel writes F(x) to its
+    block for the passes that read it later: the refining pass (far roots
+    from a shifted origin) and the two-sided Cholesky certificate, which
+    factors F(x) + t B(v) at t+ (1 -+ 1e-9).  Every certificate of a billiard
+    walk over 40 rounds (two full assemblies) holds."""
+    S = _S()
+    inst = I.gbase(50, 60, seed=102)
+    g = S.Spectrahedron(inst, certify=1)
+    _, _, st, _ = g.walk(S.BILLIARD, np.zeros((256, 50)), 1 << 30, seed=303, tau=2.0, max_rounds=40)
+    print(st)
+    assert st["rounds"] == 40 and st["calls"] == 256 * 40
+    assert st["refined"] > 0 and st["reflections"] > 0
+    assert st["chol_cert_failed"] == 0 and st["not_interior"] == 0
+
+
 @pytest.mark.parametrize("kind", ["hnr", "billiard"])
 def test_logged_pairs_parity(kind):
     """Per-segment t+- of a running walk against the oracle recomputing the

@@ -43,6 +43,10 @@ def test_status_strings_and_argument_errors():
     o = S.Options()
     assert L.spec_options_default(C.byref(o)) == S.OK
     assert o.kmax == 80 and o.tol == 1e-8 and o.refine_ratio == 1e3 and o.tol_loose == 1e-3
+    assert o.certify == 0 and o.escalate_ratio == 1e-3 and o.refresh_period == 16
+    assert C.sizeof(S.Options) == 56  # the struct of include/spec.h (8 fields and padding)
+    d = C.c_double()
+    assert L.spec_diag_assembly_rows(None, C.byref(d)) == S.EINVAL
     assert L.spec_set_options(None, C.byref(o)) == S.EINVAL
     assert L.spec_walk_state(None, 0) == S.EINVAL
 

@@ -613,7 +613,9 @@ spec_status spec_mlp_predict_dev(spec_mlp net, int rows, const double* x, const 
  * mode 1: lower end certified by Cholesky, upper end by the Ritz value;
  * mode 2: additionally tests F(x + t_hi v), t_hi = exp(log t+_hat + delta),
  * and counts a definite F there as a fallback (informational).  The network
- * must stay alive while attached and have n equal to the handle's. */
+ * must stay alive while attached and have n equal to the handle's.  A run
+ * from the network's shift tests convergence first at Lanczos step 10 (from
+ * the plain origin: step 4). */
 spec_status spec_set_mlp(spec_handle h, spec_mlp net, double delta, int mode);
 /* Autotune the bracket half-width: for each of the ncand candidates, time the
  * learned reflection (mode 1) of `batch` device pairs (x, v) on `stream` with

@@ -1098,6 +1098,12 @@ struct spec_batch_s {
     int* dCounter = nullptr;
     int2* dRList = nullptr;         // refinement queue shared by the instances
     int* dRCnt = nullptr;
+    // one launch each for every instance's coefficient rows, pencil assembly
+    // and walk update (their arguments are uploaded by each batch_rounds call)
+    ZRows* dZRows = nullptr;
+    GemmItem* dGemm = nullptr;
+    WalkArgs* dWalk = nullptr;
+    int gemm_items = 0;
     std::vector<unsigned> gens;  // handles' workspace generations the plan was built for
     struct Cls { int off, count, max_m, kmax, nblocks; };
     std::vector<Cls> all, classes;
@@ -1108,6 +1114,10 @@ struct spec_batch_s {
         dfree(dCounter);
         dfree(dRList);
         dfree(dRCnt);
+        dfree(dZRows);
+        dfree(dGemm);
+        dfree(dWalk);
+        gemm_items = 0;
         chains = 0;
         all.clear();
         classes.clear();
@@ -1189,6 +1199,9 @@ spec_status batch_plan(spec_batch_s* b, int chains) {
     HIPCHK(dalloc(&b->dArgsRef, (size_t)K, false));
     HIPCHK(dalloc(&b->dWork, work.size(), false));
     HIPCHK(dalloc(&b->dCounter, 1));
+    HIPCHK(dalloc(&b->dZRows, (size_t)K, false));
+    HIPCHK(dalloc(&b->dGemm, (size_t)K, false));
+    HIPCHK(dalloc(&b->dWalk, (size_t)K, false));
     HIPCHK(hipMemcpy(b->dArgs, args.data(), sizeof(FusedArgs) * K, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->dArgsRef, argsRef.data(), sizeof(FusedArgs) * K, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->dWork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
@@ -1196,16 +1209,38 @@ spec_status batch_plan(spec_batch_s* b, int chains) {
     return SPEC_OK;
 }
 
-// One oracle round of every instance's walk (line oracle, both ends) and the
-// walk update: per-instance assembly, the fused oracle by the batch's
-// strategy, per-instance update.
-spec_status batch_round(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, int strategy, hipStream_t s) {
+// The arguments of the batch's one-launch assembly and walk update for the
+// walks wa: every instance's coefficient rows (its walk state), its pencil
+// GEMM (rows [F; B] of 2 bp, 128 x 128 tiles numbered consecutively) and
+// its WalkArgs, copied to the plan's device arrays.
+spec_status batch_upload(spec_batch_s* b, const std::vector<WalkArgs>& wa, int chains) {
     const int K = (int)b->hs.size();
+    const int bp = round_up(chains, 64);
+    std::vector<ZRows> zr(K);
+    std::vector<GemmItem> gi(K);
+    int tile0 = 0;
     for (int i = 0; i < K; ++i) {
         spec_handle h = b->hs[i];
-        int bp = 0;
-        SPCHK(assemble(h, chains, h->wX, h->wV, &bp, s));
+        zr[i] = ZRows{h->n, h->Kpad, h->wX, h->wV, h->dZ};
+        gi[i] = GemmItem{h->dZ, h->dA, h->dFB, h->Kpad, h->ldA, h->ldA, 2 * bp, h->ldA, h->Kpad, tile0};
+        tile0 += (2 * bp / 128) * (h->ldA / 128);  // 2 bp and ldA are multiples of 128
     }
+    HIPCHK(hipMemcpy(b->dZRows, zr.data(), sizeof(ZRows) * K, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->dGemm, gi.data(), sizeof(GemmItem) * K, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->dWalk, wa.data(), sizeof(WalkArgs) * K, hipMemcpyHostToDevice));
+    b->gemm_items = tile0;
+    return SPEC_OK;
+}
+
+// One oracle round of every instance's walk (line oracle, both ends) and the
+// walk update: the assembly of every instance in one grouped GEMM launch, the
+// fused oracle by the batch's strategy, the walk updates in one launch
+// (arguments from batch_upload).
+spec_status batch_round(spec_batch_s* b, int chains, int strategy, hipStream_t s) {
+    const int K = (int)b->hs.size();
+    const int bp = round_up(chains, 64);
+    HIPCHK(launch_build_z_multi(b->dZRows, K, chains, bp, s));
+    HIPCHK(gemm_f64_grouped(b->dGemm, K, b->gemm_items, s));
     if (strategy == 3 || K == 1) {
         for (int i = 0; i < K; ++i) {
             spec_handle h = b->hs[i];
@@ -1225,7 +1260,7 @@ spec_status batch_round(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, 
         HIPCHK(launch_line_refine(none, b->dArgsRef, b->dRList, b->dRCnt, b->dRCnt + 1, a.max_m, a.kmax,
                                   persistent_blocks(a.max_m, a.kmax), s));
     }
-    for (int i = 0; i < K; ++i) HIPCHK(walk_update(wa[i], s));
+    HIPCHK(walk_update_multi(b->dWalk, K, chains, s));
     return SPEC_OK;
 }
 
@@ -1233,14 +1268,16 @@ spec_status batch_round(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, 
 spec_status batch_rounds(spec_batch_s* b, std::vector<WalkArgs>& wa, int chains, int strategy, long long rounds,
                          bool graph, hipStream_t s) {
     if (rounds <= 0) return SPEC_OK;
+    HIPCHK(hipStreamSynchronize(s));  // the previous rounds are done with the arguments
+    SPCHK(batch_upload(b, wa, chains));
     if (!graph) {
-        for (long long r = 0; r < rounds; ++r) SPCHK(batch_round(b, wa, chains, strategy, s));
+        for (long long r = 0; r < rounds; ++r) SPCHK(batch_round(b, chains, strategy, s));
         return SPEC_OK;
     }
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    spec_status rc = batch_round(b, wa, chains, strategy, s);
+    spec_status rc = batch_round(b, chains, strategy, s);
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (rc != SPEC_OK) {
         if (g) (void)hipGraphDestroy(g);

@@ -13,6 +13,7 @@
 // contiguous range of N tiles: a B panel is then fetched into one XCD's L2
 // and reused there by every M tile.
 #include "common.h"
+#include "spec_kernels.h"
 
 namespace spec {
 
@@ -261,6 +262,113 @@ __global__ __launch_bounds__(256) void k_gemm_f64_128(int M, int N, int K, const
     }
 }
 
+// A group of independent products C_k = A_k B_k (B not transposed) in one
+// persistent launch: the 128 x 128 tiles of every product are items
+// d[k].tile0 .. d[k].tile0 + tiles_k - 1 (tiles_k = M_k N_k / 128^2, M_k and
+// N_k multiples of 128, K_k of 16), walked by the workgroups in steps of the
+// grid; each tile is computed exactly as k_gemm_f64_128 computes it (the same
+// K slices, LDS stage and MFMA order), so the results are bit for bit those
+// of one launch per product.  For the many small assemblies of an uneven
+// batch, whose launches would otherwise outnumber their work.
+__global__ __launch_bounds__(256) void k_gemm_f64_128_grouped(const GemmItem* __restrict__ d, int count,
+                                                              int items) {
+    __shared__ double As[2][BT * LAS];
+    __shared__ double Bs[2][BK * LBS];
+    const int G = gridDim.x, g = blockIdx.x;
+    struct Job {
+        const double* A;
+        const double* B;
+        double* C;
+        int lda, ldb, ldc, K, row0, col0;
+    };
+    auto job_of = [&](int it) -> Job {
+        int lo = 0, hi = count - 1;  // the last product whose first item is <= it
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].tile0 <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmItem& q = d[lo];
+        const int lin = it - q.tile0, tilesM = q.M / BT;
+        return Job{q.A, q.B, q.C, q.lda, q.ldb, q.ldc, q.K, (lin % tilesM) * BT, (lin / tilesM) * BT};
+    };
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;
+    const int ar = t >> 1, ac = (t & 1) * 8;
+    const int br = t >> 4, bc = (t & 15) * 8;
+    double ra[8], rb[8];
+    auto fetch = [&](const Job& jb, int k0) {
+        const double* pa = jb.A + (size_t)(jb.row0 + ar) * jb.lda + k0 + ac;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ra[q] = pa[q];
+        const double* pb = jb.B + (size_t)(k0 + br) * jb.ldb + jb.col0 + bc;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rb[q] = pb[q];
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[buf][ar * LAS + ac + q] = ra[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[buf][br * LBS + bc + q] = rb[q];
+    };
+    int it = g;
+    if (it >= items) return;  // uniform over the workgroup
+    Job jb = job_of(it);
+    fetch(jb, 0);
+    stash(0);
+    __syncthreads();
+    for (;;) {
+        d4 acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0, s = 0; k0 < jb.K; k0 += BK, ++s) {
+            const int cur = s & 1;
+            const bool more = k0 + BK < jb.K;
+            if (more) fetch(jb, k0 + BK);
+            const double* as = As[cur];
+            const double* bs = Bs[cur];
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                double a[4], b[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] = as[(wr + q * 16 + (lane & 15)) * LAS + ks + (lane >> 4)];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[q] = bs[(ks + (lane >> 4)) * LBS + wc + q * 16 + (lane & 15)];
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p][q], 0, 0, 0);
+            }
+            if (more) stash(cur ^ 1);
+            __syncthreads();
+        }
+        const int nit = it + G;
+        Job nj{};
+        if (nit < items) {
+            nj = job_of(nit);
+            fetch(nj, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = jb.row0 + wr + p * 16 + (lane >> 4) + 4 * r;
+                    const int cc = jb.col0 + wc + q * 16 + (lane & 15);
+                    __builtin_nontemporal_store(acc[p][q][r], &jb.C[(size_t)rr * jb.ldc + cc]);
+                }
+        if (nit >= items) break;
+        stash(0);
+        __syncthreads();
+        jb = nj;
+        it = nit;
+    }
+}
+
 // C = 0 by a kernel (no memset node when the launch is captured into a graph).
 __global__ void k_zero_f64(double* __restrict__ C, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,6 +556,14 @@ hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, 
         hipLaunchKernelGGL(k_gemm_f64<true>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
     else
         hipLaunchKernelGGL(k_gemm_f64<false>, dim3(tiles), dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t gemm_f64_grouped(const GemmItem* d, int count, int items, hipStream_t s) {
+    if (count <= 0 || items <= 0) return hipSuccess;
+    const int cus = cu_count();
+    const int grid = items < 2 * cus ? items : 2 * cus;
+    hipLaunchKernelGGL(k_gemm_f64_128_grouped, dim3(grid), dim3(256), 0, s, d, count, items);
     return hipGetLastError();
 }
 

@@ -7,10 +7,8 @@ namespace spec {
 
 // Rows c < batch as above; rows batch <= c < zrow0 of both halves are zero
 // (the padding rows of the GEMM: defined whatever the buffer held before).
-__global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__ x, const double* __restrict__ v,
-                          double* __restrict__ Z, int zrow0) {
-    const int c = blockIdx.x;
-    if (c >= zrow0) return;
+__device__ __forceinline__ void build_z_row(int c, int batch, int n, int Kpad, const double* __restrict__ x,
+                                            const double* __restrict__ v, double* __restrict__ Z, int zrow0) {
     double* zf = Z + (size_t)c * Kpad;
     double* zb = Z + (size_t)(zrow0 + c) * Kpad;
     const bool live = c < batch;
@@ -26,6 +24,19 @@ __global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__
         zf[k] = fx;
         zb[k] = bv;
     }
+}
+
+__global__ void k_build_z(int batch, int n, int Kpad, const double* __restrict__ x, const double* __restrict__ v,
+                          double* __restrict__ Z, int zrow0) {
+    const int c = blockIdx.x;
+    if (c >= zrow0) return;
+    build_z_row(c, batch, n, Kpad, x, v, Z, zrow0);
+}
+
+// The rows of `count` spectrahedra in one launch: zrow0 blocks per instance.
+__global__ void k_build_z_multi(const ZRows* __restrict__ d, int batch, int zrow0) {
+    const ZRows& z = d[blockIdx.x / zrow0];
+    build_z_row(blockIdx.x % zrow0, batch, z.n, z.Kpad, z.x, z.v, z.Z, zrow0);
 }
 
 // Compact rows: for j < count, rows k * zc0 + j of Zc = rows k * z0 + list[j]
@@ -55,6 +66,13 @@ hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const dou
     if (batch <= 0) return hipSuccess;
     if (zrow0 < batch) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_build_z, dim3(zrow0), dim3(64), 0, s, batch, n, Kpad, x, v, Z, zrow0);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_z_multi(const ZRows* d, int count, int batch, int zrow0, hipStream_t s) {
+    if (batch <= 0 || count <= 0) return hipSuccess;
+    if (zrow0 < batch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_build_z_multi, dim3(count * zrow0), dim3(64), 0, s, d, batch, zrow0);
     return hipGetLastError();
 }
 

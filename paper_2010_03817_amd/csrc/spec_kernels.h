@@ -36,12 +36,33 @@ enum : int {
 
 hipError_t gemm_f64(bool transB, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                     double* C, int ldc, hipStream_t s);
+// One product of a grouped launch: C = A B (B not transposed; M, N multiples
+// of 128, K of 16), its 128 x 128 tiles numbered from tile0 (products in
+// increasing tile0, consecutive).
+struct GemmItem {
+    const double* A;
+    const double* B;
+    double* C;
+    int lda, ldb, ldc, M, N, K, tile0;
+};
+// `count` products (d: device array), `items` tiles in all, in one launch;
+// each tile bit for bit as gemm_f64 computes it.
+hipError_t gemm_f64_grouped(const GemmItem* d, int count, int items, hipStream_t s);
 hipError_t mfma_probe(double* out, hipStream_t s);
 
 // Assembly rows: Z[c] = [1, x_c] (F) and Z[zrow0 + c] = [0, v_c] (B), padded with zeros;
 // rows batch <= c < zrow0 of both halves are zero (zrow0 >= batch).
+// Coefficient rows of one spectrahedron of a batch for launch_build_z_multi.
+struct ZRows {
+    int n, Kpad;
+    const double* x;
+    const double* v;
+    double* Z;
+};
 hipError_t launch_build_z(int batch, int n, int Kpad, const double* x, const double* v, double* Z, int zrow0,
                           hipStream_t s);
+// launch_build_z of `count` spectrahedra (d: device array) in one launch.
+hipError_t launch_build_z_multi(const ZRows* d, int count, int batch, int zrow0, hipStream_t s);
 
 // Compact copy of the coefficient rows of the chains in list[0 .. count):
 // rows k * zc0 + j of Zc = rows k * z0 + list[j] of Z, k < nrows; the rows

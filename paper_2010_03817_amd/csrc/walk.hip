@@ -295,10 +295,8 @@ __device__ inline void end_step(const WalkArgs& a, int c, int lane) {
     if (k < a.steps) begin_step(a, c, k, lane);
 }
 
-// One wave per chain.
-__global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+// The round's update of chain c by one wave (lane: its lane).
+__device__ __forceinline__ void walk_update_chain(const WalkArgs& a, int c, int lane) {
     if (c >= a.chains) return;
     const WalkState& S = a.st;
     // the move of this round for a carried-over F(x) (see WalkArgs::upd_s)
@@ -598,6 +596,18 @@ __global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
     }
 }
 
+// One wave per chain.
+__global__ __launch_bounds__(256) void k_walk_update(WalkArgs a) {
+    walk_update_chain(a, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
+}
+
+// Every walk of a batch in one launch: bpi blocks of four chains per walk,
+// walk k = blockIdx.x / bpi with its arguments in args[k] (device memory).
+__global__ __launch_bounds__(256) void k_walk_update_multi(const WalkArgs* __restrict__ args, int bpi) {
+    const WalkArgs& a = args[blockIdx.x / bpi];
+    walk_update_chain(a, (blockIdx.x % bpi) * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
+}
+
 __global__ void k_walk_finish(WalkArgs a, double* __restrict__ x_out) {
     const int c = blockIdx.x;
     if (c >= a.chains) return;
@@ -739,6 +749,12 @@ hipError_t walk_init(const WalkArgs& a, const double* x0, hipStream_t s) {
 }
 hipError_t walk_update(const WalkArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_walk_update, dim3((a.chains + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t walk_update_multi(const WalkArgs* dargs, int count, int chains, hipStream_t s) {
+    if (count <= 0 || chains <= 0) return hipSuccess;
+    const int bpi = (chains + 3) / 4;
+    hipLaunchKernelGGL(k_walk_update_multi, dim3(count * bpi), dim3(256), 0, s, dargs, bpi);
     return hipGetLastError();
 }
 hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s) {

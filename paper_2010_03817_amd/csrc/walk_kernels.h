@@ -57,6 +57,9 @@ struct WalkArgs {
 
 hipError_t walk_init(const WalkArgs& a, const double* x0, hipStream_t s);
 hipError_t walk_update(const WalkArgs& a, hipStream_t s);
+// The update of `count` walks of `chains` chains each in one launch; dargs:
+// their WalkArgs in device memory.
+hipError_t walk_update_multi(const WalkArgs* dargs, int count, int chains, hipStream_t s);
 hipError_t walk_finish(const WalkArgs& a, double* x_out, hipStream_t s);
 hipError_t walk_count_active(int chains, const int32_t* active, int32_t* out, hipStream_t s);
 hipError_t walk_sum_stats(int chains, const double* stats, double* out, hipStream_t s);

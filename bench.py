@@ -219,6 +219,8 @@ def summary(run, chains, calls_per_step=None):
         "noconv": st["noconv"],
         "not_interior": st["not_interior"],
         "cert_fallback_rate": st["cert_fallback"] / max(calls, 1),
+        # calls whose t+ carries a certified interval of width <= 2e-9 t+
+        "certified_rate": 1.0 - st["uncertified"] / max(calls, 1),
         "refined_rate": st["refined"] / max(calls, 1),
         "refine_failed": st["refine_failed"],
         "stage_ms_per_round": {k: v[0] / max(v[1], 1) for k, v in run["stages"].items()},

@@ -211,8 +211,11 @@ spec_status spec_intersect_dev(spec_handle h, int batch, const double* x, const 
  * t_hi the returned t+.  The interval is a posteriori: the gap uses the second
  * Ritz value, which bounds lambda_2 from above.  Elements whose interval is
  * wider than 2e-9 t+ are counted as uncertified (spec_walk_stats) and carry
- * bit 32 in spec_diag_call_flags; NaN when there is none (no dense hit was
- * computed, or a status other than OK / NONSMOOTH / CERT_FALLBACK). */
+ * bit 32 in spec_diag_call_flags; t_lo is -inf (no certified lower end) when
+ * T_k shows no gap above theta (a second Ritz value at theta: a copy of the
+ * converged one that a run continued past convergence grows) or the run did
+ * not converge (SPEC_NOCONV); both NaN when there is no interval (no root was
+ * computed: SPEC_NOT_INTERIOR, or membership only). */
 spec_status spec_certificates(spec_handle h, int batch, double* t_lo, double* t_hi);
 
 /* REFLECTION (Alg. REFLECTION, eq. (reflection)) for lines: t_plus as above,
@@ -614,7 +617,7 @@ spec_status spec_mlp_predict_dev(spec_mlp net, int rows, const double* x, const 
  * mode 2: additionally tests F(x + t_hi v), t_hi = exp(log t+_hat + delta),
  * and counts a definite F there as a fallback (informational).  The network
  * must stay alive while attached and have n equal to the handle's.  A run
- * from the network's shift tests convergence first at Lanczos step 10 (from
+ * from the network's shift tests convergence first at Lanczos step 6 (from
  * the plain origin: step 4). */
 spec_status spec_set_mlp(spec_handle h, spec_mlp net, double delta, int mode);
 /* Autotune the bracket half-width: for each of the ncand candidates, time the

@@ -1868,7 +1868,7 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
     int flags = 0;
     // Kato-Temple interval of the dense t+ (wave 0, lane 0 keeps it)
     bool kt_set = false;
-    double kt_lo = NAN, kt_hi = NAN;
+    double kt_lo = NAN;
     int32_t st = SPEC_OK;
     long long* prof = a.prof ? a.prof + (size_t)chain * SPEC_DIAG_PHASE_SLOTS : nullptr;
 #define STAMP(i) \
@@ -2124,7 +2124,6 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
                     if (gap > 0.0 && isfinite(r)) {
                         const double d = r * r / gap;
                         kt_lo = t0 - 1.0 / (lmin - d);
-                        kt_hi = t0 - 1.0 / lmin;
                     }
                 }
             }
@@ -2162,14 +2161,20 @@ __device__ __forceinline__ void line_fused_chain(const FusedArgs& a, int chain, 
         if ((kt_set || (!REFINE && hit != HIT_DENSE)) && st != SPEC_NOT_INTERIOR && !a.membership_only) {
             double lo = tp, hi = tp;
             if (hit == HIT_DENSE) {
-                lo = kt_lo;
-                hi = kt_hi;
+                // the returned value is the upper end; no certified lower end
+                // (-inf) when T_k gave no gap or the run did not converge
+                lo = kt_lo == kt_lo ? kt_lo : -INFINITY;
+                hi = tp;
                 if (!(hi - lo <= 2e-9 * fabs(hi))) flags |= SPEC_FLAG_UNCERTIFIED;
             }
             if (a.cert) {
                 a.cert[2 * chain] = lo;
                 a.cert[2 * chain + 1] = hi;
             }
+        } else if (!REFINE && a.cert) {
+            // none (no dense root computed, or one the refining pass fixes)
+            a.cert[2 * chain] = NAN;
+            a.cert[2 * chain + 1] = NAN;
         }
         const int keep = kt_set ? ~(SPEC_FLAG_REFINE_FAILED | SPEC_FLAG_TIE | SPEC_FLAG_UNCERTIFIED)
                                 : ~(SPEC_FLAG_REFINE_FAILED | SPEC_FLAG_TIE);

@@ -217,9 +217,16 @@ def test_membership_and_statuses():
     rng = np.random.default_rng(15)
     x = rng.standard_normal((200, 8)) * 0.6
     assert np.array_equal(_np(g.membership(x)), o.membership(x))
-    # outside point: NOT_INTERIOR with NaN values
-    tm, tp, st = [_np(a) for a in g.intersect(np.full((1, 8), 20.0), np.ones((1, 8)))]
-    assert st[0] == S.NOT_INTERIOR and np.isnan(tp[0]) and np.isnan(tm[0])
+    # outside point: NOT_INTERIOR with NaN values, and a NaN certificate
+    # beside an interior call's [t_lo, t+] (an interior call first, so that a
+    # stale interval would show)
+    xs = np.vstack([np.zeros((1, 8)), np.full((1, 8), 20.0)])
+    g.intersect(np.zeros((2, 8)), np.ones((2, 8)))
+    tm, tp, st = [_np(a) for a in g.intersect(xs, np.ones((2, 8)))]
+    assert st[1] == S.NOT_INTERIOR and np.isnan(tp[1]) and np.isnan(tm[1])
+    lo, hi = g.certificates(2)
+    assert st[0] == S.OK and hi[0] == tp[0] and lo[0] <= tp[0]
+    assert np.isnan(lo[1]) and np.isnan(hi[1])
     # a half-space is unbounded
     hs = I.polytope(np.array([[1.0, 0.0]]), np.array([1.0]))
     tm, tp, st = [_np(a) for a in S.Spectrahedron(hs).intersect(np.zeros((2, 2)), np.array([[0.0, 1.0], [1, 0]]))]

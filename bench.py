@@ -12,7 +12,7 @@ for the learned-bracket path (network trained on the walk's own segment
 starts, half-width autotuned, every t+ certified by an FP64 Cholesky factor);
 `value` is the learned path's rate, the plain path's is under "plain".
 
-Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -961,7 +961,7 @@ def main():
                     help="run one device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus})", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only (asked for {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
     import torch
